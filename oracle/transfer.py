@@ -1,0 +1,89 @@
+"""Grid-transfer operators (oracle; test infrastructure only).
+
+* Coarsening (Sect. 4.1): the coarse grid keeps every second point along x, y and z,
+  both vertical boundaries included (Sect. 4.2: odd N_z at every level).
+* Restriction (Sect. 4.4): full weighting, the 27-point tensor product of the 1D
+  weights [1/4, 1/2, 1/4] centred on fine index 2c.  Periodic in x and y.  At the two
+  vertical boundary planes the reading is [1/2 self, 1/2 inward neighbour], which keeps
+  the trapezoid sum of a field exactly (the paper states full weighting conserves the
+  domain integral).  Weights are in index space.
+* Prolongation (Sect. 4.5): trilinear, the 8-point tensor product of 1D linear
+  interpolation.  In x and y (uniform, periodic) an odd fine point is the mean of its
+  two coarse neighbours; in z the weights are linear in the physical height.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _restrict_periodic(q, axis):
+    fw = 0.25 * np.roll(q, 1, axis=axis) + 0.5 * q + 0.25 * np.roll(q, -1, axis=axis)
+    sl = [slice(None)] * q.ndim
+    sl[axis] = slice(0, None, 2)
+    return fw[tuple(sl)]
+
+
+def _restrict_z(q, axis):
+    q = np.moveaxis(q, axis, 0)
+    nz = q.shape[0]
+    ncz = (nz - 1) // 2 + 1
+    out = np.empty((ncz,) + q.shape[1:])
+    out[0] = 0.5 * q[0] + 0.5 * q[1]
+    out[-1] = 0.5 * q[nz - 1] + 0.5 * q[nz - 2]
+    for K in range(1, ncz - 1):
+        out[K] = 0.25 * q[2 * K - 1] + 0.5 * q[2 * K] + 0.25 * q[2 * K + 1]
+    return np.moveaxis(out, 0, axis)
+
+
+def restrict(q):
+    """Full-weighting restriction of q[..., nz, ny, nx] to [..., (nz+1)/2, ny/2, nx/2]."""
+    q = np.asarray(q, dtype=np.float64)
+    assert q.shape[-1] % 2 == 0 and q.shape[-2] % 2 == 0 and q.shape[-3] % 2 == 1
+    q = _restrict_periodic(q, q.ndim - 1)
+    q = _restrict_periodic(q, q.ndim - 2)
+    return _restrict_z(q, q.ndim - 3)
+
+
+def _prolong_periodic(q, axis):
+    q = np.moveaxis(q, axis, 0)
+    n = q.shape[0]
+    out = np.empty((2 * n,) + q.shape[1:])
+    out[0::2] = q
+    out[1::2] = 0.5 * (q + np.roll(q, -1, axis=0))
+    return np.moveaxis(out, 0, axis)
+
+
+def _prolong_z(q, axis, zf):
+    q = np.moveaxis(q, axis, 0)
+    nzc = q.shape[0]
+    nz = 2 * (nzc - 1) + 1
+    assert len(zf) == nz
+    out = np.empty((nz,) + q.shape[1:])
+    out[0::2] = q
+    for K in range(nzc - 1):
+        t = (zf[2 * K + 1] - zf[2 * K]) / (zf[2 * K + 2] - zf[2 * K])
+        out[2 * K + 1] = (1.0 - t) * q[K] + t * q[K + 1]
+    return np.moveaxis(out, 0, axis)
+
+
+def prolong(qc, zf):
+    """Trilinear prolongation of qc[..., nzc, nyc, nxc] to the fine grid with heights zf."""
+    qc = np.asarray(qc, dtype=np.float64)
+    q = _prolong_periodic(qc, qc.ndim - 1)
+    q = _prolong_periodic(q, q.ndim - 2)
+    return _prolong_z(q, q.ndim - 3, np.asarray(zf))
+
+
+PRIMITIVES = ("T", "ne", "nH", "ntot", "vx", "vy", "vz")
+
+
+def coarsen_atmosphere(atmos):
+    """Coarse-grid model atmosphere by full weighting of the primitives (Sect. 4.7)."""
+    out = {
+        "nx": atmos["nx"] // 2, "ny": atmos["ny"] // 2, "nz": (atmos["nz"] - 1) // 2 + 1,
+        "dx": 2.0 * atmos["dx"], "dy": 2.0 * atmos["dy"], "z": np.asarray(atmos["z"])[::2].copy(),
+    }
+    for k in PRIMITIVES:
+        out[k] = restrict(atmos[k])
+    out["chi_c"] = None if atmos.get("chi_c") is None else restrict(atmos["chi_c"])
+    return out

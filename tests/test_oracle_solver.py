@@ -1,0 +1,172 @@
+"""Pins of the oracle's rate solve, MALI, FAS and FMG (no GPU).
+
+Closed forms (two-level MALI step, sqrt(eps) law), special cases (LTE limit, one grid
+= MALI, homogeneous 3D = 1D), invariants (conservation, positivity, FAS fixed point)
+and a brute-force discrete solution (dense linear solve of the two-level problem).
+"""
+import numpy as np
+import pytest
+
+from oracle import physics as ph
+from oracle.formal import formal_solution
+from oracle.levels import Level, build_hierarchy
+from oracle.rates import apply_W, fine_rhs, solve, source_function, zero_radiation
+from oracle.solver import Params, mali, solve_fas, solve_mali, vcycle
+from paper_1701_01607_amd import synth
+from tests.oracle_reference import exact_two_level_column, two_level_pops_from_S
+
+
+def column_atmos(nz, nxy=2, dz=25 * synth.KM, tau_top=1e-4, eps=1e-4):
+    """Isothermal two-level column whose top plane has line-centre tau ~ tau_top."""
+    atom = synth.two_level_atom(eps)
+    atm = synth.atmos_isothermal(nx=nxy, ny=nxy, nz=nz, dz=dz)
+    lev = Level(atom, atm)
+    n = zero_radiation(lev)
+    kk, _ = lev.line_coefficients(n)
+    chi0 = kk[0, -1, 0, 0] / (np.sqrt(np.pi) * lev.nu0[0] * lev.vD[-1, 0, 0] / ph.C)
+    atm["ntot"] = atm["ntot"] * tau_top / (chi0 * 150 * synth.KM)
+    return atom, atm
+
+
+def six_level_small(nx=8, ny=8, nz=17, nfreq=13, seed=5, thin=1e-2):
+    atom = synth.caii_like_atom(nfreq)
+    atm = synth.atmos_stratified(nx=nx, ny=ny, nz=nz, dx=150 * synth.KM, seed=seed)
+    atm["ntot"] = atm["ntot"] * thin      # moderately thick lines: fast MALI for tests
+    return atom, atm
+
+
+def test_two_level_mali_step_equals_closed_form():
+    eps = 1e-3
+    atom = synth.two_level_atom(eps)
+    atm = synth.atmos_isothermal(nx=4, ny=4, nz=10)
+    rng = np.random.default_rng(4)
+    atm["vx"] = rng.uniform(-2e5, 2e5, atm["vx"].shape)
+    lev = Level(atom, atm)
+    n = zero_radiation(lev)
+    Jeff, omL = formal_solution(lev, n)
+    n_new = solve(lev, Jeff, omL, fine_rhs(lev))
+    S_new = source_function(lev, n_new)[0]
+    B = lev.B[0]
+    closed = ((1 - eps) * Jeff[0] + eps * B) / (1 - (1 - eps) * (1 - omL[0]))
+    assert np.allclose(S_new, closed, rtol=1e-10)
+
+
+def test_conservation_and_positivity_six_level():
+    atom, atm = six_level_small(thin=1.0)
+    lev = Level(atom, atm)
+    f = fine_rhs(lev)
+    n = zero_radiation(lev)
+    for _ in range(4):
+        n, _ = mali(lev, 1, n, f, 1)
+        assert np.allclose(n.sum(axis=0), lev.ntot, rtol=1e-14)
+        assert np.all(n > 0)
+
+
+def test_W_at_n_equals_unpreconditioned_statistical_equilibrium():
+    atom, atm = six_level_small(nx=4, ny=4, nz=9)
+    lev = Level(atom, atm)
+    n = zero_radiation(lev)
+    Jeff, omL, Jbar = formal_solution(lev, n, want_jbar=True)
+    W = apply_W(lev, n, Jeff, omL)
+    # plain rates with Jbar
+    P = lev.fixed.copy()
+    for l in range(lev.nline):
+        A, Bij, Bji = lev.einstein[l]
+        i, j = lev.lower[l], lev.upper[l]
+        P[i, j] += Bij * Jbar[l]
+        P[j, i] += A + Bji * Jbar[l]
+    out = np.einsum("i...,ij...->i...", n, P) - np.einsum("j...,ji...->i...", n, P)
+    out[0] = n.sum(axis=0)
+    scale = np.einsum("i...,ij...->i...", n, P).max(axis=0)
+    assert np.max(np.abs(W[1:] - out[1:]) / scale) < 1e-9
+    assert np.allclose(W[0], out[0], rtol=1e-15)
+
+
+def test_lte_limit_when_collisions_dominate():
+    atom, atm = six_level_small(nx=4, ny=4, nz=9)
+    for c in atom["collisions"]:
+        c["c_ul"] *= 1e12
+    n, st, lev = solve_mali(atom, atm, Params(tol_C=1e-10, E_target=None, max_iter=20))
+    assert np.max(np.abs(n / lev.nstar - 1.0)) < 1e-6
+    S = source_function(lev, n)
+    assert np.allclose(S, lev.B, rtol=1e-6)
+
+
+def test_homogeneous_3d_equals_1d_column():
+    atom = synth.two_level_atom()
+    atm3 = synth.atmos_isothermal(nx=16, ny=16, nz=32)
+    atm1 = synth.atmos_isothermal(nx=1, ny=1, nz=32)
+    n3, _, _ = solve_mali(atom, atm3, Params(), iters=3)
+    n1, _, _ = solve_mali(atom, atm1, Params(), iters=3)
+    assert np.allclose(n3, np.broadcast_to(n1, n3.shape), rtol=1e-12)
+
+
+def test_one_grid_fas_is_mali_bitwise():
+    atom, atm = six_level_small(nx=4, ny=4, nz=9)
+    p = Params(nlev=1, nu1=2, nu2=1)
+    nf, _, _ = solve_fas(atom, atm, p, cycles=3)
+    nm, _, _ = solve_mali(atom, atm, p, iters=9)
+    assert np.array_equal(nf, nm)
+
+
+@pytest.fixture(scope="module")
+def exact_column():
+    atom, atm = column_atmos(nz=41, nxy=4, dz=100 * synth.KM, eps=1e-2)
+    S, n, lev = exact_two_level_column(atom, atm)
+    return atom, atm, S, n, lev
+
+
+def test_mali_fixed_point_is_the_discrete_solution(exact_column):
+    atom, atm, S, n, lev = exact_column
+    n1, C = mali(lev, 1, n, fine_rhs(lev), 1)
+    assert C < 1e-10
+    # and MALI from zero radiation approaches it
+    n0 = zero_radiation(lev)
+    err = []
+    nn = n0
+    for _ in range(3):
+        nn, _ = mali(lev, 1, nn, fine_rhs(lev), 5)
+        err.append(np.max(np.abs(nn / n - 1)))
+    assert err[0] > err[1] > err[2]
+
+
+def test_fas_fixed_point_and_convergence_to_discrete_solution(exact_column):
+    atom, atm, S, n, lev = exact_column
+    p = Params(nlev=3, nu1=2, nu2=2, nu3=6, nu_fmg=6, E_target=1e-7)
+    levels = build_hierarchy(atom, atm, 3)
+    n_after = vcycle(levels, 3, n.copy(), fine_rhs(levels[-1]), p)
+    assert np.max(np.abs(n_after / n - 1)) < 1e-9
+    nf, st, _ = solve_fas(atom, atm, p, levels=levels)
+    assert st.E_est[-1] <= 1e-7
+    assert np.max(np.abs(nf / n - 1)) < 4 * st.E_est[-1] + 1e-9
+    nfmg, st2, _ = solve_fas(atom, atm, p, fmg=True, levels=levels)
+    assert np.max(np.abs(nfmg / n - 1)) < 4 * st2.E_est[-1] + 1e-9
+
+
+def test_sqrt_epsilon_law_converges_with_resolution():
+    # The exact surface value of a semi-infinite isothermal two-level atmosphere with
+    # constant eps is S(0) = sqrt(eps) B.  The linear short-characteristics scheme is
+    # first-order accurate in the step, so halving the step halves the error and the
+    # Richardson-extrapolated value must reproduce the law.
+    eps = 1e-4
+    ratios = []
+    for nz, dz in ((81, 50 * synth.KM), (161, 25 * synth.KM)):
+        atom, atm = column_atmos(nz=nz, nxy=1, dz=dz, tau_top=1e-4, eps=eps)
+        S, n, lev = exact_two_level_column(atom, atm, tol=1e-11)
+        ratios.append(S[-1] / (np.sqrt(eps) * lev.B[0, -1, 0, 0]))
+    err = [abs(r - 1) for r in ratios]
+    assert err[1] < err[0]
+    assert 1.5 < err[0] / err[1] < 2.5
+    assert abs(2 * ratios[1] - ratios[0] - 1) < 0.04
+
+
+def test_fas_and_fmg_reach_the_mali_solution_six_level():
+    atom, atm = six_level_small(nx=4, ny=4)
+    p = Params(nlev=2, nu1=2, nu2=2, nu3=16, E_target=1e-9, max_iter=400)
+    nm, stm, _ = solve_mali(atom, atm, p)
+    nf, stf, _ = solve_fas(atom, atm, p)
+    ng, stg, _ = solve_fas(atom, atm, Params(nlev=2, nu1=2, nu2=2, nu3=16, nu_fmg=8, E_target=1e-9), fmg=True)
+    tol = 4 * (stm.E_est[-1] + stf.E_est[-1]) + 1e-12
+    assert np.max(np.abs(nf / nm - 1)) < max(tol, 1e-8)
+    assert np.max(np.abs(ng / nm - 1)) < max(tol, 1e-8)
+    assert stf.repairs == 0
