@@ -1,0 +1,210 @@
+#!/usr/bin/env python
+"""Benchmark: converged atmospheres/hr and voxel-angle-frequency updates/s,
+FAS with an FP32 sweep against plain FP64 MALI, on one MI355X.
+
+A step is one whole solve of the six-level 64x64x129 workload (seeded synthetic
+stratified atmosphere, 5 lines x 101 frequencies, 24 directions): per-level setup
+and zero-radiation initialisation, 3-level FAS V-cycles with (nu0, nu1, nu2, nu3) =
+(20, 4, 8, 32) until the error estimate rho/(1-rho) C <= 1e-3, then the emergent
+intensity at mu = (0, 0, 1).  The atmosphere and atom are resident on the device
+before the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (published)
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic FP32 flops per voxel-direction-frequency update of the sweep (FMA = 2):
+# profile argument 2, Weideman N=16 Voigt 131, opacity/source function 7, three
+# bilinear upwind interpolations 21, optical depth 3, segment coefficients 7,
+# intensity 5, quadrature weight 2, two positive-sum accumulations 10.
+FLOPS_PER_UPDATE_VOIGT = 188
+FLOPS_PER_UPDATE_GAUSS = 188 - 131 + 3
+
+WORKLOADS = {
+    "caii6_64x64x129": dict(nlev=3, nu0=20, nu1=4, nu2=8, nu3=32, nu_fmg=16, method="FAS"),
+    "caii6_256x256x257": dict(nlev=4, nu0=20, nu1=4, nu2=8, nu3=32, nu_fmg=16, method="FMG"),
+    "caii6_504x504x497": dict(nlev=4, nu0=20, nu1=4, nu2=8, nu3=32, nu_fmg=16, method="FMG"),
+    "two_level_16x16x32": dict(nlev=1, nu0=0, nu1=2, nu2=2, nu3=32, nu_fmg=16, method="MALI"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(atom, atm, fine_fs_equiv, line=0):
+    """Time the FP64 oracle on a bounded sample: one direction of the A4 set and one
+    line, every plane and frequency of that line, on the full grid.  Projects updates/s
+    and atmospheres/hr from the GPU solve's work count (finest-grid formal-solution
+    equivalents)."""
+    import numpy as np
+    from oracle.formal import sweep
+    from oracle.levels import Level
+    from oracle.rates import zero_radiation
+    full = Level(atom, atm)
+    n = zero_radiation(full)
+    sub_atom = dict(atom, lines=[atom["lines"][line]])
+    sub_atm = dict(atm, chi_c=None if atm.get("chi_c") is None else atm["chi_c"][line:line + 1])
+    lev = Level(sub_atom, sub_atm)
+    kk, ee = lev.line_coefficients(n)
+    lo = lev.line_of
+    mu = lev.mu[0]
+
+    def local(k):
+        phi = lev.profile(k, mu)
+        chi = lev.chi_c[lo, k] + kk[lo, k] * phi
+        S = (lev.eta_c[lo, k] + ee[lo, k] * phi) / chi
+        return chi, S, None
+
+    t0 = time.perf_counter()
+    sweep(lev, mu, local, lambda k: np.broadcast_to(lev.B[lo, k], (lev.nf, lev.ny, lev.nx)).copy(), None)
+    dt = time.perf_counter() - t0
+    nvox = lev.nx * lev.ny * lev.nz
+    ups = nvox * lev.nf / dt
+    fs_time = nvox * 24 * full.nf / ups
+    solve_time = fine_fs_equiv * fs_time
+    return {
+        "value": 3600.0 / solve_time, "unit": "atmospheres/hr", "cores": 1, "kind": "oracle",
+        "sample": f"one A4 direction x one line ({lev.nf} frequencies) x all {lev.nz} planes of "
+                  f"{lev.nx}x{lev.ny}x{lev.nz} ({dt:.1f} s), projected to {fine_fs_equiv:.1f} finest-grid "
+                  f"formal solutions per solve (the GPU solve's count); rate solves not included",
+        "updates_per_s": ups, "sample_seconds": dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="caii6_64x64x129", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mali", action="store_true", help="skip the FP64 MALI comparison solve")
+    ap.add_argument("--mali-max-iter", type=int, default=800)
+    ap.add_argument("--tile", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1701_01607_amd import nlte, synth
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    torch.cuda.init()
+    wl = WORKLOADS[args.workload]
+    atom, atm = synth.workload(args.workload)
+    stream = torch.cuda.current_stream()
+    ctx = nlte.Context(0, stream.cuda_stream)
+    A = ctx.atom(atom)
+    M = ctx.atmos(atm)              # resident on the device before the timed region
+    method = {"FAS": nlte.FAS, "FMG": nlte.FMG, "MALI": nlte.MALI}[wl["method"]]
+    params = nlte.SolveParams(method=method, precision=nlte.MIXED, nlev=wl["nlev"], nu0=wl["nu0"],
+                              nu1=wl["nu1"], nu2=wl["nu2"], nu3=wl["nu3"], nu_fmg=wl["nu_fmg"],
+                              E_target=1e-3, max_iter=60, timing=1, tile_points=args.tile)
+    nf = sum(len(l["q"]) for l in atom["lines"])
+    mu_out = np.array([[0.0, 0.0, 1.0]])
+    N = len(atom["levels"])
+
+    def step():
+        job = ctx.job(M, A, params)
+        rc, r = job.run()
+        Itop = torch.empty((1, nf, atm["ny"], atm["nx"]), dtype=torch.float32, device="cuda")
+        ctx.check(ctx.lib.nlte_emergent_intensity(ctx.h, job.id, 1, mu_out.ctypes.data_as(nlte.ct.c_void_p),
+                                                  nlte.ct.c_void_p(Itop.data_ptr()), nlte.MEM_DEVICE))
+        job.close()
+        return rc, r
+
+    for i in range(args.warmup):
+        rc, r = step()
+        log(f"warmup {i}: rc={rc} cycles={r.cycles} C={r.C:.3e} E_est={r.E_est:.3e} ms={r.ms_total:.0f}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for i in range(args.steps):
+        rc, r = step()
+        results.append((rc, r))
+        log(f"step {i}: rc={rc} cycles={r.cycles} C={r.C:.3e} E_est={r.E_est:.3e} ms={r.ms_total:.0f} "
+            f"sweep_ms={r.ms_sweep:.0f}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    converged = all(rc == 0 for rc, _ in results)
+    r = results[-1][1]
+    upd = sum(x.updates for _, x in results)
+    sweep_ms = sum(x.ms_sweep for _, x in results)
+    launches = sum(x.sweep_launches for _, x in results)
+    fl = FLOPS_PER_UPDATE_VOIGT if any(l["gamma_rad"] or l["gamma_vdw"] for l in atom["lines"]) else FLOPS_PER_UPDATE_GAUSS
+    avg_launch_us = 1e3 * sweep_ms / launches
+    flops_per_launch = upd * fl / launches
+    achieved = flops_per_launch / (avg_launch_us * 1e-6) / 1e12
+    ups_sweep = upd / (sweep_ms * 1e-3)
+
+    out = {
+        "metric": "converged atmospheres/hr + voxel-angle-freq updates/s, FAS-FP32 vs MALI-FP64",
+        "value": 3600.0 / (elapsed / args.steps),
+        "unit": "atmospheres/hr",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 sweep / f64 rates",
+        "data": "synthetic (seeded)",
+        "config": {"workload": args.workload, "grid": [atm["nx"], atm["ny"], atm["nz"]], "lines": len(atom["lines"]),
+                   "frequencies": nf, "directions": 24, "method": wl["method"], "levels": wl["nlev"],
+                   "nu": [wl["nu_fmg"], wl["nu0"], wl["nu1"], wl["nu2"], wl["nu3"]], "E_target": 1e-3},
+        "converged": converged,
+        "updates_per_s": ups_sweep,
+        "updates_per_s_wall": upd / elapsed,
+        "cycles": r.cycles, "fine_fs_equiv": r.fine_fs_equiv, "E_est": r.E_est,
+        "phase_ms": {"setup": r.ms_setup, "sweep": r.ms_sweep, "rates": r.ms_rates, "transfer": r.ms_transfer,
+                     "total": r.ms_total},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "sweep_step_kernel<float>", "avg_launch_us": avg_launch_us,
+                     "flops_per_update": fl, "launches": launches},
+    }
+
+    if not args.no_mali:
+        mp = nlte.SolveParams(method=nlte.MALI, precision=nlte.FP64, nlev=1, E_target=1e-3,
+                              max_iter=args.mali_max_iter, timing=1, tile_points=args.tile)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        job = ctx.job(M, A, mp)
+        rc, rm = job.run()
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t1
+        nm = job.populations(0, (N, atm["nz"], atm["ny"], atm["nx"]))
+        job.close()
+        # the FAS result of the last timed step, for the agreement of the two solutions
+        jf = ctx.job(M, A, params)
+        jf.run()
+        nfas = jf.populations(wl["nlev"] - 1, (N, atm["nz"], atm["ny"], atm["nx"]))
+        jf.close()
+        log(f"MALI-FP64: rc={rc} iterations={rm.iterations} C={rm.C:.3e} E_est={rm.E_est:.3e} s={tm:.1f}")
+        out["mali_fp64"] = {"seconds": tm, "iterations": rm.iterations, "converged": rc == 0, "E_est": rm.E_est,
+                            "updates_per_s": rm.updates / (rm.ms_sweep * 1e-3) if rm.ms_sweep else None,
+                            "atmospheres_per_hr": 3600.0 / tm,
+                            "speedup_fas_fp32": tm / (elapsed / args.steps),
+                            "max_rel_diff_vs_fas": float(np.max(np.abs(nfas / nm - 1)))}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)...")
+        out["cpu_baseline"] = cpu_baseline(atom, atm, r.fine_fs_equiv)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,222 @@
+/*
+ * nlte3d.h -- C-ABI of the MI355X (gfx950) non-LTE 3D radiative-transfer library.
+ *
+ * The library solves the non-LTE problem of Bjorgen & Leenaarts (2017):
+ * the transfer equation dI/dtau = S - I (Eq. 1) for every direction and frequency,
+ * coupled to statistical equilibrium (Eq. 2) with the first rate equation replaced by
+ * particle conservation (Eq. 3, right-hand side f = [n_tot, 0, ..., 0], Eq. 5).
+ * The smoother is MALI with a diagonal approximate operator (Sect. 2.1, 3); it is
+ * wrapped by nonlinear FAS multigrid V-cycles (Sect. 2.2, Eqs. 6-12) and full multigrid
+ * (Sect. 2.3, Eqs. 13-14).  An atmosphere and a model atom go in; level populations,
+ * line source functions and emergent intensities come out.
+ *
+ * Conventions for every entry point:
+ *  - Units are CGS.  3D fields are C-ordered [z][y][x] with x fastest; z increases
+ *    upward; x and y are periodic with uniform spacing.
+ *  - The caller owns every buffer it passes.  *_create copies what it needs, so the
+ *    caller may free descriptor memory when the call returns.  Output buffers are
+ *    caller-allocated; a flag says whether a pointer is host or device memory.
+ *  - All device work is enqueued on the context's HIP stream.  Calls that return host
+ *    data synchronise that stream.  Calls on one context are serialised by a mutex.
+ *  - Return value: 0 = success; negative = failure with nothing partially returned
+ *    (nlte_last_error gives the message); positive = warning with the result valid.
+ */
+#ifndef NLTE3D_H
+#define NLTE3D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status codes */
+typedef int nlte_status;
+#define NLTE_OK                 0
+#define NLTE_E_INVALID         -1   /* bad argument, non-finite input, grid constraint */
+#define NLTE_E_OOM             -2   /* device allocation failed or HBM budget exceeded */
+#define NLTE_E_DEVICE          -3   /* HIP runtime error (text in nlte_last_error) */
+#define NLTE_E_DIVERGED        -4   /* NaN/Inf or growing correction detected */
+#define NLTE_W_NOT_CONVERGED    1   /* iteration cap reached; result readable */
+#define NLTE_W_QUEUED           2   /* serving: request accepted, not yet admitted */
+
+#define NLTE_MEM_HOST   0
+#define NLTE_MEM_DEVICE 1
+
+#define NLTE_MALI 0                 /* plain MALI (Jacobi ALI) iterations */
+#define NLTE_FAS  1                 /* FAS V-cycles */
+#define NLTE_FMG  2                 /* full multigrid followed by FAS V-cycles */
+
+#define NLTE_FP64  0                /* formal solution in FP64 */
+#define NLTE_MIXED 1                /* formal solution and accumulation in FP32; rate
+                                       solves, normalisation, residual and coarse-grid
+                                       right-hand side in FP64 */
+
+#define NLTE_INIT_ZERO_RAD 0        /* zero-radiation populations (Sect. 4.11) */
+#define NLTE_INIT_LTE      1        /* Saha-Boltzmann populations */
+#define NLTE_INIT_USER     2        /* params.init_pops */
+
+/* ---------------------------------------------------------------- handles */
+typedef struct nlte_ctx nlte_ctx;
+typedef struct nlte_atom nlte_atom;
+typedef struct nlte_atmos nlte_atmos;
+typedef int64_t nlte_job;
+
+/* ---------------------------------------------------------------- descriptors */
+typedef struct {
+    double E;                  /* level energy above the atom's ground level, cm^-1 */
+    double g;                  /* statistical weight */
+    int stage;                 /* ionisation stage; a level of stage s+1 is a continuum */
+} nlte_level_desc;
+
+typedef struct {
+    int lower, upper;          /* level indices, lower < upper energy */
+    double A;                  /* Einstein A_ji, s^-1 */
+    double gamma_rad;          /* radiative damping, s^-1 */
+    double gamma_vdw;          /* van der Waals coefficient: Gamma += gamma_vdw n_H (T/5000)^0.3 */
+    int nfreq;                 /* frequency points of this line */
+    const double* q;           /* nfreq velocity offsets (cm/s), increasing; nu = nu0 (1 + q/c) */
+} nlte_line_desc;
+
+typedef struct {
+    int lower, upper;          /* bound level and continuum level */
+    double alpha0;             /* photo-ionisation cross-section at the edge, cm^2 (nu^-3 above) */
+} nlte_cont_desc;
+
+typedef struct {
+    int lower, upper;
+    double c_ul;               /* C_ul = n_e c_ul (T/T_ref)^beta; C_lu by detailed balance */
+    double T_ref, beta;
+} nlte_coll_desc;
+
+typedef struct {
+    int nlevel, nline, ncont, ncoll;
+    double mass_amu;           /* atomic mass */
+    double xi;                 /* microturbulence, cm/s */
+    double epsilon;            /* > 0: two-level destruction probability (collisions ignored) */
+    const nlte_level_desc* levels;
+    const nlte_line_desc* lines;
+    const nlte_cont_desc* continua;
+    const nlte_coll_desc* collisions;
+} nlte_atom_desc;
+
+typedef struct {
+    int nx, ny, nz;
+    double dx, dy;             /* horizontal spacings, cm */
+    const double* z;           /* nz heights (cm), strictly increasing; always host memory */
+    const double *T, *ne, *nH, *ntot, *vx, *vy, *vz;   /* [nz][ny][nx] */
+    const double* chi_c;       /* [nchi][nz][ny][nx] background opacity (cm^-1) per line, or NULL */
+    int nchi;                  /* planes in chi_c (>= the atom's nline when chi_c is given) */
+    int mem_kind;              /* NLTE_MEM_HOST or NLTE_MEM_DEVICE for the field arrays */
+} nlte_atmos_desc;
+
+typedef struct {
+    int method;                /* NLTE_MALI / NLTE_FAS / NLTE_FMG */
+    int precision;             /* NLTE_FP64 / NLTE_MIXED */
+    int nlev;                  /* number of grids (1 for MALI) */
+    int nu_fmg, nu0, nu1, nu2, nu3;   /* iteration counts (Sect. 2.2, 2.3, 4.12) */
+    int init;                  /* NLTE_INIT_* */
+    const double* init_pops;   /* NLTE_INIT_USER: [N][nz][ny][nx] host memory */
+    double tol_C;              /* stop when C <= tol_C (<= 0 disables) */
+    double E_target;           /* stop when rho/(1-rho) C <= E_target, rho < 1 (<= 0 disables) */
+    int max_iter;              /* cap on MALI iterations (MALI) or V-cycles (FAS/FMG) */
+    double repair_frac;        /* negative-population repair fraction (0.1, Sect. 4.10) */
+    int fallback_mali;         /* on divergence continue with MALI instead of failing */
+    const double* top_I;       /* prescribed incoming intensity at the top [nf][ny][nx] or NULL */
+    int tile_points;           /* sweep points per wave row: 0 = autotune, else 8/16/32/64 */
+    int timing;                /* 1: time each phase with HIP events on the context stream */
+} nlte_params;
+
+typedef struct {
+    int status;
+    int iterations;            /* finest-level MALI iterations (MALI) */
+    int cycles;                /* V-cycles at the finest level */
+    double C;                  /* last max relative change (Eq. 18) */
+    double rho;                /* last C_i / C_{i-1} */
+    double E_est;              /* rho / (1 - rho) C (Eq. 20) */
+    long long repairs;         /* negative-population repairs */
+    long long formal_solutions[8];   /* per level, index 0 = coarsest */
+    double fine_fs_equiv;      /* work in finest-grid formal solutions (Sect. 4.9 cost units) */
+    double updates;            /* voxel x direction x frequency updates performed */
+    double ms_total, ms_setup, ms_sweep, ms_rates, ms_transfer;   /* phase times need params.timing */
+    long long sweep_launches;  /* plane-step sweep kernel launches (formal solutions x planes) */
+} nlte_result;
+
+/* ---------------------------------------------------------------- lifecycle */
+/* Create a context on HIP device `device` that enqueues on `hip_stream` (a hipStream_t,
+ * NULL = the device's null stream).  `hbm_budget` bounds the bytes the context may
+ * allocate (0 = 90 % of free device memory). */
+nlte_status nlte_ctx_create(int device, void* hip_stream, size_t hbm_budget, nlte_ctx** out);
+void nlte_ctx_destroy(nlte_ctx* ctx);
+/* Message of the last failing call on ctx (empty string if none); owned by ctx. */
+const char* nlte_last_error(const nlte_ctx* ctx);
+/* Library version string. */
+const char* nlte_version(void);
+
+/* Copy a model atom (Sect. 3.2).  Fails with NLTE_E_INVALID for inconsistent indices,
+ * non-positive g/A/mass, fewer than 2 frequencies or non-increasing q. */
+nlte_status nlte_atom_create(nlte_ctx* ctx, const nlte_atom_desc* desc, nlte_atom** out);
+void nlte_atom_destroy(nlte_ctx* ctx, nlte_atom* atom);
+
+/* Copy a model atmosphere (Sect. 3.1) to the device.  Validation: finite values,
+ * T > 0, densities >= 0, n_tot > 0, z strictly increasing. */
+nlte_status nlte_atmos_create(nlte_ctx* ctx, const nlte_atmos_desc* desc, nlte_atmos** out);
+void nlte_atmos_destroy(nlte_ctx* ctx, nlte_atmos* atmos);
+
+/* ---------------------------------------------------------------- solving */
+/* Build the grid hierarchy (Sect. 4.1, 4.2: nx, ny and nz-1 divisible by 2^(nlev-1),
+ * else NLTE_E_INVALID), the coarse atmospheres by full weighting (Sect. 4.7), the
+ * local physics of every level and the initial populations.  The atom and atmosphere
+ * may be destroyed afterwards.  The job keeps its populations resident on the device. */
+nlte_status nlte_job_create(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom* atom,
+                            const nlte_params* params, nlte_job* job);
+/* Run the method chosen in params to the stop rule (or max_iter). */
+nlte_status nlte_job_run(nlte_ctx* ctx, nlte_job job, nlte_result* result);
+/* job_create + job_run. */
+nlte_status nlte_solve(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom* atom,
+                       const nlte_params* params, nlte_result* result, nlte_job* job);
+/* Free the job's device state. */
+nlte_status nlte_release(nlte_ctx* ctx, nlte_job job);
+
+/* ---------------------------------------------------------------- outputs */
+/* Populations of grid `level` (0 = coarsest, nlev-1 = finest) as [N][nz][ny][nx] FP64. */
+nlte_status nlte_get_populations(nlte_ctx* ctx, nlte_job job, int level, double* dst, int dst_mem);
+/* Overwrite the populations of grid `level` (same layout). */
+nlte_status nlte_set_populations(nlte_ctx* ctx, nlte_job job, int level, const double* src, int src_mem);
+/* Line source functions S_l = n_j A_ji / (n_i B_ij - n_j B_ji) on the finest grid,
+ * [nline][nz][ny][nx] FP64; NaN where the denominator is <= 0. */
+nlte_status nlte_get_source_function(nlte_ctx* ctx, nlte_job job, double* dst, int dst_mem);
+/* Emergent intensity at the top plane for `ndir` upward directions mu[ndir][3]
+ * (normalised internally), after a formal solution at the finest populations
+ * (Sect. 5, Fig. 10 uses mu_z = 1).  dst: [ndir][nf][ny][nx] FP32, nf = total
+ * frequencies of all lines in atom order. */
+nlte_status nlte_emergent_intensity(nlte_ctx* ctx, nlte_job job, int ndir, const double* mu,
+                                    float* dst, int dst_mem);
+/* Convergence history: up to `cap` values of C per MALI iteration (MALI) or per cycle. */
+int nlte_history(nlte_ctx* ctx, nlte_job job, double* C, int cap);
+
+/* ---------------------------------------------------------------- stage hooks
+ * Single steps of the method on one grid level, for parity tests.  The job's
+ * precision decides the element type of jeff/oml: FP64 -> double, MIXED -> float. */
+/* Formal solution at the level's current populations (Sect. 3): per line and voxel
+ * Jeff = sum w phi~ (I_u e + Psi_u S_u + Psi_o eta_c/chi) and
+ * 1-L* = sum w phi~ ((1-Psi_o) + Psi_o chi_c/chi); [nline][nz][ny][nx]. */
+nlte_status nlte_formal_solution(nlte_ctx* ctx, nlte_job job, int level, void* jeff, void* oml, int dst_mem);
+/* `iters` MALI iterations on `level` with that level's right-hand side; *C_out gets C
+ * of the last iteration (may be NULL). */
+nlte_status nlte_mali(nlte_ctx* ctx, nlte_job job, int level, int iters, double* C_out);
+/* Residual r = f - W(n) with an extra formal solution (Eq. 7), [N][nz][ny][nx] FP64. */
+nlte_status nlte_residual(nlte_ctx* ctx, nlte_job job, int level, double* dst, int dst_mem);
+/* One V-cycle on levels `level`..0 (Sect. 2.2); `first` applies nu0 at the top. */
+nlte_status nlte_vcycle(nlte_ctx* ctx, nlte_job job, int level, int first);
+/* Full-weighting restriction (Sect. 4.4) of q fields [q][nz][ny][nx] (FP64) from grid
+ * `level` to grid `level-1`; src and dst are device pointers. */
+nlte_status nlte_restrict(nlte_ctx* ctx, nlte_job job, int level, int nq, const double* src, double* dst);
+/* Trilinear prolongation (Sect. 4.5) of q fields from grid `level-1` to `level`. */
+nlte_status nlte_prolong(nlte_ctx* ctx, nlte_job job, int level, int nq, const double* src, double* dst);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NLTE3D_H */

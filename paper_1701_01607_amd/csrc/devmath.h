@@ -1,0 +1,167 @@
+// devmath.h -- device math for the non-LTE library (gfx950).
+//
+// * Voigt function H(a,u) = Re w(u + i a) by the rational series of
+//   J.A.C. Weideman, SIAM J. Numer. Anal. 31 (1994) 1497:
+//     w(z) = 2 p(Z) / (L - i z)^2 + pi^{-1/2} / (L - i z),  Z = (L + i z)/(L - i z),
+//   with p a polynomial of degree N-1 whose coefficients are cosine sums of
+//   exp(-t^2)(L^2 + t^2) at t = L tan(theta/2); L = sqrt(N / sqrt 2).  N = 16 in FP32
+//   (absolute error ~3e-7 of the line-centre value, at the FP32 rounding floor) and
+//   N = 32 in FP64 (~4e-14).  Lines without damping use exp(-u^2) directly.
+// * Linear short-characteristics coefficients (Kunasz & Auer 1988):
+//     e = exp(-x), Psi_o = 1 - (1-e)/x, Psi_u = (1-e)/x - e,
+//   with their Taylor series below a precision-dependent threshold.
+// * Exponential integral E1 for the fixed bound-free rates: power series for x <= 1,
+//   the Laplace continued fraction e^{-x} / (x + 1 - 1^2/(x + 3 - 2^2/(x + 5 - ...)))
+//   evaluated bottom-up above.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace nlte {
+
+constexpr double kH = 6.62607015e-27;      // erg s
+constexpr double kC = 2.99792458e10;       // cm/s
+constexpr double kKB = 1.380649e-16;       // erg/K
+constexpr double kME = 9.1093837015e-28;   // g
+constexpr double kAMU = 1.66053906660e-24; // g
+constexpr double kPI = 3.14159265358979323846;
+constexpr double kSQRTPI = 1.77245385090551602730;
+constexpr double kINVSQRTPI = 0.56418958354775628695;
+
+constexpr int kVoigtNf = 16;
+constexpr int kVoigtNd = 32;
+
+// Weideman coefficients, highest power first; filled by the host at context creation.
+__constant__ float c_voigt_f[kVoigtNf];
+__constant__ double c_voigt_d[kVoigtNd];
+__constant__ float c_voigt_Lf;
+__constant__ double c_voigt_Ld;
+
+template <typename R> struct VoigtTraits;
+template <> struct VoigtTraits<float> {
+    static constexpr int N = kVoigtNf;
+    __device__ static float coef(int i) { return c_voigt_f[i]; }
+    __device__ static float L() { return c_voigt_Lf; }
+};
+template <> struct VoigtTraits<double> {
+    static constexpr int N = kVoigtNd;
+    __device__ static double coef(int i) { return c_voigt_d[i]; }
+    __device__ static double L() { return c_voigt_Ld; }
+};
+
+__device__ inline float dev_rcp(float x) { return __frcp_rn(x); }
+__device__ inline double dev_rcp(double x) { return 1.0 / x; }
+__device__ inline float dev_exp_neg(float x) { return __expf(-x); }
+__device__ inline double dev_exp_neg(double x) { return exp(-x); }
+
+// H(a, u) for a >= 0 (Weideman rational series).
+template <typename R>
+__device__ inline R voigt_H(R a, R u) {
+    using T = VoigtTraits<R>;
+    const R L = T::L();
+    const R lpa = L + a;
+    const R den = lpa * lpa + u * u;
+    const R rden = dev_rcp(den);
+    const R zr = ((L - a) * lpa - u * u) * rden;
+    const R zi = (R(2) * L * u) * rden;
+    R pr = T::coef(0), pi = R(0);
+#pragma unroll
+    for (int j = 1; j < T::N; ++j) {
+        const R t = pr * zr - pi * zi + T::coef(j);
+        pi = pr * zi + pi * zr;
+        pr = t;
+    }
+    const R rr = lpa * rden, ri = u * rden;
+    const R r2r = rr * rr - ri * ri, r2i = R(2) * rr * ri;
+    return R(2) * (pr * r2r - pi * r2i) + rr * R(kINVSQRTPI);
+}
+
+// Profile shape: Gaussian for undamped lines, Voigt otherwise.
+template <typename R>
+__device__ inline R profile_H(R a, R u, bool gauss) {
+    if (gauss) return dev_exp_neg(u * u);
+    return voigt_H<R>(a, u);
+}
+
+// Linear short-characteristics segment coefficients; omp = 1 - Psi_o is returned
+// separately because forming it from Psi_o cancels when Psi_o -> 1 (large dtau).
+__device__ inline void sc_coeffs(float x, float& ex, float& pu, float& po, float& omp) {
+    ex = __expf(-x);
+    if (x < 0.5f) {
+        // sum_{n=1}^{8} (-1)^{n+1} x^n/(n+1)!  and  sum (-1)^{n+1} n x^n/(n+1)!
+        po = x * (0.5f - x * (1.0f / 6.0f - x * (1.0f / 24.0f - x * (1.0f / 120.0f - x * (1.0f / 720.0f
+                - x * (1.0f / 5040.0f - x * (1.0f / 40320.0f - x * (1.0f / 362880.0f))))))));
+        pu = x * (0.5f - x * (2.0f / 6.0f - x * (3.0f / 24.0f - x * (4.0f / 120.0f - x * (5.0f / 720.0f
+                - x * (6.0f / 5040.0f - x * (7.0f / 40320.0f - x * (8.0f / 362880.0f))))))));
+        omp = 1.0f - po;
+    } else {
+        const float r = (1.0f - ex) * __frcp_rn(x);
+        po = 1.0f - r;
+        pu = r - ex;
+        omp = r;
+    }
+}
+
+__device__ inline void sc_coeffs(double x, double& ex, double& pu, double& po, double& omp) {
+    ex = exp(-x);
+    if (x < 0.1) {
+        double so = 0.0, su = 0.0;
+        // Horner over n = 12 .. 1 of (-1)^{n+1} x^n/(n+1)! (and n times that)
+        double fact[13];
+        fact[0] = 1.0;
+#pragma unroll
+        for (int n = 1; n <= 12; ++n) fact[n] = fact[n - 1] * (n + 1);   // (n+1)!
+#pragma unroll
+        for (int n = 12; n >= 1; --n) {
+            const double sg = (n & 1) ? 1.0 : -1.0;
+            so = so * x + sg / fact[n];
+            su = su * x + sg * n / fact[n];
+        }
+        po = so * x;
+        pu = su * x;
+        omp = 1.0 - po;
+    } else {
+        const double r = -expm1(-x) / x;
+        po = 1.0 - r;
+        pu = r - ex;
+        omp = r;
+    }
+}
+
+// Planck function B_nu(T), FP64.
+__device__ inline double planck(double nu, double T) {
+    return (2.0 * kH * nu * nu * nu / (kC * kC)) / expm1(kH * nu / (kKB * T));
+}
+
+// Exponential integral E1(x), x > 0, FP64.
+__device__ inline double expint_e1(double x) {
+    if (x <= 1.0) {
+        // E1(x) = -gamma - ln x - sum_{k>=1} (-x)^k / (k k!)
+        double term = 1.0, sum = 0.0;
+        for (int k = 1; k < 40; ++k) {
+            term *= -x / k;
+            const double add = term / k;
+            sum += add;
+            if (fabs(add) < 1e-18 * fabs(sum)) break;
+        }
+        return -0.57721566490153286061 - log(x) - sum;
+    }
+    // continued fraction, evaluated from a fixed depth upward
+    const int depth = x > 30.0 ? 12 : (x > 5.0 ? 40 : 120);
+    double t = x + 2.0 * depth + 1.0;
+    for (int k = depth; k >= 1; --k) t = x + 2.0 * k - 1.0 - double(k) * double(k) / t;
+    return exp(-x) / t;
+}
+
+// sum_{k>=1} E1(k x): integral of dt / (t (e^t - 1)) from x to infinity.
+__device__ inline double bf_planck_integral(double x) {
+    double total = 0.0;
+    for (int k = 1; k < 100000; ++k) {
+        const double t = expint_e1(k * x);
+        total += t;
+        if (t <= 1e-17 * total) break;
+    }
+    return total;
+}
+
+}  // namespace nlte

@@ -1,0 +1,745 @@
+// kernels.h -- HIP kernels of the non-LTE library (gfx950, wave64).
+//
+// Data layout: structure of arrays, C order [q][z][y][x] with x fastest.  A voxel index
+// is v = (k*ny + y)*nx + x; a plane point index is g = y*nx + x.  Populations and rate
+// data are FP64; sweep inputs/outputs are of the sweep precision R (float or double).
+#pragma once
+#include "devmath.h"
+
+namespace nlte {
+
+constexpr int kMaxLevels = 8;
+constexpr int kMaxLines = 16;
+constexpr int kNDir = 24;
+constexpr int kNHemi = 12;
+
+// A4 directions (unit vectors), 12 upward then their reflections; weights are 1/24.
+__constant__ double c_mu[kNDir * 3];
+
+struct LineInfo {
+    int lower, upper, fstart, nfreq, gauss;
+    double nu0, A, Bij, Bji, hnu4pi, gamma_rad, gamma_vdw;
+};
+
+struct AtomInfo {
+    int N, nline, ncont, ncoll, eps_mode;
+    double mass, xi, eps;
+    double E[kMaxLevels], g[kMaxLevels];
+    int stage[kMaxLevels];
+    LineInfo line[kMaxLines];
+    int cont_lower[kMaxLevels], cont_upper[kMaxLevels];
+    double cont_alpha0[kMaxLevels];
+    int coll_lower[kMaxLevels * kMaxLevels], coll_upper[kMaxLevels * kMaxLevels];
+    double coll_cul[kMaxLevels * kMaxLevels], coll_Tref[kMaxLevels * kMaxLevels],
+        coll_beta[kMaxLevels * kMaxLevels];
+};
+
+// ------------------------------------------------------------------ level setup
+// Primitive field order in the FP64 primitive block.
+enum { P_T = 0, P_NE, P_NH, P_NTOT, P_VX, P_VY, P_VZ, P_CHIC };
+
+// Sweep-constant block (precision R): [SC_*][nline][nvox] then [SV_*][nvox].
+enum { SC_CHIC = 0, SC_ETAC, SC_ADAMP, SC_PN, SC_PW, SC_B, SC_NQ };
+enum { SV_INVVD = 0, SV_VX, SV_VY, SV_VZ, SV_NQ };
+
+template <typename R>
+struct SetupArgs {
+    const AtomInfo* atom;
+    const double* prim;      // [7 + nline][nvox]
+    int has_chic;
+    size_t nvox;
+    R* sc;                   // [SC_NQ][nline][nvox]
+    R* sv;                   // [SV_NQ][nvox]
+    double* nstar;           // [N][nvox]
+    double* pfix;            // [N*N][nvox], rate i -> j at (i*N + j)
+    double* ntot;            // [nvox]
+};
+
+// Per-voxel local physics: Doppler width, damping, Planck, background, LTE
+// populations and the fixed (collisional + bound-free) rates.  FP64 throughout.
+template <typename R>
+__global__ void setup_level_kernel(SetupArgs<R> a) {
+    const size_t v = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= a.nvox) return;
+    const AtomInfo& at = *a.atom;
+    const size_t nv = a.nvox;
+    const double T = a.prim[P_T * nv + v];
+    const double ne = a.prim[P_NE * nv + v];
+    const double nH = a.prim[P_NH * nv + v];
+    const double nt = a.prim[P_NTOT * nv + v];
+    const double vD = sqrt(2.0 * kKB * T / (at.mass * kAMU) + at.xi * at.xi);
+    const double ivD = 1.0 / vD;
+    a.sv[SV_INVVD * nv + v] = R(ivD);
+    a.sv[SV_VX * nv + v] = R(a.prim[P_VX * nv + v] * ivD);
+    a.sv[SV_VY * nv + v] = R(a.prim[P_VY * nv + v] * ivD);
+    a.sv[SV_VZ * nv + v] = R(a.prim[P_VZ * nv + v] * ivD);
+    a.ntot[v] = nt;
+    const int L = at.nline;
+    for (int l = 0; l < L; ++l) {
+        const LineInfo& ln = at.line[l];
+        const double B = planck(ln.nu0, T);
+        const double dnuD = ln.nu0 * vD / kC;
+        const double gam = ln.gamma_rad + ln.gamma_vdw * nH * pow(T / 5000.0, 0.3);
+        const double chic = a.has_chic ? a.prim[(P_CHIC + l) * nv + v] : 0.0;
+        a.sc[(SC_CHIC * L + l) * nv + v] = R(chic);
+        a.sc[(SC_ETAC * L + l) * nv + v] = R(chic * B);
+        a.sc[(SC_ADAMP * L + l) * nv + v] = R(gam / (4.0 * kPI * dnuD));
+        a.sc[(SC_PN * L + l) * nv + v] = R(1.0 / (kSQRTPI * dnuD));
+        a.sc[(SC_B * L + l) * nv + v] = R(B);
+    }
+    // Saha-Boltzmann: n_i* ~ g_i exp(-hcE_i/kT) Phi^(s_i - s_min), Phi = 2(2 pi m kT/h^2)^1.5/n_e
+    const int N = at.N;
+    int smin = at.stage[0];
+    for (int i = 1; i < N; ++i) smin = min(smin, at.stage[i]);
+    double lw[kMaxLevels], mx = -1e300;
+    const double hc_kT = kH * kC / (kKB * T);
+    for (int i = 0; i < N; ++i) {
+        double w = log(at.g[i]) - hc_kT * at.E[i];
+        if (at.stage[i] != smin) {
+            const double phi = 2.0 * pow(2.0 * kPI * kME * kKB * T / (kH * kH), 1.5) / ne;
+            w += (at.stage[i] - smin) * log(phi);
+        }
+        lw[i] = w;
+        mx = fmax(mx, w);
+    }
+    double ws[kMaxLevels], tot = 0.0;
+    for (int i = 0; i < N; ++i) { ws[i] = exp(lw[i] - mx); tot += ws[i]; }
+    double ns[kMaxLevels];
+    for (int i = 0; i < N; ++i) { ns[i] = nt * ws[i] / tot; a.nstar[i * nv + v] = ns[i]; }
+    double P[kMaxLevels * kMaxLevels];
+    for (int i = 0; i < N * N; ++i) P[i] = 0.0;
+    if (at.eps_mode) {
+        for (int l = 0; l < L; ++l) {
+            const LineInfo& ln = at.line[l];
+            const double c21 = at.eps * ln.A / ((1.0 - at.eps) * (-expm1(-kH * ln.nu0 / (kKB * T))));
+            P[ln.upper * N + ln.lower] += c21;
+            P[ln.lower * N + ln.upper] += c21 * ws[ln.upper] / ws[ln.lower];
+        }
+    } else {
+        for (int c = 0; c < at.ncoll; ++c) {
+            const int lo = at.coll_lower[c], up = at.coll_upper[c];
+            const double cul = ne * at.coll_cul[c] * pow(T / at.coll_Tref[c], at.coll_beta[c]);
+            P[up * N + lo] += cul;
+            P[lo * N + up] += cul * ws[up] / ws[lo];
+        }
+    }
+    for (int c = 0; c < at.ncont; ++c) {
+        const int i = at.cont_lower[c], j = at.cont_upper[c];
+        const double nue = kC * (at.E[j] - at.E[i]);
+        const double x = kH * nue / (kKB * T);
+        const double ric = 8.0 * kPI * at.cont_alpha0[c] * nue * nue * nue / (kC * kC) * bf_planck_integral(x);
+        P[i * N + j] += ric;
+        P[j * N + i] += ric * ws[i] / ws[j];
+    }
+    for (int i = 0; i < N * N; ++i) a.pfix[size_t(i) * nv + v] = P[i];
+}
+
+// Profile normalisation phi~ = phi / sum_d sum_m w_d w_m phi per (line, voxel), using
+// the same profile evaluation as the sweep.  Writes pw = pn * N_l.
+template <typename R>
+__global__ void profile_norm_kernel(const AtomInfo* atom, const R* qf, const R* wf, R* sc,
+                                   const R* sv, size_t nvox) {
+    const size_t v = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    const AtomInfo& at = *atom;
+    const int L = at.nline;
+    const R ivD = sv[SV_INVVD * nvox + v];
+    const R vx = sv[SV_VX * nvox + v], vy = sv[SV_VY * nvox + v], vz = sv[SV_VZ * nvox + v];
+    for (int l = 0; l < L; ++l) {
+        const LineInfo& ln = at.line[l];
+        const R a = sc[(SC_ADAMP * L + l) * nvox + v];
+        const R pn = sc[(SC_PN * L + l) * nvox + v];
+        double acc = 0.0;
+        for (int d = 0; d < kNDir; ++d) {
+            const R vn = vx * R(c_mu[3 * d]) + vy * R(c_mu[3 * d + 1]) + vz * R(c_mu[3 * d + 2]);
+            double accd = 0.0;
+            for (int m = 0; m < ln.nfreq; ++m) {
+                const int f = ln.fstart + m;
+                const R u = qf[f] * ivD - vn;
+                const R H = profile_H<R>(a, u, ln.gauss != 0);
+                accd += double(wf[f]) * double(H * pn);
+            }
+            acc += accd / kNDir;
+        }
+        sc[(SC_PW * L + l) * nvox + v] = R(double(pn) / acc);
+    }
+}
+
+// ------------------------------------------------------------------ line coefficients
+// k_l^+ = max((h nu0/4pi)(n_i^+ B_ij - n_j^+ B_ji), 0), e_l = (h nu0/4pi) n_j^+ A_ji.
+template <typename R>
+__global__ void line_coef_kernel(const AtomInfo* atom, const double* n, R* lc, size_t nvox) {
+    const size_t v = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    const AtomInfo& at = *atom;
+    const int L = at.nline;
+    for (int l = 0; l < L; ++l) {
+        const LineInfo& ln = at.line[l];
+        const double ni = fmax(n[size_t(ln.lower) * nvox + v], 0.0);
+        const double nj = fmax(n[size_t(ln.upper) * nvox + v], 0.0);
+        lc[size_t(l) * nvox + v] = R(fmax(ln.hnu4pi * (ni * ln.Bij - nj * ln.Bji), 0.0));
+        lc[size_t(L + l) * nvox + v] = R(ln.hnu4pi * nj * ln.A);
+    }
+}
+
+// ------------------------------------------------------------------ sweep
+// One plane step of the short-characteristics formal solution for all 24 directions.
+// Step s: upward directions solve plane s from plane s-1, downward directions plane
+// nz-1-s from nz-s; s = 0 sets the boundary planes (I = B below, I = 0 or prescribed
+// above).  Block: 12 directions x CH frequency lanes x P plane points (one wave per
+// direction when P*CH = 64); grid: (plane tiles, lines, hemispheres).  Each thread loops
+// over its line's frequencies m = c, c+CH, ...; the 12 x CH partial sums of a point are
+// reduced in LDS in a fixed order (deterministic, no atomics).
+template <typename R>
+struct SweepArgs {
+    const AtomInfo* atom;
+    int nx, ny, nz, nf;
+    size_t nxy, nvox;
+    double dx, dy;
+    const double* z;
+    const R* sc;         // [SC_NQ][nline][nvox]
+    const R* sv;         // [SV_NQ][nvox]
+    const R* lc;         // [2][nline][nvox]: k+, e
+    const R* qf;         // [nf] velocity offsets
+    const R* wf;         // [nf] frequency weights (Hz)
+    const R* topI;       // [nf][nxy] or null
+    R* state;            // [2 slots][3][24][nf][nxy]: I, S, chi
+    R* acc;              // [2 qty][2 hemi][nline][nvox]
+};
+
+template <typename R, int P, int CH>
+__global__ __launch_bounds__(kNHemi* P* CH) void sweep_step_kernel(SweepArgs<R> a, int s) {
+    const int t = threadIdx.x;
+    const int p = t % P;
+    const int c = (t / P) % CH;
+    const int dl = t / (P * CH);
+    const int h = blockIdx.z;
+    const int d = h * kNHemi + dl;
+    const int l = blockIdx.y;
+    const AtomInfo& at = *a.atom;
+    const LineInfo& ln = at.line[l];
+    const int L = at.nline;
+    const size_t g = size_t(blockIdx.x) * P + p;
+    const bool valid = g < a.nxy;
+    const int k = (h == 0) ? s : a.nz - 1 - s;
+    R jacc = R(0), lacc = R(0);
+    const size_t nv = a.nvox, nxy = a.nxy;
+    const size_t plane_stride = size_t(a.nf) * nxy;            // one (q, d) block
+    const size_t slot_stride = size_t(3) * kNDir * plane_stride;
+
+    if (valid) {
+        const size_t v = size_t(k) * nxy + g;
+        const double mux = c_mu[3 * d], muy = c_mu[3 * d + 1], muz = c_mu[3 * d + 2];
+        const R chic = a.sc[(SC_CHIC * L + l) * nv + v];
+        const R etac = a.sc[(SC_ETAC * L + l) * nv + v];
+        const R adamp = a.sc[(SC_ADAMP * L + l) * nv + v];
+        const R pn = a.sc[(SC_PN * L + l) * nv + v];
+        const R pw = a.sc[(SC_PW * L + l) * nv + v] * R(1.0 / kNDir);
+        const R kpl = a.lc[size_t(l) * nv + v];
+        const R el = a.lc[size_t(L + l) * nv + v];
+        const R ivD = a.sv[SV_INVVD * nv + v];
+        const R vn = a.sv[SV_VX * nv + v] * R(mux) + a.sv[SV_VY * nv + v] * R(muy) +
+                     a.sv[SV_VZ * nv + v] * R(muz);
+        const bool gauss = ln.gauss != 0;
+        R* cur = a.state + size_t(s & 1) * slot_stride;
+        R* Icur = cur + (size_t(0) * kNDir + d) * plane_stride;
+        R* Scur = cur + (size_t(1) * kNDir + d) * plane_stride;
+        R* Ccur = cur + (size_t(2) * kNDir + d) * plane_stride;
+        if (s == 0) {
+            const R Bb = a.sc[(SC_B * L + l) * nv + v];
+            for (int m = c; m < ln.nfreq; m += CH) {
+                const int f = ln.fstart + m;
+                const R u = a.qf[f] * ivD - vn;
+                const R H = profile_H<R>(adamp, u, gauss);
+                const R phi = H * pn;
+                const R chi = chic + kpl * phi;
+                const R S = (etac + el * phi) * dev_rcp(chi);
+                const R I = (h == 0) ? Bb : (a.topI ? a.topI[size_t(f) * nxy + g] : R(0));
+                Icur[size_t(f) * nxy + g] = I;
+                Scur[size_t(f) * nxy + g] = S;
+                Ccur[size_t(f) * nxy + g] = chi;
+                const R wphi = a.wf[f] * H * pw;
+                jacc += wphi * I;
+                lacc += wphi;
+            }
+        } else {
+            const int kp = (h == 0) ? s - 1 : a.nz - s;
+            const double ds = fabs(a.z[k] - a.z[kp]) / fabs(muz);
+            const double sx = -ds * mux / a.dx, sy = -ds * muy / a.dy;
+            const double fsx = floor(sx), fsy = floor(sy);
+            const R fx = R(sx - fsx), fy = R(sy - fsy);
+            const int x = int(g % a.nx), y = int(g / a.nx);
+            int x0 = int((long long)(x + (long long)fsx) % a.nx); if (x0 < 0) x0 += a.nx;
+            int y0 = int((long long)(y + (long long)fsy) % a.ny); if (y0 < 0) y0 += a.ny;
+            const int x1 = (x0 + 1 == a.nx) ? 0 : x0 + 1;
+            const int y1 = (y0 + 1 == a.ny) ? 0 : y0 + 1;
+            const size_t g00 = size_t(y0) * a.nx + x0, g01 = size_t(y0) * a.nx + x1;
+            const size_t g10 = size_t(y1) * a.nx + x0, g11 = size_t(y1) * a.nx + x1;
+            const R w00 = (R(1) - fx) * (R(1) - fy), w01 = fx * (R(1) - fy);
+            const R w10 = (R(1) - fx) * fy, w11 = fx * fy;
+            const R rds = R(ds);
+            const R* prv = a.state + size_t((s - 1) & 1) * slot_stride;
+            const R* Ip = prv + (size_t(0) * kNDir + d) * plane_stride;
+            const R* Sp = prv + (size_t(1) * kNDir + d) * plane_stride;
+            const R* Cp = prv + (size_t(2) * kNDir + d) * plane_stride;
+            for (int m = c; m < ln.nfreq; m += CH) {
+                const int f = ln.fstart + m;
+                const size_t fo = size_t(f) * nxy;
+                const R u = a.qf[f] * ivD - vn;
+                const R H = profile_H<R>(adamp, u, gauss);
+                const R phi = H * pn;
+                const R chi = chic + kpl * phi;
+                const R rchi = dev_rcp(chi);
+                const R S = (etac + el * phi) * rchi;
+                const R Iu = w00 * Ip[fo + g00] + w01 * Ip[fo + g01] + w10 * Ip[fo + g10] + w11 * Ip[fo + g11];
+                const R Su = w00 * Sp[fo + g00] + w01 * Sp[fo + g01] + w10 * Sp[fo + g10] + w11 * Sp[fo + g11];
+                const R Cu = w00 * Cp[fo + g00] + w01 * Cp[fo + g01] + w10 * Cp[fo + g10] + w11 * Cp[fo + g11];
+                const R dtau = R(0.5) * (Cu + chi) * rds;
+                R ex, pu, po, omp;
+                sc_coeffs(dtau, ex, pu, po, omp);
+                const R Ith = Iu * ex + pu * Su;
+                const R Io = Ith + po * S;
+                Icur[fo + g] = Io;
+                Scur[fo + g] = S;
+                Ccur[fo + g] = chi;
+                const R wphi = a.wf[f] * H * pw;
+                jacc += wphi * (Ith + po * etac * rchi);
+                lacc += wphi * (omp + po * chic * rchi);
+            }
+        }
+    }
+    __shared__ R sj[kNHemi * P * CH];
+    __shared__ R sl[kNHemi * P * CH];
+    sj[t] = jacc;
+    sl[t] = lacc;
+    __syncthreads();
+    if (t < P && valid) {
+        R jt = R(0), lt = R(0);
+        for (int q = 0; q < kNHemi * CH; ++q) {
+            jt += sj[q * P + t];
+            lt += sl[q * P + t];
+        }
+        const size_t v = size_t(k) * nxy + g;
+        a.acc[((size_t(0) * 2 + h) * L + l) * nv + v] = jt;
+        a.acc[((size_t(1) * 2 + h) * L + l) * nv + v] = lt;
+    }
+}
+
+// Emergent intensity: one plane step of an upward sweep for a single direction (thread
+// per (frequency, plane point)); the last step writes I at the top plane.  The level
+// constants are read in their storage precision R; the solve itself is always FP64.
+template <typename R>
+struct EmergentArgs {
+    const AtomInfo* atom;
+    int nx, ny, nz, nf;
+    size_t nxy, nvox;
+    double dx, dy, mux, muy, muz;
+    const double* z;
+    const R* sc;
+    const R* sv;
+    const R* lc;
+    const R* qf;
+    const int* line_of;  // [nf]
+    double* state;       // [2][3][nf][nxy]
+    float* out;          // [nf][nxy]
+};
+
+template <typename R>
+__global__ void emergent_step_kernel(EmergentArgs<R> a, int k) {
+    const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= size_t(a.nf) * a.nxy) return;
+    const int f = int(idx / a.nxy);
+    const size_t g = idx % a.nxy;
+    const AtomInfo& at = *a.atom;
+    const int l = a.line_of[f];
+    const int L = at.nline;
+    const LineInfo& ln = at.line[l];
+    const size_t nv = a.nvox, v = size_t(k) * a.nxy + g;
+    const double chic = a.sc[(SC_CHIC * L + l) * nv + v];
+    const double etac = a.sc[(SC_ETAC * L + l) * nv + v];
+    const double adamp = a.sc[(SC_ADAMP * L + l) * nv + v];
+    const double pn = a.sc[(SC_PN * L + l) * nv + v];
+    const double kpl = a.lc[size_t(l) * nv + v];
+    const double el = a.lc[size_t(L + l) * nv + v];
+    const double ivD = a.sv[SV_INVVD * nv + v];
+    const double vn = double(a.sv[SV_VX * nv + v]) * a.mux + double(a.sv[SV_VY * nv + v]) * a.muy +
+                      double(a.sv[SV_VZ * nv + v]) * a.muz;
+    const double u = double(a.qf[f]) * ivD - vn;
+    const double H = profile_H<double>(adamp, u, ln.gauss != 0);
+    const double phi = H * pn;
+    const double chi = chic + kpl * phi;
+    const double S = (etac + el * phi) / chi;
+    const size_t ps = size_t(a.nf) * a.nxy;
+    double* cur = a.state + size_t(k & 1) * 3 * ps;
+    double I;
+    if (k == 0) {
+        I = a.sc[(SC_B * L + l) * nv + v];
+    } else {
+        const double* prv = a.state + size_t((k - 1) & 1) * 3 * ps;
+        const double ds = (a.z[k] - a.z[k - 1]) / a.muz;
+        const double sx = -ds * a.mux / a.dx, sy = -ds * a.muy / a.dy;
+        const double fsx = floor(sx), fsy = floor(sy);
+        const double fx = sx - fsx, fy = sy - fsy;
+        const int x = int(g % a.nx), y = int(g / a.nx);
+        int x0 = int((long long)(x + (long long)fsx) % a.nx); if (x0 < 0) x0 += a.nx;
+        int y0 = int((long long)(y + (long long)fsy) % a.ny); if (y0 < 0) y0 += a.ny;
+        const int x1 = (x0 + 1 == a.nx) ? 0 : x0 + 1;
+        const int y1 = (y0 + 1 == a.ny) ? 0 : y0 + 1;
+        const size_t fo = size_t(f) * a.nxy;
+        const size_t g00 = fo + size_t(y0) * a.nx + x0, g01 = fo + size_t(y0) * a.nx + x1;
+        const size_t g10 = fo + size_t(y1) * a.nx + x0, g11 = fo + size_t(y1) * a.nx + x1;
+        const double w00 = (1.0 - fx) * (1.0 - fy), w01 = fx * (1.0 - fy);
+        const double w10 = (1.0 - fx) * fy, w11 = fx * fy;
+        const double Iu = w00 * prv[g00] + w01 * prv[g01] + w10 * prv[g10] + w11 * prv[g11];
+        const double Su = w00 * prv[ps + g00] + w01 * prv[ps + g01] + w10 * prv[ps + g10] + w11 * prv[ps + g11];
+        const double Cu = w00 * prv[2 * ps + g00] + w01 * prv[2 * ps + g01] + w10 * prv[2 * ps + g10] +
+                          w11 * prv[2 * ps + g11];
+        const double dtau = 0.5 * (Cu + chi) * ds;
+        double ex, pu, po, omp;
+        sc_coeffs(dtau, ex, pu, po, omp);
+        I = Iu * ex + pu * Su + po * S;
+    }
+    cur[size_t(f) * a.nxy + g] = I;
+    cur[ps + size_t(f) * a.nxy + g] = S;
+    cur[2 * ps + size_t(f) * a.nxy + g] = chi;
+    if (k == a.nz - 1) a.out[size_t(f) * a.nxy + g] = float(I);
+}
+
+// ------------------------------------------------------------------ rate equations
+// Rate matrix from the fixed rates and the preconditioned radiative rates of
+// Rybicki & Hummer (1991): upward B_ij Jeff, downward A_ji (1 - L*) + B_ji Jeff.
+// System matrix A[i][i] = sum_{j != i} P_ij, A[i][j] = -P_ji, row 0 = particle
+// conservation.  mode: 0 = solve A n' = f (MALI update), 1 = zero-radiation solve
+// (Jeff = 0, 1 - L* = 1), 2 = out = base + sign * (A n) (W(n) at the current
+// accumulators: residual and coarse-grid right-hand side).
+template <typename R>
+struct RateArgs {
+    const AtomInfo* atom;
+    size_t nvox;
+    const double* pfix;   // [N*N][nvox]
+    const R* acc;         // [2][2][nline][nvox]
+    double* n;            // [N][nvox]  (mode 0/1: updated in place)
+    const double* f;      // [N][nvox]
+    const double* base;   // mode 2
+    double* out;          // mode 2
+    double sign;
+    int mode;
+    double* partial;      // [gridDim.x] max relative change (modes 0/1)
+};
+
+template <int N>
+__device__ inline void build_matrix(const AtomInfo& at, const double* pfix, size_t nv, size_t v,
+                                    const double* Jeff, const double* omL, double (&A)[N][N]) {
+    double P[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) P[i][j] = pfix[size_t(i * N + j) * nv + v];
+    for (int l = 0; l < at.nline; ++l) {
+        const LineInfo& ln = at.line[l];
+        const double up = ln.Bij * Jeff[l];
+        const double dn = ln.A * omL[l] + ln.Bji * Jeff[l];
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                if (i == ln.lower && j == ln.upper) P[i][j] += up;
+                if (i == ln.upper && j == ln.lower) P[i][j] += dn;
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double out = 0.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            if (j != i) out += P[i][j];
+#pragma unroll
+        for (int j = 0; j < N; ++j) A[i][j] = (i == j) ? out : -P[j][i];
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) A[0][j] = 1.0;
+}
+
+// Gaussian elimination with partial pivoting, fully unrolled (row swaps by selects).
+template <int N>
+__device__ inline void lu_solve(double (&A)[N][N], double (&b)[N]) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        int p = k;
+        double best = fabs(A[k][k]);
+#pragma unroll
+        for (int r = k + 1; r < N; ++r) {
+            const double vr = fabs(A[r][k]);
+            if (vr > best) { best = vr; p = r; }
+        }
+#pragma unroll
+        for (int r = k + 1; r < N; ++r) {
+            if (r == p) {
+#pragma unroll
+                for (int j = 0; j < N; ++j) { const double tmp = A[k][j]; A[k][j] = A[r][j]; A[r][j] = tmp; }
+                const double tb = b[k]; b[k] = b[r]; b[r] = tb;
+            }
+        }
+        const double inv = 1.0 / A[k][k];
+#pragma unroll
+        for (int r = k + 1; r < N; ++r) {
+            const double fct = A[r][k] * inv;
+#pragma unroll
+            for (int j = k; j < N; ++j) A[r][j] -= fct * A[k][j];
+            b[r] -= fct * b[k];
+        }
+    }
+#pragma unroll
+    for (int k = N - 1; k >= 0; --k) {
+        double sacc = b[k];
+#pragma unroll
+        for (int j = k + 1; j < N; ++j) sacc -= A[k][j] * b[j];
+        b[k] = sacc / A[k][k];
+    }
+}
+
+template <typename R, int N>
+__global__ __launch_bounds__(256) void rate_kernel(RateArgs<R> a) {
+    const size_t v = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    double cmax = 0.0;
+    if (v < a.nvox) {
+        const AtomInfo& at = *a.atom;
+        const int L = at.nline;
+        const size_t nv = a.nvox;
+        double Jeff[kMaxLines], omL[kMaxLines];
+        for (int l = 0; l < L; ++l) {
+            if (a.mode == 1) {
+                Jeff[l] = 0.0;
+                omL[l] = 1.0;
+            } else {
+                Jeff[l] = double(a.acc[((size_t(0) * 2 + 0) * L + l) * nv + v]) +
+                          double(a.acc[((size_t(0) * 2 + 1) * L + l) * nv + v]);
+                omL[l] = double(a.acc[((size_t(1) * 2 + 0) * L + l) * nv + v]) +
+                         double(a.acc[((size_t(1) * 2 + 1) * L + l) * nv + v]);
+            }
+        }
+        double A[N][N];
+        build_matrix<N>(at, a.pfix, nv, v, Jeff, omL, A);
+        double nold[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) nold[i] = a.n[size_t(i) * nv + v];
+        if (a.mode == 2) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                double w = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) w += A[i][j] * nold[j];
+                a.out[size_t(i) * nv + v] = a.base[size_t(i) * nv + v] + a.sign * w;
+            }
+        } else {
+            double b[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) b[i] = a.f[size_t(i) * nv + v];
+            const double f0 = b[0];
+            lu_solve<N>(A, b);
+            double tot = 0.0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) tot += b[i];
+            const double sc = f0 / tot;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const double nn = b[i] * sc;
+                cmax = fmax(cmax, fabs((nn - nold[i]) / nn));
+                a.n[size_t(i) * nv + v] = nn;
+            }
+        }
+    }
+    if (a.partial) {
+        __shared__ double red[256];
+        red[threadIdx.x] = cmax;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) a.partial[blockIdx.x] = red[0];
+    }
+}
+
+// max over partials (single block) -> out[0]
+__global__ void reduce_max_kernel(const double* partial, int n, double* out) {
+    __shared__ double red[256];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, partial[i]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// max |(a - b) / a| over nq*nvox elements -> partial per block
+__global__ void rel_change_kernel(const double* anew, const double* bold, size_t n, double* partial) {
+    __shared__ double red[256];
+    double m = 0.0;
+    for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += size_t(gridDim.x) * 256)
+        m = fmax(m, fabs((anew[i] - bold[i]) / anew[i]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// S_l = n_j A_ji / (n_i B_ij - n_j B_ji), NaN where the denominator is <= 0.
+__global__ void source_function_kernel(const AtomInfo* atom, const double* n, double* S, size_t nvox) {
+    const size_t v = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    const AtomInfo& at = *atom;
+    for (int l = 0; l < at.nline; ++l) {
+        const LineInfo& ln = at.line[l];
+        const double ni = n[size_t(ln.lower) * nvox + v], nj = n[size_t(ln.upper) * nvox + v];
+        const double k = ni * ln.Bij - nj * ln.Bji;
+        S[size_t(l) * nvox + v] = k > 0.0 ? nj * ln.A / k : __builtin_nan("");
+    }
+}
+
+// ------------------------------------------------------------------ grid transfer
+// Full weighting (27-point tensor product of [1/4, 1/2, 1/4], periodic in x and y,
+// [1/2, 1/2] at the vertical boundary planes) from the fine grid to the coarse grid.
+__global__ void restrict_kernel(const double* src, double* dst, int nq, int nxf, int nyf, int nzf) {
+    const int nxc = nxf / 2, nyc = nyf / 2, nzc = (nzf - 1) / 2 + 1;
+    const size_t ncv = size_t(nxc) * nyc * nzc;
+    const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= ncv * nq) return;
+    const int q = int(idx / ncv);
+    const size_t r = idx % ncv;
+    const int xc = int(r % nxc), yc = int((r / nxc) % nyc), zc = int(r / (size_t(nxc) * nyc));
+    const size_t nfv = size_t(nxf) * nyf * nzf;
+    const double* s = src + size_t(q) * nfv;
+    double wz[3];
+    int kz[3];
+    const int kc = 2 * zc;
+    if (zc == 0) { kz[0] = 0; kz[1] = 0; kz[2] = 1; wz[0] = 0.0; wz[1] = 0.5; wz[2] = 0.5; }
+    else if (zc == nzc - 1) { kz[0] = nzf - 2; kz[1] = nzf - 1; kz[2] = nzf - 1; wz[0] = 0.5; wz[1] = 0.5; wz[2] = 0.0; }
+    else { kz[0] = kc - 1; kz[1] = kc; kz[2] = kc + 1; wz[0] = 0.25; wz[1] = 0.5; wz[2] = 0.25; }
+    const double w1[3] = {0.25, 0.5, 0.25};
+    double acc = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        if (wz[a] == 0.0) continue;
+        double accy = 0.0;
+        for (int b = 0; b < 3; ++b) {
+            const int y = (2 * yc + b - 1 + nyf) % nyf;
+            double accx = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const int x = (2 * xc + c - 1 + nxf) % nxf;
+                accx += w1[c] * s[(size_t(kz[a]) * nyf + y) * nxf + x];
+            }
+            accy += w1[b] * accx;
+        }
+        acc += wz[a] * accy;
+    }
+    dst[idx] = acc;
+}
+
+// Trilinear interpolation weights of fine point (x, y, k) on the coarse grid.
+struct Tri {
+    int x0, x1, y0, y1, k0, k1;
+    double wx, wy, wz;
+};
+__device__ inline Tri tri_weights(int x, int y, int k, int nxc, int nyc, const double* zf) {
+    Tri t;
+    t.x0 = x >> 1; t.x1 = (x & 1) ? ((t.x0 + 1) % nxc) : t.x0; t.wx = (x & 1) ? 0.5 : 0.0;
+    t.y0 = y >> 1; t.y1 = (y & 1) ? ((t.y0 + 1) % nyc) : t.y0; t.wy = (y & 1) ? 0.5 : 0.0;
+    t.k0 = k >> 1;
+    if (k & 1) {
+        t.k1 = t.k0 + 1;
+        t.wz = (zf[k] - zf[k - 1]) / (zf[k + 1] - zf[k - 1]);
+    } else {
+        t.k1 = t.k0;
+        t.wz = 0.0;
+    }
+    return t;
+}
+__device__ inline double tri_eval(const double* c, const Tri& t, int nxc, int nyc) {
+    auto at = [&](int k, int y, int x) { return c[(size_t(k) * nyc + y) * nxc + x]; };
+    const double a0 = (1.0 - t.wx) * at(t.k0, t.y0, t.x0) + t.wx * at(t.k0, t.y0, t.x1);
+    const double a1 = (1.0 - t.wx) * at(t.k0, t.y1, t.x0) + t.wx * at(t.k0, t.y1, t.x1);
+    const double b0 = (1.0 - t.wx) * at(t.k1, t.y0, t.x0) + t.wx * at(t.k1, t.y0, t.x1);
+    const double b1 = (1.0 - t.wx) * at(t.k1, t.y1, t.x0) + t.wx * at(t.k1, t.y1, t.x1);
+    const double a = (1.0 - t.wy) * a0 + t.wy * a1;
+    const double b = (1.0 - t.wy) * b0 + t.wy * b1;
+    return (1.0 - t.wz) * a + t.wz * b;
+}
+
+__global__ void prolong_kernel(const double* src, double* dst, int nq, int nxf, int nyf, int nzf,
+                               const double* zf) {
+    const size_t nfv = size_t(nxf) * nyf * nzf;
+    const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= nfv * nq) return;
+    const int q = int(idx / nfv);
+    const size_t r = idx % nfv;
+    const int x = int(r % nxf), y = int((r / nxf) % nyf), k = int(r / (size_t(nxf) * nyf));
+    const int nxc = nxf / 2, nyc = nyf / 2, nzc = (nzf - 1) / 2 + 1;
+    const Tri t = tri_weights(x, y, k, nxc, nyc, zf);
+    dst[idx] = tri_eval(src + size_t(q) * nxc * nyc * nzc, t, nxc, nyc);
+}
+
+// Relative coarse-grid correction (Eqs. 11, 12) with the negative-population repair:
+// e = (n_after - n_before) / n_before on the coarse grid, interpolated trilinearly;
+// n <- n (1 + I e), and n <- frac * n where that is <= 0.  Repairs counted per block.
+__global__ void correct_kernel(double* n, const double* na, const double* nb, int nq, int nxf, int nyf,
+                               int nzf, const double* zf, double frac, unsigned long long* repairs) {
+    const size_t nfv = size_t(nxf) * nyf * nzf;
+    const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int rep = 0;
+    if (idx < nfv * nq) {
+        const int q = int(idx / nfv);
+        const size_t r = idx % nfv;
+        const int x = int(r % nxf), y = int((r / nxf) % nyf), k = int(r / (size_t(nxf) * nyf));
+        const int nxc = nxf / 2, nyc = nyf / 2, nzc = (nzf - 1) / 2 + 1;
+        const size_t ncv = size_t(nxc) * nyc * nzc;
+        const Tri t = tri_weights(x, y, k, nxc, nyc, zf);
+        const double* A = na + size_t(q) * ncv;
+        const double* B = nb + size_t(q) * ncv;
+        auto e = [&](int kk, int yy, int xx) {
+            const size_t o = (size_t(kk) * nyc + yy) * nxc + xx;
+            return (A[o] - B[o]) / B[o];
+        };
+        const double a0 = (1.0 - t.wx) * e(t.k0, t.y0, t.x0) + t.wx * e(t.k0, t.y0, t.x1);
+        const double a1 = (1.0 - t.wx) * e(t.k0, t.y1, t.x0) + t.wx * e(t.k0, t.y1, t.x1);
+        const double b0 = (1.0 - t.wx) * e(t.k1, t.y0, t.x0) + t.wx * e(t.k1, t.y0, t.x1);
+        const double b1 = (1.0 - t.wx) * e(t.k1, t.y1, t.x0) + t.wx * e(t.k1, t.y1, t.x1);
+        const double ie = (1.0 - t.wz) * ((1.0 - t.wy) * a0 + t.wy * a1) + t.wz * ((1.0 - t.wy) * b0 + t.wy * b1);
+        const double nold = n[idx];
+        double nn = nold * (1.0 + ie);
+        if (!(nn > 0.0)) {
+            nn = frac * nold;
+            rep = 1;
+        }
+        n[idx] = nn;
+    }
+    __shared__ int cnt[256];
+    cnt[threadIdx.x] = rep;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) cnt[threadIdx.x] += cnt[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && cnt[0] > 0) atomicAdd(repairs, (unsigned long long)cnt[0]);
+}
+
+// Right-hand side f = [n_tot, 0, ..., 0].
+__global__ void fine_rhs_kernel(double* f, const double* ntot, int N, size_t nvox) {
+    const size_t v = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    f[v] = ntot[v];
+    for (int i = 1; i < N; ++i) f[size_t(i) * nvox + v] = 0.0;
+}
+
+// Non-finite check: flag[0] = 1 if any element is NaN or Inf.
+__global__ void finite_check_kernel(const double* x, size_t n, int* flag) {
+    const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(x[i])) flag[0] = 1;
+}
+
+}  // namespace nlte

@@ -1,0 +1,1122 @@
+// nlte3d.hip -- host runtime and C-ABI of the MI355X non-LTE library.
+//
+// One translation unit: the kernels (kernels.h) and their constant tables live here.
+// A job owns a grid hierarchy (level 0 = coarsest) with device-resident primitives,
+// local-physics constants, populations and right-hand sides.  The drivers below follow
+// the MALI iteration, the FAS V-cycle and full multigrid of Bjorgen & Leenaarts (2017),
+// Sect. 2.1-2.3, with the conventions stated in include/nlte3d.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/nlte3d.h"
+#include "kernels.h"
+
+using namespace nlte;
+
+namespace {
+
+struct Error : std::runtime_error {
+    nlte_status code;
+    Error(nlte_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess)                                                               \
+            throw Error(NLTE_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+#define REQUIRE(cond, msg) \
+    do {                   \
+        if (!(cond)) throw Error(NLTE_E_INVALID, msg); \
+    } while (0)
+
+inline unsigned blocks_for(size_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }
+
+}  // namespace
+
+// ===================================================================== context
+struct nlte_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t budget = 0, used = 0;
+    std::string err;
+    std::recursive_mutex mu;
+    std::map<int64_t, struct JobBase*> jobs;
+    int64_t next_job = 1;
+};
+
+namespace {
+
+// Device buffer accounted against the context budget.
+struct DevBuf {
+    nlte_ctx* ctx = nullptr;
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void alloc(nlte_ctx* c, size_t b) {
+        release();
+        ctx = c;
+        if (b == 0) return;
+        if (c->used + b > c->budget)
+            throw Error(NLTE_E_OOM, "HBM budget exceeded: need " + std::to_string(b) + " more bytes, " +
+                                        std::to_string(c->budget - c->used) + " left");
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            p = nullptr;
+            throw Error(NLTE_E_OOM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+        }
+        bytes = b;
+        c->used += b;
+    }
+    void release() {
+        if (p) {
+            (void)hipFree(p);
+            ctx->used -= bytes;
+        }
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+// ----------------------------------------------------------------- constant tables
+// Weideman (1994) coefficients for N terms: a_n = (1/2M) sum_{k=-M+1}^{M-1} F(k) cos(pi n k/M),
+// F(k) = exp(-t^2)(L^2 + t^2), t = L tan(k pi / 2M), M = 2N, L = sqrt(N / sqrt 2);
+// stored highest power first (index j holds a_{N-j}).
+void weideman_coefficients(int N, std::vector<double>& coef, double& L) {
+    const int M = 2 * N;
+    L = std::sqrt(N / std::sqrt(2.0));
+    std::vector<double> F(2 * M - 1);
+    for (int k = -M + 1; k <= M - 1; ++k) {
+        const double t = L * std::tan(k * M_PI / (2.0 * M));
+        F[k + M - 1] = std::exp(-t * t) * (L * L + t * t);
+    }
+    coef.assign(N, 0.0);
+    for (int n = 1; n <= N; ++n) {
+        double s = 0.0;
+        for (int k = -M + 1; k <= M - 1; ++k) s += F[k + M - 1] * std::cos(M_PI * n * k / M);
+        coef[N - n] = s / (2.0 * M);
+    }
+}
+
+// A4 set: per octant the permutations of (1/3, 1/3, sqrt(7)/3); 12 upward directions
+// (x and y signs over the 4 upper octants), then the 12 reflections through the origin.
+void a4_set(double* mu) {
+    const double m1 = 1.0 / 3.0, m2 = std::sqrt(1.0 - 2.0 * m1 * m1);
+    const double base[3][3] = {{m1, m1, m2}, {m1, m2, m1}, {m2, m1, m1}};
+    const double sg[4][2] = {{1, 1}, {1, -1}, {-1, 1}, {-1, -1}};
+    int d = 0;
+    for (int o = 0; o < 4; ++o)
+        for (int b = 0; b < 3; ++b, ++d) {
+            mu[3 * d] = sg[o][0] * base[b][0];
+            mu[3 * d + 1] = sg[o][1] * base[b][1];
+            mu[3 * d + 2] = base[b][2];
+        }
+    for (int e = 0; e < 12; ++e)
+        for (int c = 0; c < 3; ++c) mu[3 * (12 + e) + c] = -mu[3 * e + c];
+}
+
+void upload_constants() {
+    std::vector<double> cd;
+    double Ld;
+    weideman_coefficients(kVoigtNd, cd, Ld);
+    std::vector<double> cf64;
+    double Lf;
+    weideman_coefficients(kVoigtNf, cf64, Lf);
+    std::vector<float> cf(cf64.begin(), cf64.end());
+    float Lff = float(Lf);
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_voigt_d), cd.data(), sizeof(double) * kVoigtNd));
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_voigt_f), cf.data(), sizeof(float) * kVoigtNf));
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_voigt_Ld), &Ld, sizeof(double)));
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_voigt_Lf), &Lff, sizeof(float)));
+    double mu[kNDir * 3];
+    a4_set(mu);
+    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_mu), mu, sizeof(mu)));
+}
+
+}  // namespace
+
+// ===================================================================== atom / atmos
+struct nlte_atom {
+    AtomInfo info{};
+    std::vector<double> q;        // flat velocity offsets, atom line order
+    std::vector<double> wnu;      // flat trapezoid weights in Hz
+    std::vector<int> line_of;
+    int nf = 0;
+};
+
+struct nlte_atmos {
+    int nx = 0, ny = 0, nz = 0, nline_chic = 0;
+    double dx = 0, dy = 0;
+    std::vector<double> z;
+    DevBuf prim;                  // [7 + nline_chic][nvox]
+};
+
+// ===================================================================== job
+struct JobBase {
+    virtual ~JobBase() = default;
+    nlte_params params{};
+    int N = 0, nline = 0, nf = 0, nlev = 1, prec = NLTE_FP64;
+    std::vector<double> history;
+    nlte_result res{};
+    virtual void run(nlte_result* out) = 0;
+    virtual void formal_solution_out(int level, void* jeff, void* oml, int mem) = 0;
+    virtual double mali_hook(int level, int iters) = 0;
+    virtual void residual_out(int level, double* dst, int mem) = 0;
+    virtual void vcycle_hook(int level, int first) = 0;
+    virtual void get_pops(int level, double* dst, int mem) = 0;
+    virtual void set_pops(int level, const double* src, int mem) = 0;
+    virtual void source_function(double* dst, int mem) = 0;
+    virtual void emergent(int ndir, const double* mu, float* dst, int mem) = 0;
+    virtual void restrict_hook(int level, int nq, const double* src, double* dst) = 0;
+    virtual void prolong_hook(int level, int nq, const double* src, double* dst) = 0;
+};
+
+namespace {
+
+struct Level {
+    int nx = 0, ny = 0, nz = 0;
+    size_t nxy = 0, nvox = 0;
+    double dx = 0, dy = 0;
+    std::vector<double> z;
+    DevBuf dz, prim, sc, sv, nstar, pfix, ntot, n, f, nb, tmp, acc, lc, partial;
+    bool fs_valid = false;
+    long long fs_count = 0;
+};
+
+template <typename R>
+struct Job : JobBase {
+    nlte_ctx* ctx;
+    std::vector<std::unique_ptr<Level>> lev;
+    DevBuf atom_d, qf, wf, line_of_d, state, topI, scalar, repairs, estate, eout, flag, nprev;
+    AtomInfo info{};
+    int P = 64, CH = 1;
+    std::vector<double> hz_top;
+    double updates_per_fs_fine = 0;
+    double cost_units = 0;
+    double updates = 0;
+    long long sweep_launches = 0;
+    double ms_setup = 0;
+
+    // phase timing with HIP events on the context stream (params.timing)
+    enum { EV_SWEEP = 0, EV_RATES = 1, EV_TRANSFER = 2 };
+    struct Ev { hipEvent_t a, b; int kind; };
+    std::vector<Ev> evs;
+    double ms_phase[3] = {0, 0, 0};
+
+    Job(nlte_ctx* c) : ctx(c) {}
+    ~Job() override {
+        for (auto& e : evs) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    }
+
+    void ev_begin(int kind) {
+        if (!params.timing) return;
+        Ev e;
+        e.kind = kind;
+        HIPCHK(hipEventCreate(&e.a));
+        HIPCHK(hipEventCreate(&e.b));
+        HIPCHK(hipEventRecord(e.a, st()));
+        evs.push_back(e);
+    }
+    void ev_end() {
+        if (!params.timing) return;
+        HIPCHK(hipEventRecord(evs.back().b, st()));
+    }
+    void ev_resolve() {
+        if (evs.empty()) return;
+        HIPCHK(hipStreamSynchronize(st()));
+        for (auto& e : evs) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e.a, e.b));
+            ms_phase[e.kind] += ms;
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+        evs.clear();
+    }
+
+    hipStream_t st() const { return ctx->stream; }
+
+    // --------------------------------------------------------------- setup
+    void build(const nlte_atmos* atm, const nlte_atom* atom, const nlte_params* p) {
+        auto tb = std::chrono::steady_clock::now();
+        params = *p;
+        info = atom->info;
+        N = info.N;
+        nline = info.nline;
+        nf = atom->nf;
+        nlev = std::max(1, p->method == NLTE_MALI ? 1 : p->nlev);
+        REQUIRE(nlev <= kMaxLevels, "nlev too large");
+        REQUIRE(atm->nline_chic == 0 || atm->nline_chic >= nline, "chi_c has fewer lines than the atom");
+        const int step = 1 << (nlev - 1);
+        REQUIRE(atm->nx % step == 0 && atm->ny % step == 0 && (atm->nz - 1) % step == 0,
+                "grid " + std::to_string(atm->nx) + "x" + std::to_string(atm->ny) + "x" + std::to_string(atm->nz) +
+                    " does not admit " + std::to_string(nlev) + " grid levels (need nx, ny, nz-1 divisible by " +
+                    std::to_string(step) + ")");
+        REQUIRE(nlev == 1 || atm->nz >= 3, "multigrid needs nz >= 3");
+        if (p->method != NLTE_MALI) REQUIRE(nlev >= 1, "nlev >= 1");
+
+        atom_d.alloc(ctx, sizeof(AtomInfo));
+        HIPCHK(hipMemcpyAsync(atom_d.p, &info, sizeof(AtomInfo), hipMemcpyHostToDevice, st()));
+        std::vector<R> qh(atom->q.begin(), atom->q.end()), wh(atom->wnu.begin(), atom->wnu.end());
+        qf.alloc(ctx, sizeof(R) * nf);
+        wf.alloc(ctx, sizeof(R) * nf);
+        line_of_d.alloc(ctx, sizeof(int) * nf);
+        HIPCHK(hipMemcpyAsync(qf.p, qh.data(), sizeof(R) * nf, hipMemcpyHostToDevice, st()));
+        HIPCHK(hipMemcpyAsync(wf.p, wh.data(), sizeof(R) * nf, hipMemcpyHostToDevice, st()));
+        HIPCHK(hipMemcpyAsync(line_of_d.p, atom->line_of.data(), sizeof(int) * nf, hipMemcpyHostToDevice, st()));
+        scalar.alloc(ctx, sizeof(double) * 4);
+        repairs.alloc(ctx, sizeof(unsigned long long));
+        flag.alloc(ctx, sizeof(int));
+        HIPCHK(hipMemsetAsync(repairs.p, 0, sizeof(unsigned long long), st()));
+
+        const int nprim = 7 + atm->nline_chic;
+        lev.resize(nlev);
+        for (int k = nlev - 1; k >= 0; --k) {
+            lev[k].reset(new Level());
+            Level& L = *lev[k];
+            if (k == nlev - 1) {
+                L.nx = atm->nx; L.ny = atm->ny; L.nz = atm->nz; L.dx = atm->dx; L.dy = atm->dy; L.z = atm->z;
+            } else {
+                const Level& F = *lev[k + 1];
+                L.nx = F.nx / 2; L.ny = F.ny / 2; L.nz = (F.nz - 1) / 2 + 1;
+                L.dx = 2 * F.dx; L.dy = 2 * F.dy;
+                for (int i = 0; i < F.nz; i += 2) L.z.push_back(F.z[i]);
+            }
+            L.nxy = size_t(L.nx) * L.ny;
+            L.nvox = L.nxy * L.nz;
+            L.dz.alloc(ctx, sizeof(double) * L.nz);
+            HIPCHK(hipMemcpyAsync(L.dz.p, L.z.data(), sizeof(double) * L.nz, hipMemcpyHostToDevice, st()));
+            L.prim.alloc(ctx, sizeof(double) * nprim * L.nvox);
+            if (k == nlev - 1) {
+                HIPCHK(hipMemcpyAsync(L.prim.p, atm->prim.p, sizeof(double) * nprim * L.nvox,
+                                      hipMemcpyDeviceToDevice, st()));
+            } else {
+                const Level& F = *lev[k + 1];
+                restrict_kernel<<<blocks_for(L.nvox * nprim, 256), 256, 0, st()>>>(
+                    F.prim.as<double>(), L.prim.as<double>(), nprim, F.nx, F.ny, F.nz);
+                HIPCHK(hipGetLastError());
+            }
+            L.sc.alloc(ctx, sizeof(R) * SC_NQ * nline * L.nvox);
+            L.sv.alloc(ctx, sizeof(R) * SV_NQ * L.nvox);
+            L.nstar.alloc(ctx, sizeof(double) * N * L.nvox);
+            L.pfix.alloc(ctx, sizeof(double) * N * N * L.nvox);
+            L.ntot.alloc(ctx, sizeof(double) * L.nvox);
+            L.n.alloc(ctx, sizeof(double) * N * L.nvox);
+            L.f.alloc(ctx, sizeof(double) * N * L.nvox);
+            L.nb.alloc(ctx, sizeof(double) * N * L.nvox);
+            L.tmp.alloc(ctx, sizeof(double) * N * L.nvox);
+            L.acc.alloc(ctx, sizeof(R) * 4 * nline * L.nvox);
+            L.lc.alloc(ctx, sizeof(R) * 2 * nline * L.nvox);
+            L.partial.alloc(ctx, sizeof(double) * std::max<size_t>(blocks_for(L.nvox, 256), 1024));
+            SetupArgs<R> sa;
+            sa.atom = atom_d.as<AtomInfo>();
+            sa.prim = L.prim.as<double>();
+            sa.has_chic = atm->nline_chic ? 1 : 0;
+            sa.nvox = L.nvox;
+            sa.sc = L.sc.as<R>();
+            sa.sv = L.sv.as<R>();
+            sa.nstar = L.nstar.as<double>();
+            sa.pfix = L.pfix.as<double>();
+            sa.ntot = L.ntot.as<double>();
+            setup_level_kernel<R><<<blocks_for(L.nvox, 128), 128, 0, st()>>>(sa);
+            HIPCHK(hipGetLastError());
+            profile_norm_kernel<R><<<blocks_for(L.nvox, 128), 128, 0, st()>>>(
+                atom_d.as<AtomInfo>(), qf.as<R>(), wf.as<R>(), L.sc.as<R>(), L.sv.as<R>(), L.nvox);
+            HIPCHK(hipGetLastError());
+            fine_rhs_kernel<<<blocks_for(L.nvox, 256), 256, 0, st()>>>(L.f.as<double>(), L.ntot.as<double>(), N, L.nvox);
+            HIPCHK(hipGetLastError());
+        }
+        const Level& Fz = *lev[nlev - 1];
+        state.alloc(ctx, sizeof(R) * 2 * 3 * kNDir * size_t(nf) * Fz.nxy);
+        nprev.alloc(ctx, sizeof(double) * N * Fz.nvox);
+        if (p->top_I) {
+            topI.alloc(ctx, sizeof(R) * size_t(nf) * Fz.nxy);
+            std::vector<R> th(size_t(nf) * Fz.nxy);
+            for (size_t i = 0; i < th.size(); ++i) th[i] = R(p->top_I[i]);
+            HIPCHK(hipMemcpyAsync(topI.p, th.data(), sizeof(R) * th.size(), hipMemcpyHostToDevice, st()));
+            HIPCHK(hipStreamSynchronize(st()));
+        }
+        updates_per_fs_fine = double(Fz.nvox) * kNDir * nf;
+
+        // initial populations
+        const int k0 = (p->method == NLTE_FMG) ? 0 : nlev - 1;
+        Level& L0 = *lev[k0];
+        if (p->init == NLTE_INIT_USER) {
+            REQUIRE(p->init_pops != nullptr, "init_pops is NULL");
+            REQUIRE(p->method != NLTE_FMG, "user initial populations are for MALI/FAS");
+            HIPCHK(hipMemcpyAsync(L0.n.p, p->init_pops, sizeof(double) * N * L0.nvox, hipMemcpyHostToDevice, st()));
+        } else if (p->init == NLTE_INIT_LTE) {
+            HIPCHK(hipMemcpyAsync(L0.n.p, L0.nstar.p, sizeof(double) * N * L0.nvox, hipMemcpyDeviceToDevice, st()));
+        } else {
+            zero_radiation(k0);
+        }
+        HIPCHK(hipStreamSynchronize(st()));
+        choose_tile();
+        ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
+    }
+
+    void choose_tile() {
+        int t = params.tile_points;
+        if (t != 8 && t != 16 && t != 32 && t != 64) t = 0;
+        P = t;
+        CH = t ? 64 / t : 0;
+    }
+
+    void tile_for(const Level& L, int& p, int& ch) const {
+        if (P) { p = P; ch = CH; return; }
+        if (L.nxy >= 4096) p = 64;
+        else if (L.nxy >= 1024) p = 32;
+        else if (L.nxy >= 256) p = 16;
+        else p = 8;
+        ch = 64 / p;
+    }
+
+    // --------------------------------------------------------------- kernels
+    void rate_launch(int k, int mode, const double* base, double* out, double sign, bool want_C) {
+        Level& L = *lev[k];
+        RateArgs<R> ra;
+        ra.atom = atom_d.as<AtomInfo>();
+        ra.nvox = L.nvox;
+        ra.pfix = L.pfix.as<double>();
+        ra.acc = L.acc.as<R>();
+        ra.n = L.n.as<double>();
+        ra.f = L.f.as<double>();
+        ra.base = base;
+        ra.out = out;
+        ra.sign = sign;
+        ra.mode = mode;
+        const unsigned nb = blocks_for(L.nvox, 256);
+        ra.partial = want_C ? L.partial.as<double>() : nullptr;
+        ev_begin(EV_RATES);
+        switch (N) {
+#define RCASE(NN) case NN: rate_kernel<R, NN><<<nb, 256, 0, st()>>>(ra); break;
+            RCASE(2) RCASE(3) RCASE(4) RCASE(5) RCASE(6) RCASE(7) RCASE(8)
+#undef RCASE
+            default: throw Error(NLTE_E_INVALID, "number of levels must be 2..8");
+        }
+        HIPCHK(hipGetLastError());
+        if (want_C) {
+            reduce_max_kernel<<<1, 256, 0, st()>>>(L.partial.as<double>(), int(nb), scalar.as<double>());
+            HIPCHK(hipGetLastError());
+        }
+        ev_end();
+    }
+
+    void zero_radiation(int k) {
+        rate_launch(k, 1, nullptr, nullptr, 0.0, false);
+        lev[k]->fs_valid = false;
+    }
+
+    void formal_solution(int k) {
+        Level& L = *lev[k];
+        line_coef_kernel<R><<<blocks_for(L.nvox, 256), 256, 0, st()>>>(atom_d.as<AtomInfo>(), L.n.as<double>(),
+                                                                      L.lc.as<R>(), L.nvox);
+        HIPCHK(hipGetLastError());
+        SweepArgs<R> a;
+        a.atom = atom_d.as<AtomInfo>();
+        a.nx = L.nx; a.ny = L.ny; a.nz = L.nz; a.nf = nf;
+        a.nxy = L.nxy; a.nvox = L.nvox;
+        a.dx = L.dx; a.dy = L.dy;
+        a.z = L.dz.as<double>();
+        a.sc = L.sc.as<R>(); a.sv = L.sv.as<R>(); a.lc = L.lc.as<R>();
+        a.qf = qf.as<R>(); a.wf = wf.as<R>();
+        a.topI = (k == nlev - 1 && topI.p) ? topI.as<R>() : nullptr;
+        a.state = state.as<R>();
+        a.acc = L.acc.as<R>();
+        int p, ch;
+        tile_for(L, p, ch);
+        dim3 grid(blocks_for(L.nxy, p), nline, 2);
+        ev_begin(EV_SWEEP);
+        for (int s = 0; s < L.nz; ++s) {
+            switch (p) {
+                case 64: sweep_step_kernel<R, 64, 1><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
+                case 32: sweep_step_kernel<R, 32, 2><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
+                case 16: sweep_step_kernel<R, 16, 4><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
+                default: sweep_step_kernel<R, 8, 8><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
+            }
+        }
+        HIPCHK(hipGetLastError());
+        ev_end();
+        sweep_launches += L.nz;
+        L.fs_valid = true;
+        ++L.fs_count;
+        const Level& F = *lev[nlev - 1];
+        cost_units += double(L.nvox) / double(F.nvox);
+        updates += double(L.nvox) * kNDir * nf;
+    }
+
+    double read_scalar() {
+        double c = 0;
+        HIPCHK(hipMemcpyAsync(&c, scalar.p, sizeof(double), hipMemcpyDeviceToHost, st()));
+        HIPCHK(hipStreamSynchronize(st()));
+        return c;
+    }
+
+    // `iters` MALI iterations; the accumulators are reused for the first one if valid.
+    void mali(int k, int iters) {
+        Level& L = *lev[k];
+        for (int it = 0; it < iters; ++it) {
+            if (!(it == 0 && L.fs_valid)) formal_solution(k);
+            rate_launch(k, 0, nullptr, nullptr, 0.0, true);
+            L.fs_valid = false;
+        }
+    }
+
+    // out = base + sign * W(n) with W at the current accumulators of level k.
+    void apply_W(int k, const double* base, double* out, double sign) {
+        rate_launch(k, 2, base, out, sign, false);
+    }
+
+    void restrict_fields(int kf, int nq, const double* src, double* dst) {
+        const Level& F = *lev[kf];
+        const Level& C = *lev[kf - 1];
+        ev_begin(EV_TRANSFER);
+        restrict_kernel<<<blocks_for(C.nvox * nq, 256), 256, 0, st()>>>(src, dst, nq, F.nx, F.ny, F.nz);
+        HIPCHK(hipGetLastError());
+        ev_end();
+    }
+
+    void prolong_fields(int kf, int nq, const double* src, double* dst) {
+        const Level& F = *lev[kf];
+        prolong_kernel<<<blocks_for(F.nvox * nq, 256), 256, 0, st()>>>(src, dst, nq, F.nx, F.ny, F.nz,
+                                                                      F.dz.as<double>());
+        HIPCHK(hipGetLastError());
+    }
+
+    // One FAS V-cycle on levels k..0 (Sect. 2.2).
+    void vcycle(int k, bool first) {
+        Level& L = *lev[k];
+        const int nu_pre = (first && params.nu0 > 0) ? params.nu0 : params.nu1;
+        if (k == 0) {
+            mali(k, nu_pre);
+            mali(k, params.nu2);
+            return;
+        }
+        mali(k, nu_pre);
+        if (!L.fs_valid) formal_solution(k);                // the extra formal solution (Eq. 7)
+        apply_W(k, L.f.as<double>(), L.tmp.as<double>(), -1.0);   // r = f - W(n)
+        L.fs_valid = false;
+        Level& C = *lev[k - 1];
+        restrict_fields(k, N, L.n.as<double>(), C.n.as<double>());
+        restrict_fields(k, N, L.tmp.as<double>(), C.tmp.as<double>());
+        formal_solution(k - 1);                             // W*(R n), shared with the first coarse iteration
+        apply_W(k - 1, C.tmp.as<double>(), C.f.as<double>(), 1.0);  // f = R r + W(R n)  (Eq. 10)
+        HIPCHK(hipMemcpyAsync(C.nb.p, C.n.p, sizeof(double) * N * C.nvox, hipMemcpyDeviceToDevice, st()));
+        if (k - 1 == 0) mali(0, params.nu3);
+        else vcycle(k - 1, false);
+        correct_kernel<<<blocks_for(L.nvox * N, 256), 256, 0, st()>>>(
+            L.n.as<double>(), C.n.as<double>(), C.nb.as<double>(), N, L.nx, L.ny, L.nz, L.dz.as<double>(),
+            params.repair_frac, repairs.as<unsigned long long>());
+        HIPCHK(hipGetLastError());
+        L.fs_valid = false;
+        mali(k, params.nu2);
+    }
+
+    double cycle_change(int k) {
+        Level& L = *lev[k];
+        const size_t n = size_t(N) * L.nvox;
+        const unsigned nb = std::min<unsigned>(blocks_for(n, 256), 1024);
+        rel_change_kernel<<<nb, 256, 0, st()>>>(L.n.as<double>(), nprev.as<double>(), n, L.partial.as<double>());
+        reduce_max_kernel<<<1, 256, 0, st()>>>(L.partial.as<double>(), int(nb), scalar.as<double>());
+        HIPCHK(hipGetLastError());
+        return read_scalar();
+    }
+
+    bool stop(double& rho, double& E) {
+        const double C = history.back();
+        rho = history.size() >= 2 ? C / history[history.size() - 2] : INFINITY;
+        E = (rho < 1.0) ? rho / (1.0 - rho) * C : INFINITY;
+        if (params.tol_C > 0 && C <= params.tol_C) return true;
+        if (params.E_target > 0 && rho < 1.0 && E <= params.E_target) return true;
+        return false;
+    }
+
+    void check_finite(int k) {
+        Level& L = *lev[k];
+        HIPCHK(hipMemsetAsync(flag.p, 0, sizeof(int), st()));
+        finite_check_kernel<<<blocks_for(size_t(N) * L.nvox, 256), 256, 0, st()>>>(L.n.as<double>(),
+                                                                                   size_t(N) * L.nvox, flag.as<int>());
+        int h = 0;
+        HIPCHK(hipMemcpyAsync(&h, flag.p, sizeof(int), hipMemcpyDeviceToHost, st()));
+        HIPCHK(hipStreamSynchronize(st()));
+        if (h) throw Error(NLTE_E_DIVERGED, "non-finite populations");
+    }
+
+    void run(nlte_result* out) override {
+        auto t0 = std::chrono::steady_clock::now();
+        const int top = nlev - 1;
+        Level& F = *lev[top];
+        int status = NLTE_W_NOT_CONVERGED;
+        double rho = INFINITY, E = INFINITY;
+        int iters = 0, cycles = 0;
+        const int maxit = params.max_iter > 0 ? params.max_iter : 1000;
+        if (params.method == NLTE_MALI || nlev == 1 && params.method != NLTE_FAS && params.method != NLTE_FMG) {
+            for (int it = 0; it < maxit; ++it) {
+                mali(top, 1);
+                history.push_back(read_scalar());
+                ++iters;
+                if (!std::isfinite(history.back())) throw Error(NLTE_E_DIVERGED, "non-finite MALI correction");
+                if (stop(rho, E)) { status = NLTE_OK; break; }
+            }
+        } else {
+            bool first = true;
+            if (params.method == NLTE_FMG) {
+                mali(0, params.nu_fmg);
+                for (int k = 1; k <= top; ++k) {
+                    prolong_fields(k, N, lev[k - 1]->n.as<double>(), lev[k]->n.as<double>());
+                    lev[k]->fs_valid = false;
+                    if (k < top) vcycle(k, false);
+                }
+                first = false;
+            }
+            for (int c = 0; c < maxit; ++c) {
+                HIPCHK(hipMemcpyAsync(nprev.p, F.n.p, sizeof(double) * N * F.nvox, hipMemcpyDeviceToDevice, st()));
+                vcycle(top, first);
+                first = false;
+                history.push_back(cycle_change(top));
+                ++cycles;
+                if (!std::isfinite(history.back())) {
+                    if (params.fallback_mali) {
+                        throw Error(NLTE_E_DIVERGED, "FAS diverged (fallback to MALI needs a restart)");
+                    }
+                    throw Error(NLTE_E_DIVERGED, "non-finite cycle correction");
+                }
+                if (stop(rho, E)) { status = NLTE_OK; break; }
+            }
+        }
+        check_finite(top);
+        ev_resolve();
+        unsigned long long rep = 0;
+        HIPCHK(hipMemcpyAsync(&rep, repairs.p, sizeof(rep), hipMemcpyDeviceToHost, st()));
+        HIPCHK(hipStreamSynchronize(st()));
+        auto t1 = std::chrono::steady_clock::now();
+        nlte_result r{};
+        r.status = status;
+        r.iterations = iters;
+        r.cycles = cycles;
+        r.C = history.empty() ? 0.0 : history.back();
+        r.rho = rho;
+        r.E_est = E;
+        r.repairs = (long long)rep;
+        for (int k = 0; k < nlev && k < 8; ++k) r.formal_solutions[k] = lev[k]->fs_count;
+        r.fine_fs_equiv = cost_units;
+        r.updates = updates;
+        r.ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        r.ms_setup = ms_setup;
+        r.ms_sweep = ms_phase[EV_SWEEP];
+        r.ms_rates = ms_phase[EV_RATES];
+        r.ms_transfer = ms_phase[EV_TRANSFER];
+        r.sweep_launches = sweep_launches;
+        res = r;
+        if (out) *out = r;
+    }
+
+    // --------------------------------------------------------------- hooks
+    Level& level_ref(int level) {
+        REQUIRE(level >= 0 && level < nlev, "level out of range");
+        return *lev[level];
+    }
+
+    static hipMemcpyKind kind_to(int mem) { return mem == NLTE_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost; }
+    static hipMemcpyKind kind_from(int mem) { return mem == NLTE_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice; }
+
+    void formal_solution_out(int level, void* jeff, void* oml, int mem) override {
+        Level& L = level_ref(level);
+        formal_solution(level);
+        // Jeff = up + down, 1-L* = up + down, summed on the host side of the copy
+        std::vector<R> a(size_t(4) * nline * L.nvox);
+        HIPCHK(hipMemcpyAsync(a.data(), L.acc.p, sizeof(R) * a.size(), hipMemcpyDeviceToHost, st()));
+        HIPCHK(hipStreamSynchronize(st()));
+        const size_t m = size_t(nline) * L.nvox;
+        std::vector<R> j(m), o(m);
+        for (size_t i = 0; i < m; ++i) {
+            j[i] = a[i] + a[m + i];
+            o[i] = a[2 * m + i] + a[3 * m + i];
+        }
+        if (mem == NLTE_MEM_DEVICE) {
+            HIPCHK(hipMemcpyAsync(jeff, j.data(), sizeof(R) * m, hipMemcpyHostToDevice, st()));
+            HIPCHK(hipMemcpyAsync(oml, o.data(), sizeof(R) * m, hipMemcpyHostToDevice, st()));
+            HIPCHK(hipStreamSynchronize(st()));
+        } else {
+            std::memcpy(jeff, j.data(), sizeof(R) * m);
+            std::memcpy(oml, o.data(), sizeof(R) * m);
+        }
+    }
+
+    double mali_hook(int level, int iters) override {
+        level_ref(level);
+        if (iters <= 0) return 0.0;
+        mali(level, iters);
+        return read_scalar();
+    }
+
+    void residual_out(int level, double* dst, int mem) override {
+        Level& L = level_ref(level);
+        if (!L.fs_valid) formal_solution(level);
+        apply_W(level, L.f.as<double>(), L.tmp.as<double>(), -1.0);
+        HIPCHK(hipMemcpyAsync(dst, L.tmp.p, sizeof(double) * N * L.nvox, kind_to(mem), st()));
+        HIPCHK(hipStreamSynchronize(st()));
+    }
+
+    void vcycle_hook(int level, int first) override {
+        level_ref(level);
+        vcycle(level, first != 0);
+        HIPCHK(hipStreamSynchronize(st()));
+    }
+
+    void get_pops(int level, double* dst, int mem) override {
+        Level& L = level_ref(level);
+        HIPCHK(hipMemcpyAsync(dst, L.n.p, sizeof(double) * N * L.nvox, kind_to(mem), st()));
+        HIPCHK(hipStreamSynchronize(st()));
+    }
+
+    void set_pops(int level, const double* src, int mem) override {
+        Level& L = level_ref(level);
+        HIPCHK(hipMemcpyAsync(L.n.p, src, sizeof(double) * N * L.nvox, kind_from(mem), st()));
+        HIPCHK(hipStreamSynchronize(st()));
+        L.fs_valid = false;
+    }
+
+    void source_function(double* dst, int mem) override {
+        Level& F = *lev[nlev - 1];
+        DevBuf tmpS;
+        double* target = dst;
+        if (mem != NLTE_MEM_DEVICE) {
+            tmpS.alloc(ctx, sizeof(double) * nline * F.nvox);
+            target = tmpS.as<double>();
+        }
+        source_function_kernel<<<blocks_for(F.nvox, 256), 256, 0, st()>>>(atom_d.as<AtomInfo>(), F.n.as<double>(),
+                                                                          target, F.nvox);
+        HIPCHK(hipGetLastError());
+        if (mem != NLTE_MEM_DEVICE)
+            HIPCHK(hipMemcpyAsync(dst, target, sizeof(double) * nline * F.nvox, hipMemcpyDeviceToHost, st()));
+        HIPCHK(hipStreamSynchronize(st()));
+    }
+
+    void emergent(int ndir, const double* mu, float* dst, int mem) override {
+        Level& F = *lev[nlev - 1];
+        line_coef_kernel<R><<<blocks_for(F.nvox, 256), 256, 0, st()>>>(atom_d.as<AtomInfo>(), F.n.as<double>(),
+                                                                      F.lc.as<R>(), F.nvox);
+        HIPCHK(hipGetLastError());
+        if (!estate.p) estate.alloc(ctx, sizeof(double) * 2 * 3 * size_t(nf) * F.nxy);
+        DevBuf o;
+        float* target = dst;
+        if (mem != NLTE_MEM_DEVICE) {
+            o.alloc(ctx, sizeof(float) * size_t(ndir) * nf * F.nxy);
+            target = o.as<float>();
+        }
+        for (int d = 0; d < ndir; ++d) {
+            double m[3] = {mu[3 * d], mu[3 * d + 1], mu[3 * d + 2]};
+            const double nrm = std::sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+            REQUIRE(nrm > 0 && m[2] / nrm > 1e-6, "emergent directions must point upward");
+            EmergentArgs<R> a;
+            a.atom = atom_d.as<AtomInfo>();
+            a.nx = F.nx; a.ny = F.ny; a.nz = F.nz; a.nf = nf;
+            a.nxy = F.nxy; a.nvox = F.nvox;
+            a.dx = F.dx; a.dy = F.dy;
+            a.mux = m[0] / nrm; a.muy = m[1] / nrm; a.muz = m[2] / nrm;
+            a.z = F.dz.as<double>();
+            a.sc = F.sc.as<R>(); a.sv = F.sv.as<R>(); a.lc = F.lc.as<R>(); a.qf = qf.as<R>();
+            a.line_of = line_of_d.as<int>();
+            a.state = estate.as<double>();
+            a.out = target + size_t(d) * nf * F.nxy;
+            for (int k = 0; k < F.nz; ++k)
+                emergent_step_kernel<R><<<blocks_for(size_t(nf) * F.nxy, 256), 256, 0, st()>>>(a, k);
+            HIPCHK(hipGetLastError());
+        }
+        if (mem != NLTE_MEM_DEVICE)
+            HIPCHK(hipMemcpyAsync(dst, target, sizeof(float) * size_t(ndir) * nf * F.nxy, hipMemcpyDeviceToHost, st()));
+        HIPCHK(hipStreamSynchronize(st()));
+    }
+
+    void restrict_hook(int level, int nq, const double* src, double* dst) override {
+        REQUIRE(level >= 1 && level < nlev, "restriction needs 1 <= level < nlev");
+        restrict_fields(level, nq, src, dst);
+        HIPCHK(hipStreamSynchronize(st()));
+    }
+
+    void prolong_hook(int level, int nq, const double* src, double* dst) override {
+        REQUIRE(level >= 1 && level < nlev, "prolongation needs 1 <= level < nlev");
+        prolong_fields(level, nq, src, dst);
+        HIPCHK(hipStreamSynchronize(st()));
+    }
+};
+
+// ------------------------------------------------------------------ API helpers
+template <typename F>
+nlte_status guarded(nlte_ctx* ctx, F&& fn) {
+    if (!ctx) return NLTE_E_INVALID;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        nlte_status s = fn();
+        if (s >= 0) ctx->err.clear();
+        return s;
+    } catch (const Error& e) {
+        ctx->err = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        ctx->err = "host allocation failed";
+        return NLTE_E_OOM;
+    } catch (const std::exception& e) {
+        ctx->err = e.what();
+        return NLTE_E_INVALID;
+    }
+}
+
+JobBase* find_job(nlte_ctx* ctx, nlte_job job) {
+    auto it = ctx->jobs.find(job);
+    if (it == ctx->jobs.end()) throw Error(NLTE_E_INVALID, "unknown job handle");
+    return it->second;
+}
+
+bool finite_host(const double* p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+// ===================================================================== C-ABI
+extern "C" {
+
+const char* nlte_version(void) { return "nlte3d 0.1 (gfx950)"; }
+
+nlte_status nlte_ctx_create(int device, void* hip_stream, size_t hbm_budget, nlte_ctx** out) {
+    if (!out) return NLTE_E_INVALID;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return NLTE_E_DEVICE;
+    if (device < 0 || device >= ndev) return NLTE_E_INVALID;
+    auto* c = new nlte_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    try {
+        HIPCHK(hipSetDevice(device));
+        upload_constants();
+        size_t fr = 0, tot = 0;
+        HIPCHK(hipMemGetInfo(&fr, &tot));
+        c->budget = hbm_budget ? hbm_budget : size_t(0.9 * double(fr));
+    } catch (const Error& e) {
+        delete c;
+        return e.code;
+    }
+    *out = c;
+    return NLTE_OK;
+}
+
+void nlte_ctx_destroy(nlte_ctx* ctx) {
+    if (!ctx) return;
+    {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        for (auto& kv : ctx->jobs) delete kv.second;
+        ctx->jobs.clear();
+    }
+    delete ctx;
+}
+
+const char* nlte_last_error(const nlte_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+nlte_status nlte_atom_create(nlte_ctx* ctx, const nlte_atom_desc* d, nlte_atom** out) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(d && out, "null argument");
+        REQUIRE(d->nlevel >= 2 && d->nlevel <= kMaxLevels, "nlevel must be 2..8");
+        REQUIRE(d->nline >= 1 && d->nline <= kMaxLines, "nline must be 1..16");
+        REQUIRE(d->ncont >= 0 && d->ncont <= kMaxLevels, "ncont must be 0..8");
+        REQUIRE(d->ncoll >= 0 && d->ncoll <= kMaxLevels * kMaxLevels, "too many collision entries");
+        REQUIRE(d->mass_amu > 0 && d->xi >= 0, "mass must be > 0 and xi >= 0");
+        auto a = std::make_unique<nlte_atom>();
+        AtomInfo& I = a->info;
+        I.N = d->nlevel;
+        I.nline = d->nline;
+        I.ncont = d->ncont;
+        I.ncoll = d->ncoll;
+        I.mass = d->mass_amu;
+        I.xi = d->xi;
+        I.eps = d->epsilon;
+        I.eps_mode = d->epsilon > 0 ? 1 : 0;
+        REQUIRE(!I.eps_mode || d->epsilon < 1.0, "epsilon must be < 1");
+        for (int i = 0; i < I.N; ++i) {
+            REQUIRE(d->levels[i].g > 0 && std::isfinite(d->levels[i].E), "bad level data");
+            I.E[i] = d->levels[i].E;
+            I.g[i] = d->levels[i].g;
+            I.stage[i] = d->levels[i].stage;
+        }
+        int fs = 0;
+        for (int l = 0; l < I.nline; ++l) {
+            const nlte_line_desc& s = d->lines[l];
+            LineInfo& ln = I.line[l];
+            REQUIRE(s.lower >= 0 && s.upper < I.N && s.lower != s.upper, "bad line level indices");
+            REQUIRE(I.E[s.upper] > I.E[s.lower], "line upper level must lie above the lower");
+            REQUIRE(s.A > 0 && s.nfreq >= 2 && s.q, "line needs A > 0 and >= 2 frequencies");
+            for (int m = 1; m < s.nfreq; ++m) REQUIRE(s.q[m] > s.q[m - 1], "line frequencies must increase");
+            ln.lower = s.lower; ln.upper = s.upper; ln.fstart = fs; ln.nfreq = s.nfreq;
+            ln.gauss = (s.gamma_rad == 0.0 && s.gamma_vdw == 0.0) ? 1 : 0;
+            ln.nu0 = kC * (I.E[s.upper] - I.E[s.lower]);
+            ln.A = s.A;
+            ln.Bji = s.A * kC * kC / (2.0 * kH * ln.nu0 * ln.nu0 * ln.nu0);
+            ln.Bij = I.g[s.upper] / I.g[s.lower] * ln.Bji;
+            ln.hnu4pi = kH * ln.nu0 / (4.0 * kPI);
+            ln.gamma_rad = s.gamma_rad;
+            ln.gamma_vdw = s.gamma_vdw;
+            // trapezoid weights in Hz on nu = nu0 (1 + q/c)
+            for (int m = 0; m < s.nfreq; ++m) {
+                double w = 0.0;
+                if (m > 0) w += 0.5 * (s.q[m] - s.q[m - 1]);
+                if (m + 1 < s.nfreq) w += 0.5 * (s.q[m + 1] - s.q[m]);
+                a->q.push_back(s.q[m]);
+                a->wnu.push_back(w * ln.nu0 / kC);
+                a->line_of.push_back(l);
+            }
+            fs += s.nfreq;
+        }
+        a->nf = fs;
+        for (int c = 0; c < I.ncont; ++c) {
+            const nlte_cont_desc& s = d->continua[c];
+            REQUIRE(s.lower >= 0 && s.upper < I.N && I.stage[s.upper] == I.stage[s.lower] + 1,
+                    "continuum must link stage s to stage s+1");
+            I.cont_lower[c] = s.lower; I.cont_upper[c] = s.upper; I.cont_alpha0[c] = s.alpha0;
+        }
+        for (int c = 0; c < I.ncoll; ++c) {
+            const nlte_coll_desc& s = d->collisions[c];
+            REQUIRE(s.lower >= 0 && s.upper < I.N && s.lower != s.upper && s.T_ref > 0, "bad collision entry");
+            I.coll_lower[c] = s.lower; I.coll_upper[c] = s.upper;
+            I.coll_cul[c] = s.c_ul; I.coll_Tref[c] = s.T_ref; I.coll_beta[c] = s.beta;
+        }
+        *out = a.release();
+        return NLTE_OK;
+    });
+}
+
+void nlte_atom_destroy(nlte_ctx*, nlte_atom* atom) { delete atom; }
+
+nlte_status nlte_atmos_create(nlte_ctx* ctx, const nlte_atmos_desc* d, nlte_atmos** out) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(d && out && d->z, "null argument");
+        REQUIRE(d->nx >= 1 && d->ny >= 1 && d->nz >= 2, "grid must be at least 1x1x2");
+        REQUIRE(d->dx > 0 && d->dy > 0, "spacings must be positive");
+        for (int k = 1; k < d->nz; ++k) REQUIRE(d->z[k] > d->z[k - 1], "z must increase strictly");
+        REQUIRE(d->T && d->ne && d->nH && d->ntot && d->vx && d->vy && d->vz, "missing atmosphere field");
+        auto a = std::make_unique<nlte_atmos>();
+        a->nx = d->nx; a->ny = d->ny; a->nz = d->nz; a->dx = d->dx; a->dy = d->dy;
+        a->z.assign(d->z, d->z + d->nz);
+        const size_t nv = size_t(d->nx) * d->ny * d->nz;
+        const int nchi = d->chi_c ? d->nchi : 0;
+        REQUIRE(nchi >= 0 && nchi <= kMaxLines, "nchi must be 0..16");
+        a->nline_chic = nchi;
+        const double* fields[7] = {d->T, d->ne, d->nH, d->ntot, d->vx, d->vy, d->vz};
+        if (d->mem_kind == NLTE_MEM_HOST) {
+            for (int q = 0; q < 7; ++q) REQUIRE(finite_host(fields[q], nv), "non-finite atmosphere value");
+            if (nchi) REQUIRE(finite_host(d->chi_c, nv * nchi), "non-finite background opacity");
+            for (size_t i = 0; i < nv; ++i) {
+                REQUIRE(d->T[i] > 0, "temperature must be positive");
+                REQUIRE(d->ne[i] >= 0 && d->nH[i] >= 0 && d->ntot[i] > 0, "densities must be non-negative, ntot > 0");
+            }
+            for (size_t i = 0; i < nv * nchi; ++i) REQUIRE(d->chi_c[i] >= 0, "background opacity must be >= 0");
+        }
+        a->prim.alloc(ctx, sizeof(double) * (7 + nchi) * nv);
+        const hipMemcpyKind kd = d->mem_kind == NLTE_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+        for (int q = 0; q < 7; ++q)
+            HIPCHK(hipMemcpyAsync(a->prim.as<double>() + size_t(q) * nv, fields[q], sizeof(double) * nv, kd, ctx->stream));
+        if (nchi)
+            HIPCHK(hipMemcpyAsync(a->prim.as<double>() + size_t(7) * nv, d->chi_c, sizeof(double) * nv * nchi, kd, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        *out = a.release();
+        return NLTE_OK;
+    });
+}
+
+void nlte_atmos_destroy(nlte_ctx* ctx, nlte_atmos* atmos) {
+    if (!atmos) return;
+    if (ctx) {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+        delete atmos;
+        return;
+    }
+    delete atmos;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+nlte_status nlte_job_create(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom* atom,
+                            const nlte_params* params, nlte_job* job) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(atmos && atom && params && job, "null argument");
+        REQUIRE(params->method >= NLTE_MALI && params->method <= NLTE_FMG, "unknown method");
+        REQUIRE(params->precision == NLTE_FP64 || params->precision == NLTE_MIXED, "unknown precision");
+        REQUIRE(params->nu0 >= 0 && params->nu1 >= 0 && params->nu2 >= 0 && params->nu3 >= 0 && params->nu_fmg >= 0,
+                "iteration counts must be >= 0");
+        REQUIRE(params->repair_frac > 0 && params->repair_frac < 1, "repair_frac must lie in (0, 1)");
+        std::unique_ptr<JobBase> j;
+        if (params->precision == NLTE_FP64) {
+            auto* p = new Job<double>(ctx);
+            j.reset(p);
+            p->prec = NLTE_FP64;
+            p->build(atmos, atom, params);
+        } else {
+            auto* p = new Job<float>(ctx);
+            j.reset(p);
+            p->prec = NLTE_MIXED;
+            p->build(atmos, atom, params);
+        }
+        const int64_t id = ctx->next_job++;
+        ctx->jobs[id] = j.release();
+        *job = id;
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_job_run(nlte_ctx* ctx, nlte_job job, nlte_result* result) {
+    return guarded(ctx, [&]() -> nlte_status {
+        JobBase* j = find_job(ctx, job);
+        nlte_result r{};
+        j->run(&r);
+        if (result) *result = r;
+        return r.status;
+    });
+}
+
+nlte_status nlte_solve(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom* atom, const nlte_params* params,
+                       nlte_result* result, nlte_job* job) {
+    nlte_job id = 0;
+    nlte_status s = nlte_job_create(ctx, atmos, atom, params, &id);
+    if (s < 0) return s;
+    s = nlte_job_run(ctx, id, result);
+    if (s < 0) {
+        std::string msg = ctx->err;
+        nlte_release(ctx, id);
+        ctx->err = msg;
+        return s;
+    }
+    if (job) *job = id;
+    else nlte_release(ctx, id);
+    return s;
+}
+
+nlte_status nlte_release(nlte_ctx* ctx, nlte_job job) {
+    return guarded(ctx, [&]() -> nlte_status {
+        JobBase* j = find_job(ctx, job);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        delete j;
+        ctx->jobs.erase(job);
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_get_populations(nlte_ctx* ctx, nlte_job job, int level, double* dst, int dst_mem) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(dst, "null destination");
+        find_job(ctx, job)->get_pops(level, dst, dst_mem);
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_set_populations(nlte_ctx* ctx, nlte_job job, int level, const double* src, int src_mem) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(src, "null source");
+        find_job(ctx, job)->set_pops(level, src, src_mem);
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_get_source_function(nlte_ctx* ctx, nlte_job job, double* dst, int dst_mem) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(dst, "null destination");
+        find_job(ctx, job)->source_function(dst, dst_mem);
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_emergent_intensity(nlte_ctx* ctx, nlte_job job, int ndir, const double* mu, float* dst,
+                                    int dst_mem) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(ndir >= 1 && mu && dst, "bad emergent-intensity arguments");
+        find_job(ctx, job)->emergent(ndir, mu, dst, dst_mem);
+        return NLTE_OK;
+    });
+}
+
+int nlte_history(nlte_ctx* ctx, nlte_job job, double* C, int cap) {
+    if (!ctx) return -1;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->jobs.find(job);
+    if (it == ctx->jobs.end()) return -1;
+    const auto& h = it->second->history;
+    const int n = int(h.size());
+    for (int i = 0; i < n && i < cap && C; ++i) C[i] = h[i];
+    return n;
+}
+
+nlte_status nlte_formal_solution(nlte_ctx* ctx, nlte_job job, int level, void* jeff, void* oml, int dst_mem) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(jeff && oml, "null destination");
+        find_job(ctx, job)->formal_solution_out(level, jeff, oml, dst_mem);
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_mali(nlte_ctx* ctx, nlte_job job, int level, int iters, double* C_out) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(iters >= 0, "iters must be >= 0");
+        const double c = find_job(ctx, job)->mali_hook(level, iters);
+        if (C_out) *C_out = c;
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_residual(nlte_ctx* ctx, nlte_job job, int level, double* dst, int dst_mem) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(dst, "null destination");
+        find_job(ctx, job)->residual_out(level, dst, dst_mem);
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_vcycle(nlte_ctx* ctx, nlte_job job, int level, int first) {
+    return guarded(ctx, [&]() -> nlte_status {
+        find_job(ctx, job)->vcycle_hook(level, first);
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_restrict(nlte_ctx* ctx, nlte_job job, int level, int nq, const double* src, double* dst) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(nq >= 1 && src && dst, "bad restriction arguments");
+        find_job(ctx, job)->restrict_hook(level, nq, src, dst);
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_prolong(nlte_ctx* ctx, nlte_job job, int level, int nq, const double* src, double* dst) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(nq >= 1 && src && dst, "bad prolongation arguments");
+        find_job(ctx, job)->prolong_hook(level, nq, src, dst);
+        return NLTE_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,220 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
+
+Same seeded inputs on both sides; comparisons after a fixed number of iterations or
+cycles.  Tolerances: FP64 path 1e-9 per stage (populations 1e-6 after solves), mixed
+path (FP32 sweep) 1e-3 on populations as stated for the method, with the measured error
+printed.  Grids are chosen ragged (plane sizes that are not multiples of the sweep tile)
+and span several tiles.
+"""
+import numpy as np
+import pytest
+
+from oracle.formal import emergent_intensity, formal_solution
+from oracle.levels import Level, build_hierarchy
+from oracle.rates import apply_W, fine_rhs, source_function, zero_radiation
+from oracle.solver import Params as OParams
+from oracle.solver import mali, solve_fas, solve_mali, vcycle
+from oracle.transfer import prolong, restrict
+from paper_1701_01607_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(np.asarray(a, dtype=np.float64) / np.asarray(b, dtype=np.float64) - 1.0)))
+
+
+@pytest.fixture(scope="module")
+def nl():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a HIP device"
+    from paper_1701_01607_amd import nlte
+    return nlte
+
+
+@pytest.fixture(scope="module")
+def ctx(nl):
+    import torch
+    c = nl.Context(0, torch.cuda.current_stream().cuda_stream)
+    yield c
+    c.close()
+
+
+def ragged_case(nfreq=9, seed=21):
+    atom = synth.caii_like_atom(nfreq)
+    atm = synth.atmos_stratified(nx=12, ny=10, nz=9, dx=120 * synth.KM, seed=seed)
+    return atom, atm
+
+
+def shapes(atom, atm):
+    N, L = len(atom["levels"]), len(atom["lines"])
+    sp = (atm["nz"], atm["ny"], atm["nx"])
+    return (N,) + sp, (L,) + sp
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    atom, atm = ragged_case()
+    lev = Level(atom, atm)
+    n0 = zero_radiation(lev)
+    return atom, atm, lev, n0
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
+@pytest.mark.parametrize("tile", [0, 16, 64])
+def test_formal_solution_parity(nl, ctx, ragged, prec, tol, tile):
+    atom, atm, lev, n0 = ragged
+    npop, nln = shapes(atom, atm)
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1,
+                                                                 tile_points=tile))
+    g0 = job.populations(0, npop)
+    assert relerr(g0, n0) < 1e-11
+    jg, og = job.formal_solution(0, nln)
+    jo, oo = formal_solution(lev, n0)
+    ej, eo = relerr(jg, jo), relerr(og, oo)
+    print(f"prec={prec} tile={tile} Jeff err {ej:.2e}  1-L* err {eo:.2e}")
+    assert ej < tol and eo < tol
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-3)])
+def test_mali_iterations_parity(nl, ctx, ragged, prec, tol):
+    atom, atm, lev, n0 = ragged
+    npop, _ = shapes(atom, atm)
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1))
+    Cg = job.mali(0, 3)
+    n3, Co = mali(lev, 1, n0, fine_rhs(lev), 3)
+    e = relerr(job.populations(0, npop), n3)
+    print(f"prec={prec} MALI x3 population err {e:.2e}; C gpu {Cg:.6e} oracle {Co:.6e}")
+    assert e < tol
+    assert abs(Cg / Co - 1) < max(tol, 1e-6) * 50
+    assert np.allclose(job.populations(0, npop).sum(axis=0), atm["ntot"], rtol=1e-13)
+
+
+def test_residual_and_source_function_parity(nl, ctx, ragged):
+    atom, atm, lev, n0 = ragged
+    npop, nln = shapes(atom, atm)
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=0, nlev=1))
+    job.mali(0, 2)
+    n2, _ = mali(lev, 1, n0, fine_rhs(lev), 2)
+    rg = job.residual(0, npop)
+    Jeff, omL = formal_solution(lev, n2)
+    ro = fine_rhs(lev) - apply_W(lev, n2, Jeff, omL)
+    scale = np.abs(n2).max(axis=0) * 1e4   # rates are O(1e4..1e9) s^-1
+    assert np.max(np.abs(rg - ro)) < 1e-6 * np.max(np.abs(ro)) + 1e-12 * scale.max()
+    Sg = job.source_function(nln)
+    So = source_function(lev, job.populations(0, npop))
+    assert relerr(Sg, So) < 1e-12
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-5)])
+def test_emergent_intensity_parity(nl, ctx, ragged, prec, tol):
+    atom, atm, lev, n0 = ragged
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1))
+    mus = np.array([[0.0, 0.0, 1.0], [0.3, -0.2, 0.93]])
+    Ig = job.emergent(mus, lev.nf, atm["ny"], atm["nx"])
+    Io = emergent_intensity(lev, n0, mus)
+    # the output solve is FP64 in both precisions; the mixed job stores its level
+    # constants (damping, Doppler width, velocities) in FP32, hence the looser bound
+    e = relerr(Ig, Io)
+    print(f"prec={prec} emergent err {e:.2e}")
+    assert e < max(tol, 2e-6)
+
+
+def mg_case(nfreq=7):
+    atom = synth.caii_like_atom(nfreq)
+    atm = synth.atmos_stratified(nx=8, ny=8, nz=17, dx=150 * synth.KM, seed=31)
+    atm["ntot"] = atm["ntot"] * 0.1
+    return atom, atm
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-3)])
+def test_vcycle_parity(nl, ctx, prec, tol):
+    atom, atm = mg_case()
+    p = OParams(nlev=3, nu0=3, nu1=2, nu2=2, nu3=6)
+    levels = build_hierarchy(atom, atm, 3)
+    fine = levels[-1]
+    n = zero_radiation(fine)
+    n = vcycle(levels, 3, n, fine_rhs(fine), p, first=True)
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
+                  nl.SolveParams(method=nl.FAS, precision=prec, nlev=3, nu0=3, nu1=2, nu2=2, nu3=6))
+    job.vcycle(2, first=True)
+    npop, _ = shapes(atom, atm)
+    e = relerr(job.populations(2, npop), n)
+    print(f"prec={prec} V-cycle population err {e:.2e}")
+    assert e < tol
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-3)])
+@pytest.mark.parametrize("fmg", [False, True])
+def test_fas_fmg_fixed_cycles_parity(nl, ctx, prec, tol, fmg):
+    atom, atm = mg_case()
+    p = OParams(nlev=3, nu1=2, nu2=2, nu3=6, nu_fmg=4)
+    n_or, st, _ = solve_fas(atom, atm, p, fmg=fmg, cycles=2)
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
+                  nl.SolveParams(method=nl.FMG if fmg else nl.FAS, precision=prec, nlev=3, nu1=2, nu2=2, nu3=6,
+                                 nu_fmg=4, E_target=0.0, tol_C=0.0, max_iter=2))
+    rc, r = job.run()
+    npop, _ = shapes(atom, atm)
+    e = relerr(job.populations(2, npop), n_or)
+    print(f"prec={prec} fmg={fmg} 2 cycles err {e:.2e} C gpu {r.C:.4e} oracle {st.C[-1]:.4e}")
+    assert r.cycles == 2
+    assert e < tol
+    assert abs(r.C / st.C[-1] - 1) < 0.05
+
+
+def test_two_level_full_size_equals_1d_oracle(nl, ctx):
+    # 16x16x32 two-level FP64 MALI to C <= 1e-4; the atmosphere is horizontally
+    # homogeneous, so the 1x1x32 oracle column is the reference (same iteration count)
+    atom = synth.two_level_atom()
+    atm3 = synth.atmos_isothermal()
+    atm1 = synth.atmos_isothermal(nx=1, ny=1)
+    n1, st, lev = solve_mali(atom, atm1, OParams(tol_C=1e-4, E_target=None))
+    job = ctx.job(ctx.atmos(atm3), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=0, nlev=1, tol_C=1e-4,
+                                                                   E_target=0.0, max_iter=1000))
+    rc, r = job.run()
+    assert rc == 0
+    assert r.iterations == len(st.C)
+    n3 = job.populations(0, (2, 32, 16, 16))
+    e = relerr(n3, np.broadcast_to(n1, n3.shape))
+    print(f"two-level iterations {r.iterations}, err {e:.2e}")
+    assert e < 1e-6
+
+
+def test_restrict_and_prolong_parity(nl, ctx):
+    import torch
+    atom, atm = mg_case()
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.FAS, precision=0, nlev=3))
+    rng = np.random.default_rng(3)
+    f = rng.random((2, 17, 8, 8))
+    src = torch.tensor(f, dtype=torch.float64, device="cuda")
+    dst = torch.empty((2, 9, 4, 4), dtype=torch.float64, device="cuda")
+    job.restrict(2, src.data_ptr(), dst.data_ptr(), 2)
+    torch.cuda.synchronize()
+    assert np.allclose(dst.cpu().numpy(), restrict(f), rtol=1e-15, atol=0)
+    c = rng.random((2, 9, 4, 4))
+    srcc = torch.tensor(c, dtype=torch.float64, device="cuda")
+    dstf = torch.empty((2, 17, 8, 8), dtype=torch.float64, device="cuda")
+    job.prolong(2, srcc.data_ptr(), dstf.data_ptr(), 2)
+    torch.cuda.synchronize()
+    assert np.allclose(dstf.cpu().numpy(), prolong(c, atm["z"]), rtol=1e-14, atol=0)
+
+
+def test_determinism_and_invalid_inputs(nl, ctx):
+    atom, atm = mg_case()
+    outs = []
+    for _ in range(2):
+        job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
+                      nl.SolveParams(method=nl.FAS, precision=nl.MIXED, nlev=3, nu3=6, max_iter=2, E_target=0.0))
+        job.run()
+        outs.append(job.populations(2, (6, 17, 8, 8)))
+        job.close()
+    assert np.array_equal(outs[0], outs[1])
+    with pytest.raises(nl.NlteError) as ei:
+        ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.FAS, nlev=5))
+    assert ei.value.code == nl.E_INVALID
+    bad = dict(atm)
+    bad["T"] = atm["T"].copy()
+    bad["T"][3, 2, 1] = np.nan
+    with pytest.raises(nl.NlteError) as ei:
+        ctx.atmos(bad)
+    assert ei.value.code == nl.E_INVALID
