@@ -92,6 +92,9 @@ def main():
     ap.add_argument("--no-mali", action="store_true", help="skip the FP64 MALI comparison solve")
     ap.add_argument("--mali-max-iter", type=int, default=800)
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--kernel-probe", action="store_true",
+                    help="only one MALI iteration (one formal solution + rate solve) and a 512 MiB "
+                         "device copy, for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -119,6 +122,20 @@ def main():
     nf = sum(len(l["q"]) for l in atom["lines"])
     mu_out = np.array([[0.0, 0.0, 1.0]])
     N = len(atom["levels"])
+
+    if args.kernel_probe:
+        probe = nlte.SolveParams(method=nlte.MALI, precision=nlte.MIXED, nlev=1, E_target=0.0, max_iter=1,
+                                 tile_points=args.tile or 32)
+        job = ctx.job(M, A, probe)
+        rc, r = job.run()
+        job.close()
+        src = torch.empty(512 * 2 ** 20 // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": args.workload, "updates": r.updates, "sweep_launches": r.sweep_launches,
+                          "copy_bytes": src.numel() * 4}))
+        return
 
     def step():
         job = ctx.job(M, A, params)

@@ -6,7 +6,8 @@
 //   with p a polynomial of degree N-1 whose coefficients are cosine sums of
 //   exp(-t^2)(L^2 + t^2) at t = L tan(theta/2); L = sqrt(N / sqrt 2).  N = 16 in FP32
 //   (absolute error ~3e-7 of the line-centre value, at the FP32 rounding floor) and
-//   N = 32 in FP64 (~4e-14).  Lines without damping use exp(-u^2) directly.
+//   N = 32 in FP64 (~4e-14).  In FP32 the far wings (|u| >= 6) use the asymptotic
+//   series of w(z) instead.  Lines without damping use exp(-u^2) directly.
 // * Linear short-characteristics coefficients (Kunasz & Auer 1988):
 //     e = exp(-x), Psi_o = 1 - (1-e)/x, Psi_u = (1-e)/x - e,
 //   with their Taylor series below a precision-dependent threshold.
@@ -49,31 +50,49 @@ template <> struct VoigtTraits<double> {
     __device__ static double L() { return c_voigt_Ld; }
 };
 
-__device__ inline float dev_rcp(float x) { return __frcp_rn(x); }
+__device__ inline float dev_rcp(float x) { return __builtin_amdgcn_rcpf(x); }   // v_rcp_f32, 1 ulp
 __device__ inline double dev_rcp(double x) { return 1.0 / x; }
 __device__ inline float dev_exp_neg(float x) { return __expf(-x); }
 __device__ inline double dev_exp_neg(double x) { return exp(-x); }
 
-// H(a, u) for a >= 0 (Weideman rational series).
+// H(a, u) for a >= 0 (Weideman rational series), complex Horner with explicit FMAs.
 template <typename R>
 __device__ inline R voigt_H(R a, R u) {
     using T = VoigtTraits<R>;
     const R L = T::L();
     const R lpa = L + a;
-    const R den = lpa * lpa + u * u;
+    const R den = fma(lpa, lpa, u * u);
     const R rden = dev_rcp(den);
-    const R zr = ((L - a) * lpa - u * u) * rden;
+    const R zr = fma(L - a, lpa, -u * u) * rden;
     const R zi = (R(2) * L * u) * rden;
     R pr = T::coef(0), pi = R(0);
 #pragma unroll
     for (int j = 1; j < T::N; ++j) {
-        const R t = pr * zr - pi * zi + T::coef(j);
-        pi = pr * zi + pi * zr;
+        const R t = fma(pr, zr, fma(-pi, zi, T::coef(j)));
+        pi = fma(pr, zi, pi * zr);
         pr = t;
     }
     const R rr = lpa * rden, ri = u * rden;
-    const R r2r = rr * rr - ri * ri, r2i = R(2) * rr * ri;
-    return R(2) * (pr * r2r - pi * r2i) + rr * R(kINVSQRTPI);
+    const R r2r = fma(rr, rr, -ri * ri), r2i = R(2) * rr * ri;
+    return fma(R(2), fma(pr, r2r, -pi * r2i), rr * R(kINVSQRTPI));
+}
+
+// Far wings, |u| >= 6: w(z) ~ (i/sqrt(pi)) z^-1 sum_n (2n-1)!!/2^n z^-2n (8 terms); the
+// Gaussian part exp(-z^2) is below 3e-16 there.  Relative error <= 4e-7 in FP32.
+__device__ inline float voigt_H_wing(float a, float u) {
+    const float rd = __builtin_amdgcn_rcpf(fmaf(u, u, a * a));
+    const float rr = u * rd, ri = -a * rd;                       // 1/z
+    const float r2r = fmaf(rr, rr, -ri * ri), r2i = 2.0f * rr * ri;
+    const float cf[8] = {1.0f, 0.5f, 0.75f, 1.875f, 6.5625f, 29.53125f, 162.421875f, 1055.7421875f};
+    float sr = cf[7], si = 0.0f;
+#pragma unroll
+    for (int n = 6; n >= 0; --n) {
+        const float t = fmaf(sr, r2r, fmaf(-si, r2i, cf[n]));
+        si = fmaf(sr, r2i, si * r2r);
+        sr = t;
+    }
+    const float ti = fmaf(rr, si, ri * sr);
+    return -ti * float(kINVSQRTPI);
 }
 
 // Profile shape: Gaussian for undamped lines, Voigt otherwise.
@@ -81,6 +100,12 @@ template <typename R>
 __device__ inline R profile_H(R a, R u, bool gauss) {
     if (gauss) return dev_exp_neg(u * u);
     return voigt_H<R>(a, u);
+}
+template <>
+__device__ inline float profile_H<float>(float a, float u, bool gauss) {
+    if (gauss) return __expf(-u * u);
+    if (fabsf(u) >= 6.0f) return voigt_H_wing(a, u);
+    return voigt_H<float>(a, u);
 }
 
 // Linear short-characteristics segment coefficients; omp = 1 - Psi_o is returned
@@ -95,7 +120,7 @@ __device__ inline void sc_coeffs(float x, float& ex, float& pu, float& po, float
                 - x * (6.0f / 5040.0f - x * (7.0f / 40320.0f - x * (8.0f / 362880.0f))))))));
         omp = 1.0f - po;
     } else {
-        const float r = (1.0f - ex) * __frcp_rn(x);
+        const float r = (1.0f - ex) * __builtin_amdgcn_rcpf(x);
         po = 1.0f - r;
         pu = r - ex;
         omp = r;

@@ -183,6 +183,13 @@ __global__ void line_coef_kernel(const AtomInfo* atom, const double* n, R* lc, s
 }
 
 // ------------------------------------------------------------------ sweep
+// Plane state of one (direction, frequency, point): intensity, source function and
+// opacity, stored together so one 12-byte load fetches an upwind corner.
+template <typename R>
+struct Cell {
+    R I, S, C;
+};
+
 // One plane step of the short-characteristics formal solution for all 24 directions.
 // Step s: upward directions solve plane s from plane s-1, downward directions plane
 // nz-1-s from nz-s; s = 0 sets the boundary planes (I = B below, I = 0 or prescribed
@@ -203,8 +210,10 @@ struct SweepArgs {
     const R* qf;         // [nf] velocity offsets
     const R* wf;         // [nf] frequency weights (Hz)
     const R* topI;       // [nf][nxy] or null
-    R* state;            // [2 slots][3][24][nf][nxy]: I, S, chi
+    Cell<R>* state;      // [2 slots][24][nline * Q][nxy]
     R* acc;              // [2 qty][2 hemi][nline][nvox]
+    int m0, Q;           // this pass covers frequencies m0 .. m0+Q-1 of every line
+    int add;             // 1: add this pass's sums to acc; 0: overwrite
 };
 
 template <typename R, int P, int CH>
@@ -219,13 +228,19 @@ __global__ __launch_bounds__(kNHemi* P* CH) void sweep_step_kernel(SweepArgs<R> 
     const AtomInfo& at = *a.atom;
     const LineInfo& ln = at.line[l];
     const int L = at.nline;
-    const size_t g = size_t(blockIdx.x) * P + p;
+    // XCD-aware tile order: the dispatcher deals consecutive blocks round-robin to the
+    // 8 XCDs, so when the tile count divides by 8, tile t of XCD x is tile x*(T/8) + t.
+    // Neighbouring tiles, which read each other's upwind rows, then share an L2.
+    const unsigned T = gridDim.x;
+    const unsigned bx = (T % 8u == 0u) ? (blockIdx.x % 8u) * (T / 8u) + blockIdx.x / 8u : blockIdx.x;
+    const size_t g = size_t(bx) * P + p;
     const bool valid = g < a.nxy;
     const int k = (h == 0) ? s : a.nz - 1 - s;
     R jacc = R(0), lacc = R(0);
     const size_t nv = a.nvox, nxy = a.nxy;
-    const size_t plane_stride = size_t(a.nf) * nxy;            // one (q, d) block
-    const size_t slot_stride = size_t(3) * kNDir * plane_stride;
+    const size_t dstride = size_t(L) * a.Q * nxy;            // one direction's planes in this pass
+    const size_t slot_stride = size_t(kNDir) * dstride;
+    const int mend = min(ln.nfreq, a.m0 + a.Q);
 
     if (valid) {
         const size_t v = size_t(k) * nxy + g;
@@ -241,24 +256,24 @@ __global__ __launch_bounds__(kNHemi* P* CH) void sweep_step_kernel(SweepArgs<R> 
         const R vn = a.sv[SV_VX * nv + v] * R(mux) + a.sv[SV_VY * nv + v] * R(muy) +
                      a.sv[SV_VZ * nv + v] * R(muz);
         const bool gauss = ln.gauss != 0;
-        R* cur = a.state + size_t(s & 1) * slot_stride;
-        R* Icur = cur + (size_t(0) * kNDir + d) * plane_stride;
-        R* Scur = cur + (size_t(1) * kNDir + d) * plane_stride;
-        R* Ccur = cur + (size_t(2) * kNDir + d) * plane_stride;
+        // this thread's (direction, line) column of plane cells; cell (m - m0) of the pass
+        Cell<R>* cur = a.state + size_t(s & 1) * slot_stride + size_t(d) * dstride + size_t(l) * a.Q * nxy;
+        const R* qf = a.qf + ln.fstart;
+        const R* wf = a.wf + ln.fstart;
         if (s == 0) {
             const R Bb = a.sc[(SC_B * L + l) * nv + v];
-            for (int m = c; m < ln.nfreq; m += CH) {
-                const int f = ln.fstart + m;
-                const R u = a.qf[f] * ivD - vn;
+            const R* top = a.topI ? a.topI + size_t(ln.fstart) * nxy + g : nullptr;
+            for (int m = a.m0 + c; m < mend; m += CH) {
+                const R u = qf[m] * ivD - vn;
                 const R H = profile_H<R>(adamp, u, gauss);
                 const R phi = H * pn;
                 const R chi = chic + kpl * phi;
                 const R S = (etac + el * phi) * dev_rcp(chi);
-                const R I = (h == 0) ? Bb : (a.topI ? a.topI[size_t(f) * nxy + g] : R(0));
-                Icur[size_t(f) * nxy + g] = I;
-                Scur[size_t(f) * nxy + g] = S;
-                Ccur[size_t(f) * nxy + g] = chi;
-                const R wphi = a.wf[f] * H * pw;
+                const R I = (h == 0) ? Bb : (top ? top[size_t(m) * nxy] : R(0));
+                Cell<R> cell;
+                cell.I = I; cell.S = S; cell.C = chi;
+                cur[size_t(m - a.m0) * nxy + g] = cell;
+                const R wphi = wf[m] * H * pw;
                 jacc += wphi * I;
                 lacc += wphi;
             }
@@ -273,38 +288,51 @@ __global__ __launch_bounds__(kNHemi* P* CH) void sweep_step_kernel(SweepArgs<R> 
             int y0 = int((long long)(y + (long long)fsy) % a.ny); if (y0 < 0) y0 += a.ny;
             const int x1 = (x0 + 1 == a.nx) ? 0 : x0 + 1;
             const int y1 = (y0 + 1 == a.ny) ? 0 : y0 + 1;
-            const size_t g00 = size_t(y0) * a.nx + x0, g01 = size_t(y0) * a.nx + x1;
-            const size_t g10 = size_t(y1) * a.nx + x0, g11 = size_t(y1) * a.nx + x1;
+            const unsigned g00 = unsigned(y0 * a.nx + x0), g01 = unsigned(y0 * a.nx + x1);
+            const unsigned g10 = unsigned(y1 * a.nx + x0), g11 = unsigned(y1 * a.nx + x1);
             const R w00 = (R(1) - fx) * (R(1) - fy), w01 = fx * (R(1) - fy);
             const R w10 = (R(1) - fx) * fy, w11 = fx * fy;
             const R rds = R(ds);
-            const R* prv = a.state + size_t((s - 1) & 1) * slot_stride;
-            const R* Ip = prv + (size_t(0) * kNDir + d) * plane_stride;
-            const R* Sp = prv + (size_t(1) * kNDir + d) * plane_stride;
-            const R* Cp = prv + (size_t(2) * kNDir + d) * plane_stride;
-            for (int m = c; m < ln.nfreq; m += CH) {
-                const int f = ln.fstart + m;
-                const size_t fo = size_t(f) * nxy;
-                const R u = a.qf[f] * ivD - vn;
+            const R etac_s = etac, chic_s = chic;
+            // wave-uniform base of this (direction, line) column and 32-bit byte offsets
+            const char* pb = reinterpret_cast<const char*>(a.state + size_t((s - 1) & 1) * slot_stride +
+                                                           size_t(d) * dstride + size_t(l) * a.Q * nxy);
+            char* cb = reinterpret_cast<char*>(cur);
+            const unsigned csz = sizeof(Cell<R>);
+            const unsigned inc = unsigned(CH) * unsigned(nxy) * csz;
+            unsigned o00 = (unsigned(c) * unsigned(nxy) + g00) * csz;
+            unsigned o01 = (unsigned(c) * unsigned(nxy) + g01) * csz;
+            unsigned o10 = (unsigned(c) * unsigned(nxy) + g10) * csz;
+            unsigned o11 = (unsigned(c) * unsigned(nxy) + g11) * csz;
+            unsigned oc = (unsigned(c) * unsigned(nxy) + unsigned(g)) * csz;
+#pragma unroll 2
+            for (int m = a.m0 + c; m < mend; m += CH, o00 += inc, o01 += inc, o10 += inc, o11 += inc, oc += inc) {
+                const Cell<R> c00 = *reinterpret_cast<const Cell<R>*>(pb + o00);
+                const Cell<R> c01 = *reinterpret_cast<const Cell<R>*>(pb + o01);
+                const Cell<R> c10 = *reinterpret_cast<const Cell<R>*>(pb + o10);
+                const Cell<R> c11 = *reinterpret_cast<const Cell<R>*>(pb + o11);
+                const R u = qf[m] * ivD - vn;
                 const R H = profile_H<R>(adamp, u, gauss);
                 const R phi = H * pn;
-                const R chi = chic + kpl * phi;
+                const R chi = fma(kpl, phi, chic);
                 const R rchi = dev_rcp(chi);
-                const R S = (etac + el * phi) * rchi;
-                const R Iu = w00 * Ip[fo + g00] + w01 * Ip[fo + g01] + w10 * Ip[fo + g10] + w11 * Ip[fo + g11];
-                const R Su = w00 * Sp[fo + g00] + w01 * Sp[fo + g01] + w10 * Sp[fo + g10] + w11 * Sp[fo + g11];
-                const R Cu = w00 * Cp[fo + g00] + w01 * Cp[fo + g01] + w10 * Cp[fo + g10] + w11 * Cp[fo + g11];
+                const R S = fma(el, phi, etac) * rchi;
+                const R Iu = fma(w00, c00.I, fma(w01, c01.I, fma(w10, c10.I, w11 * c11.I)));
+                const R Su = fma(w00, c00.S, fma(w01, c01.S, fma(w10, c10.S, w11 * c11.S)));
+                const R Cu = fma(w00, c00.C, fma(w01, c01.C, fma(w10, c10.C, w11 * c11.C)));
                 const R dtau = R(0.5) * (Cu + chi) * rds;
                 R ex, pu, po, omp;
                 sc_coeffs(dtau, ex, pu, po, omp);
-                const R Ith = Iu * ex + pu * Su;
-                const R Io = Ith + po * S;
-                Icur[fo + g] = Io;
-                Scur[fo + g] = S;
-                Ccur[fo + g] = chi;
-                const R wphi = a.wf[f] * H * pw;
-                jacc += wphi * (Ith + po * etac * rchi);
-                lacc += wphi * (omp + po * chic * rchi);
+                const R Ith = fma(Iu, ex, pu * Su);
+                Cell<R> cell;
+                cell.I = fma(po, S, Ith);
+                cell.S = S;
+                cell.C = chi;
+                *reinterpret_cast<Cell<R>*>(cb + oc) = cell;
+                const R wphi = wf[m] * H * pw;
+                const R por = po * rchi;
+                jacc = fma(wphi, fma(por, etac_s, Ith), jacc);
+                lacc = fma(wphi, fma(por, chic_s, omp), lacc);
             }
         }
     }
@@ -320,8 +348,11 @@ __global__ __launch_bounds__(kNHemi* P* CH) void sweep_step_kernel(SweepArgs<R> 
             lt += sl[q * P + t];
         }
         const size_t v = size_t(k) * nxy + g;
-        a.acc[((size_t(0) * 2 + h) * L + l) * nv + v] = jt;
-        a.acc[((size_t(1) * 2 + h) * L + l) * nv + v] = lt;
+        R* aj = a.acc + ((size_t(0) * 2 + h) * L + l) * nv + v;
+        R* al = a.acc + ((size_t(1) * 2 + h) * L + l) * nv + v;
+        if (a.add) { jt += *aj; lt += *al; }
+        *aj = jt;
+        *al = lt;
     }
 }
 

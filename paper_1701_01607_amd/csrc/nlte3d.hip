@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -49,6 +50,7 @@ inline unsigned blocks_for(size_t n, unsigned bs) { return unsigned((n + bs - 1)
 
 // ===================================================================== context
 struct nlte_ctx {
+    std::map<std::string, int> tile_cache;   // autotuned sweep tile per level shape
     int device = 0;
     hipStream_t stream = nullptr;
     size_t budget = 0, used = 0;
@@ -344,7 +346,17 @@ struct Job : JobBase {
             HIPCHK(hipGetLastError());
         }
         const Level& Fz = *lev[nlev - 1];
-        state.alloc(ctx, sizeof(R) * 2 * 3 * kNDir * size_t(nf) * Fz.nxy);
+        // Frequency passes: each pass sweeps Q frequencies of every line.  One pass is the
+        // default; the plane state (2 x 24 x nline x Q cells per plane point) is split into
+        // more passes only when a single pass would take more than a quarter of the
+        // remaining HBM budget (NLTE3D_SWEEP_STATE_MB overrides the state size cap).
+        maxfreq = 0;
+        for (int l = 0; l < nline; ++l) maxfreq = std::max(maxfreq, info.line[l].nfreq);
+        const char* envb = std::getenv("NLTE3D_SWEEP_STATE_MB");
+        const double cap_bytes = envb ? std::atof(envb) * 1048576.0 : 0.25 * double(ctx->budget - ctx->used);
+        const double per_q = double(sizeof(Cell<R>)) * 2 * kNDir * nline * Fz.nxy;
+        Qpass = std::max(1, std::min(maxfreq, int(cap_bytes / per_q)));
+        state.alloc(ctx, sizeof(Cell<R>) * 2 * kNDir * size_t(nline) * Qpass * Fz.nxy);
         nprev.alloc(ctx, sizeof(double) * N * Fz.nvox);
         if (p->top_I) {
             topI.alloc(ctx, sizeof(R) * size_t(nf) * Fz.nxy);
@@ -379,12 +391,66 @@ struct Job : JobBase {
         CH = t ? 64 / t : 0;
     }
 
-    void tile_for(const Level& L, int& p, int& ch) const {
+    std::vector<int> level_tile;   // autotuned points per wave row, per level
+    int maxfreq = 0, Qpass = 1;    // frequencies per line swept per pass
+
+    std::string tile_key(const Level& L) const {
+        return std::to_string(sizeof(R)) + ":" + std::to_string(L.nx) + "x" + std::to_string(L.ny) + "x" +
+               std::to_string(L.nz) + ":" + std::to_string(nline) + ":" + std::to_string(nf);
+    }
+
+    void launch_step(const SweepArgs<R>& a, dim3 grid, int p, int s) {
+        switch (p) {
+            case 64: sweep_step_kernel<R, 64, 1><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
+            case 32: sweep_step_kernel<R, 32, 2><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
+            case 16: sweep_step_kernel<R, 16, 4><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
+            default: sweep_step_kernel<R, 8, 8><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
+        }
+    }
+
+    // Autotuner: time plane steps 1..3 of a formal solution for each tile width and keep
+    // the fastest.  The result is cached per (precision, shape, lines, frequencies) in the
+    // context, so a shape is tuned once per process.
+    int autotune_tile(int k, SweepArgs<R>& a) {
+        Level& L = *lev[k];
+        const std::string key = tile_key(L);
+        auto it = ctx->tile_cache.find(key);
+        if (it != ctx->tile_cache.end()) return it->second;
+        const int cand[4] = {64, 32, 16, 8};
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        int best = 64;
+        float best_ms = 1e30f;
+        const int steps = std::min(L.nz, 4);
+        for (int c : cand) {
+            if (c > 8 && L.nxy < size_t(c) * 4 && c != 8) continue;   // keep >= 4 tiles per row block
+            dim3 grid(blocks_for(L.nxy, c), nline, 2);
+            launch_step(a, grid, c, 0);
+            HIPCHK(hipEventRecord(e0, st()));
+            for (int s = 1; s < steps; ++s) launch_step(a, grid, c, s);
+            HIPCHK(hipEventRecord(e1, st()));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) { best_ms = ms; best = c; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ctx->tile_cache[key] = best;
+        return best;
+    }
+
+    void tile_for(int k, SweepArgs<R>& a, int& p, int& ch) {
         if (P) { p = P; ch = CH; return; }
-        if (L.nxy >= 4096) p = 64;
-        else if (L.nxy >= 1024) p = 32;
-        else if (L.nxy >= 256) p = 16;
-        else p = 8;
+        if (level_tile.size() != size_t(nlev)) level_tile.assign(nlev, 0);
+        if (!level_tile[k]) {
+            a.m0 = 0;
+            a.Q = Qpass;
+            a.add = 0;
+            level_tile[k] = autotune_tile(k, a);
+        }
+        p = level_tile[k];
         ch = 64 / p;
     }
 
@@ -438,23 +504,21 @@ struct Job : JobBase {
         a.sc = L.sc.as<R>(); a.sv = L.sv.as<R>(); a.lc = L.lc.as<R>();
         a.qf = qf.as<R>(); a.wf = wf.as<R>();
         a.topI = (k == nlev - 1 && topI.p) ? topI.as<R>() : nullptr;
-        a.state = state.as<R>();
+        a.state = state.as<Cell<R>>();
         a.acc = L.acc.as<R>();
         int p, ch;
-        tile_for(L, p, ch);
+        tile_for(k, a, p, ch);
         dim3 grid(blocks_for(L.nxy, p), nline, 2);
         ev_begin(EV_SWEEP);
-        for (int s = 0; s < L.nz; ++s) {
-            switch (p) {
-                case 64: sweep_step_kernel<R, 64, 1><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
-                case 32: sweep_step_kernel<R, 32, 2><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
-                case 16: sweep_step_kernel<R, 16, 4><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
-                default: sweep_step_kernel<R, 8, 8><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
-            }
+        for (int m0 = 0; m0 < maxfreq; m0 += Qpass) {
+            a.m0 = m0;
+            a.Q = Qpass;
+            a.add = m0 > 0 ? 1 : 0;
+            for (int s = 0; s < L.nz; ++s) launch_step(a, grid, p, s);
+            sweep_launches += L.nz;
         }
         HIPCHK(hipGetLastError());
         ev_end();
-        sweep_launches += L.nz;
         L.fs_valid = true;
         ++L.fs_count;
         const Level& F = *lev[nlev - 1];
