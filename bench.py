@@ -92,6 +92,7 @@ def main():
     ap.add_argument("--no-mali", action="store_true", help="skip the FP64 MALI comparison solve")
     ap.add_argument("--mali-max-iter", type=int, default=800)
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--graph", type=int, default=0, help="1: replay V-cycles from a captured HIP graph")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only one MALI iteration (one formal solution + rate solve) and a 512 MiB "
                          "device copy, for hardware-counter runs")
@@ -118,7 +119,8 @@ def main():
     method = {"FAS": nlte.FAS, "FMG": nlte.FMG, "MALI": nlte.MALI}[wl["method"]]
     params = nlte.SolveParams(method=method, precision=nlte.MIXED, nlev=wl["nlev"], nu0=wl["nu0"],
                               nu1=wl["nu1"], nu2=wl["nu2"], nu3=wl["nu3"], nu_fmg=wl["nu_fmg"],
-                              E_target=1e-3, max_iter=60, timing=1, tile_points=args.tile)
+                              E_target=1e-3, max_iter=60, timing=0 if args.graph else 1, tile_points=args.tile,
+                              graph=args.graph)
     nf = sum(len(l["q"]) for l in atom["lines"])
     mu_out = np.array([[0.0, 0.0, 1.0]])
     N = len(atom["levels"])
@@ -166,10 +168,13 @@ def main():
     sweep_ms = sum(x.ms_sweep for _, x in results)
     launches = sum(x.sweep_launches for _, x in results)
     fl = FLOPS_PER_UPDATE_VOIGT if any(l["gamma_rad"] or l["gamma_vdw"] for l in atom["lines"]) else FLOPS_PER_UPDATE_GAUSS
-    avg_launch_us = 1e3 * sweep_ms / launches
-    flops_per_launch = upd * fl / launches
-    achieved = flops_per_launch / (avg_launch_us * 1e-6) / 1e12
-    ups_sweep = upd / (sweep_ms * 1e-3)
+    if sweep_ms > 0:
+        avg_launch_us = 1e3 * sweep_ms / launches
+        flops_per_launch = upd * fl / launches
+        achieved = flops_per_launch / (avg_launch_us * 1e-6) / 1e12
+        ups_sweep = upd / (sweep_ms * 1e-3)
+    else:   # graph replay: no per-phase events
+        avg_launch_us = achieved = ups_sweep = None
 
     out = {
         "metric": "converged atmospheres/hr + voxel-angle-freq updates/s, FAS-FP32 vs MALI-FP64",
@@ -190,7 +195,7 @@ def main():
         "phase_ms": {"setup": r.ms_setup, "sweep": r.ms_sweep, "rates": r.ms_rates, "transfer": r.ms_transfer,
                      "total": r.ms_total},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS if achieved else None, "traffic": None,
                      "kernel": "sweep_step_kernel<float>", "avg_launch_us": avg_launch_us,
                      "flops_per_update": fl, "launches": launches},
     }

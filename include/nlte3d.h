@@ -126,6 +126,10 @@ typedef struct {
     const double* top_I;       /* prescribed incoming intensity at the top [nf][ny][nx] or NULL */
     int tile_points;           /* sweep points per wave row: 0 = autotune, else 8/16/32/64 */
     int timing;                /* 1: time each phase with HIP events on the context stream */
+    int graph;                 /* 1: capture one V-cycle (FAS/FMG) or one MALI iteration as a
+                                  HIP graph on a job-private stream and replay it; the first
+                                  cycle (nu0) runs eagerly.  Phase timing is not available
+                                  for replayed work. */
 } nlte_params;
 
 typedef struct {
@@ -215,6 +219,47 @@ nlte_status nlte_vcycle(nlte_ctx* ctx, nlte_job job, int level, int first);
 nlte_status nlte_restrict(nlte_ctx* ctx, nlte_job job, int level, int nq, const double* src, double* dst);
 /* Trilinear prolongation (Sect. 4.5) of q fields from grid `level-1` to `level`. */
 nlte_status nlte_prolong(nlte_ctx* ctx, nlte_job job, int level, int nq, const double* src, double* dst);
+
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of many solves on one context.  nlte_submit queues a solve and
+ * returns NLTE_W_QUEUED at once; worker threads admit queued solves in FIFO order as
+ * soon as their device footprint fits the unreserved part of the HBM budget (the memory
+ * of finished jobs counts until nlte_release; a job larger than the whole budget is
+ * rejected at submission), build and run each on its own HIP stream, so the
+ * kernels of concurrent solves overlap on the device, and keep the populations resident
+ * until nlte_release.  The caller keeps `atmos` and `atom` alive until the job leaves
+ * the queue (state >= NLTE_JOB_RUNNING has been observed) and passes no host arrays in
+ * `params` (init_pops, top_I must be NULL).  Results are read with the output calls
+ * above once the job is done.  Each solve is computed exactly as it would be alone. */
+#define NLTE_JOB_QUEUED  0
+#define NLTE_JOB_RUNNING 1
+#define NLTE_JOB_DONE    2
+#define NLTE_JOB_FAILED  3
+
+typedef struct {
+    int state;                 /* NLTE_JOB_* */
+    int status;                /* final status of a finished job */
+    double t_submit, t_admit, t_done;   /* seconds on a monotonic clock */
+    size_t footprint;          /* device bytes reserved at admission */
+    nlte_result result;        /* valid when state == NLTE_JOB_DONE */
+    char error[256];           /* message of a failed job */
+} nlte_job_info_t;
+
+/* Start up to `max_running` worker threads (1..16): the number of concurrent solves. */
+nlte_status nlte_serve_config(nlte_ctx* ctx, int max_running);
+/* Device bytes a job with these inputs will allocate (its admission footprint). */
+nlte_status nlte_estimate_footprint(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom* atom,
+                                    const nlte_params* params, size_t* bytes);
+/* Queue a solve; returns NLTE_W_QUEUED with *job set, or a negative error. */
+nlte_status nlte_submit(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom* atom,
+                        const nlte_params* params, nlte_job* job);
+/* Current NLTE_JOB_* state of a submitted job. */
+nlte_status nlte_poll(nlte_ctx* ctx, nlte_job job, int* state);
+/* Block until the job finishes (its final status) or `timeout_ms` passes (NLTE_W_QUEUED;
+ * a negative timeout waits forever). */
+nlte_status nlte_wait(nlte_ctx* ctx, nlte_job job, int timeout_ms);
+/* State, timestamps, footprint and result of a submitted job. */
+nlte_status nlte_job_info(nlte_ctx* ctx, nlte_job job, nlte_job_info_t* info);
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,10 @@ Readings of the geometry and boundaries:
   dtau = (chi_u + chi_o) ds / 2.
 * Lower boundary (upward rays): I = B_nu0(T) at the local gas temperature.  Upper
   boundary (downward rays): I = 0, or a prescribed array (Sect. 4.2).
+* Where the total opacity vanishes (the profile underflows far out in a wing, or a
+  clipped line opacity without background), S is the limit of (eta_c + e phi) /
+  (chi_c + k phi) as phi -> 0: eta_c/chi_c with a background, else the line source
+  function e/k, else 0.  A segment from an opaque upwind point still sees this S.
 * Segment update: e = exp(-dtau), e0 = 1 - e, Psi_o = 1 - e0/dtau, Psi_u = e0/dtau - e,
   I_o = I_u e + Psi_u S_u + Psi_o S_o; for dtau < 1e-2 the exact series of Psi_o and
   Psi_u (6 terms) replaces the direct formula.
@@ -70,6 +74,19 @@ def upwind_interp(Q, sx, sy):
     q10 = np.roll(Q, (-iy - 1, -ix), axis=(-2, -1))
     q11 = np.roll(Q, (-iy - 1, -ix - 1), axis=(-2, -1))
     return (1.0 - fy) * ((1.0 - fx) * q00 + fx * q01) + fy * ((1.0 - fx) * q10 + fx * q11)
+
+
+def safe_div(num, chi):
+    """num / chi where chi > 0, else 0."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.where(chi > 0.0, num / chi, 0.0)
+
+
+def source_function(chi, chi_c, eta_c, k, e, phi):
+    """(eta_c + e phi) / chi, or its limit as phi -> 0 where chi vanishes."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        lim = np.where(chi_c > 0.0, eta_c / chi_c, np.where(k > 0.0, e / k, 0.0))
+        return np.where(chi > 0.0, (eta_c + e * phi) / chi, lim)
 
 
 def plane_order(nz, mu_z):
@@ -133,7 +150,7 @@ def formal_solution(lev, n, want_jbar=False):
             chi_c = lev.chi_c[lo, k]
             eta_c = lev.eta_c[lo, k]
             chi = chi_c + kk[lo, k] * phi
-            S = (eta_c + ee[lo, k] * phi) / chi
+            S = source_function(chi, chi_c, eta_c, kk[lo, k], ee[lo, k], phi)
             wphi = lev.wmu[d] * lev.wnu[:, None, None] * phi * norm[lo, k]
             return chi, S, (wphi, chi_c, eta_c)
 
@@ -153,8 +170,8 @@ def formal_solution(lev, n, want_jbar=False):
                     Jbar[:, k] += np.add.reduceat(wphi * I, fs, axis=0)
                 return
             I_u, S_u, ex, psi_u, psi_o, I_o, chi, S, (wphi, chi_c, eta_c) = data
-            Jeff[:, k] += np.add.reduceat(wphi * (I_u * ex + psi_u * S_u + psi_o * eta_c / chi), fs, axis=0)
-            omL[:, k] += np.add.reduceat(wphi * ((1.0 - psi_o) + psi_o * chi_c / chi), fs, axis=0)
+            Jeff[:, k] += np.add.reduceat(wphi * (I_u * ex + psi_u * S_u + psi_o * safe_div(eta_c, chi)), fs, axis=0)
+            omL[:, k] += np.add.reduceat(wphi * ((1.0 - psi_o) + psi_o * safe_div(chi_c, chi)), fs, axis=0)
             if want_jbar:
                 Jbar[:, k] += np.add.reduceat(wphi * I_o, fs, axis=0)
 
@@ -177,7 +194,7 @@ def emergent_intensity(lev, n, mus):
         def local(k, mu=mu):
             phi = lev.profile(k, mu)
             chi = lev.chi_c[lo, k] + kk[lo, k] * phi
-            S = (lev.eta_c[lo, k] + ee[lo, k] * phi) / chi
+            S = source_function(chi, lev.chi_c[lo, k], lev.eta_c[lo, k], kk[lo, k], ee[lo, k], phi)
             return chi, S, None
 
         def boundary(k):

@@ -51,9 +51,35 @@ template <> struct VoigtTraits<double> {
 };
 
 __device__ inline float dev_rcp(float x) { return __builtin_amdgcn_rcpf(x); }   // v_rcp_f32, 1 ulp
+
 __device__ inline double dev_rcp(double x) { return 1.0 / x; }
 __device__ inline float dev_exp_neg(float x) { return __expf(-x); }
 __device__ inline double dev_exp_neg(double x) { return exp(-x); }
+
+// An opacity counts as zero (a transparent point) below 1e-30 cm^-1 in FP32 and
+// 1e-150 cm^-1 in FP64: any segment through such a point has optical depth below
+// ~1e-20, while the reciprocal of the opacity must stay finite (v_rcp_f32 flushes
+// denormal inputs, and the FP64 reciprocal expansion overflows long before the
+// smallest normal double).
+__device__ inline bool opaque(float chi) { return chi >= 1e-30f; }
+__device__ inline bool opaque(double chi) { return chi >= 1e-150; }
+
+// Source function S = (eta_c + e phi) / (chi_c + k phi) and rchi = 1/chi.  Where the
+// opacity is negligible (the profile underflowed far out in a wing), S is the limit
+// of that ratio as phi -> 0: eta_c/chi_c with a background, else
+// the line source function e/k, else 0; rchi is 0 there (the point's own weight
+// w phi~ vanishes with phi, but a segment from an opaque upwind point still sees S).
+template <typename R>
+__device__ inline R source_fn(R chi, R chic, R etac, R kpl, R el, R phi, R& rchi) {
+    if (opaque(chi)) {
+        rchi = dev_rcp(chi);
+        return fma(el, phi, etac) * rchi;
+    }
+    rchi = R(0);
+    if (opaque(chic)) return etac * dev_rcp(chic);
+    if (opaque(kpl)) return el * dev_rcp(kpl);
+    return R(0);
+}
 
 // H(a, u) for a >= 0 (Weideman rational series), complex Horner with explicit FMAs.
 template <typename R>

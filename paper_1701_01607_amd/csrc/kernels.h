@@ -268,7 +268,8 @@ __global__ __launch_bounds__(kNHemi* P* CH) void sweep_step_kernel(SweepArgs<R> 
                 const R H = profile_H<R>(adamp, u, gauss);
                 const R phi = H * pn;
                 const R chi = chic + kpl * phi;
-                const R S = (etac + el * phi) * dev_rcp(chi);
+                R rchi_b;
+                const R S = source_fn(chi, chic, etac, kpl, el, phi, rchi_b);
                 const R I = (h == 0) ? Bb : (top ? top[size_t(m) * nxy] : R(0));
                 Cell<R> cell;
                 cell.I = I; cell.S = S; cell.C = chi;
@@ -315,8 +316,8 @@ __global__ __launch_bounds__(kNHemi* P* CH) void sweep_step_kernel(SweepArgs<R> 
                 const R H = profile_H<R>(adamp, u, gauss);
                 const R phi = H * pn;
                 const R chi = fma(kpl, phi, chic);
-                const R rchi = dev_rcp(chi);
-                const R S = fma(el, phi, etac) * rchi;
+                R rchi;
+                const R S = source_fn(chi, chic, etac, kpl, el, phi, rchi);
                 const R Iu = fma(w00, c00.I, fma(w01, c01.I, fma(w10, c10.I, w11 * c11.I)));
                 const R Su = fma(w00, c00.S, fma(w01, c01.S, fma(w10, c10.S, w11 * c11.S)));
                 const R Cu = fma(w00, c00.C, fma(w01, c01.C, fma(w10, c10.C, w11 * c11.C)));
@@ -399,7 +400,8 @@ __global__ void emergent_step_kernel(EmergentArgs<R> a, int k) {
     const double H = profile_H<double>(adamp, u, ln.gauss != 0);
     const double phi = H * pn;
     const double chi = chic + kpl * phi;
-    const double S = (etac + el * phi) / chi;
+    double rchi_e;
+    const double S = source_fn(chi, chic, etac, kpl, el, phi, rchi_e);
     const size_t ps = size_t(a.nf) * a.nxy;
     double* cur = a.state + size_t(k & 1) * 3 * ps;
     double I;
@@ -757,6 +759,12 @@ __global__ void correct_kernel(double* n, const double* na, const double* nb, in
         __syncthreads();
     }
     if (threadIdx.x == 0 && cnt[0] > 0) atomicAdd(repairs, (unsigned long long)cnt[0]);
+}
+
+// dst = src (FP64), a kernel so that graph-captured work holds no copy nodes.
+__global__ void copy_kernel(const double* src, double* dst, size_t n) {
+    for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+        dst[i] = src[i];
 }
 
 // Right-hand side f = [n_tot, 0, ..., 0].

@@ -8,7 +8,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -51,13 +55,23 @@ inline unsigned blocks_for(size_t n, unsigned bs) { return unsigned((n + bs - 1)
 // ===================================================================== context
 struct nlte_ctx {
     std::map<std::string, int> tile_cache;   // autotuned sweep tile per level shape
+    std::mutex tune_mu;
     int device = 0;
     hipStream_t stream = nullptr;
-    size_t budget = 0, used = 0;
+    size_t budget = 0;
+    std::atomic<size_t> used{0};             // bytes allocated by this context
+    std::atomic<size_t> reserved{0};         // bytes reserved for admitted served jobs
     std::string err;
-    std::recursive_mutex mu;
+    std::recursive_mutex mu;                 // API calls and the job map
     std::map<int64_t, struct JobBase*> jobs;
     int64_t next_job = 1;
+    // serving: FIFO admission by HBM footprint, one worker thread per running job
+    std::mutex qmu;
+    std::condition_variable qcv;
+    std::deque<struct JobBase*> queue;       // lock order: mu before qmu; workers take qmu only
+    std::vector<std::thread> workers;
+    int max_running = 0, running = 0;
+    bool stopping = false;
 };
 
 namespace {
@@ -71,13 +85,14 @@ struct DevBuf {
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
-    void alloc(nlte_ctx* c, size_t b) {
+    // `reserved`: the bytes were already reserved at admission (served jobs)
+    void alloc(nlte_ctx* c, size_t b, bool reserved = false) {
         release();
         ctx = c;
         if (b == 0) return;
-        if (c->used + b > c->budget)
+        if (!reserved && c->used + c->reserved + b > c->budget)
             throw Error(NLTE_E_OOM, "HBM budget exceeded: need " + std::to_string(b) + " more bytes, " +
-                                        std::to_string(c->budget - c->used) + " left");
+                                        std::to_string(c->budget - c->used - c->reserved) + " left");
         hipError_t e = hipMalloc(&p, b);
         if (e != hipSuccess) {
             p = nullptr;
@@ -173,6 +188,17 @@ struct nlte_atmos {
 // ===================================================================== job
 struct JobBase {
     virtual ~JobBase() = default;
+    // serving state (jobs created by nlte_submit)
+    bool served = false;
+    std::atomic<int> state{2};       // 0 queued, 1 running, 2 done, 3 failed
+    nlte_status final_status = NLTE_OK;
+    std::string error;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    size_t footprint = 0;
+    const nlte_atmos* src_atmos = nullptr;
+    const nlte_atom* src_atom = nullptr;
+    hipStream_t own_stream = nullptr;
+    virtual void build_served() = 0;
     nlte_params params{};
     int N = 0, nline = 0, nf = 0, nlev = 1, prec = NLTE_FP64;
     std::vector<double> history;
@@ -225,10 +251,24 @@ struct Job : JobBase {
     Job(nlte_ctx* c) : ctx(c) {}
     ~Job() override {
         for (auto& e : evs) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (own_stream) {
+            (void)hipStreamSynchronize(own_stream);
+            lev.clear();
+            (void)hipStreamDestroy(own_stream);
+        }
     }
 
+    bool capturing = false;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<long long> graph_fs;
+    double graph_cost = 0, graph_updates = 0;
+    long long graph_launches = 0;
+
     void ev_begin(int kind) {
-        if (!params.timing) return;
+        if (!params.timing || capturing) return;
         Ev e;
         e.kind = kind;
         HIPCHK(hipEventCreate(&e.a));
@@ -237,7 +277,7 @@ struct Job : JobBase {
         evs.push_back(e);
     }
     void ev_end() {
-        if (!params.timing) return;
+        if (!params.timing || capturing) return;
         HIPCHK(hipEventRecord(evs.back().b, st()));
     }
     void ev_resolve() {
@@ -253,7 +293,12 @@ struct Job : JobBase {
         evs.clear();
     }
 
-    hipStream_t st() const { return ctx->stream; }
+    hipStream_t st() const { return own_stream ? own_stream : ctx->stream; }
+
+    // all device buffers of a job come through here
+    void dalloc(DevBuf& b, size_t bytes) { b.alloc(ctx, bytes, served); }
+
+    void build_served() override { build(src_atmos, src_atom, &params); }
 
     // --------------------------------------------------------------- setup
     void build(const nlte_atmos* atm, const nlte_atom* atom, const nlte_params* p) {
@@ -274,18 +319,18 @@ struct Job : JobBase {
         REQUIRE(nlev == 1 || atm->nz >= 3, "multigrid needs nz >= 3");
         if (p->method != NLTE_MALI) REQUIRE(nlev >= 1, "nlev >= 1");
 
-        atom_d.alloc(ctx, sizeof(AtomInfo));
+        dalloc(atom_d, sizeof(AtomInfo));
         HIPCHK(hipMemcpyAsync(atom_d.p, &info, sizeof(AtomInfo), hipMemcpyHostToDevice, st()));
         std::vector<R> qh(atom->q.begin(), atom->q.end()), wh(atom->wnu.begin(), atom->wnu.end());
-        qf.alloc(ctx, sizeof(R) * nf);
-        wf.alloc(ctx, sizeof(R) * nf);
-        line_of_d.alloc(ctx, sizeof(int) * nf);
+        dalloc(qf, sizeof(R) * nf);
+        dalloc(wf, sizeof(R) * nf);
+        dalloc(line_of_d, sizeof(int) * nf);
         HIPCHK(hipMemcpyAsync(qf.p, qh.data(), sizeof(R) * nf, hipMemcpyHostToDevice, st()));
         HIPCHK(hipMemcpyAsync(wf.p, wh.data(), sizeof(R) * nf, hipMemcpyHostToDevice, st()));
         HIPCHK(hipMemcpyAsync(line_of_d.p, atom->line_of.data(), sizeof(int) * nf, hipMemcpyHostToDevice, st()));
-        scalar.alloc(ctx, sizeof(double) * 4);
-        repairs.alloc(ctx, sizeof(unsigned long long));
-        flag.alloc(ctx, sizeof(int));
+        dalloc(scalar, sizeof(double) * 4);
+        dalloc(repairs, sizeof(unsigned long long));
+        dalloc(flag, sizeof(int));
         HIPCHK(hipMemsetAsync(repairs.p, 0, sizeof(unsigned long long), st()));
 
         const int nprim = 7 + atm->nline_chic;
@@ -303,9 +348,9 @@ struct Job : JobBase {
             }
             L.nxy = size_t(L.nx) * L.ny;
             L.nvox = L.nxy * L.nz;
-            L.dz.alloc(ctx, sizeof(double) * L.nz);
+            dalloc(L.dz, sizeof(double) * L.nz);
             HIPCHK(hipMemcpyAsync(L.dz.p, L.z.data(), sizeof(double) * L.nz, hipMemcpyHostToDevice, st()));
-            L.prim.alloc(ctx, sizeof(double) * nprim * L.nvox);
+            dalloc(L.prim, sizeof(double) * nprim * L.nvox);
             if (k == nlev - 1) {
                 HIPCHK(hipMemcpyAsync(L.prim.p, atm->prim.p, sizeof(double) * nprim * L.nvox,
                                       hipMemcpyDeviceToDevice, st()));
@@ -315,18 +360,18 @@ struct Job : JobBase {
                     F.prim.as<double>(), L.prim.as<double>(), nprim, F.nx, F.ny, F.nz);
                 HIPCHK(hipGetLastError());
             }
-            L.sc.alloc(ctx, sizeof(R) * SC_NQ * nline * L.nvox);
-            L.sv.alloc(ctx, sizeof(R) * SV_NQ * L.nvox);
-            L.nstar.alloc(ctx, sizeof(double) * N * L.nvox);
-            L.pfix.alloc(ctx, sizeof(double) * N * N * L.nvox);
-            L.ntot.alloc(ctx, sizeof(double) * L.nvox);
-            L.n.alloc(ctx, sizeof(double) * N * L.nvox);
-            L.f.alloc(ctx, sizeof(double) * N * L.nvox);
-            L.nb.alloc(ctx, sizeof(double) * N * L.nvox);
-            L.tmp.alloc(ctx, sizeof(double) * N * L.nvox);
-            L.acc.alloc(ctx, sizeof(R) * 4 * nline * L.nvox);
-            L.lc.alloc(ctx, sizeof(R) * 2 * nline * L.nvox);
-            L.partial.alloc(ctx, sizeof(double) * std::max<size_t>(blocks_for(L.nvox, 256), 1024));
+            dalloc(L.sc, sizeof(R) * SC_NQ * nline * L.nvox);
+            dalloc(L.sv, sizeof(R) * SV_NQ * L.nvox);
+            dalloc(L.nstar, sizeof(double) * N * L.nvox);
+            dalloc(L.pfix, sizeof(double) * N * N * L.nvox);
+            dalloc(L.ntot, sizeof(double) * L.nvox);
+            dalloc(L.n, sizeof(double) * N * L.nvox);
+            dalloc(L.f, sizeof(double) * N * L.nvox);
+            dalloc(L.nb, sizeof(double) * N * L.nvox);
+            dalloc(L.tmp, sizeof(double) * N * L.nvox);
+            dalloc(L.acc, sizeof(R) * 4 * nline * L.nvox);
+            dalloc(L.lc, sizeof(R) * 2 * nline * L.nvox);
+            dalloc(L.partial, sizeof(double) * std::max<size_t>(blocks_for(L.nvox, 256), 1024));
             SetupArgs<R> sa;
             sa.atom = atom_d.as<AtomInfo>();
             sa.prim = L.prim.as<double>();
@@ -349,17 +394,17 @@ struct Job : JobBase {
         // Frequency passes: each pass sweeps Q frequencies of every line.  One pass is the
         // default; the plane state (2 x 24 x nline x Q cells per plane point) is split into
         // more passes only when a single pass would take more than a quarter of the
-        // remaining HBM budget (NLTE3D_SWEEP_STATE_MB overrides the state size cap).
+        // context's HBM budget (NLTE3D_SWEEP_STATE_MB overrides the state size cap).
         maxfreq = 0;
         for (int l = 0; l < nline; ++l) maxfreq = std::max(maxfreq, info.line[l].nfreq);
         const char* envb = std::getenv("NLTE3D_SWEEP_STATE_MB");
-        const double cap_bytes = envb ? std::atof(envb) * 1048576.0 : 0.25 * double(ctx->budget - ctx->used);
+        const double cap_bytes = envb ? std::atof(envb) * 1048576.0 : 0.25 * double(ctx->budget);
         const double per_q = double(sizeof(Cell<R>)) * 2 * kNDir * nline * Fz.nxy;
         Qpass = std::max(1, std::min(maxfreq, int(cap_bytes / per_q)));
-        state.alloc(ctx, sizeof(Cell<R>) * 2 * kNDir * size_t(nline) * Qpass * Fz.nxy);
-        nprev.alloc(ctx, sizeof(double) * N * Fz.nvox);
+        dalloc(state, sizeof(Cell<R>) * 2 * kNDir * size_t(nline) * Qpass * Fz.nxy);
+        dalloc(nprev, sizeof(double) * N * Fz.nvox);
         if (p->top_I) {
-            topI.alloc(ctx, sizeof(R) * size_t(nf) * Fz.nxy);
+            dalloc(topI, sizeof(R) * size_t(nf) * Fz.nxy);
             std::vector<R> th(size_t(nf) * Fz.nxy);
             for (size_t i = 0; i < th.size(); ++i) th[i] = R(p->top_I[i]);
             HIPCHK(hipMemcpyAsync(topI.p, th.data(), sizeof(R) * th.size(), hipMemcpyHostToDevice, st()));
@@ -414,8 +459,11 @@ struct Job : JobBase {
     int autotune_tile(int k, SweepArgs<R>& a) {
         Level& L = *lev[k];
         const std::string key = tile_key(L);
-        auto it = ctx->tile_cache.find(key);
-        if (it != ctx->tile_cache.end()) return it->second;
+        {
+            std::lock_guard<std::mutex> lk(ctx->tune_mu);
+            auto it = ctx->tile_cache.find(key);
+            if (it != ctx->tile_cache.end()) return it->second;
+        }
         const int cand[4] = {64, 32, 16, 8};
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
@@ -437,6 +485,9 @@ struct Job : JobBase {
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        std::lock_guard<std::mutex> lk(ctx->tune_mu);
+        auto it = ctx->tile_cache.find(key);
+        if (it != ctx->tile_cache.end()) return it->second;   // another job tuned it first
         ctx->tile_cache[key] = best;
         return best;
     }
@@ -582,7 +633,7 @@ struct Job : JobBase {
         restrict_fields(k, N, L.tmp.as<double>(), C.tmp.as<double>());
         formal_solution(k - 1);                             // W*(R n), shared with the first coarse iteration
         apply_W(k - 1, C.tmp.as<double>(), C.f.as<double>(), 1.0);  // f = R r + W(R n)  (Eq. 10)
-        HIPCHK(hipMemcpyAsync(C.nb.p, C.n.p, sizeof(double) * N * C.nvox, hipMemcpyDeviceToDevice, st()));
+        dcopy(C.n.as<double>(), C.nb.as<double>(), size_t(N) * C.nvox);
         if (k - 1 == 0) mali(0, params.nu3);
         else vcycle(k - 1, false);
         correct_kernel<<<blocks_for(L.nvox * N, 256), 256, 0, st()>>>(
@@ -593,14 +644,71 @@ struct Job : JobBase {
         mali(k, params.nu2);
     }
 
-    double cycle_change(int k) {
+    void cycle_change_enqueue(int k) {
         Level& L = *lev[k];
         const size_t n = size_t(N) * L.nvox;
         const unsigned nb = std::min<unsigned>(blocks_for(n, 256), 1024);
         rel_change_kernel<<<nb, 256, 0, st()>>>(L.n.as<double>(), nprev.as<double>(), n, L.partial.as<double>());
         reduce_max_kernel<<<1, 256, 0, st()>>>(L.partial.as<double>(), int(nb), scalar.as<double>());
         HIPCHK(hipGetLastError());
+    }
+
+    double cycle_change(int k) {
+        cycle_change_enqueue(k);
         return read_scalar();
+    }
+
+    void dcopy(const double* src, double* dst, size_t n) {
+        copy_kernel<<<std::min<unsigned>(blocks_for(n, 256), 2048), 256, 0, st()>>>(src, dst, n);
+        HIPCHK(hipGetLastError());
+    }
+
+    // Capture `work` once into a HIP graph on the job's private stream, then launch the
+    // graph (the captured work must be the same every time it is called).
+    template <typename F>
+    void replay(F&& work) {
+        if (!own_stream) {
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            HIPCHK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+        }
+        if (!gexec) {
+            std::vector<long long> fs0(lev.size());
+            for (size_t k = 0; k < lev.size(); ++k) fs0[k] = lev[k]->fs_count;
+            const double c0 = cost_units, u0 = updates;
+            const long long l0 = sweep_launches;
+            capturing = true;
+            HIPCHK(hipStreamBeginCapture(own_stream, hipStreamCaptureModeThreadLocal));
+            try {
+                work();
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(own_stream, &g);
+                if (g) (void)hipGraphDestroy(g);
+                capturing = false;
+                throw;
+            }
+            HIPCHK(hipStreamEndCapture(own_stream, &graph));
+            capturing = false;
+            HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+            // the capture ran the host side once; record its bookkeeping as per-launch deltas
+            graph_fs.assign(lev.size(), 0);
+            for (size_t k = 0; k < lev.size(); ++k) {
+                graph_fs[k] = lev[k]->fs_count - fs0[k];
+                lev[k]->fs_count = fs0[k];
+            }
+            graph_cost = cost_units - c0;
+            graph_updates = updates - u0;
+            graph_launches = sweep_launches - l0;
+            cost_units = c0;
+            updates = u0;
+            sweep_launches = l0;
+        }
+        HIPCHK(hipGraphLaunch(gexec, own_stream));
+        // bookkeeping the captured work did on the host (formal-solution counts) repeats
+        for (size_t k = 0; k < lev.size(); ++k) lev[k]->fs_count += graph_fs[k];
+        cost_units += graph_cost;
+        updates += graph_updates;
+        sweep_launches += graph_launches;
     }
 
     bool stop(double& rho, double& E) {
@@ -633,7 +741,8 @@ struct Job : JobBase {
         const int maxit = params.max_iter > 0 ? params.max_iter : 1000;
         if (params.method == NLTE_MALI || nlev == 1 && params.method != NLTE_FAS && params.method != NLTE_FMG) {
             for (int it = 0; it < maxit; ++it) {
-                mali(top, 1);
+                if (params.graph && it > 0) replay([&]() { mali(top, 1); });
+                else mali(top, 1);
                 history.push_back(read_scalar());
                 ++iters;
                 if (!std::isfinite(history.back())) throw Error(NLTE_E_DIVERGED, "non-finite MALI correction");
@@ -651,10 +760,19 @@ struct Job : JobBase {
                 first = false;
             }
             for (int c = 0; c < maxit; ++c) {
-                HIPCHK(hipMemcpyAsync(nprev.p, F.n.p, sizeof(double) * N * F.nvox, hipMemcpyDeviceToDevice, st()));
-                vcycle(top, first);
+                if (params.graph && !first) {
+                    replay([&]() {
+                        dcopy(F.n.as<double>(), nprev.as<double>(), size_t(N) * F.nvox);
+                        vcycle(top, false);
+                        cycle_change_enqueue(top);
+                    });
+                    history.push_back(read_scalar());
+                } else {
+                    dcopy(F.n.as<double>(), nprev.as<double>(), size_t(N) * F.nvox);
+                    vcycle(top, first);
+                    history.push_back(cycle_change(top));
+                }
                 first = false;
-                history.push_back(cycle_change(top));
                 ++cycles;
                 if (!std::isfinite(history.back())) {
                     if (params.fallback_mali) {
@@ -763,7 +881,7 @@ struct Job : JobBase {
         DevBuf tmpS;
         double* target = dst;
         if (mem != NLTE_MEM_DEVICE) {
-            tmpS.alloc(ctx, sizeof(double) * nline * F.nvox);
+            dalloc(tmpS, sizeof(double) * nline * F.nvox);
             target = tmpS.as<double>();
         }
         source_function_kernel<<<blocks_for(F.nvox, 256), 256, 0, st()>>>(atom_d.as<AtomInfo>(), F.n.as<double>(),
@@ -779,11 +897,11 @@ struct Job : JobBase {
         line_coef_kernel<R><<<blocks_for(F.nvox, 256), 256, 0, st()>>>(atom_d.as<AtomInfo>(), F.n.as<double>(),
                                                                       F.lc.as<R>(), F.nvox);
         HIPCHK(hipGetLastError());
-        if (!estate.p) estate.alloc(ctx, sizeof(double) * 2 * 3 * size_t(nf) * F.nxy);
+        if (!estate.p) dalloc(estate, sizeof(double) * 2 * 3 * size_t(nf) * F.nxy);
         DevBuf o;
         float* target = dst;
         if (mem != NLTE_MEM_DEVICE) {
-            o.alloc(ctx, sizeof(float) * size_t(ndir) * nf * F.nxy);
+            dalloc(o, sizeof(float) * size_t(ndir) * nf * F.nxy);
             target = o.as<float>();
         }
         for (int d = 0; d < ndir; ++d) {
@@ -823,6 +941,104 @@ struct Job : JobBase {
     }
 };
 
+
+// Device bytes a job will allocate (same formulas as Job::build; the emergent-intensity
+// state is included so that an admitted job never exceeds its reservation).
+size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom* atom, const nlte_params* p) {
+    const size_t R = p->precision == NLTE_FP64 ? 8 : 4;
+    const int nline = atom->info.nline, N = atom->info.N, nf = atom->nf;
+    const int nlev = std::max(1, p->method == NLTE_MALI ? 1 : p->nlev);
+    const int nprim = 7 + atm->nline_chic;
+    size_t bytes = sizeof(AtomInfo) + (2 * R + 4) * size_t(nf) + 64;
+    int nx = atm->nx, ny = atm->ny, nz = atm->nz;
+    size_t fine_nxy = size_t(nx) * ny, fine_nvox = fine_nxy * nz;
+    for (int k = nlev - 1; k >= 0; --k) {
+        const size_t nvox = size_t(nx) * ny * nz;
+        bytes += 8 * size_t(nz) + 8 * size_t(nprim) * nvox + R * (6 * nline + 4) * nvox;
+        bytes += 8 * (size_t(N) * 6 + size_t(N) * N + 1) * nvox + R * 6 * nline * nvox;
+        bytes += 8 * std::max<size_t>((nvox + 255) / 256, 1024);
+        nx /= 2; ny /= 2; nz = (nz - 1) / 2 + 1;
+    }
+    int maxfreq = 0;
+    for (int l = 0; l < nline; ++l) maxfreq = std::max(maxfreq, atom->info.line[l].nfreq);
+    const char* envb = std::getenv("NLTE3D_SWEEP_STATE_MB");
+    const double cap = envb ? std::atof(envb) * 1048576.0 : 0.25 * double(ctx->budget);
+    const double per_q = double(3 * R) * 2 * kNDir * nline * fine_nxy;
+    const int Q = std::max(1, std::min(maxfreq, int(cap / per_q)));
+    bytes += size_t(3 * R) * 2 * kNDir * size_t(nline) * Q * fine_nxy;
+    bytes += 8 * size_t(N) * fine_nvox;
+    if (p->top_I) bytes += R * size_t(nf) * fine_nxy;
+    bytes += 8 * 6 * size_t(nf) * fine_nxy;             // emergent-intensity state
+    bytes += 4 * size_t(nf) * fine_nxy;                  // one direction of host-bound output
+    bytes += 8 * size_t(nline) * fine_nvox;              // source-function staging
+    return bytes;
+}
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Serving worker: admits the queue head when its footprint fits the unreserved budget
+// (submission already checked that it fits an empty context),
+// then builds and runs it on its own stream; several workers run jobs concurrently, so
+// their kernels overlap on the device and a queued job starts as soon as memory frees.
+void serve_worker(nlte_ctx* ctx) {
+    (void)hipSetDevice(ctx->device);
+    for (;;) {
+        JobBase* j = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(ctx->qmu);
+            for (;;) {
+                if (ctx->stopping) return;
+                if (!ctx->queue.empty()) {
+                    JobBase* head = ctx->queue.front();
+                    // memory of finished jobs counts until they are released
+                    const bool fits = ctx->used + ctx->reserved + head->footprint <= ctx->budget;
+                    if (fits) {
+                        ctx->queue.pop_front();
+                        ctx->reserved += head->footprint;
+                        ctx->running++;
+                        j = head;
+                        break;
+                    }
+                }
+                ctx->qcv.wait(lk);
+            }
+        }
+        j->t_admit = now_s();
+        j->state = 1;
+        bool reservation_held = true;
+        try {
+            HIPCHK(hipStreamCreateWithFlags(&j->own_stream, hipStreamNonBlocking));
+            j->build_served();
+            {   // the job's buffers now count in `used`; drop the reservation
+                std::lock_guard<std::mutex> lk(ctx->qmu);
+                ctx->reserved -= j->footprint;
+                reservation_held = false;
+            }
+            nlte_result r{};
+            j->run(&r);
+            j->final_status = r.status;
+            j->state = 2;
+        } catch (const Error& e) {
+            j->final_status = e.code;
+            j->error = e.what();
+            j->state = 3;
+        } catch (const std::exception& e) {
+            j->final_status = NLTE_E_INVALID;
+            j->error = e.what();
+            j->state = 3;
+        }
+        j->t_done = now_s();
+        {
+            std::lock_guard<std::mutex> lk(ctx->qmu);
+            ctx->running--;
+            if (reservation_held) ctx->reserved -= j->footprint;
+        }
+        ctx->qcv.notify_all();
+    }
+}
+
 // ------------------------------------------------------------------ API helpers
 template <typename F>
 nlte_status guarded(nlte_ctx* ctx, F&& fn) {
@@ -845,10 +1061,13 @@ nlte_status guarded(nlte_ctx* ctx, F&& fn) {
     }
 }
 
-JobBase* find_job(nlte_ctx* ctx, nlte_job job) {
+JobBase* find_job(nlte_ctx* ctx, nlte_job job, bool need_done = true) {
     auto it = ctx->jobs.find(job);
     if (it == ctx->jobs.end()) throw Error(NLTE_E_INVALID, "unknown job handle");
-    return it->second;
+    JobBase* j = it->second;
+    if (need_done && j->served && j->state < 2) throw Error(NLTE_E_INVALID, "job not finished");
+    if (need_done && j->served && j->state == 3) throw Error(NLTE_E_INVALID, "job failed: " + j->error);
+    return j;
 }
 
 bool finite_host(const double* p, size_t n) {
@@ -889,6 +1108,14 @@ nlte_status nlte_ctx_create(int device, void* hip_stream, size_t hbm_budget, nlt
 
 void nlte_ctx_destroy(nlte_ctx* ctx) {
     if (!ctx) return;
+    {
+        std::lock_guard<std::mutex> lk(ctx->qmu);
+        ctx->stopping = true;
+        ctx->queue.clear();
+    }
+    ctx->qcv.notify_all();
+    for (auto& t : ctx->workers) t.join();
+    ctx->workers.clear();
     {
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         (void)hipSetDevice(ctx->device);
@@ -1083,10 +1310,25 @@ nlte_status nlte_solve(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom* 
 
 nlte_status nlte_release(nlte_ctx* ctx, nlte_job job) {
     return guarded(ctx, [&]() -> nlte_status {
-        JobBase* j = find_job(ctx, job);
-        HIPCHK(hipStreamSynchronize(ctx->stream));
+        JobBase* j = find_job(ctx, job, false);
+        if (j->served) {
+            {
+                std::lock_guard<std::mutex> lk(ctx->qmu);
+                auto it = std::find(ctx->queue.begin(), ctx->queue.end(), j);
+                if (it != ctx->queue.end()) ctx->queue.erase(it);
+                else
+                    while (j->state == 1) {   // running: let it finish
+                        ctx->qmu.unlock();
+                        std::this_thread::sleep_for(std::chrono::milliseconds(1));
+                        ctx->qmu.lock();
+                    }
+            }
+        } else {
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+        }
         delete j;
         ctx->jobs.erase(job);
+        ctx->qcv.notify_all();               // freed memory may admit a queued job
         return NLTE_OK;
     });
 }
@@ -1179,6 +1421,114 @@ nlte_status nlte_prolong(nlte_ctx* ctx, nlte_job job, int level, int nq, const d
     return guarded(ctx, [&]() -> nlte_status {
         REQUIRE(nq >= 1 && src && dst, "bad prolongation arguments");
         find_job(ctx, job)->prolong_hook(level, nq, src, dst);
+        return NLTE_OK;
+    });
+}
+
+}  // extern "C"
+
+extern "C" {
+
+nlte_status nlte_serve_config(nlte_ctx* ctx, int max_running) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(max_running >= 1 && max_running <= 16, "max_running must be 1..16");
+        std::lock_guard<std::mutex> lk(ctx->qmu);
+        while (int(ctx->workers.size()) < max_running) ctx->workers.emplace_back(serve_worker, ctx);
+        ctx->max_running = int(ctx->workers.size());
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_estimate_footprint(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom* atom,
+                                    const nlte_params* params, size_t* bytes) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(atmos && atom && params && bytes, "null argument");
+        *bytes = job_footprint(ctx, atmos, atom, params);
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_submit(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom* atom, const nlte_params* params,
+                        nlte_job* job) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(atmos && atom && params && job, "null argument");
+        REQUIRE(params->method >= NLTE_MALI && params->method <= NLTE_FMG, "unknown method");
+        REQUIRE(params->precision == NLTE_FP64 || params->precision == NLTE_MIXED, "unknown precision");
+        REQUIRE(params->init != NLTE_INIT_USER && params->top_I == nullptr,
+                "served jobs take no host arrays in params");
+        const int nlev = std::max(1, params->method == NLTE_MALI ? 1 : params->nlev);
+        const int step = 1 << (nlev - 1);
+        REQUIRE(atmos->nx % step == 0 && atmos->ny % step == 0 && (atmos->nz - 1) % step == 0,
+                "grid does not admit the requested number of levels");
+        if (ctx->workers.empty()) {
+            std::lock_guard<std::mutex> lk(ctx->qmu);
+            ctx->workers.emplace_back(serve_worker, ctx);
+            ctx->max_running = 1;
+        }
+        std::unique_ptr<JobBase> j;
+        if (params->precision == NLTE_FP64) j.reset(new Job<double>(ctx));
+        else j.reset(new Job<float>(ctx));
+        j->prec = params->precision;
+        j->params = *params;
+        j->served = true;
+        j->src_atmos = atmos;
+        j->src_atom = atom;
+        j->footprint = job_footprint(ctx, atmos, atom, params);
+        REQUIRE(j->footprint <= ctx->budget, "job footprint exceeds the context's HBM budget");
+        j->state = 0;
+        j->t_submit = now_s();
+        const int64_t id = ctx->next_job++;
+        JobBase* raw = j.release();
+        ctx->jobs[id] = raw;
+        {
+            std::lock_guard<std::mutex> lk(ctx->qmu);
+            ctx->queue.push_back(raw);
+        }
+        ctx->qcv.notify_all();
+        *job = id;
+        return NLTE_W_QUEUED;
+    });
+}
+
+nlte_status nlte_poll(nlte_ctx* ctx, nlte_job job, int* state) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(state, "null state");
+        *state = find_job(ctx, job, false)->state;
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_wait(nlte_ctx* ctx, nlte_job job, int timeout_ms) {
+    if (!ctx) return NLTE_E_INVALID;
+    JobBase* j = nullptr;
+    {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        auto it = ctx->jobs.find(job);
+        if (it == ctx->jobs.end()) return NLTE_E_INVALID;
+        j = it->second;
+    }
+    const double t0 = now_s();
+    std::unique_lock<std::mutex> lk(ctx->qmu);
+    while (j->state < 2) {
+        if (timeout_ms >= 0 && (now_s() - t0) * 1e3 >= timeout_ms) return NLTE_W_QUEUED;
+        ctx->qcv.wait_for(lk, std::chrono::milliseconds(2));
+    }
+    return j->state == 2 ? j->final_status : j->final_status;
+}
+
+nlte_status nlte_job_info(nlte_ctx* ctx, nlte_job job, nlte_job_info_t* info) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(info, "null info");
+        JobBase* j = find_job(ctx, job, false);
+        std::memset(info, 0, sizeof(*info));
+        info->state = j->state;
+        info->status = j->final_status;
+        info->t_submit = j->t_submit;
+        info->t_admit = j->t_admit;
+        info->t_done = j->t_done;
+        info->footprint = j->footprint;
+        if (j->state >= 2) info->result = j->res;
+        std::snprintf(info->error, sizeof(info->error), "%s", j->error.c_str());
         return NLTE_OK;
     });
 }

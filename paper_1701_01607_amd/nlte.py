@@ -31,7 +31,10 @@ SYMBOLS = (
     "nlte_emergent_intensity", "nlte_history",
     "nlte_formal_solution", "nlte_mali", "nlte_residual", "nlte_vcycle",
     "nlte_restrict", "nlte_prolong",
+    "nlte_serve_config", "nlte_estimate_footprint", "nlte_submit", "nlte_poll", "nlte_wait",
+    "nlte_job_info",
 )
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 
 class NlteError(RuntimeError):
@@ -81,7 +84,8 @@ class Params(ct.Structure):
                 ("init", ct.c_int), ("init_pops", ct.POINTER(ct.c_double)),
                 ("tol_C", ct.c_double), ("E_target", ct.c_double), ("max_iter", ct.c_int),
                 ("repair_frac", ct.c_double), ("fallback_mali", ct.c_int),
-                ("top_I", ct.POINTER(ct.c_double)), ("tile_points", ct.c_int), ("timing", ct.c_int)]
+                ("top_I", ct.POINTER(ct.c_double)), ("tile_points", ct.c_int), ("timing", ct.c_int),
+                ("graph", ct.c_int)]
 
 
 class Result(ct.Structure):
@@ -96,6 +100,11 @@ class Result(ct.Structure):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "formal_solutions"}
         d["formal_solutions"] = list(self.formal_solutions)
         return d
+
+
+class JobInfo(ct.Structure):
+    _fields_ = [("state", ct.c_int), ("status", ct.c_int), ("t_submit", ct.c_double), ("t_admit", ct.c_double),
+                ("t_done", ct.c_double), ("footprint", ct.c_size_t), ("result", Result), ("error", ct.c_char * 256)]
 
 
 _lib = None
@@ -139,6 +148,12 @@ def load(path=None):
     lib.nlte_vcycle.argtypes = [P, I64, ct.c_int, ct.c_int]
     lib.nlte_restrict.argtypes = [P, I64, ct.c_int, ct.c_int, P, P]
     lib.nlte_prolong.argtypes = [P, I64, ct.c_int, ct.c_int, P, P]
+    lib.nlte_serve_config.argtypes = [P, ct.c_int]
+    lib.nlte_estimate_footprint.argtypes = [P, P, P, ct.POINTER(Params), ct.POINTER(ct.c_size_t)]
+    lib.nlte_submit.argtypes = [P, P, P, ct.POINTER(Params), ct.POINTER(I64)]
+    lib.nlte_poll.argtypes = [P, I64, ct.POINTER(ct.c_int)]
+    lib.nlte_wait.argtypes = [P, I64, ct.c_int]
+    lib.nlte_job_info.argtypes = [P, I64, ct.POINTER(JobInfo)]
     _lib = lib
     return lib
 
@@ -169,6 +184,7 @@ class SolveParams:
     fallback_mali: int = 0
     tile_points: int = 0
     timing: int = 0
+    graph: int = 0
     init_pops: np.ndarray | None = None
     top_I: np.ndarray | None = None
     _keep: list = field(default_factory=list, repr=False)
@@ -176,7 +192,7 @@ class SolveParams:
     def to_c(self):
         p = Params()
         for k in ("method", "precision", "nlev", "nu_fmg", "nu0", "nu1", "nu2", "nu3", "init",
-                  "max_iter", "fallback_mali", "tile_points", "timing"):
+                  "max_iter", "fallback_mali", "tile_points", "timing", "graph"):
             setattr(p, k, int(getattr(self, k)))
         for k in ("tol_C", "E_target", "repair_frac"):
             setattr(p, k, float(getattr(self, k)))
@@ -256,6 +272,25 @@ class Context:
         self.check(self.lib.nlte_job_create(self.h, atmos_h.h, atom_h.h, ct.byref(p), ct.byref(j)))
         return Job(self, j.value, params)
 
+    # ---- serving
+    def serve_config(self, max_running):
+        self.check(self.lib.nlte_serve_config(self.h, int(max_running)))
+
+    def footprint(self, atmos_h, atom_h, params: SolveParams):
+        b = ct.c_size_t()
+        p = params.to_c()
+        self.check(self.lib.nlte_estimate_footprint(self.h, atmos_h.h, atom_h.h, ct.byref(p), ct.byref(b)))
+        return b.value
+
+    def submit(self, atmos_h, atom_h, params: SolveParams):
+        """Queue a solve (returns at once); the handles must stay alive until it runs."""
+        j = ct.c_int64()
+        p = params.to_c()
+        self.check(self.lib.nlte_submit(self.h, atmos_h.h, atom_h.h, ct.byref(p), ct.byref(j)))
+        job = Job(self, j.value, params)
+        job._inputs = (atmos_h, atom_h)
+        return job
+
 
 class Handle:
     def __init__(self, ctx, h, destroy):
@@ -291,6 +326,19 @@ class Job:
             self.close()
         except Exception:
             pass
+
+    def poll(self):
+        st = ct.c_int()
+        self.ctx.check(self.lib.nlte_poll(self.ctx.h, self.id, ct.byref(st)))
+        return st.value
+
+    def wait(self, timeout_ms=-1):
+        return self.lib.nlte_wait(self.ctx.h, self.id, int(timeout_ms))
+
+    def info(self):
+        inf = JobInfo()
+        self.ctx.check(self.lib.nlte_job_info(self.ctx.h, self.id, ct.byref(inf)))
+        return inf
 
     def run(self):
         r = Result()

@@ -54,12 +54,14 @@ def line_grid(n, q_core, q_max, n_core):
     return np.concatenate([-pos[:0:-1], pos])
 
 
-def two_level_atom(epsilon=1.0e-4):
+def two_level_atom(epsilon=1.0e-4, q_max=5.0 * KM, nfreq=21):
     """Two-level atom with a pure Doppler line and a constant destruction probability.
 
     The lower level has g = 1, the upper g = 3, the line sits at 500 nm
     (20000 cm^-1).  The atomic mass 83.14 amu makes the thermal Doppler width at
-    5000 K equal to 1 km/s.  No damping, no continuum, no background.
+    5000 K equal to 1 km/s.  No damping, no continuum, no background.  The default
+    grid (21 points over +-5 km/s) suits a static atmosphere; moving atmospheres need
+    q_max beyond the largest velocity plus a few Doppler widths.
     """
     return {
         "name": "two-level",
@@ -71,7 +73,8 @@ def two_level_atom(epsilon=1.0e-4):
         ],
         "lines": [
             {"lower": 0, "upper": 1, "A": 1.0e7, "gamma_rad": 0.0, "gamma_vdw": 0.0,
-             "q": doppler_grid_two_level()},
+             "q": doppler_grid_two_level() if (q_max == 5.0 * KM and nfreq == 21)
+             else np.linspace(-q_max, q_max, nfreq)},
         ],
         "continua": [],
         "collisions": [],

@@ -218,3 +218,43 @@ def test_determinism_and_invalid_inputs(nl, ctx):
     with pytest.raises(nl.NlteError) as ei:
         ctx.atmos(bad)
     assert ei.value.code == nl.E_INVALID
+
+
+@pytest.mark.parametrize("method", ["FAS", "MALI"])
+def test_graph_replay_equals_eager(nl, ctx, method):
+    # every replay is checked: the per-cycle (per-iteration) histories and the final
+    # populations must be bitwise identical to eager execution
+    atom, atm = mg_case()
+    m = nl.FAS if method == "FAS" else nl.MALI
+    outs = []
+    for graph in (0, 1):
+        job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
+                      nl.SolveParams(method=m, precision=nl.MIXED, nlev=3 if m == nl.FAS else 1, nu0=3, nu1=2,
+                                     nu2=2, nu3=6, E_target=0.0, max_iter=5, graph=graph, tile_points=16))
+        rc, r = job.run()
+        outs.append((job.history(), job.populations(job.params.nlev - 1 if m == nl.FAS else 0, (6, 17, 8, 8)),
+                     r.fine_fs_equiv, list(r.formal_solutions)))
+        job.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == pytest.approx(outs[1][2]) and outs[0][3] == outs[1][3]
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-3)])
+def test_undamped_line_far_wings_stay_finite(nl, ctx, prec, tol):
+    # Doppler line with velocities up to 10 km/s and v_D ~ 1 km/s: exp(-u^2) and the
+    # opacity underflow (or become denormal) in FP32 far out in the wings; those points
+    # must be treated as transparent
+    atom = synth.two_level_atom(1e-2, q_max=16 * synth.KM, nfreq=49)
+    atm = synth.atmos_stratified(nx=8, ny=8, nz=9, dx=150 * synth.KM, seed=501)
+    atm["chi_c"] = None
+    n_or, st, _ = solve_fas(atom, atm, OParams(nlev=2, nu1=2, nu2=2, nu3=8), cycles=2)
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
+                  nl.SolveParams(method=nl.FAS, precision=prec, nlev=2, nu1=2, nu2=2, nu3=8, E_target=0.0,
+                                 max_iter=2))
+    rc, r = job.run()
+    g = job.populations(1, (2, 9, 8, 8))
+    assert np.all(np.isfinite(g))
+    e = relerr(g, n_or)
+    print(f"prec={prec} two-level stratified 2 cycles err {e:.2e}")
+    assert e < tol

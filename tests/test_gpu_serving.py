@@ -1,0 +1,114 @@
+"""Serving: continuous batching through the C-ABI (nlte_submit / nlte_wait).
+
+Each solve must give the same populations alone and in a mix of concurrent solves of
+different sizes and atoms (bitwise: every kernel is deterministic and every job has its
+own buffers and stream), and a solve that does not fit the HBM budget waits in the
+queue instead of failing.
+"""
+import numpy as np
+import pytest
+
+from paper_1701_01607_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nl():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1701_01607_amd import nlte
+    return nlte
+
+
+def requests(nl):
+    out = []
+    for j, (n, nz, two) in enumerate([(16, 17, False), (8, 9, True), (16, 33, True), (8, 17, False),
+                                      (32, 17, False), (16, 17, True)]):
+        atm = synth.atmos_stratified(nx=n, ny=n, nz=nz, dx=150 * synth.KM, seed=500 + j)
+        if two:
+            atom = synth.two_level_atom(1e-2)
+            atm["chi_c"] = None
+        else:
+            atom = synth.caii_like_atom(9)
+            atm["ntot"] = atm["ntot"] * 0.1
+        p = nl.SolveParams(method=nl.FAS, precision=nl.MIXED, nlev=2, nu1=2, nu2=2, nu3=8, E_target=1e-4,
+                           max_iter=20, tile_points=16)
+        out.append((atom, atm, p))
+    return out
+
+
+def test_each_result_is_the_same_alone_and_in_the_mix(nl):
+    import torch
+    ctx = nl.Context(0, torch.cuda.current_stream().cuda_stream)
+    reqs = requests(nl)
+    alone = []
+    for atom, atm, p in reqs:
+        job = ctx.job(ctx.atmos(atm), ctx.atom(atom), p)
+        rc, r = job.run()
+        N = len(atom["levels"])
+        alone.append(job.populations(1, (N, atm["nz"], atm["ny"], atm["nx"])))
+        job.close()
+    ctx.serve_config(4)
+    for order in (list(range(len(reqs))), list(reversed(range(len(reqs))))):
+        jobs = {}
+        for i in order:
+            atom, atm, p = reqs[i]
+            jobs[i] = ctx.submit(ctx.atmos(atm), ctx.atom(atom), p)
+        for i in order:
+            assert jobs[i].wait() >= 0
+        overlap = 0
+        infos = {i: jobs[i].info() for i in order}
+        for i in order:
+            for k in order:
+                if i < k and infos[i].t_admit < infos[k].t_done and infos[k].t_admit < infos[i].t_done:
+                    overlap += 1
+        for i in order:
+            atom, atm, p = reqs[i]
+            N = len(atom["levels"])
+            got = jobs[i].populations(1, (N, atm["nz"], atm["ny"], atm["nx"]))
+            assert np.array_equal(got, alone[i]), f"request {i} differs in the mix"
+            jobs[i].close()
+        print(f"order {order[:2]}...: {overlap} overlapping pairs")
+        assert overlap > 0
+    ctx.close()
+
+
+def test_over_budget_requests_wait_instead_of_failing(nl):
+    import torch
+    # three solves of equal footprint; the budget holds the atmospheres and 1.5 solves
+    reqs = []
+    for j in range(3):
+        atm = synth.atmos_stratified(nx=16, ny=16, nz=17, dx=150 * synth.KM, seed=700 + j)
+        atm["ntot"] = atm["ntot"] * 0.1
+        reqs.append((synth.caii_like_atom(9), atm,
+                     nl.SolveParams(method=nl.FAS, precision=nl.MIXED, nlev=2, nu1=2, nu2=2, nu3=8, E_target=1e-4,
+                                    max_iter=20, tile_points=16)))
+    probe = nl.Context(0, torch.cuda.current_stream().cuda_stream)
+    fp = probe.footprint(probe.atmos(reqs[0][1]), probe.atom(reqs[0][0]), reqs[0][2])
+    probe.close()
+    atmos_bytes = sum(8 * 12 * a["nx"] * a["ny"] * a["nz"] for _, a, _ in reqs)
+    ctx = nl.Context(0, torch.cuda.current_stream().cuda_stream, hbm_budget=atmos_bytes + fp + fp // 2)
+    ctx.serve_config(3)
+    jobs = [ctx.submit(ctx.atmos(atm), ctx.atom(atom), p) for atom, atm, p in reqs]
+    infos = []
+    for j in jobs:
+        assert j.wait() >= 0
+        infos.append(j.info())
+        j.close()           # frees memory for the next queued job
+    for a, b in zip(infos[:-1], infos[1:]):
+        assert b.t_admit >= a.t_done - 1e-3, "a job was admitted beyond the budget"
+    assert infos[1].t_admit - infos[1].t_submit > 0   # it did wait in the queue
+    ctx.close()
+
+
+def test_submit_rejects_what_can_never_fit(nl):
+    import torch
+    atom, atm, p = requests(nl)[0]
+    ctx = nl.Context(0, torch.cuda.current_stream().cuda_stream, hbm_budget=64 << 20)
+    big = synth.atmos_stratified(nx=64, ny=64, nz=65, seed=3)
+    M, A = ctx.atmos(big), ctx.atom(atom)
+    with pytest.raises(nl.NlteError) as ei:
+        ctx.submit(M, A, p)
+    assert ei.value.code in (nl.E_INVALID, nl.E_OOM)
+    ctx.close()
