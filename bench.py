@@ -21,14 +21,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (published)
-PEAK_HBM_GBS = 8000.0
+PEAK_HBM_GBS = 8000.0           # MI355X HBM3E (published)
 
-# Algorithmic FP32 flops per voxel-direction-frequency update of the sweep (FMA = 2):
-# profile argument 2, Weideman N=16 Voigt 131, opacity/source function 7, three
-# bilinear upwind interpolations 21, optical depth 3, segment coefficients 7,
-# intensity 5, quadrature weight 2, two positive-sum accumulations 10.
-FLOPS_PER_UPDATE_VOIGT = 188
-FLOPS_PER_UPDATE_GAUSS = 188 - 131 + 3
+# Algorithmic HBM bytes per voxel-direction-frequency update of the sweep.  The plane
+# state (I, S, chi per direction, frequency and plane point, 12 B in FP32) lives in HBM
+# between plane steps: each cell is written once and read back once by the next step
+# (its four upwind readers share it through L2).  Per (voxel, line, direction group)
+# the block also reads 11 per-voxel constants and writes 2 partial sums.
+STATE_BYTES_PER_UPDATE = 24.0
+# HBM bytes per sweep launch from FETCH_SIZE + WRITE_SIZE counter runs of
+# `bench.py --kernel-probe`, each scaled by the counter's reading for a plain device
+# copy of known size; keyed by (workload, directions per block).  None until counters
+# are taken for the current kernel.
+MEASURED_BYTES_PER_LAUNCH = {}
+VOXEL_BYTES_PER_GROUP = (11 + 2) * 4.0
+
+# FP32 flops per update (FMA = 2) for the ALU side of the roofline: profile argument
+# 2, opacity/source function 7, three bilinear interpolations 21, optical depth 3,
+# segment coefficients 7, intensity 5, quadrature weight 2, accumulations 10 (57),
+# plus the profile: Weideman N=16 core (|u| < 6) 88, asymptotic wing 46, Gaussian 3.
+FLOPS_PER_UPDATE_BASE = 57
+FLOPS_VOIGT_CORE, FLOPS_VOIGT_WING, FLOPS_GAUSS = 88, 46, 3
 
 WORKLOADS = {
     "caii6_64x64x129": dict(nlev=3, nu0=20, nu1=4, nu2=8, nu3=32, nu_fmg=16, method="FAS"),
@@ -42,13 +55,44 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def flops_per_update(atom, atm, stride=61):
+    """Mean FP32 flops per update on the finest grid: the profile costs the Weideman
+    core where |u| < 6 and the asymptotic wing elsewhere, so the fraction of core
+    evaluations is counted on a sample of voxels over all directions and frequencies."""
+    import numpy as np
+    kb, amu = 1.380649e-16, 1.66053906660e-24
+    sl = slice(None, None, stride)
+    T = np.asarray(atm["T"], dtype=np.float64).ravel()[sl]
+    vD = np.sqrt(2.0 * kb * T / (atom["mass_amu"] * amu) + atom["xi"] ** 2)
+    v = np.stack([np.asarray(atm[c], dtype=np.float64).ravel()[sl] for c in ("vx", "vy", "vz")])
+    m1, m2 = 1.0 / 3.0, np.sqrt(7.0) / 3.0
+    up = [(sx * a, sy * b, c) for sx, sy in ((1, 1), (1, -1), (-1, 1), (-1, -1))
+          for a, b, c in ((m1, m1, m2), (m1, m2, m1), (m2, m1, m1))]
+    mus = np.array(up + [(-a, -b, -c) for a, b, c in up])
+    vn = mus @ v                                                   # [24][sample]
+    total = core = 0.0
+    flops = 0.0
+    for ln in atom["lines"]:
+        q = np.asarray(ln["q"], dtype=np.float64)
+        n = q.size * vn.size
+        total += n
+        if not (ln["gamma_rad"] or ln["gamma_vdw"]):
+            flops += n * (FLOPS_PER_UPDATE_BASE + FLOPS_GAUSS)
+            continue
+        u = (q[:, None, None] - vn[None]) / vD[None, None]
+        c = float(np.count_nonzero(np.abs(u) < 6.0))
+        core += c
+        flops += n * FLOPS_PER_UPDATE_BASE + c * FLOPS_VOIGT_CORE + (n - c) * FLOPS_VOIGT_WING
+    return flops / total, core / total
+
+
 def cpu_baseline(atom, atm, fine_fs_equiv, line=0):
     """Time the FP64 oracle on a bounded sample: one direction of the A4 set and one
     line, every plane and frequency of that line, on the full grid.  Projects updates/s
     and atmospheres/hr from the GPU solve's work count (finest-grid formal-solution
     equivalents)."""
     import numpy as np
-    from oracle.formal import sweep
+    from oracle.formal import source_function, sweep
     from oracle.levels import Level
     from oracle.rates import zero_radiation
     full = Level(atom, atm)
@@ -63,7 +107,7 @@ def cpu_baseline(atom, atm, fine_fs_equiv, line=0):
     def local(k):
         phi = lev.profile(k, mu)
         chi = lev.chi_c[lo, k] + kk[lo, k] * phi
-        S = (lev.eta_c[lo, k] + ee[lo, k] * phi) / chi
+        S = source_function(chi, lev.chi_c[lo, k], lev.eta_c[lo, k], kk[lo, k], ee[lo, k], phi)
         return chi, S, None
 
     t0 = time.perf_counter()
@@ -91,7 +135,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mali", action="store_true", help="skip the FP64 MALI comparison solve")
     ap.add_argument("--mali-max-iter", type=int, default=800)
-    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--dirs-per-block", type=int, default=0, help="sweep block shape (0: autotune)")
     ap.add_argument("--graph", type=int, default=0, help="1: replay V-cycles from a captured HIP graph")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only one MALI iteration (one formal solution + rate solve) and a 512 MiB "
@@ -119,7 +163,8 @@ def main():
     method = {"FAS": nlte.FAS, "FMG": nlte.FMG, "MALI": nlte.MALI}[wl["method"]]
     params = nlte.SolveParams(method=method, precision=nlte.MIXED, nlev=wl["nlev"], nu0=wl["nu0"],
                               nu1=wl["nu1"], nu2=wl["nu2"], nu3=wl["nu3"], nu_fmg=wl["nu_fmg"],
-                              E_target=1e-3, max_iter=60, timing=0 if args.graph else 1, tile_points=args.tile,
+                              E_target=1e-3, max_iter=60, timing=0 if args.graph else 1,
+                              dirs_per_block=args.dirs_per_block,
                               graph=args.graph)
     nf = sum(len(l["q"]) for l in atom["lines"])
     mu_out = np.array([[0.0, 0.0, 1.0]])
@@ -127,7 +172,7 @@ def main():
 
     if args.kernel_probe:
         probe = nlte.SolveParams(method=nlte.MALI, precision=nlte.MIXED, nlev=1, E_target=0.0, max_iter=1,
-                                 tile_points=args.tile or 32)
+                                 dirs_per_block=args.dirs_per_block)
         job = ctx.job(M, A, probe)
         rc, r = job.run()
         job.close()
@@ -167,14 +212,21 @@ def main():
     upd = sum(x.updates for _, x in results)
     sweep_ms = sum(x.ms_sweep for _, x in results)
     launches = sum(x.sweep_launches for _, x in results)
-    fl = FLOPS_PER_UPDATE_VOIGT if any(l["gamma_rad"] or l["gamma_vdw"] for l in atom["lines"]) else FLOPS_PER_UPDATE_GAUSS
+    fl, core_frac = flops_per_update(atom, atm)
+    nslot = 24 // r.dirs_per_block if r.dirs_per_block else 8
+    nfl = nf / len(atom["lines"])
+    bytes_upd = STATE_BYTES_PER_UPDATE + VOXEL_BYTES_PER_GROUP * nslot / (24.0 * nfl)
+    measured = MEASURED_BYTES_PER_LAUNCH.get((args.workload, r.dirs_per_block))
+    traffic = None
     if sweep_ms > 0:
         avg_launch_us = 1e3 * sweep_ms / launches
-        flops_per_launch = upd * fl / launches
-        achieved = flops_per_launch / (avg_launch_us * 1e-6) / 1e12
+        if measured:
+            traffic = measured / (avg_launch_us * 1e-6) / 1e9
+        achieved = upd * bytes_upd / launches / (avg_launch_us * 1e-6) / 1e9
+        achieved_alu = upd * fl / launches / (avg_launch_us * 1e-6) / 1e12
         ups_sweep = upd / (sweep_ms * 1e-3)
     else:   # graph replay: no per-phase events
-        avg_launch_us = achieved = ups_sweep = None
+        avg_launch_us = achieved = achieved_alu = ups_sweep = None
 
     out = {
         "metric": "converged atmospheres/hr + voxel-angle-freq updates/s, FAS-FP32 vs MALI-FP64",
@@ -194,15 +246,19 @@ def main():
         "cycles": r.cycles, "fine_fs_equiv": r.fine_fs_equiv, "E_est": r.E_est,
         "phase_ms": {"setup": r.ms_setup, "sweep": r.ms_sweep, "rates": r.ms_rates, "transfer": r.ms_transfer,
                      "total": r.ms_total},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS if achieved else None, "traffic": None,
-                     "kernel": "sweep_step_kernel<float>", "avg_launch_us": avg_launch_us,
-                     "flops_per_update": fl, "launches": launches},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": traffic,
+                     "kernel": f"sweep_step_kernel<float,{r.dirs_per_block}>", "avg_launch_us": avg_launch_us,
+                     "bytes_per_update": bytes_upd, "launches": launches,
+                     "alu": {"achieved": achieved_alu, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                             "frac": achieved_alu / PEAK_FP32_TFLOPS if achieved_alu else None,
+                             "flops_per_update": fl, "voigt_core_fraction": core_frac}},
     }
 
     if not args.no_mali:
         mp = nlte.SolveParams(method=nlte.MALI, precision=nlte.FP64, nlev=1, E_target=1e-3,
-                              max_iter=args.mali_max_iter, timing=1, tile_points=args.tile)
+                              max_iter=args.mali_max_iter, timing=1,
+                              dirs_per_block=args.dirs_per_block)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         job = ctx.job(M, A, mp)

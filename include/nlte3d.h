@@ -124,7 +124,7 @@ typedef struct {
     double repair_frac;        /* negative-population repair fraction (0.1, Sect. 4.10) */
     int fallback_mali;         /* on divergence continue with MALI instead of failing */
     const double* top_I;       /* prescribed incoming intensity at the top [nf][ny][nx] or NULL */
-    int tile_points;           /* sweep points per wave row: 0 = autotune, else 8/16/32/64 */
+    int dirs_per_block;        /* sweep directions per workgroup: 0 = autotune, else 3/6/12 (results do not depend on it) */
     int timing;                /* 1: time each phase with HIP events on the context stream */
     int graph;                 /* 1: capture one V-cycle (FAS/FMG) or one MALI iteration as a
                                   HIP graph on a job-private stream and replay it; the first
@@ -145,6 +145,7 @@ typedef struct {
     double updates;            /* voxel x direction x frequency updates performed */
     double ms_total, ms_setup, ms_sweep, ms_rates, ms_transfer;   /* phase times need params.timing */
     long long sweep_launches;  /* plane-step sweep kernel launches (formal solutions x planes) */
+    int dirs_per_block;        /* sweep block shape used on the finest level (3, 6 or 12; 0 if none ran) */
 } nlte_result;
 
 /* ---------------------------------------------------------------- lifecycle */

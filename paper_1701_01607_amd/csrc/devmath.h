@@ -7,7 +7,9 @@
 //   exp(-t^2)(L^2 + t^2) at t = L tan(theta/2); L = sqrt(N / sqrt 2).  N = 16 in FP32
 //   (absolute error ~3e-7 of the line-centre value, at the FP32 rounding floor) and
 //   N = 32 in FP64 (~4e-14).  In FP32 the far wings (|u| >= 6) use the asymptotic
-//   series of w(z) instead.  Lines without damping use exp(-u^2) directly.
+//   series of w(z) instead.  Lines without damping use exp(-u^2) directly.  Both
+//   series have real coefficients and are summed with Goertzel's second-order
+//   recurrence rather than complex Horner steps.
 // * Linear short-characteristics coefficients (Kunasz & Auer 1988):
 //     e = exp(-x), Psi_o = 1 - (1-e)/x, Psi_u = (1-e)/x - e,
 //   with their Taylor series below a precision-dependent threshold.
@@ -81,42 +83,54 @@ __device__ inline R source_fn(R chi, R chic, R etac, R kpl, R el, R phi, R& rchi
     return R(0);
 }
 
-// H(a, u) for a >= 0 (Weideman rational series), complex Horner with explicit FMAs.
+// H(a, u) for a >= 0 (Weideman rational series).  p has real coefficients, so p(Z) is
+// evaluated by the second-order recurrence for a real polynomial at a complex point
+// (Knuth, TAOCP vol. 2, sect. 4.6.4): with r = 2 Re Z and s = |Z|^2,
+//   b_j = c_j + r b_{j-1} - s b_{j-2},   p(Z) = Z b_{N-2} + (c_{N-1} - s b_{N-3}),
+// two FMAs per coefficient instead of the four of a complex Horner step.
 template <typename R>
 __device__ inline R voigt_H(R a, R u) {
     using T = VoigtTraits<R>;
     const R L = T::L();
-    const R lpa = L + a;
-    const R den = fma(lpa, lpa, u * u);
-    const R rden = dev_rcp(den);
-    const R zr = fma(L - a, lpa, -u * u) * rden;
+    const R lpa = L + a, lma = L - a;
+    const R u2 = u * u;
+    const R rden = dev_rcp(fma(lpa, lpa, u2));
+    const R zr = fma(lma, lpa, -u2) * rden;
     const R zi = (R(2) * L * u) * rden;
-    R pr = T::coef(0), pi = R(0);
+    const R r = R(2) * zr;
+    const R sq = fma(lma, lma, u2) * rden;   // |Z|^2
+    R b1 = T::coef(0), b2 = R(0);
 #pragma unroll
-    for (int j = 1; j < T::N; ++j) {
-        const R t = fma(pr, zr, fma(-pi, zi, T::coef(j)));
-        pi = fma(pr, zi, pi * zr);
-        pr = t;
+    for (int j = 1; j < T::N - 1; ++j) {
+        const R b0 = fma(r, b1, fma(-sq, b2, T::coef(j)));
+        b2 = b1;
+        b1 = b0;
     }
+    const R pr = fma(zr, b1, fma(-sq, b2, T::coef(T::N - 1)));
+    const R pi = zi * b1;
     const R rr = lpa * rden, ri = u * rden;
     const R r2r = fma(rr, rr, -ri * ri), r2i = R(2) * rr * ri;
     return fma(R(2), fma(pr, r2r, -pi * r2i), rr * R(kINVSQRTPI));
 }
 
 // Far wings, |u| >= 6: w(z) ~ (i/sqrt(pi)) z^-1 sum_n (2n-1)!!/2^n z^-2n (8 terms); the
-// Gaussian part exp(-z^2) is below 3e-16 there.  Relative error <= 4e-7 in FP32.
+// Gaussian part exp(-z^2) is below 3e-16 there.  Relative error <= 5e-7 in FP32.  The
+// sum is a real polynomial in 1/z^2, evaluated with the same recurrence as above.
 __device__ inline float voigt_H_wing(float a, float u) {
     const float rd = __builtin_amdgcn_rcpf(fmaf(u, u, a * a));
     const float rr = u * rd, ri = -a * rd;                       // 1/z
-    const float r2r = fmaf(rr, rr, -ri * ri), r2i = 2.0f * rr * ri;
+    const float r2r = fmaf(rr, rr, -ri * ri), r2i = 2.0f * rr * ri;  // 1/z^2
+    const float r = 2.0f * r2r, sq = rd * rd;                    // 2 Re z^-2, |z^-2|^2
     const float cf[8] = {1.0f, 0.5f, 0.75f, 1.875f, 6.5625f, 29.53125f, 162.421875f, 1055.7421875f};
-    float sr = cf[7], si = 0.0f;
+    float b1 = cf[7], b2 = 0.0f;
 #pragma unroll
-    for (int n = 6; n >= 0; --n) {
-        const float t = fmaf(sr, r2r, fmaf(-si, r2i, cf[n]));
-        si = fmaf(sr, r2i, si * r2r);
-        sr = t;
+    for (int n = 6; n >= 1; --n) {
+        const float b0 = fmaf(r, b1, fmaf(-sq, b2, cf[n]));
+        b2 = b1;
+        b1 = b0;
     }
+    const float sr = fmaf(r2r, b1, fmaf(-sq, b2, cf[0]));
+    const float si = r2i * b1;
     const float ti = fmaf(rr, si, ri * sr);
     return -ti * float(kINVSQRTPI);
 }

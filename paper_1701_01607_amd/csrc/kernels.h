@@ -190,18 +190,78 @@ struct Cell {
     R I, S, C;
 };
 
+// Cells move through raw buffer instructions: the resource holds the wave-uniform base
+// of one (direction, line) column and its size, the lane supplies a fixed byte offset
+// within a frequency row and the scalar offset selects the row, so addressing costs no
+// vector instructions.  Accesses past the resource size read 0 and write nothing.
+// Word 3 is the raw-buffer format of the gfx9 family.
+__device__ inline __amdgpu_buffer_rsrc_t cell_rsrc(const void* base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, int(bytes), 0x00020000);
+}
+
+typedef float f32x3 __attribute__((ext_vector_type(3)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline Cell<float> cell_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    const f32x3 x = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
+    return Cell<float>{x.x, x.y, x.z};
+}
+__device__ inline Cell<double> cell_load_d(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    const f64x2 a = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    const double c = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff + 16u, soff, 0));
+    return Cell<double>{a.x, a.y, c};
+}
+template <typename R> __device__ inline Cell<R> cell_get(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <> __device__ inline Cell<float> cell_get<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return cell_load(r, voff, soff);
+}
+template <> __device__ inline Cell<double> cell_get<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return cell_load_d(r, voff, soff);
+}
+__device__ inline void cell_put(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, const Cell<float>& c) {
+    __builtin_amdgcn_raw_buffer_store_b96(f32x3{c.I, c.S, c.C}, r, voff, soff, 0);
+}
+__device__ inline void cell_put(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, const Cell<double>& c) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned,
+                                                              f64x2{c.I, c.S}), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, c.C),
+                                          r, voff + 16u, soff, 0);
+}
+
+// Read-only tables read through the constant address space, so that loads at a
+// wave-uniform index become scalar loads.
+template <typename R>
+using const_as = __attribute__((address_space(4))) const R;
+
+// Partial sums of the sweep.  Every thread sums one direction's contributions over
+// its frequencies in order; directions are then combined by one fixed tree, whatever
+// the block shape:  g_i = (d_3i + d_3i+1) + d_3i+2  (8 groups of 3),
+// hemisphere = (g_0 + g_1) + (g_2 + g_3), total = up + down.  A block of DB directions
+// evaluates the part of the tree it holds and stores one slot per block; the readers
+// finish the tree over the 24/DB slots with tree_slots().
+constexpr int kMaxSlots = 8;
+
+template <typename R>
+__device__ __host__ inline R tree_slots(const R* x, size_t stride, int nslot) {
+    if (nslot == 2) return x[0] + x[stride];
+    if (nslot == 4) return (x[0] + x[stride]) + (x[2 * stride] + x[3 * stride]);
+    return ((x[0] + x[stride]) + (x[2 * stride] + x[3 * stride])) +
+           ((x[4 * stride] + x[5 * stride]) + (x[6 * stride] + x[7 * stride]));
+}
+
 // One plane step of the short-characteristics formal solution for all 24 directions.
 // Step s: upward directions solve plane s from plane s-1, downward directions plane
 // nz-1-s from nz-s; s = 0 sets the boundary planes (I = B below, I = 0 or prescribed
-// above).  Block: 12 directions x CH frequency lanes x P plane points (one wave per
-// direction when P*CH = 64); grid: (plane tiles, lines, hemispheres).  Each thread loops
-// over its line's frequencies m = c, c+CH, ...; the 12 x CH partial sums of a point are
-// reduced in LDS in a fixed order (deterministic, no atomics).
+// above).  Block: DB waves, wave w = direction grp*DB + w over 64 consecutive plane
+// points; grid: (plane tiles of 64 points, lines, 24/DB direction groups).  Direction
+// and frequency are uniform across a wave, so the frequency tables are scalar loads
+// and every cell access is a scalar base plus a fixed 32-bit lane offset.
 template <typename R>
 struct SweepArgs {
     const AtomInfo* atom;
     int nx, ny, nz, nf;
-    size_t nxy, nvox;
+    unsigned nxy;
+    size_t nvox;
     double dx, dy;
     const double* z;
     const R* sc;         // [SC_NQ][nline][nvox]
@@ -211,19 +271,20 @@ struct SweepArgs {
     const R* wf;         // [nf] frequency weights (Hz)
     const R* topI;       // [nf][nxy] or null
     Cell<R>* state;      // [2 slots][24][nline * Q][nxy]
-    R* acc;              // [2 qty][2 hemi][nline][nvox]
+    R* acc;              // [2 qty][24/DB slots][nline][nvox]
     int m0, Q;           // this pass covers frequencies m0 .. m0+Q-1 of every line
     int add;             // 1: add this pass's sums to acc; 0: overwrite
 };
 
-template <typename R, int P, int CH>
-__global__ __launch_bounds__(kNHemi* P* CH) void sweep_step_kernel(SweepArgs<R> a, int s) {
-    const int t = threadIdx.x;
-    const int p = t % P;
-    const int c = (t / P) % CH;
-    const int dl = t / (P * CH);
-    const int h = blockIdx.z;
-    const int d = h * kNHemi + dl;
+template <typename R, int DB>
+__global__ __launch_bounds__(DB * 64) void sweep_step_kernel(SweepArgs<R> a, int s) {
+    static_assert(DB == 3 || DB == 6 || DB == 12, "direction groups follow the fixed tree");
+    constexpr int kW = 64;
+    const int lane = int(threadIdx.x) & (kW - 1);
+    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kW);
+    const int grp = blockIdx.z;
+    const int d = grp * DB + w;
+    const int h = (grp * DB) / kNHemi;
     const int l = blockIdx.y;
     const AtomInfo& at = *a.atom;
     const LineInfo& ln = at.line[l];
@@ -233,124 +294,125 @@ __global__ __launch_bounds__(kNHemi* P* CH) void sweep_step_kernel(SweepArgs<R> 
     // Neighbouring tiles, which read each other's upwind rows, then share an L2.
     const unsigned T = gridDim.x;
     const unsigned bx = (T % 8u == 0u) ? (blockIdx.x % 8u) * (T / 8u) + blockIdx.x / 8u : blockIdx.x;
-    const size_t g = size_t(bx) * P + p;
-    const bool valid = g < a.nxy;
+    const unsigned nxy = a.nxy;
+    const unsigned graw = bx * kW + unsigned(lane);
+    const bool valid = graw < nxy;
+    const unsigned g = valid ? graw : nxy - 1;   // lanes past the plane compute a copy, store nothing
     const int k = (h == 0) ? s : a.nz - 1 - s;
-    R jacc = R(0), lacc = R(0);
-    const size_t nv = a.nvox, nxy = a.nxy;
+    const size_t nv = a.nvox;
+    const size_t v = size_t(k) * nxy + g;
     const size_t dstride = size_t(L) * a.Q * nxy;            // one direction's planes in this pass
     const size_t slot_stride = size_t(kNDir) * dstride;
     const int mend = min(ln.nfreq, a.m0 + a.Q);
-
-    if (valid) {
-        const size_t v = size_t(k) * nxy + g;
-        const double mux = c_mu[3 * d], muy = c_mu[3 * d + 1], muz = c_mu[3 * d + 2];
-        const R chic = a.sc[(SC_CHIC * L + l) * nv + v];
-        const R etac = a.sc[(SC_ETAC * L + l) * nv + v];
-        const R adamp = a.sc[(SC_ADAMP * L + l) * nv + v];
-        const R pn = a.sc[(SC_PN * L + l) * nv + v];
-        const R pw = a.sc[(SC_PW * L + l) * nv + v] * R(1.0 / kNDir);
-        const R kpl = a.lc[size_t(l) * nv + v];
-        const R el = a.lc[size_t(L + l) * nv + v];
-        const R ivD = a.sv[SV_INVVD * nv + v];
-        const R vn = a.sv[SV_VX * nv + v] * R(mux) + a.sv[SV_VY * nv + v] * R(muy) +
-                     a.sv[SV_VZ * nv + v] * R(muz);
-        const bool gauss = ln.gauss != 0;
-        // this thread's (direction, line) column of plane cells; cell (m - m0) of the pass
-        Cell<R>* cur = a.state + size_t(s & 1) * slot_stride + size_t(d) * dstride + size_t(l) * a.Q * nxy;
-        const R* qf = a.qf + ln.fstart;
-        const R* wf = a.wf + ln.fstart;
-        if (s == 0) {
-            const R Bb = a.sc[(SC_B * L + l) * nv + v];
-            const R* top = a.topI ? a.topI + size_t(ln.fstart) * nxy + g : nullptr;
-            for (int m = a.m0 + c; m < mend; m += CH) {
-                const R u = qf[m] * ivD - vn;
-                const R H = profile_H<R>(adamp, u, gauss);
-                const R phi = H * pn;
-                const R chi = chic + kpl * phi;
-                R rchi_b;
-                const R S = source_fn(chi, chic, etac, kpl, el, phi, rchi_b);
-                const R I = (h == 0) ? Bb : (top ? top[size_t(m) * nxy] : R(0));
-                Cell<R> cell;
-                cell.I = I; cell.S = S; cell.C = chi;
-                cur[size_t(m - a.m0) * nxy + g] = cell;
-                const R wphi = wf[m] * H * pw;
-                jacc += wphi * I;
-                lacc += wphi;
-            }
-        } else {
-            const int kp = (h == 0) ? s - 1 : a.nz - s;
-            const double ds = fabs(a.z[k] - a.z[kp]) / fabs(muz);
-            const double sx = -ds * mux / a.dx, sy = -ds * muy / a.dy;
-            const double fsx = floor(sx), fsy = floor(sy);
-            const R fx = R(sx - fsx), fy = R(sy - fsy);
-            const int x = int(g % a.nx), y = int(g / a.nx);
-            int x0 = int((long long)(x + (long long)fsx) % a.nx); if (x0 < 0) x0 += a.nx;
-            int y0 = int((long long)(y + (long long)fsy) % a.ny); if (y0 < 0) y0 += a.ny;
-            const int x1 = (x0 + 1 == a.nx) ? 0 : x0 + 1;
-            const int y1 = (y0 + 1 == a.ny) ? 0 : y0 + 1;
-            const unsigned g00 = unsigned(y0 * a.nx + x0), g01 = unsigned(y0 * a.nx + x1);
-            const unsigned g10 = unsigned(y1 * a.nx + x0), g11 = unsigned(y1 * a.nx + x1);
-            const R w00 = (R(1) - fx) * (R(1) - fy), w01 = fx * (R(1) - fy);
-            const R w10 = (R(1) - fx) * fy, w11 = fx * fy;
-            const R rds = R(ds);
-            const R etac_s = etac, chic_s = chic;
-            // wave-uniform base of this (direction, line) column and 32-bit byte offsets
-            const char* pb = reinterpret_cast<const char*>(a.state + size_t((s - 1) & 1) * slot_stride +
-                                                           size_t(d) * dstride + size_t(l) * a.Q * nxy);
-            char* cb = reinterpret_cast<char*>(cur);
-            const unsigned csz = sizeof(Cell<R>);
-            const unsigned inc = unsigned(CH) * unsigned(nxy) * csz;
-            unsigned o00 = (unsigned(c) * unsigned(nxy) + g00) * csz;
-            unsigned o01 = (unsigned(c) * unsigned(nxy) + g01) * csz;
-            unsigned o10 = (unsigned(c) * unsigned(nxy) + g10) * csz;
-            unsigned o11 = (unsigned(c) * unsigned(nxy) + g11) * csz;
-            unsigned oc = (unsigned(c) * unsigned(nxy) + unsigned(g)) * csz;
-#pragma unroll 2
-            for (int m = a.m0 + c; m < mend; m += CH, o00 += inc, o01 += inc, o10 += inc, o11 += inc, oc += inc) {
-                const Cell<R> c00 = *reinterpret_cast<const Cell<R>*>(pb + o00);
-                const Cell<R> c01 = *reinterpret_cast<const Cell<R>*>(pb + o01);
-                const Cell<R> c10 = *reinterpret_cast<const Cell<R>*>(pb + o10);
-                const Cell<R> c11 = *reinterpret_cast<const Cell<R>*>(pb + o11);
-                const R u = qf[m] * ivD - vn;
-                const R H = profile_H<R>(adamp, u, gauss);
-                const R phi = H * pn;
-                const R chi = fma(kpl, phi, chic);
-                R rchi;
-                const R S = source_fn(chi, chic, etac, kpl, el, phi, rchi);
-                const R Iu = fma(w00, c00.I, fma(w01, c01.I, fma(w10, c10.I, w11 * c11.I)));
-                const R Su = fma(w00, c00.S, fma(w01, c01.S, fma(w10, c10.S, w11 * c11.S)));
-                const R Cu = fma(w00, c00.C, fma(w01, c01.C, fma(w10, c10.C, w11 * c11.C)));
-                const R dtau = R(0.5) * (Cu + chi) * rds;
-                R ex, pu, po, omp;
-                sc_coeffs(dtau, ex, pu, po, omp);
-                const R Ith = fma(Iu, ex, pu * Su);
-                Cell<R> cell;
-                cell.I = fma(po, S, Ith);
-                cell.S = S;
-                cell.C = chi;
-                *reinterpret_cast<Cell<R>*>(cb + oc) = cell;
-                const R wphi = wf[m] * H * pw;
-                const R por = po * rchi;
-                jacc = fma(wphi, fma(por, etac_s, Ith), jacc);
-                lacc = fma(wphi, fma(por, chic_s, omp), lacc);
-            }
+    const double mux = c_mu[3 * d], muy = c_mu[3 * d + 1], muz = c_mu[3 * d + 2];
+    const R chic = a.sc[(SC_CHIC * L + l) * nv + v];
+    const R etac = a.sc[(SC_ETAC * L + l) * nv + v];
+    const R adamp = a.sc[(SC_ADAMP * L + l) * nv + v];
+    const R pn = a.sc[(SC_PN * L + l) * nv + v];
+    const R pw = a.sc[(SC_PW * L + l) * nv + v] * R(1.0 / kNDir);
+    const R kpl = a.lc[size_t(l) * nv + v];
+    const R el = a.lc[size_t(L + l) * nv + v];
+    const R ivD = a.sv[SV_INVVD * nv + v];
+    const R vn = a.sv[SV_VX * nv + v] * R(mux) + a.sv[SV_VY * nv + v] * R(muy) +
+                 a.sv[SV_VZ * nv + v] * R(muz);
+    const bool gauss = ln.gauss != 0;
+    const const_as<R>* qf = (const const_as<R>*)(a.qf + ln.fstart);
+    const const_as<R>* wf = (const const_as<R>*)(a.wf + ln.fstart);
+    const size_t col = size_t(d) * dstride + size_t(l) * a.Q * nxy;   // this (direction, line) column
+    const unsigned csz = sizeof(Cell<R>);
+    const unsigned rowb = nxy * csz;                                  // bytes per frequency row
+    const unsigned colb = unsigned(mend - a.m0) * rowb;
+    const auto rcur = cell_rsrc(a.state + size_t(s & 1) * slot_stride + col, colb);
+    R jacc = R(0), lacc = R(0);
+    const unsigned oc = g * csz;
+    if (s == 0) {
+        const R Bb = a.sc[(SC_B * L + l) * nv + v];
+        const R* top = a.topI ? a.topI + size_t(ln.fstart) * nxy + g : nullptr;
+        for (int m = a.m0; m < mend; ++m) {
+            const R u = qf[m] * ivD - vn;
+            const R H = profile_H<R>(adamp, u, gauss);
+            const R phi = H * pn;
+            const R chi = chic + kpl * phi;
+            R rchi_b;
+            const R S = source_fn(chi, chic, etac, kpl, el, phi, rchi_b);
+            const R I = (h == 0) ? Bb : (top ? top[size_t(m) * nxy] : R(0));
+            Cell<R> cell;
+            cell.I = I; cell.S = S; cell.C = chi;
+            if (valid) cell_put(rcur, oc, unsigned(m - a.m0) * rowb, cell);
+            const R wphi = wf[m] * H * pw;
+            jacc += wphi * I;
+            lacc += wphi;
+        }
+    } else {
+        const int kp = (h == 0) ? s - 1 : a.nz - s;
+        const double ds = fabs(a.z[k] - a.z[kp]) / fabs(muz);
+        const double sx = -ds * mux / a.dx, sy = -ds * muy / a.dy;
+        const double fsx = floor(sx), fsy = floor(sy);
+        const R fx = R(sx - fsx), fy = R(sy - fsy);
+        const int x = int(g % unsigned(a.nx)), y = int(g / unsigned(a.nx));
+        int x0 = int((long long)(x + (long long)fsx) % a.nx); if (x0 < 0) x0 += a.nx;
+        int y0 = int((long long)(y + (long long)fsy) % a.ny); if (y0 < 0) y0 += a.ny;
+        const int x1 = (x0 + 1 == a.nx) ? 0 : x0 + 1;
+        const int y1 = (y0 + 1 == a.ny) ? 0 : y0 + 1;
+        const unsigned o00 = unsigned(y0 * a.nx + x0) * csz, o01 = unsigned(y0 * a.nx + x1) * csz;
+        const unsigned o10 = unsigned(y1 * a.nx + x0) * csz, o11 = unsigned(y1 * a.nx + x1) * csz;
+        const R w00 = (R(1) - fx) * (R(1) - fy), w01 = fx * (R(1) - fy);
+        const R w10 = (R(1) - fx) * fy, w11 = fx * fy;
+        const R rds = R(ds);
+        const auto rprv = cell_rsrc(a.state + size_t((s - 1) & 1) * slot_stride + col, colb);
+        for (int m = a.m0; m < mend; ++m) {
+            const unsigned so = unsigned(m - a.m0) * rowb;
+            const Cell<R> c00 = cell_get<R>(rprv, o00, so), c01 = cell_get<R>(rprv, o01, so);
+            const Cell<R> c10 = cell_get<R>(rprv, o10, so), c11 = cell_get<R>(rprv, o11, so);
+            const R u = qf[m] * ivD - vn;
+            const R H = profile_H<R>(adamp, u, gauss);
+            const R phi = H * pn;
+            const R chi = fma(kpl, phi, chic);
+            R rchi;
+            const R S = source_fn(chi, chic, etac, kpl, el, phi, rchi);
+            const R Iu = fma(w00, c00.I, fma(w01, c01.I, fma(w10, c10.I, w11 * c11.I)));
+            const R Su = fma(w00, c00.S, fma(w01, c01.S, fma(w10, c10.S, w11 * c11.S)));
+            const R Cu = fma(w00, c00.C, fma(w01, c01.C, fma(w10, c10.C, w11 * c11.C)));
+            const R dtau = R(0.5) * (Cu + chi) * rds;
+            R ex, pu, po, omp;
+            sc_coeffs(dtau, ex, pu, po, omp);
+            const R Ith = fma(Iu, ex, pu * Su);
+            Cell<R> cell;
+            cell.I = fma(po, S, Ith);
+            cell.S = S;
+            cell.C = chi;
+            if (valid) cell_put(rcur, oc, so, cell);
+            const R wphi = wf[m] * H * pw;
+            const R por = po * rchi;
+            jacc = fma(wphi, fma(por, etac, Ith), jacc);
+            lacc = fma(wphi, fma(por, chic, omp), lacc);
         }
     }
-    __shared__ R sj[kNHemi * P * CH];
-    __shared__ R sl[kNHemi * P * CH];
-    sj[t] = jacc;
-    sl[t] = lacc;
+    __shared__ R sj[DB * kW];
+    __shared__ R sl[DB * kW];
+    sj[threadIdx.x] = jacc;
+    sl[threadIdx.x] = lacc;
     __syncthreads();
-    if (t < P && valid) {
-        R jt = R(0), lt = R(0);
-        for (int q = 0; q < kNHemi * CH; ++q) {
-            jt += sj[q * P + t];
-            lt += sl[q * P + t];
+    if (int(threadIdx.x) < kW && valid) {
+        // groups of three directions, then pairs of groups (the fixed tree)
+        R gj[DB / 3], gl[DB / 3];
+#pragma unroll
+        for (int q = 0; q < DB / 3; ++q) {
+            gj[q] = (sj[(3 * q) * kW + lane] + sj[(3 * q + 1) * kW + lane]) + sj[(3 * q + 2) * kW + lane];
+            gl[q] = (sl[(3 * q) * kW + lane] + sl[(3 * q + 1) * kW + lane]) + sl[(3 * q + 2) * kW + lane];
         }
-        const size_t v = size_t(k) * nxy + g;
-        R* aj = a.acc + ((size_t(0) * 2 + h) * L + l) * nv + v;
-        R* al = a.acc + ((size_t(1) * 2 + h) * L + l) * nv + v;
+        R jt, lt;
+        if constexpr (DB == 3) {
+            jt = gj[0]; lt = gl[0];
+        } else if constexpr (DB == 6) {
+            jt = gj[0] + gj[1]; lt = gl[0] + gl[1];
+        } else {
+            jt = (gj[0] + gj[1]) + (gj[2] + gj[3]);
+            lt = (gl[0] + gl[1]) + (gl[2] + gl[3]);
+        }
+        constexpr int nslot = kNDir / DB;
+        R* aj = a.acc + ((size_t(0) * nslot + grp) * L + l) * nv + v;
+        R* al = a.acc + ((size_t(1) * nslot + grp) * L + l) * nv + v;
         if (a.add) { jt += *aj; lt += *al; }
         *aj = jt;
         *al = lt;
@@ -450,7 +512,8 @@ struct RateArgs {
     const AtomInfo* atom;
     size_t nvox;
     const double* pfix;   // [N*N][nvox]
-    const R* acc;         // [2][2][nline][nvox]
+    const R* acc;         // [2][nslot][nline][nvox]
+    int nslot;            // 2, 4 or 8 direction-group slots per quantity
     double* n;            // [N][nvox]  (mode 0/1: updated in place)
     const double* f;      // [N][nvox]
     const double* base;   // mode 2
@@ -545,10 +608,9 @@ __global__ __launch_bounds__(256) void rate_kernel(RateArgs<R> a) {
                 Jeff[l] = 0.0;
                 omL[l] = 1.0;
             } else {
-                Jeff[l] = double(a.acc[((size_t(0) * 2 + 0) * L + l) * nv + v]) +
-                          double(a.acc[((size_t(0) * 2 + 1) * L + l) * nv + v]);
-                omL[l] = double(a.acc[((size_t(1) * 2 + 0) * L + l) * nv + v]) +
-                         double(a.acc[((size_t(1) * 2 + 1) * L + l) * nv + v]);
+                const size_t ss = size_t(L) * nv;
+                Jeff[l] = double(tree_slots(a.acc + (size_t(0) * a.nslot * L + l) * nv + v, ss, a.nslot));
+                omL[l] = double(tree_slots(a.acc + (size_t(1) * a.nslot * L + l) * nv + v, ss, a.nslot));
             }
         }
         double A[N][N];

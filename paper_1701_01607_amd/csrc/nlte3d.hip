@@ -226,6 +226,7 @@ struct Level {
     DevBuf dz, prim, sc, sv, nstar, pfix, ntot, n, f, nb, tmp, acc, lc, partial;
     bool fs_valid = false;
     long long fs_count = 0;
+    int nslot = 2;   // direction-group slots in acc written by the last formal solution
 };
 
 template <typename R>
@@ -234,7 +235,7 @@ struct Job : JobBase {
     std::vector<std::unique_ptr<Level>> lev;
     DevBuf atom_d, qf, wf, line_of_d, state, topI, scalar, repairs, estate, eout, flag, nprev;
     AtomInfo info{};
-    int P = 64, CH = 1;
+    int DB = 0;   // directions per sweep block (0: autotuned per level)
     std::vector<double> hz_top;
     double updates_per_fs_fine = 0;
     double cost_units = 0;
@@ -369,7 +370,7 @@ struct Job : JobBase {
             dalloc(L.f, sizeof(double) * N * L.nvox);
             dalloc(L.nb, sizeof(double) * N * L.nvox);
             dalloc(L.tmp, sizeof(double) * N * L.nvox);
-            dalloc(L.acc, sizeof(R) * 4 * nline * L.nvox);
+            dalloc(L.acc, sizeof(R) * 2 * kMaxSlots * nline * L.nvox);
             dalloc(L.lc, sizeof(R) * 2 * nline * L.nvox);
             dalloc(L.partial, sizeof(double) * std::max<size_t>(blocks_for(L.nvox, 256), 1024));
             SetupArgs<R> sa;
@@ -401,6 +402,9 @@ struct Job : JobBase {
         const double cap_bytes = envb ? std::atof(envb) * 1048576.0 : 0.25 * double(ctx->budget);
         const double per_q = double(sizeof(Cell<R>)) * 2 * kNDir * nline * Fz.nxy;
         Qpass = std::max(1, std::min(maxfreq, int(cap_bytes / per_q)));
+        // a pass's (direction, line) column is addressed by 32-bit buffer offsets
+        const double colmax = 4294967295.0 / (double(sizeof(Cell<R>)) * double(Fz.nxy));
+        Qpass = std::max(1, std::min(Qpass, int(colmax)));
         dalloc(state, sizeof(Cell<R>) * 2 * kNDir * size_t(nline) * Qpass * Fz.nxy);
         dalloc(nprev, sizeof(double) * N * Fz.nvox);
         if (p->top_I) {
@@ -430,13 +434,11 @@ struct Job : JobBase {
     }
 
     void choose_tile() {
-        int t = params.tile_points;
-        if (t != 8 && t != 16 && t != 32 && t != 64) t = 0;
-        P = t;
-        CH = t ? 64 / t : 0;
+        const int t = params.dirs_per_block;
+        DB = (t == 3 || t == 6 || t == 12) ? t : 0;
     }
 
-    std::vector<int> level_tile;   // autotuned points per wave row, per level
+    std::vector<int> level_tile;   // autotuned directions per block, per level
     int maxfreq = 0, Qpass = 1;    // frequencies per line swept per pass
 
     std::string tile_key(const Level& L) const {
@@ -444,17 +446,21 @@ struct Job : JobBase {
                std::to_string(L.nz) + ":" + std::to_string(nline) + ":" + std::to_string(nf);
     }
 
-    void launch_step(const SweepArgs<R>& a, dim3 grid, int p, int s) {
-        switch (p) {
-            case 64: sweep_step_kernel<R, 64, 1><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
-            case 32: sweep_step_kernel<R, 32, 2><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
-            case 16: sweep_step_kernel<R, 16, 4><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
-            default: sweep_step_kernel<R, 8, 8><<<grid, kNHemi * 64, 0, st()>>>(a, s); break;
+    static dim3 sweep_grid(const Level& L, int nline, int db) {
+        return dim3(blocks_for(L.nxy, 64), nline, kNDir / db);
+    }
+
+    void launch_step(const SweepArgs<R>& a, dim3 grid, int db, int s) {
+        switch (db) {
+            case 12: sweep_step_kernel<R, 12><<<grid, 12 * 64, 0, st()>>>(a, s); break;
+            case 6: sweep_step_kernel<R, 6><<<grid, 6 * 64, 0, st()>>>(a, s); break;
+            default: sweep_step_kernel<R, 3><<<grid, 3 * 64, 0, st()>>>(a, s); break;
         }
     }
 
-    // Autotuner: time plane steps 1..3 of a formal solution for each tile width and keep
-    // the fastest.  The result is cached per (precision, shape, lines, frequencies) in the
+    // Autotuner: time plane steps 1..3 of a formal solution for each block shape and keep
+    // the fastest.  Every shape sums the directions by the same tree, so the choice does
+    // not change results.  It is cached per (precision, shape, lines, frequencies) in the
     // context, so a shape is tuned once per process.
     int autotune_tile(int k, SweepArgs<R>& a) {
         Level& L = *lev[k];
@@ -464,16 +470,15 @@ struct Job : JobBase {
             auto it = ctx->tile_cache.find(key);
             if (it != ctx->tile_cache.end()) return it->second;
         }
-        const int cand[4] = {64, 32, 16, 8};
+        const int cand[3] = {12, 6, 3};
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        int best = 64;
+        int best = 12;
         float best_ms = 1e30f;
         const int steps = std::min(L.nz, 4);
         for (int c : cand) {
-            if (c > 8 && L.nxy < size_t(c) * 4 && c != 8) continue;   // keep >= 4 tiles per row block
-            dim3 grid(blocks_for(L.nxy, c), nline, 2);
+            const dim3 grid = sweep_grid(L, nline, c);
             launch_step(a, grid, c, 0);
             HIPCHK(hipEventRecord(e0, st()));
             for (int s = 1; s < steps; ++s) launch_step(a, grid, c, s);
@@ -492,8 +497,8 @@ struct Job : JobBase {
         return best;
     }
 
-    void tile_for(int k, SweepArgs<R>& a, int& p, int& ch) {
-        if (P) { p = P; ch = CH; return; }
+    int tile_for(int k, SweepArgs<R>& a) {
+        if (DB) return DB;
         if (level_tile.size() != size_t(nlev)) level_tile.assign(nlev, 0);
         if (!level_tile[k]) {
             a.m0 = 0;
@@ -501,8 +506,7 @@ struct Job : JobBase {
             a.add = 0;
             level_tile[k] = autotune_tile(k, a);
         }
-        p = level_tile[k];
-        ch = 64 / p;
+        return level_tile[k];
     }
 
     // --------------------------------------------------------------- kernels
@@ -513,6 +517,7 @@ struct Job : JobBase {
         ra.nvox = L.nvox;
         ra.pfix = L.pfix.as<double>();
         ra.acc = L.acc.as<R>();
+        ra.nslot = L.nslot;
         ra.n = L.n.as<double>();
         ra.f = L.f.as<double>();
         ra.base = base;
@@ -549,7 +554,7 @@ struct Job : JobBase {
         SweepArgs<R> a;
         a.atom = atom_d.as<AtomInfo>();
         a.nx = L.nx; a.ny = L.ny; a.nz = L.nz; a.nf = nf;
-        a.nxy = L.nxy; a.nvox = L.nvox;
+        a.nxy = unsigned(L.nxy); a.nvox = L.nvox;
         a.dx = L.dx; a.dy = L.dy;
         a.z = L.dz.as<double>();
         a.sc = L.sc.as<R>(); a.sv = L.sv.as<R>(); a.lc = L.lc.as<R>();
@@ -557,19 +562,19 @@ struct Job : JobBase {
         a.topI = (k == nlev - 1 && topI.p) ? topI.as<R>() : nullptr;
         a.state = state.as<Cell<R>>();
         a.acc = L.acc.as<R>();
-        int p, ch;
-        tile_for(k, a, p, ch);
-        dim3 grid(blocks_for(L.nxy, p), nline, 2);
+        const int db = tile_for(k, a);
+        const dim3 grid = sweep_grid(L, nline, db);
         ev_begin(EV_SWEEP);
         for (int m0 = 0; m0 < maxfreq; m0 += Qpass) {
             a.m0 = m0;
             a.Q = Qpass;
             a.add = m0 > 0 ? 1 : 0;
-            for (int s = 0; s < L.nz; ++s) launch_step(a, grid, p, s);
+            for (int s = 0; s < L.nz; ++s) launch_step(a, grid, db, s);
             sweep_launches += L.nz;
         }
         HIPCHK(hipGetLastError());
         ev_end();
+        L.nslot = kNDir / db;
         L.fs_valid = true;
         ++L.fs_count;
         const Level& F = *lev[nlev - 1];
@@ -806,6 +811,7 @@ struct Job : JobBase {
         r.ms_rates = ms_phase[EV_RATES];
         r.ms_transfer = ms_phase[EV_TRANSFER];
         r.sweep_launches = sweep_launches;
+        r.dirs_per_block = level_tile.size() == size_t(nlev) && !DB ? level_tile[nlev - 1] : DB;
         res = r;
         if (out) *out = r;
     }
@@ -822,15 +828,16 @@ struct Job : JobBase {
     void formal_solution_out(int level, void* jeff, void* oml, int mem) override {
         Level& L = level_ref(level);
         formal_solution(level);
-        // Jeff = up + down, 1-L* = up + down, summed on the host side of the copy
-        std::vector<R> a(size_t(4) * nline * L.nvox);
+        // direction-group slots summed on the host side of the copy, by the same tree
+        // as the rate equations
+        const size_t m = size_t(nline) * L.nvox;
+        std::vector<R> a(size_t(2) * L.nslot * m);
         HIPCHK(hipMemcpyAsync(a.data(), L.acc.p, sizeof(R) * a.size(), hipMemcpyDeviceToHost, st()));
         HIPCHK(hipStreamSynchronize(st()));
-        const size_t m = size_t(nline) * L.nvox;
         std::vector<R> j(m), o(m);
         for (size_t i = 0; i < m; ++i) {
-            j[i] = a[i] + a[m + i];
-            o[i] = a[2 * m + i] + a[3 * m + i];
+            j[i] = tree_slots(a.data() + i, m, L.nslot);
+            o[i] = tree_slots(a.data() + size_t(L.nslot) * m + i, m, L.nslot);
         }
         if (mem == NLTE_MEM_DEVICE) {
             HIPCHK(hipMemcpyAsync(jeff, j.data(), sizeof(R) * m, hipMemcpyHostToDevice, st()));
@@ -955,7 +962,7 @@ size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom
     for (int k = nlev - 1; k >= 0; --k) {
         const size_t nvox = size_t(nx) * ny * nz;
         bytes += 8 * size_t(nz) + 8 * size_t(nprim) * nvox + R * (6 * nline + 4) * nvox;
-        bytes += 8 * (size_t(N) * 6 + size_t(N) * N + 1) * nvox + R * 6 * nline * nvox;
+        bytes += 8 * (size_t(N) * 6 + size_t(N) * N + 1) * nvox + R * (2 * kMaxSlots + 2) * nline * nvox;
         bytes += 8 * std::max<size_t>((nvox + 255) / 256, 1024);
         nx /= 2; ny /= 2; nz = (nz - 1) / 2 + 1;
     }
@@ -964,7 +971,8 @@ size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom
     const char* envb = std::getenv("NLTE3D_SWEEP_STATE_MB");
     const double cap = envb ? std::atof(envb) * 1048576.0 : 0.25 * double(ctx->budget);
     const double per_q = double(3 * R) * 2 * kNDir * nline * fine_nxy;
-    const int Q = std::max(1, std::min(maxfreq, int(cap / per_q)));
+    int Q = std::max(1, std::min(maxfreq, int(cap / per_q)));
+    Q = std::max(1, std::min(Q, int(4294967295.0 / (double(3 * R) * double(fine_nxy)))));
     bytes += size_t(3 * R) * 2 * kNDir * size_t(nline) * Q * fine_nxy;
     bytes += 8 * size_t(N) * fine_nvox;
     if (p->top_I) bytes += R * size_t(nf) * fine_nxy;
@@ -1205,6 +1213,8 @@ nlte_status nlte_atmos_create(nlte_ctx* ctx, const nlte_atmos_desc* d, nlte_atmo
     return guarded(ctx, [&]() -> nlte_status {
         REQUIRE(d && out && d->z, "null argument");
         REQUIRE(d->nx >= 1 && d->ny >= 1 && d->nz >= 2, "grid must be at least 1x1x2");
+        // sweep cells are addressed by 32-bit byte offsets within a plane row
+        REQUIRE(double(d->nx) * d->ny * 24.0 < 4294967296.0, "nx*ny must stay below 178,956,970");
         REQUIRE(d->dx > 0 && d->dy > 0, "spacings must be positive");
         for (int k = 1; k < d->nz; ++k) REQUIRE(d->z[k] > d->z[k - 1], "z must increase strictly");
         REQUIRE(d->T && d->ne && d->nH && d->ntot && d->vx && d->vy && d->vz, "missing atmosphere field");

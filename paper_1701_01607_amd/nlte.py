@@ -84,7 +84,7 @@ class Params(ct.Structure):
                 ("init", ct.c_int), ("init_pops", ct.POINTER(ct.c_double)),
                 ("tol_C", ct.c_double), ("E_target", ct.c_double), ("max_iter", ct.c_int),
                 ("repair_frac", ct.c_double), ("fallback_mali", ct.c_int),
-                ("top_I", ct.POINTER(ct.c_double)), ("tile_points", ct.c_int), ("timing", ct.c_int),
+                ("top_I", ct.POINTER(ct.c_double)), ("dirs_per_block", ct.c_int), ("timing", ct.c_int),
                 ("graph", ct.c_int)]
 
 
@@ -94,7 +94,8 @@ class Result(ct.Structure):
                 ("repairs", ct.c_longlong), ("formal_solutions", ct.c_longlong * 8),
                 ("fine_fs_equiv", ct.c_double), ("updates", ct.c_double),
                 ("ms_total", ct.c_double), ("ms_setup", ct.c_double), ("ms_sweep", ct.c_double),
-                ("ms_rates", ct.c_double), ("ms_transfer", ct.c_double), ("sweep_launches", ct.c_longlong)]
+                ("ms_rates", ct.c_double), ("ms_transfer", ct.c_double), ("sweep_launches", ct.c_longlong),
+                ("dirs_per_block", ct.c_int)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "formal_solutions"}
@@ -182,7 +183,7 @@ class SolveParams:
     max_iter: int = 100
     repair_frac: float = 0.1
     fallback_mali: int = 0
-    tile_points: int = 0
+    dirs_per_block: int = 0
     timing: int = 0
     graph: int = 0
     init_pops: np.ndarray | None = None
@@ -192,7 +193,7 @@ class SolveParams:
     def to_c(self):
         p = Params()
         for k in ("method", "precision", "nlev", "nu_fmg", "nu0", "nu1", "nu2", "nu3", "init",
-                  "max_iter", "fallback_mali", "tile_points", "timing", "graph"):
+                  "max_iter", "fallback_mali", "dirs_per_block", "timing", "graph"):
             setattr(p, k, int(getattr(self, k)))
         for k in ("tol_C", "E_target", "repair_frac"):
             setattr(p, k, float(getattr(self, k)))

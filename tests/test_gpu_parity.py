@@ -61,18 +61,18 @@ def ragged():
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
-@pytest.mark.parametrize("tile", [0, 16, 64])
-def test_formal_solution_parity(nl, ctx, ragged, prec, tol, tile):
+@pytest.mark.parametrize("dpb", [0, 3, 12])
+def test_formal_solution_parity(nl, ctx, ragged, prec, tol, dpb):
     atom, atm, lev, n0 = ragged
     npop, nln = shapes(atom, atm)
     job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1,
-                                                                 tile_points=tile))
+                                                                 dirs_per_block=dpb))
     g0 = job.populations(0, npop)
     assert relerr(g0, n0) < 1e-11
     jg, og = job.formal_solution(0, nln)
     jo, oo = formal_solution(lev, n0)
     ej, eo = relerr(jg, jo), relerr(og, oo)
-    print(f"prec={prec} tile={tile} Jeff err {ej:.2e}  1-L* err {eo:.2e}")
+    print(f"prec={prec} dirs_per_block={dpb} Jeff err {ej:.2e}  1-L* err {eo:.2e}")
     assert ej < tol and eo < tol
 
 
@@ -230,7 +230,7 @@ def test_graph_replay_equals_eager(nl, ctx, method):
     for graph in (0, 1):
         job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
                       nl.SolveParams(method=m, precision=nl.MIXED, nlev=3 if m == nl.FAS else 1, nu0=3, nu1=2,
-                                     nu2=2, nu3=6, E_target=0.0, max_iter=5, graph=graph, tile_points=16))
+                                     nu2=2, nu3=6, E_target=0.0, max_iter=5, graph=graph, dirs_per_block=6))
         rc, r = job.run()
         outs.append((job.history(), job.populations(job.params.nlev - 1 if m == nl.FAS else 0, (6, 17, 8, 8)),
                      r.fine_fs_equiv, list(r.formal_solutions)))
@@ -258,3 +258,21 @@ def test_undamped_line_far_wings_stay_finite(nl, ctx, prec, tol):
     e = relerr(g, n_or)
     print(f"prec={prec} two-level stratified 2 cycles err {e:.2e}")
     assert e < tol
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_block_shape_does_not_change_results(nl, ctx, prec):
+    """Directions are summed by one fixed tree whatever the sweep block shape, so formal
+    solutions and solves are bitwise equal for 3, 6 and 12 directions per block."""
+    atom, atm = ragged_case(nfreq=9, seed=23)
+    npop, nln = shapes(atom, atm)
+    A, M = ctx.atmos(atm), ctx.atom(atom)
+    outs = []
+    for dpb in (3, 6, 12):
+        job = ctx.job(A, M, nl.SolveParams(method=nl.MALI, precision=prec, nlev=1, dirs_per_block=dpb))
+        jg, og = job.formal_solution(0, nln)
+        job.mali(0, 3)
+        outs.append((jg, og, job.populations(0, npop)))
+    for o in outs[1:]:
+        for x, y in zip(outs[0], o):
+            assert np.array_equal(x, y)

@@ -33,7 +33,7 @@ def requests(nl):
             atom = synth.caii_like_atom(9)
             atm["ntot"] = atm["ntot"] * 0.1
         p = nl.SolveParams(method=nl.FAS, precision=nl.MIXED, nlev=2, nu1=2, nu2=2, nu3=8, E_target=1e-4,
-                           max_iter=20, tile_points=16)
+                           max_iter=20, dirs_per_block=6)
         out.append((atom, atm, p))
     return out
 
@@ -83,7 +83,7 @@ def test_over_budget_requests_wait_instead_of_failing(nl):
         atm["ntot"] = atm["ntot"] * 0.1
         reqs.append((synth.caii_like_atom(9), atm,
                      nl.SolveParams(method=nl.FAS, precision=nl.MIXED, nlev=2, nu1=2, nu2=2, nu3=8, E_target=1e-4,
-                                    max_iter=20, tile_points=16)))
+                                    max_iter=20, dirs_per_block=6)))
     probe = nl.Context(0, torch.cuda.current_stream().cuda_stream)
     fp = probe.footprint(probe.atmos(reqs[0][1]), probe.atom(reqs[0][0]), reqs[0][2])
     probe.close()
