@@ -23,7 +23,10 @@ Follows Sect. 2.2 and 2.3 of the paper in its order and notation:
   every intermediate level; at the finest level regular V-cycles follow.
 * Convergence (Sect. 3.3): C_i = max |(n_i - n_{i-1}) / n_i| (Eq. 18) over all levels
   and voxels; for cycles it is taken between successive finest-level cycle ends.  The
-  error estimate is E = rho / (1 - rho) C with rho = C_{i}/C_{i-1} (Eq. 20).
+  error estimate is E = rho / (1 - rho) C with rho = C_{i}/C_{i-1} (Eq. 20), which holds
+  once the corrections are in their asymptotic linear regime; the first correction,
+  made from the initial populations, is not, so rho is taken from the second
+  correction on (three or more corrections before E is used).
 * With a single grid a "cycle" is nu_1 (or nu_0) + nu_2 plain MALI iterations.
 """
 from __future__ import annotations
@@ -130,7 +133,7 @@ def _converged(hist, p):
     C = hist[-1]
     if p.tol_C is not None and C <= p.tol_C:
         return True
-    if p.E_target is not None and len(hist) >= 2:
+    if p.E_target is not None and len(hist) >= 3:
         rho = hist[-1] / hist[-2]
         if rho < 1.0 and rho / (1.0 - rho) * C <= p.E_target:
             return True
@@ -138,7 +141,7 @@ def _converged(hist, p):
 
 
 def _record(stats, hist):
-    if len(hist) >= 2 and hist[-1] < hist[-2]:
+    if len(hist) >= 3 and hist[-1] < hist[-2]:
         rho = hist[-1] / hist[-2]
         stats.E_est.append(rho / (1.0 - rho) * hist[-1])
     else:

@@ -4,12 +4,11 @@
 //   J.A.C. Weideman, SIAM J. Numer. Anal. 31 (1994) 1497:
 //     w(z) = 2 p(Z) / (L - i z)^2 + pi^{-1/2} / (L - i z),  Z = (L + i z)/(L - i z),
 //   with p a polynomial of degree N-1 whose coefficients are cosine sums of
-//   exp(-t^2)(L^2 + t^2) at t = L tan(theta/2); L = sqrt(N / sqrt 2).  N = 16 in FP32
-//   (absolute error ~3e-7 of the line-centre value, at the FP32 rounding floor) and
-//   N = 32 in FP64 (~4e-14).  In FP32 the far wings (|u| >= 6) use the asymptotic
-//   series of w(z) instead.  Lines without damping use exp(-u^2) directly.  Both
-//   series have real coefficients and are summed with Goertzel's second-order
-//   recurrence rather than complex Horner steps.
+//   exp(-t^2)(L^2 + t^2) at t = L tan(theta/2); L = sqrt(N / sqrt 2).  N = 32, in FP64
+//   (relative error <= 2e-8 for a >= 1e-4).  FP32 sweeps evaluate the same FP64 series for |u| < 5 and
+//   the asymptotic series of w(z) in FP32 beyond.  Lines without damping use exp(-u^2)
+//   directly.  Both series have real coefficients and are summed with Goertzel's
+//   second-order recurrence rather than complex Horner steps.
 // * Linear short-characteristics coefficients (Kunasz & Auer 1988):
 //     e = exp(-x), Psi_o = 1 - (1-e)/x, Psi_u = (1-e)/x - e,
 //   with their Taylor series below a precision-dependent threshold.
@@ -31,21 +30,13 @@ constexpr double kPI = 3.14159265358979323846;
 constexpr double kSQRTPI = 1.77245385090551602730;
 constexpr double kINVSQRTPI = 0.56418958354775628695;
 
-constexpr int kVoigtNf = 16;
 constexpr int kVoigtNd = 32;
 
 // Weideman coefficients, highest power first; filled by the host at context creation.
-__constant__ float c_voigt_f[kVoigtNf];
 __constant__ double c_voigt_d[kVoigtNd];
-__constant__ float c_voigt_Lf;
 __constant__ double c_voigt_Ld;
 
 template <typename R> struct VoigtTraits;
-template <> struct VoigtTraits<float> {
-    static constexpr int N = kVoigtNf;
-    __device__ static float coef(int i) { return c_voigt_f[i]; }
-    __device__ static float L() { return c_voigt_Lf; }
-};
 template <> struct VoigtTraits<double> {
     static constexpr int N = kVoigtNd;
     __device__ static double coef(int i) { return c_voigt_d[i]; }
@@ -113,18 +104,23 @@ __device__ inline R voigt_H(R a, R u) {
     return fma(R(2), fma(pr, r2r, -pi * r2i), rr * R(kINVSQRTPI));
 }
 
-// Far wings, |u| >= 6: w(z) ~ (i/sqrt(pi)) z^-1 sum_n (2n-1)!!/2^n z^-2n (8 terms); the
-// Gaussian part exp(-z^2) is below 3e-16 there.  Relative error <= 5e-7 in FP32.  The
-// sum is a real polynomial in 1/z^2, evaluated with the same recurrence as above.
+// Wings, |u| >= 5, FP32: w(z) = exp(-z^2) + (2i/sqrt(pi)) F(z) with Dawson's F, whose
+// asymptotic series gives (i/sqrt(pi)) z^-1 sum_n (2n-1)!!/2^n z^-2n (10 terms).  Near
+// the real axis (a < |u|/2) the real part of exp(-z^2), exp(a^2 - u^2) cos(2au) <=
+// e^{-18.75}, is added; further from it that term is cancelled by the continuation of
+// F (Stokes phenomenon) and the series alone is w.  Relative error <= 5e-7 for
+// 1e-5 <= a <= 500.  The sum is a real polynomial in 1/z^2, evaluated with the same
+// recurrence as above.
 __device__ inline float voigt_H_wing(float a, float u) {
     const float rd = __builtin_amdgcn_rcpf(fmaf(u, u, a * a));
     const float rr = u * rd, ri = -a * rd;                       // 1/z
     const float r2r = fmaf(rr, rr, -ri * ri), r2i = 2.0f * rr * ri;  // 1/z^2
     const float r = 2.0f * r2r, sq = rd * rd;                    // 2 Re z^-2, |z^-2|^2
-    const float cf[8] = {1.0f, 0.5f, 0.75f, 1.875f, 6.5625f, 29.53125f, 162.421875f, 1055.7421875f};
-    float b1 = cf[7], b2 = 0.0f;
+    const float cf[10] = {1.0f, 0.5f, 0.75f, 1.875f, 6.5625f, 29.53125f, 162.421875f, 1055.7421875f,
+                          7918.06640625f, 67303.564453125f};
+    float b1 = cf[9], b2 = 0.0f;
 #pragma unroll
-    for (int n = 6; n >= 1; --n) {
+    for (int n = 8; n >= 1; --n) {
         const float b0 = fmaf(r, b1, fmaf(-sq, b2, cf[n]));
         b2 = b1;
         b1 = b0;
@@ -132,7 +128,8 @@ __device__ inline float voigt_H_wing(float a, float u) {
     const float sr = fmaf(r2r, b1, fmaf(-sq, b2, cf[0]));
     const float si = r2i * b1;
     const float ti = fmaf(rr, si, ri * sr);
-    return -ti * float(kINVSQRTPI);
+    const float gauss = (a < 0.5f * fabsf(u)) ? __expf(fmaf(a, a, -u * u)) * __cosf(2.0f * a * u) : 0.0f;
+    return fmaf(-ti, float(kINVSQRTPI), gauss);
 }
 
 // Profile shape: Gaussian for undamped lines, Voigt otherwise.
@@ -141,11 +138,15 @@ __device__ inline R profile_H(R a, R u, bool gauss) {
     if (gauss) return dev_exp_neg(u * u);
     return voigt_H<R>(a, u);
 }
+// FP32 sweeps: the Weideman series loses relative accuracy to cancellation in FP32
+// where H is small (|u| ~ 3-5, a << 1), so inside |u| < 5 it runs in FP64 with the FP64
+// coefficients (relative error ~2e-8 before the final rounding to FP32); the wings use
+// the FP32 asymptotic form.
 template <>
 __device__ inline float profile_H<float>(float a, float u, bool gauss) {
     if (gauss) return __expf(-u * u);
-    if (fabsf(u) >= 6.0f) return voigt_H_wing(a, u);
-    return voigt_H<float>(a, u);
+    if (fabsf(u) >= 5.0f) return voigt_H_wing(a, u);
+    return float(voigt_H<double>(double(a), double(u)));
 }
 
 // Linear short-characteristics segment coefficients; omp = 1 - Psi_o is returned

@@ -252,10 +252,14 @@ __device__ __host__ inline R tree_slots(const R* x, size_t stride, int nslot) {
 // One plane step of the short-characteristics formal solution for all 24 directions.
 // Step s: upward directions solve plane s from plane s-1, downward directions plane
 // nz-1-s from nz-s; s = 0 sets the boundary planes (I = B below, I = 0 or prescribed
-// above).  Block: DB waves, wave w = direction grp*DB + w over 64 consecutive plane
-// points; grid: (plane tiles of 64 points, lines, 24/DB direction groups).  Direction
-// and frequency are uniform across a wave, so the frequency tables are scalar loads
-// and every cell access is a scalar base plus a fixed 32-bit lane offset.
+// above).  Block: DB x FC waves; wave (c, w) takes direction grp*DB + w and the c-th of
+// FC contiguous chunks of the line's frequencies over 64 consecutive plane points.
+// Grid: (plane tiles of 64 points, lines, 24/DB direction groups), dealt to the XCDs
+// so that all tiles of a (line, direction group) share one L2.  Direction and frequency
+// are uniform across a wave, so the frequency tables are scalar loads and every cell
+// access is a scalar base plus a fixed 32-bit lane offset.  A wave sums its chunk in
+// frequency order; chunks are added in order, then directions by the fixed tree.  FC
+// changes the rounding of the frequency sum, so it is fixed by the level shape alone.
 template <typename R>
 struct SweepArgs {
     const AtomInfo* atom;
@@ -276,24 +280,33 @@ struct SweepArgs {
     int add;             // 1: add this pass's sums to acc; 0: overwrite
 };
 
+constexpr int kMaxSweepWaves = 12;
+
 template <typename R, int DB>
-__global__ __launch_bounds__(DB * 64) void sweep_step_kernel(SweepArgs<R> a, int s) {
+__global__ __launch_bounds__((sizeof(R) == 4 ? kMaxSweepWaves : DB) * 64) void sweep_step_kernel(SweepArgs<R> a,
+                                                                                                   int s) {
     static_assert(DB == 3 || DB == 6 || DB == 12, "direction groups follow the fixed tree");
     constexpr int kW = 64;
     const int lane = int(threadIdx.x) & (kW - 1);
-    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kW);
-    const int grp = blockIdx.z;
+    const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kW);
+    const int FC = int(blockDim.x) / (kW * DB);
+    const int w = wv % DB, c = wv / DB;
+    // XCD-aware order: the dispatcher deals consecutive blocks round-robin to the 8 XCDs;
+    // when the block count divides by 8, XCD x takes the x-th contiguous eighth of the
+    // (tile, line, group) work list, so the tiles that read each other's upwind rows
+    // (same line and directions) share an L2.
+    const unsigned T = gridDim.x;
+    const unsigned nb = T * gridDim.y * gridDim.z;
+    const unsigned lin = blockIdx.x + T * (blockIdx.y + gridDim.y * blockIdx.z);
+    const unsigned work = (nb % 8u == 0u) ? (lin % 8u) * (nb / 8u) + lin / 8u : lin;
+    const unsigned bx = work % T;
+    const int l = int((work / T) % gridDim.y);
+    const int grp = int(work / (T * gridDim.y));
     const int d = grp * DB + w;
     const int h = (grp * DB) / kNHemi;
-    const int l = blockIdx.y;
     const AtomInfo& at = *a.atom;
     const LineInfo& ln = at.line[l];
     const int L = at.nline;
-    // XCD-aware tile order: the dispatcher deals consecutive blocks round-robin to the
-    // 8 XCDs, so when the tile count divides by 8, tile t of XCD x is tile x*(T/8) + t.
-    // Neighbouring tiles, which read each other's upwind rows, then share an L2.
-    const unsigned T = gridDim.x;
-    const unsigned bx = (T % 8u == 0u) ? (blockIdx.x % 8u) * (T / 8u) + blockIdx.x / 8u : blockIdx.x;
     const unsigned nxy = a.nxy;
     const unsigned graw = bx * kW + unsigned(lane);
     const bool valid = graw < nxy;
@@ -304,6 +317,8 @@ __global__ __launch_bounds__(DB * 64) void sweep_step_kernel(SweepArgs<R> a, int
     const size_t dstride = size_t(L) * a.Q * nxy;            // one direction's planes in this pass
     const size_t slot_stride = size_t(kNDir) * dstride;
     const int mend = min(ln.nfreq, a.m0 + a.Q);
+    const int clen = (mend - a.m0 + FC - 1) / FC;
+    const int mb = min(mend, a.m0 + c * clen), me = min(mend, mb + clen);   // this wave's chunk
     const double mux = c_mu[3 * d], muy = c_mu[3 * d + 1], muz = c_mu[3 * d + 2];
     const R chic = a.sc[(SC_CHIC * L + l) * nv + v];
     const R etac = a.sc[(SC_ETAC * L + l) * nv + v];
@@ -328,7 +343,7 @@ __global__ __launch_bounds__(DB * 64) void sweep_step_kernel(SweepArgs<R> a, int
     if (s == 0) {
         const R Bb = a.sc[(SC_B * L + l) * nv + v];
         const R* top = a.topI ? a.topI + size_t(ln.fstart) * nxy + g : nullptr;
-        for (int m = a.m0; m < mend; ++m) {
+        for (int m = mb; m < me; ++m) {
             const R u = qf[m] * ivD - vn;
             const R H = profile_H<R>(adamp, u, gauss);
             const R phi = H * pn;
@@ -360,7 +375,7 @@ __global__ __launch_bounds__(DB * 64) void sweep_step_kernel(SweepArgs<R> a, int
         const R w10 = (R(1) - fx) * fy, w11 = fx * fy;
         const R rds = R(ds);
         const auto rprv = cell_rsrc(a.state + size_t((s - 1) & 1) * slot_stride + col, colb);
-        for (int m = a.m0; m < mend; ++m) {
+        for (int m = mb; m < me; ++m) {
             const unsigned so = unsigned(m - a.m0) * rowb;
             const Cell<R> c00 = cell_get<R>(rprv, o00, so), c01 = cell_get<R>(rprv, o01, so);
             const Cell<R> c10 = cell_get<R>(rprv, o10, so), c11 = cell_get<R>(rprv, o11, so);
@@ -388,18 +403,29 @@ __global__ __launch_bounds__(DB * 64) void sweep_step_kernel(SweepArgs<R> a, int
             lacc = fma(wphi, fma(por, chic, omp), lacc);
         }
     }
-    __shared__ R sj[DB * kW];
-    __shared__ R sl[DB * kW];
+    __shared__ R sj[kMaxSweepWaves * kW];
+    __shared__ R sl[kMaxSweepWaves * kW];
     sj[threadIdx.x] = jacc;
     sl[threadIdx.x] = lacc;
     __syncthreads();
     if (int(threadIdx.x) < kW && valid) {
+        // frequency chunks in order, per direction
+        R dj[DB], dl[DB];
+#pragma unroll
+        for (int q = 0; q < DB; ++q) {
+            dj[q] = sj[q * kW + lane];
+            dl[q] = sl[q * kW + lane];
+            for (int cc = 1; cc < FC; ++cc) {
+                dj[q] += sj[(cc * DB + q) * kW + lane];
+                dl[q] += sl[(cc * DB + q) * kW + lane];
+            }
+        }
         // groups of three directions, then pairs of groups (the fixed tree)
         R gj[DB / 3], gl[DB / 3];
 #pragma unroll
         for (int q = 0; q < DB / 3; ++q) {
-            gj[q] = (sj[(3 * q) * kW + lane] + sj[(3 * q + 1) * kW + lane]) + sj[(3 * q + 2) * kW + lane];
-            gl[q] = (sl[(3 * q) * kW + lane] + sl[(3 * q + 1) * kW + lane]) + sl[(3 * q + 2) * kW + lane];
+            gj[q] = (dj[3 * q] + dj[3 * q + 1]) + dj[3 * q + 2];
+            gl[q] = (dl[3 * q] + dl[3 * q + 1]) + dl[3 * q + 2];
         }
         R jt, lt;
         if constexpr (DB == 3) {

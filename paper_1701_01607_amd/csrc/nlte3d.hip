@@ -27,6 +27,8 @@
 #include "../../include/nlte3d.h"
 #include "kernels.h"
 
+#include <cstdarg>
+
 using namespace nlte;
 
 namespace {
@@ -75,6 +77,22 @@ struct nlte_ctx {
 };
 
 namespace {
+
+// Progress lines on stderr when NLTE3D_LOG is set (long solves: one line per finest-level
+// smoothing pass and per cycle, printed after the work has finished on the device).
+bool log_enabled() {
+    static const bool on = std::getenv("NLTE3D_LOG") != nullptr;
+    return on;
+}
+void log_line(const char* fmt, ...) {
+    std::va_list ap;
+    va_start(ap, fmt);
+    std::fprintf(stderr, "[nlte3d] ");
+    std::vfprintf(stderr, fmt, ap);
+    std::fprintf(stderr, "\n");
+    std::fflush(stderr);
+    va_end(ap);
+}
 
 // Device buffer accounted against the context budget.
 struct DevBuf {
@@ -153,15 +171,8 @@ void upload_constants() {
     std::vector<double> cd;
     double Ld;
     weideman_coefficients(kVoigtNd, cd, Ld);
-    std::vector<double> cf64;
-    double Lf;
-    weideman_coefficients(kVoigtNf, cf64, Lf);
-    std::vector<float> cf(cf64.begin(), cf64.end());
-    float Lff = float(Lf);
     HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_voigt_d), cd.data(), sizeof(double) * kVoigtNd));
-    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_voigt_f), cf.data(), sizeof(float) * kVoigtNf));
     HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_voigt_Ld), &Ld, sizeof(double)));
-    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_voigt_Lf), &Lff, sizeof(float)));
     double mu[kNDir * 3];
     a4_set(mu);
     HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_mu), mu, sizeof(mu)));
@@ -227,7 +238,16 @@ struct Level {
     bool fs_valid = false;
     long long fs_count = 0;
     int nslot = 2;   // direction-group slots in acc written by the last formal solution
+    int fc = 1;      // frequency chunks per (direction, tile): fixed by the level shape
+    int maxslot = 8; // direction-group slots allocated in acc (8 allows every block shape)
 };
+
+// Accumulator slots for a level: every block shape (down to 3 directions, 8 slots) on
+// levels whose 8-slot accumulators stay under 4 GiB; larger levels keep 2 slots and
+// sweep with 12-direction blocks.
+inline int acc_slots(size_t nvox, int nline, size_t rbytes) {
+    return double(2 * kMaxSlots) * nline * double(nvox) * double(rbytes) <= 4294967296.0 ? kMaxSlots : 2;
+}
 
 template <typename R>
 struct Job : JobBase {
@@ -236,6 +256,7 @@ struct Job : JobBase {
     DevBuf atom_d, qf, wf, line_of_d, state, topI, scalar, repairs, estate, eout, flag, nprev;
     AtomInfo info{};
     int DB = 0;   // directions per sweep block (0: autotuned per level)
+    int fine_db = 0;   // block shape of the last finest-level formal solution
     std::vector<double> hz_top;
     double updates_per_fs_fine = 0;
     double cost_units = 0;
@@ -370,7 +391,8 @@ struct Job : JobBase {
             dalloc(L.f, sizeof(double) * N * L.nvox);
             dalloc(L.nb, sizeof(double) * N * L.nvox);
             dalloc(L.tmp, sizeof(double) * N * L.nvox);
-            dalloc(L.acc, sizeof(R) * 2 * kMaxSlots * nline * L.nvox);
+            L.maxslot = acc_slots(L.nvox, nline, sizeof(R));
+            dalloc(L.acc, sizeof(R) * 2 * L.maxslot * nline * L.nvox);
             dalloc(L.lc, sizeof(R) * 2 * nline * L.nvox);
             dalloc(L.partial, sizeof(double) * std::max<size_t>(blocks_for(L.nvox, 256), 1024));
             SetupArgs<R> sa;
@@ -429,6 +451,7 @@ struct Job : JobBase {
             zero_radiation(k0);
         }
         HIPCHK(hipStreamSynchronize(st()));
+        for (auto& Lp : lev) Lp->fc = freq_chunks(*Lp);
         choose_tile();
         ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
     }
@@ -450,11 +473,23 @@ struct Job : JobBase {
         return dim3(blocks_for(L.nxy, 64), nline, kNDir / db);
     }
 
-    void launch_step(const SweepArgs<R>& a, dim3 grid, int db, int s) {
+    // Frequency chunks per (direction, tile) wave group: small planes give too few waves
+    // to fill the GPU with one wave per (direction, tile, line), so their frequencies
+    // are split over 2 or 4 waves.  FP32 only (the FP64 kernel's registers allow one).
+    int freq_chunks(const Level& L) const {
+        if (sizeof(R) != 4) return 1;
+        const double waves = double(blocks_for(L.nxy, 64)) * nline * kNDir;
+        int fc = 1;
+        while (fc < 4 && waves * fc < 4096.0) fc *= 2;
+        return fc;
+    }
+
+    void launch_step(const SweepArgs<R>& a, dim3 grid, int db, int fc, int s) {
+        const unsigned threads = unsigned(db * fc * 64);
         switch (db) {
-            case 12: sweep_step_kernel<R, 12><<<grid, 12 * 64, 0, st()>>>(a, s); break;
-            case 6: sweep_step_kernel<R, 6><<<grid, 6 * 64, 0, st()>>>(a, s); break;
-            default: sweep_step_kernel<R, 3><<<grid, 3 * 64, 0, st()>>>(a, s); break;
+            case 12: sweep_step_kernel<R, 12><<<grid, threads, 0, st()>>>(a, s); break;
+            case 6: sweep_step_kernel<R, 6><<<grid, threads, 0, st()>>>(a, s); break;
+            default: sweep_step_kernel<R, 3><<<grid, threads, 0, st()>>>(a, s); break;
         }
     }
 
@@ -474,19 +509,30 @@ struct Job : JobBase {
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        int best = 12;
+        // three rounds, candidate order rotated each round, plane steps 1..6 timed
+        float total[3] = {0.f, 0.f, 0.f};
+        const int steps = std::min(L.nz, 7);
+        for (int round = 0; round < 3; ++round) {
+            for (int q = 0; q < 3; ++q) {
+                const int i = (q + round) % 3;
+                const int c = cand[i];
+                if (c * L.fc > kMaxSweepWaves || kNDir / c > L.maxslot) continue;
+                const dim3 grid = sweep_grid(L, nline, c);
+                launch_step(a, grid, c, L.fc, 0);
+                HIPCHK(hipEventRecord(e0, st()));
+                for (int s = 1; s < steps; ++s) launch_step(a, grid, c, L.fc, s);
+                HIPCHK(hipEventRecord(e1, st()));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                total[i] += ms;
+            }
+        }
+        int best = L.maxslot >= kMaxSlots ? 3 : 12;
         float best_ms = 1e30f;
-        const int steps = std::min(L.nz, 4);
-        for (int c : cand) {
-            const dim3 grid = sweep_grid(L, nline, c);
-            launch_step(a, grid, c, 0);
-            HIPCHK(hipEventRecord(e0, st()));
-            for (int s = 1; s < steps; ++s) launch_step(a, grid, c, s);
-            HIPCHK(hipEventRecord(e1, st()));
-            HIPCHK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best_ms) { best_ms = ms; best = c; }
+        for (int i = 0; i < 3; ++i) {
+            if (cand[i] * L.fc > kMaxSweepWaves || kNDir / cand[i] > L.maxslot) continue;
+            if (total[i] < best_ms) { best_ms = total[i]; best = cand[i]; }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -498,7 +544,7 @@ struct Job : JobBase {
     }
 
     int tile_for(int k, SweepArgs<R>& a) {
-        if (DB) return DB;
+        if (DB && DB * lev[k]->fc <= kMaxSweepWaves && kNDir / DB <= lev[k]->maxslot) return DB;
         if (level_tile.size() != size_t(nlev)) level_tile.assign(nlev, 0);
         if (!level_tile[k]) {
             a.m0 = 0;
@@ -563,13 +609,14 @@ struct Job : JobBase {
         a.state = state.as<Cell<R>>();
         a.acc = L.acc.as<R>();
         const int db = tile_for(k, a);
+        if (k == nlev - 1) fine_db = db;
         const dim3 grid = sweep_grid(L, nline, db);
         ev_begin(EV_SWEEP);
         for (int m0 = 0; m0 < maxfreq; m0 += Qpass) {
             a.m0 = m0;
             a.Q = Qpass;
             a.add = m0 > 0 ? 1 : 0;
-            for (int s = 0; s < L.nz; ++s) launch_step(a, grid, db, s);
+            for (int s = 0; s < L.nz; ++s) launch_step(a, grid, db, L.fc, s);
             sweep_launches += L.nz;
         }
         HIPCHK(hipGetLastError());
@@ -596,6 +643,10 @@ struct Job : JobBase {
             if (!(it == 0 && L.fs_valid)) formal_solution(k);
             rate_launch(k, 0, nullptr, nullptr, 0.0, true);
             L.fs_valid = false;
+        }
+        if (log_enabled() && !capturing && k == nlev - 1 && iters > 0) {
+            HIPCHK(hipStreamSynchronize(st()));
+            log_line("level %d (%dx%dx%d): %d MALI iterations done", k, L.nx, L.ny, L.nz, iters);
         }
     }
 
@@ -716,9 +767,12 @@ struct Job : JobBase {
         sweep_launches += graph_launches;
     }
 
+    // Stop rule (Eq. 20): E = rho/(1-rho) C, rho = C_i/C_{i-1}, valid in the asymptotic
+    // linear regime; the first correction (from the initial populations) is excluded, so
+    // rho needs the second and a later correction.
     bool stop(double& rho, double& E) {
         const double C = history.back();
-        rho = history.size() >= 2 ? C / history[history.size() - 2] : INFINITY;
+        rho = history.size() >= 3 ? C / history[history.size() - 2] : INFINITY;
         E = (rho < 1.0) ? rho / (1.0 - rho) * C : INFINITY;
         if (params.tol_C > 0 && C <= params.tol_C) return true;
         if (params.E_target > 0 && rho < 1.0 && E <= params.E_target) return true;
@@ -785,7 +839,9 @@ struct Job : JobBase {
                     }
                     throw Error(NLTE_E_DIVERGED, "non-finite cycle correction");
                 }
-                if (stop(rho, E)) { status = NLTE_OK; break; }
+                const bool done = stop(rho, E);
+                if (log_enabled()) log_line("cycle %d: C = %.3e  rho = %.3e  E = %.3e", cycles, history.back(), rho, E);
+                if (done) { status = NLTE_OK; break; }
             }
         }
         check_finite(top);
@@ -811,7 +867,7 @@ struct Job : JobBase {
         r.ms_rates = ms_phase[EV_RATES];
         r.ms_transfer = ms_phase[EV_TRANSFER];
         r.sweep_launches = sweep_launches;
-        r.dirs_per_block = level_tile.size() == size_t(nlev) && !DB ? level_tile[nlev - 1] : DB;
+        r.dirs_per_block = fine_db;
         res = r;
         if (out) *out = r;
     }
@@ -962,7 +1018,7 @@ size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom
     for (int k = nlev - 1; k >= 0; --k) {
         const size_t nvox = size_t(nx) * ny * nz;
         bytes += 8 * size_t(nz) + 8 * size_t(nprim) * nvox + R * (6 * nline + 4) * nvox;
-        bytes += 8 * (size_t(N) * 6 + size_t(N) * N + 1) * nvox + R * (2 * kMaxSlots + 2) * nline * nvox;
+        bytes += 8 * (size_t(N) * 6 + size_t(N) * N + 1) * nvox + R * (2 * acc_slots(nvox, nline, R) + 2) * nline * nvox;
         bytes += 8 * std::max<size_t>((nvox + 255) / 256, 1024);
         nx /= 2; ny /= 2; nz = (nz - 1) / 2 + 1;
     }

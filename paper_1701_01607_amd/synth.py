@@ -150,27 +150,19 @@ def gaussian_random_field(rng, nx, ny, nz, corr_xy, corr_z):
     """Unit-variance Gaussian random field, periodic in x and y.
 
     White noise is filtered with a Gaussian spectrum of correlation length
-    ``corr_xy`` cells horizontally (FFT, hence periodic) and ``corr_z`` cells
-    vertically (direct Gaussian smoothing with reflecting ends).
+    ``corr_xy`` cells horizontally (FFT, hence periodic) and smoothed with a Gaussian of
+    ``corr_z`` cells vertically (truncated at 3 sigma, mirrored ends).
     """
+    from scipy.ndimage import gaussian_filter1d
+
     noise = rng.standard_normal((nz, ny, nx))
-    kx = np.fft.fftfreq(nx)[None, :]
+    kx = np.fft.rfftfreq(nx)[None, :]
     ky = np.fft.fftfreq(ny)[:, None]
     filt = np.exp(-2.0 * (np.pi * corr_xy) ** 2 * (kx ** 2 + ky ** 2))
-    out = np.empty_like(noise)
-    for k in range(nz):
-        out[k] = np.fft.irfft2(np.fft.rfft2(noise[k]) * filt[:, : nx // 2 + 1], s=(ny, nx))
+    out = np.fft.irfft2(np.fft.rfft2(noise, axes=(-2, -1)) * filt[None], s=(ny, nx), axes=(-2, -1))
+    del noise
     if corr_z > 0 and nz > 1:
-        half = int(np.ceil(3 * corr_z))
-        t = np.arange(-half, half + 1)
-        ker = np.exp(-0.5 * (t / corr_z) ** 2)
-        ker /= ker.sum()
-        pad = np.concatenate([out[half:0:-1], out, out[-2:-half - 2:-1]], axis=0) if half < nz else out
-        if half < nz:
-            sm = np.zeros_like(out)
-            for i, c in enumerate(ker):
-                sm += c * pad[i:i + nz]
-            out = sm
+        out = gaussian_filter1d(out, corr_z, axis=0, mode="mirror", truncate=3.0)
     sd = out.std()
     return out / sd if sd > 0 else out
 

@@ -261,18 +261,57 @@ def test_undamped_line_far_wings_stay_finite(nl, ctx, prec, tol):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_block_shape_does_not_change_results(nl, ctx, prec):
+@pytest.mark.parametrize("nx,ny,shapes_", [(48, 48, (3, 6, 12)), (48, 24, (3, 6))])
+def test_block_shape_does_not_change_results(nl, ctx, prec, nx, ny, shapes_):
     """Directions are summed by one fixed tree whatever the sweep block shape, so formal
-    solutions and solves are bitwise equal for 3, 6 and 12 directions per block."""
-    atom, atm = ragged_case(nfreq=9, seed=23)
+    solutions and solves are bitwise equal for 3, 6 and 12 directions per block.  The
+    48x48 plane runs one frequency chunk per wave, the 48x24 plane two (FP32)."""
+    atom = synth.caii_like_atom(9)
+    atm = synth.atmos_stratified(nx=nx, ny=ny, nz=9, dx=120 * synth.KM, seed=23)
     npop, nln = shapes(atom, atm)
     A, M = ctx.atmos(atm), ctx.atom(atom)
     outs = []
-    for dpb in (3, 6, 12):
-        job = ctx.job(A, M, nl.SolveParams(method=nl.MALI, precision=prec, nlev=1, dirs_per_block=dpb))
+    for dpb in shapes_:
+        job = ctx.job(A, M, nl.SolveParams(method=nl.MALI, precision=prec, nlev=1, dirs_per_block=dpb, timing=1))
         jg, og = job.formal_solution(0, nln)
         job.mali(0, 3)
         outs.append((jg, og, job.populations(0, npop)))
     for o in outs[1:]:
         for x, y in zip(outs[0], o):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
+def test_formal_solution_parity_one_chunk_per_wave(nl, ctx, prec, tol):
+    """A plane large enough for one frequency chunk per wave (the layout of the bench's
+    finest grid), against the oracle."""
+    atom = synth.caii_like_atom(9)
+    atm = synth.atmos_stratified(nx=48, ny=48, nz=9, dx=120 * synth.KM, seed=29)
+    lev = Level(atom, atm)
+    n0 = zero_radiation(lev)
+    npop, nln = shapes(atom, atm)
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1))
+    jg, og = job.formal_solution(0, nln)
+    jo, oo = formal_solution(lev, n0)
+    ej, eo = relerr(jg, jo), relerr(og, oo)
+    print(f"prec={prec} Jeff err {ej:.2e}  1-L* err {eo:.2e}")
+    assert ej < tol and eo < tol
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
+def test_strongly_damped_line_parity(nl, ctx, prec, tol):
+    """Damping well above the Doppler width (a ~ 40), so that the profile wings beyond
+    |u| = 5 lie far off the real axis of the Faddeeva function."""
+    atom = synth.two_level_atom(1e-2, q_max=16 * synth.KM, nfreq=33)
+    atom["lines"][0]["gamma_rad"] = 1e12
+    atm = synth.atmos_isothermal(nx=8, ny=6, nz=10)
+    lev = Level(atom, atm)
+    n0 = zero_radiation(lev)
+    npop, nln = shapes(atom, atm)
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1))
+    jg, og = job.formal_solution(0, nln)
+    jo, oo = formal_solution(lev, n0)
+    assert np.isfinite(jg).all() and np.isfinite(og).all()
+    ej, eo = relerr(jg, jo), relerr(og, oo)
+    print(f"prec={prec} Jeff err {ej:.2e}  1-L* err {eo:.2e}")
+    assert ej < tol and eo < tol
