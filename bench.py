@@ -22,19 +22,20 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (published)
 PEAK_HBM_GBS = 8000.0           # MI355X HBM3E (published)
+PEAK_FP64_TFLOPS = 78.6         # MI355X vector FP64 (published)
 
 # Algorithmic HBM bytes per voxel-direction-frequency update of the sweep.  The plane
 # state (I, S, chi per direction, frequency and plane point, 12 B in FP32) lives in HBM
 # between plane steps: each cell is written once and read back once by the next step
 # (its four upwind readers share it through L2).  Per (voxel, line, direction group)
 # the block also reads 11 per-voxel constants and writes 2 partial sums.
-STATE_BYTES_PER_UPDATE = 24.0
-# HBM bytes per sweep launch from FETCH_SIZE + WRITE_SIZE counter runs of
-# `bench.py --kernel-probe`, each scaled by the counter's reading for a plain device
-# copy of known size; keyed by (workload, directions per block).  None until counters
-# are taken for the current kernel.
-MEASURED_BYTES_PER_LAUNCH = {}
-VOXEL_BYTES_PER_GROUP = (11 + 2) * 4.0
+STATE_BYTES_PER_UPDATE = 24.0        # FP32 cells; FP64 cells are twice that
+# HBM bytes per update of the finest-grid sweep launches from FETCH_SIZE + WRITE_SIZE
+# counter runs of `bench.py --kernel-probe` (each scaled by the counter's reading for a
+# plain device copy of known size), keyed by (workload, directions per block).  Only for
+# the kernel as it was when the counters were taken.
+MEASURED_BYTES_PER_UPDATE = {("caii6_64x64x129", 3): 25.23}
+VOXEL_BYTES_PER_GROUP = (11 + 2) * 4.0   # FP32; twice that in FP64
 
 # FP32 flops per update (FMA = 2) for the ALU side of the roofline: profile argument
 # 2, opacity/source function 7, three bilinear interpolations 21, optical depth 3,
@@ -44,10 +45,15 @@ FLOPS_PER_UPDATE_BASE = 57
 FLOPS_VOIGT_CORE, FLOPS_VOIGT_WING, FLOPS_GAUSS = 88, 46, 3
 
 WORKLOADS = {
-    "caii6_64x64x129": dict(nlev=3, nu0=20, nu1=4, nu2=8, nu3=32, nu_fmg=16, method="FAS"),
-    "caii6_256x256x257": dict(nlev=4, nu0=20, nu1=4, nu2=8, nu3=32, nu_fmg=16, method="FMG"),
-    "caii6_504x504x497": dict(nlev=4, nu0=20, nu1=4, nu2=8, nu3=32, nu_fmg=16, method="FMG"),
-    "two_level_16x16x32": dict(nlev=1, nu0=0, nu1=2, nu2=2, nu3=32, nu_fmg=16, method="MALI"),
+    "caii6_64x64x129": dict(nlev=3, nu0=20, nu1=4, nu2=8, nu3=32, nu_fmg=16, method="FAS", fp64=False,
+                            E_target=1e-3, tol_C=0.0),
+    "caii6_256x256x257": dict(nlev=4, nu0=20, nu1=4, nu2=8, nu3=32, nu_fmg=16, method="FMG", fp64=False,
+                              E_target=1e-3, tol_C=0.0),
+    "caii6_504x504x497": dict(nlev=4, nu0=20, nu1=4, nu2=8, nu3=32, nu_fmg=16, method="FMG", fp64=False,
+                              E_target=1e-3, tol_C=0.0),
+    # plain FP64 MALI to a maximum relative correction of 1e-4
+    "two_level_16x16x32": dict(nlev=1, nu0=0, nu1=2, nu2=2, nu3=32, nu_fmg=16, method="MALI", fp64=True,
+                               E_target=0.0, tol_C=1e-4),
 }
 
 
@@ -168,9 +174,10 @@ def main():
     A = ctx.atom(atom)
     M = ctx.atmos(atm)              # resident on the device before the timed region
     method = {"FAS": nlte.FAS, "FMG": nlte.FMG, "MALI": nlte.MALI}[wl["method"]]
-    params = nlte.SolveParams(method=method, precision=nlte.MIXED, nlev=wl["nlev"], nu0=wl["nu0"],
-                              nu1=wl["nu1"], nu2=wl["nu2"], nu3=wl["nu3"], nu_fmg=wl["nu_fmg"],
-                              E_target=1e-3, max_iter=60, timing=0 if args.graph else 1,
+    params = nlte.SolveParams(method=method, precision=nlte.FP64 if wl["fp64"] else nlte.MIXED, nlev=wl["nlev"],
+                              nu0=wl["nu0"], nu1=wl["nu1"], nu2=wl["nu2"], nu3=wl["nu3"], nu_fmg=wl["nu_fmg"],
+                              E_target=wl["E_target"], tol_C=wl["tol_C"], max_iter=60 if method != nlte.MALI else 2000,
+                              timing=0 if args.graph else 1,
                               dirs_per_block=args.dirs_per_block,
                               graph=args.graph)
     nf = sum(len(l["q"]) for l in atom["lines"])
@@ -222,13 +229,15 @@ def main():
     fl, core_frac = flops_per_update(atom, atm)
     nslot = 24 // r.dirs_per_block if r.dirs_per_block else 8
     nfl = nf / len(atom["lines"])
-    bytes_upd = STATE_BYTES_PER_UPDATE + VOXEL_BYTES_PER_GROUP * nslot / (24.0 * nfl)
-    measured = MEASURED_BYTES_PER_LAUNCH.get((args.workload, r.dirs_per_block))
+    wbytes = 2.0 if wl["fp64"] else 1.0
+    bytes_upd = wbytes * (STATE_BYTES_PER_UPDATE + VOXEL_BYTES_PER_GROUP * nslot / (24.0 * nfl))
+    peak_alu = PEAK_FP64_TFLOPS if wl["fp64"] else PEAK_FP32_TFLOPS
+    measured = MEASURED_BYTES_PER_UPDATE.get((args.workload, r.dirs_per_block))
     traffic = None
     if sweep_ms > 0:
         avg_launch_us = 1e3 * sweep_ms / launches
         if measured:
-            traffic = measured / (avg_launch_us * 1e-6) / 1e9
+            traffic = upd * measured / launches / (avg_launch_us * 1e-6) / 1e9
         achieved = upd * bytes_upd / launches / (avg_launch_us * 1e-6) / 1e9
         achieved_alu = upd * fl / launches / (avg_launch_us * 1e-6) / 1e12
         ups_sweep = upd / (sweep_ms * 1e-3)
@@ -242,11 +251,12 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 sweep / f64 rates",
+        "dtype": "f64" if wl["fp64"] else "f32 sweep / f64 rates",
         "data": "synthetic (seeded)",
         "config": {"workload": args.workload, "grid": [atm["nx"], atm["ny"], atm["nz"]], "lines": len(atom["lines"]),
                    "frequencies": nf, "directions": 24, "method": wl["method"], "levels": wl["nlev"],
-                   "nu": [wl["nu_fmg"], wl["nu0"], wl["nu1"], wl["nu2"], wl["nu3"]], "E_target": 1e-3},
+                   "nu": [wl["nu_fmg"], wl["nu0"], wl["nu1"], wl["nu2"], wl["nu3"]],
+                   "E_target": wl["E_target"] or None, "tol_C": wl["tol_C"] or None},
         "converged": converged,
         "updates_per_s": ups_sweep,
         "updates_per_s_wall": upd / elapsed,
@@ -255,14 +265,15 @@ def main():
                      "total": r.ms_total},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS if achieved else None, "traffic": traffic,
-                     "kernel": f"sweep_step_kernel<float,{r.dirs_per_block}>", "avg_launch_us": avg_launch_us,
+                     "kernel": f"sweep_step_kernel<{'double' if wl['fp64'] else 'float'},{r.dirs_per_block}>",
+                     "avg_launch_us": avg_launch_us,
                      "bytes_per_update": bytes_upd, "launches": launches,
-                     "alu": {"achieved": achieved_alu, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                             "frac": achieved_alu / PEAK_FP32_TFLOPS if achieved_alu else None,
+                     "alu": {"achieved": achieved_alu, "peak": peak_alu, "unit": "TFLOP/s",
+                             "frac": achieved_alu / peak_alu if achieved_alu else None,
                              "flops_per_update": fl, "voigt_core_fraction": core_frac}},
     }
 
-    if not args.no_mali:
+    if not args.no_mali and not wl["fp64"]:
         mp = nlte.SolveParams(method=nlte.MALI, precision=nlte.FP64, nlev=1, E_target=1e-3,
                               max_iter=args.mali_max_iter, timing=1,
                               dirs_per_block=args.dirs_per_block)

@@ -89,13 +89,32 @@ def run_stream(ctx, requests, rate_hz, seed=1607005, max_running=4, log=None):
     return recs
 
 
+def busy_fraction(recs, t0, t1):
+    """Fraction of [t0, t1] during which at least one solve was running on the device."""
+    iv = sorted((r["t_submit"] + r["queue_s"], r["t_done"]) for r in recs)
+    busy, cur_a, cur_b = 0.0, None, None
+    for a, b in iv:
+        if cur_b is None or a > cur_b:
+            if cur_b is not None:
+                busy += cur_b - cur_a
+            cur_a, cur_b = a, b
+        else:
+            cur_b = max(cur_b, b)
+    if cur_b is not None:
+        busy += cur_b - cur_a
+    return busy / (t1 - t0) if t1 > t0 else 0.0
+
+
 def summarize(recs):
     lat = np.array([r["latency_s"] for r in recs])
-    span = max(r["t_done"] for r in recs) - min(r["t_submit"] for r in recs)
+    t0 = min(r["t_submit"] for r in recs)
+    t1 = max(r["t_done"] for r in recs)
+    span = t1 - t0
     return {"requests": len(recs), "converged": int(sum(r["status"] == 0 for r in recs)),
             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
             "atmospheres_per_hr": 3600.0 * len(recs) / span, "makespan_s": span,
-            "mean_queue_s": float(np.mean([r["queue_s"] for r in recs]))}
+            "mean_queue_s": float(np.mean([r["queue_s"] for r in recs])),
+            "device_busy_fraction": busy_fraction(recs, t0, t1)}
 
 
 def main():

@@ -155,3 +155,30 @@ def test_lambda_star_is_the_diagonal_of_the_brute_force_operator():
     assert np.allclose(diag, 1.0 - omL[0].reshape(-1), rtol=1e-11, atol=1e-15)
     # and the operator is non-negative with row sums below one
     assert Lam.min() >= -1e-15
+
+
+def test_source_function_is_continuous_where_the_opacity_vanishes():
+    """Where the total opacity is zero the source function takes its limit as the
+    profile goes to zero: eta_c/chi_c with a background, else the line's e/k, else 0.
+    The value at phi = 0 must equal the value an infinitesimal phi away."""
+    from oracle.formal import source_function
+    tiny = 1e-300
+    cases = [  # chi_c, eta_c, k, e
+        (2.0, 3.0, 5.0, 7.0),     # background and line
+        (0.0, 0.0, 5.0, 7.0),     # line only: S = e/k at any phi > 0
+        (2.0, 3.0, 0.0, 0.0),     # background only
+        (0.0, 0.0, 0.0, 0.0),     # nothing: S = 0
+    ]
+    for chi_c, eta_c, k, e in cases:
+        chi_c, eta_c, k, e = (np.array([x]) for x in (chi_c, eta_c, k, e))
+        at0 = source_function(chi_c + k * 0.0, chi_c, eta_c, k, e, np.array([0.0]))
+        near = source_function(chi_c + k * tiny, chi_c, eta_c, k, e, np.array([tiny]))
+        if chi_c[0] + k[0] > 0.0:
+            np.testing.assert_allclose(at0, near, rtol=1e-12)
+        else:
+            assert at0[0] == 0.0
+    # away from the limit it is the plain ratio (eta_c + e phi)/(chi_c + k phi)
+    phi = np.array([0.3])
+    s = source_function(np.array([2.0 + 5.0 * 0.3]), np.array([2.0]), np.array([3.0]), np.array([5.0]),
+                        np.array([7.0]), phi)
+    np.testing.assert_allclose(s, (3.0 + 7.0 * 0.3) / (2.0 + 5.0 * 0.3), rtol=1e-15)

@@ -1,0 +1,35 @@
+"""Host-side logic of the serving driver (no GPU)."""
+import importlib.util
+import os
+import sys
+
+import numpy as np
+import pytest
+
+
+def _serve():
+    if importlib.util.find_spec("torch") is None:
+        pytest.skip("torch not importable")
+    from paper_1701_01607_amd import serve
+    return serve
+
+
+def rec(sub, queue, done, status=0):
+    return {"t_submit": sub, "queue_s": queue, "t_done": done, "latency_s": done - sub, "status": status}
+
+
+def test_busy_fraction_merges_overlapping_solves():
+    serve = _serve()
+    recs = [rec(0.0, 0.0, 2.0), rec(1.0, 0.0, 3.0), rec(5.0, 1.0, 8.0)]
+    # running intervals [0,2] u [1,3] u [6,8] = 3 + 2 = 5 of [0, 8]
+    assert serve.busy_fraction(recs, 0.0, 8.0) == pytest.approx(5.0 / 8.0)
+
+
+def test_summary_percentiles_and_rate():
+    serve = _serve()
+    recs = [rec(float(i), 0.0, float(i) + 1.0 + (i % 3)) for i in range(10)]
+    out = serve.summarize(recs)
+    lat = np.array([1.0 + (i % 3) for i in range(10)])
+    assert out["p50_s"] == pytest.approx(np.percentile(lat, 50))
+    assert out["converged"] == 10
+    assert out["atmospheres_per_hr"] == pytest.approx(3600.0 * 10 / (max(r["t_done"] for r in recs)))
