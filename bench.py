@@ -273,6 +273,19 @@ def main():
                              "flops_per_update": fl, "voigt_core_fraction": core_frac}},
     }
 
+    # this box's achievable HBM bandwidth for context: a 2 GiB device-to-device copy
+    src = torch.empty(2 ** 29, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    out["hbm_copy_gbs"] = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+
     if not args.no_mali and not wl["fp64"]:
         mp = nlte.SolveParams(method=nlte.MALI, precision=nlte.FP64, nlev=1, E_target=1e-3,
                               max_iter=args.mali_max_iter, timing=1,
