@@ -445,6 +445,164 @@ __global__ __launch_bounds__((sizeof(R) == 4 ? kMaxSweepWaves : DB) * 64) void s
     }
 }
 
+// Plane-resident sweep for planes that fit in LDS.  One workgroup takes one direction,
+// one line and a chunk of F consecutive frequencies and marches through every plane of
+// the sweep in one launch, keeping its F planes of cells (I, S and chi as separate arrays)
+// in F + 1 LDS buffers: the new plane of frequency f is written into the spare buffer,
+// which then becomes frequency f's plane while the old one becomes the spare.  At the
+// start of plane step s frequency f lives in buffer (f - s) mod (F + 1) and its new plane
+// goes to buffer (f - s - 1) mod (F + 1); one barrier per (plane, frequency) orders the
+// reads of a buffer before it is overwritten.  No cell leaves the chip.  Thread t owns
+// plane points t, t + T, ...  Per plane the block writes the partial sums of its F
+// frequencies for each point to its own slot (direction, chunk); the rate equations add
+// the slots in a fixed order (deterministic).  Same arithmetic per update as the
+// plane-step kernel.
+template <typename R>
+struct MarchArgs {
+    const AtomInfo* atom;
+    int nx, ny, nz;
+    unsigned nxy;
+    size_t nvox;
+    double dx, dy;
+    const double* z;
+    const R* sc;
+    const R* sv;
+    const R* lc;
+    const R* qf;
+    const R* wf;
+    const R* topI;       // [nf][nxy] or null
+    R* acc;              // [2 qty][24 * nchunk slots][nline][nvox]
+    int F, nchunk;       // frequencies per chunk, chunks per line (largest line)
+};
+
+template <int PPT>
+__global__ __launch_bounds__(1024) void march_kernel(MarchArgs<float> a) {
+    using R = float;
+    extern __shared__ float march_lds[];
+    const int c = blockIdx.x, l = blockIdx.y, d = blockIdx.z;
+    const AtomInfo& at = *a.atom;
+    const LineInfo& ln = at.line[l];
+    const int L = at.nline;
+    const int mb = c * a.F;
+    const int nfh = min(ln.nfreq - mb, a.F);   // frequencies of this chunk (uniform)
+    if (nfh <= 0) return;                        // the whole block leaves: no barrier reached
+    const unsigned nxy = a.nxy;
+    const size_t nv = a.nvox;
+    const unsigned T = blockDim.x;
+    const int NB = a.F + 1;                      // LDS buffers
+    const size_t bstride = size_t(3) * nxy;      // one buffer: I, S, chi planes
+    const double mux = c_mu[3 * d], muy = c_mu[3 * d + 1], muz = c_mu[3 * d + 2];
+    const bool up = d < kNHemi;
+    const bool gauss = ln.gauss != 0;
+    const const_as<R>* qf = (const const_as<R>*)(a.qf + ln.fstart + mb);
+    const const_as<R>* wf = (const const_as<R>*)(a.wf + ln.fstart + mb);
+    const size_t nslot = size_t(kNDir) * a.nchunk;
+    R* pj = a.acc + ((size_t(0) * nslot + size_t(d) * a.nchunk + c) * L + l) * nv;
+    R* pl = a.acc + ((size_t(1) * nslot + size_t(d) * a.nchunk + c) * L + l) * nv;
+    for (int s = 0; s < a.nz; ++s) {
+        const int k = up ? s : a.nz - 1 - s;
+        R fx = R(0), fy = R(0), rds = R(0);
+        double fsx = 0.0, fsy = 0.0;
+        if (s > 0) {
+            const int kp = up ? s - 1 : a.nz - s;
+            const double ds = fabs(a.z[k] - a.z[kp]) / fabs(muz);
+            const double sx = -ds * mux / a.dx, sy = -ds * muy / a.dy;
+            fsx = floor(sx);
+            fsy = floor(sy);
+            fx = R(sx - fsx);
+            fy = R(sy - fsy);
+            rds = R(ds);
+        }
+        const R w00 = (R(1) - fx) * (R(1) - fy), w01 = fx * (R(1) - fy);
+        const R w10 = (R(1) - fx) * fy, w11 = fx * fy;
+        R jp[PPT], lp[PPT];
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            jp[i] = R(0);
+            lp[i] = R(0);
+        }
+        for (int f = 0; f < nfh; ++f) {
+            const int src = ((f - s) % NB + NB) % NB, dst = ((f - s - 1) % NB + NB) % NB;
+            const R* oI = march_lds + size_t(src) * bstride;
+            const R* oS = oI + nxy;
+            const R* oC = oI + 2 * size_t(nxy);
+            R* nI = march_lds + size_t(dst) * bstride;
+            R* nS = nI + nxy;
+            R* nC = nI + 2 * size_t(nxy);
+            const R qv = qf[f], wv = wf[f];
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                const unsigned p = threadIdx.x + unsigned(i) * T;
+                const bool valid = p < nxy;
+                unsigned g = valid ? p : nxy - 1;
+                // an empty asm makes g opaque to the optimiser, so the point's constants are
+                // loaded here for every frequency (L1 hits) instead of being hoisted out of
+                // the frequency loop and held in registers for all points
+                asm volatile("" : "+v"(g));
+                const size_t v = size_t(k) * nxy + g;
+                const R chic = a.sc[(SC_CHIC * L + l) * nv + v];
+                const R etac = a.sc[(SC_ETAC * L + l) * nv + v];
+                const R adamp = a.sc[(SC_ADAMP * L + l) * nv + v];
+                const R pn = a.sc[(SC_PN * L + l) * nv + v];
+                const R pw = a.sc[(SC_PW * L + l) * nv + v] * R(1.0 / kNDir);
+                const R kpl = a.lc[size_t(l) * nv + v];
+                const R el = a.lc[size_t(L + l) * nv + v];
+                const R ivD = a.sv[SV_INVVD * nv + v];
+                const R vn = a.sv[SV_VX * nv + v] * R(mux) + a.sv[SV_VY * nv + v] * R(muy) +
+                             a.sv[SV_VZ * nv + v] * R(muz);
+                const R u = qv * ivD - vn;
+                const R H = profile_H<R>(adamp, u, gauss);
+                const R phi = H * pn;
+                const R chi = fma(kpl, phi, chic);
+                R rchi;
+                const R S = source_fn(chi, chic, etac, kpl, el, phi, rchi);
+                const R wphi = wv * H * pw;
+                R Inew;
+                if (s == 0) {
+                    Inew = up ? a.sc[(SC_B * L + l) * nv + v]
+                              : (a.topI ? a.topI[size_t(ln.fstart + mb + f) * nxy + g] : R(0));
+                    jp[i] += wphi * Inew;
+                    lp[i] += wphi;
+                } else {
+                    const int x = int(g % unsigned(a.nx)), y = int(g / unsigned(a.nx));
+                    int x0 = int((long long)(x + (long long)fsx) % a.nx); if (x0 < 0) x0 += a.nx;
+                    int y0 = int((long long)(y + (long long)fsy) % a.ny); if (y0 < 0) y0 += a.ny;
+                    const int x1 = (x0 + 1 == a.nx) ? 0 : x0 + 1;
+                    const int y1 = (y0 + 1 == a.ny) ? 0 : y0 + 1;
+                    const unsigned g00 = unsigned(y0 * a.nx + x0), g01 = unsigned(y0 * a.nx + x1);
+                    const unsigned g10 = unsigned(y1 * a.nx + x0), g11 = unsigned(y1 * a.nx + x1);
+                    const R Iu = fma(w00, oI[g00], fma(w01, oI[g01], fma(w10, oI[g10], w11 * oI[g11])));
+                    const R Su = fma(w00, oS[g00], fma(w01, oS[g01], fma(w10, oS[g10], w11 * oS[g11])));
+                    const R Cu = fma(w00, oC[g00], fma(w01, oC[g01], fma(w10, oC[g10], w11 * oC[g11])));
+                    const R dtau = R(0.5) * (Cu + chi) * rds;
+                    R ex, pu, po, omp;
+                    sc_coeffs(dtau, ex, pu, po, omp);
+                    const R Ith = fma(Iu, ex, pu * Su);
+                    Inew = fma(po, S, Ith);
+                    const R por = po * rchi;
+                    jp[i] = fma(wphi, fma(por, etac, Ith), jp[i]);
+                    lp[i] = fma(wphi, fma(por, chic, omp), lp[i]);
+                }
+                if (valid) {
+                    nI[p] = Inew;
+                    nS[p] = S;
+                    nC[p] = chi;
+                }
+            }
+            __syncthreads();   // frequency f's new plane is complete and its old one unread
+        }
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            const unsigned p = threadIdx.x + unsigned(i) * T;
+            if (p < nxy) {
+                const size_t v = size_t(k) * nxy + p;
+                pj[v] = jp[i];
+                pl[v] = lp[i];
+            }
+        }
+    }
+}
+
 // Emergent intensity: one plane step of an upward sweep for a single direction (thread
 // per (frequency, plane point)); the last step writes I at the top plane.  The level
 // constants are read in their storage precision R; the solve itself is always FP64.
@@ -539,7 +697,9 @@ struct RateArgs {
     size_t nvox;
     const double* pfix;   // [N*N][nvox]
     const R* acc;         // [2][nslot][nline][nvox]
-    int nslot;            // 2, 4 or 8 direction-group slots per quantity
+    int nslot;            // 2, 4 or 8 direction-group slots per quantity (plane-step sweep)
+    int march_F;          // > 0: plane-resident sweep, slots (direction, chunk of march_F)
+    int nchunk;           //      chunks per direction
     double* n;            // [N][nvox]  (mode 0/1: updated in place)
     const double* f;      // [N][nvox]
     const double* base;   // mode 2
@@ -633,6 +793,19 @@ __global__ __launch_bounds__(256) void rate_kernel(RateArgs<R> a) {
             if (a.mode == 1) {
                 Jeff[l] = 0.0;
                 omL[l] = 1.0;
+            } else if (a.march_F > 0) {
+                // directions in order, each over its chunks in order, in FP64
+                const int nch = (at.line[l].nfreq + a.march_F - 1) / a.march_F;
+                const size_t ns = size_t(kNDir) * a.nchunk;
+                double sj = 0.0, so = 0.0;
+                for (int d = 0; d < kNDir; ++d)
+                    for (int c = 0; c < nch; ++c) {
+                        const size_t slot = size_t(d) * a.nchunk + c;
+                        sj += double(a.acc[(slot * L + l) * nv + v]);
+                        so += double(a.acc[((ns + slot) * L + l) * nv + v]);
+                    }
+                Jeff[l] = sj;
+                omL[l] = so;
             } else {
                 const size_t ss = size_t(L) * nv;
                 Jeff[l] = double(tree_slots(a.acc + (size_t(0) * a.nslot * L + l) * nv + v, ss, a.nslot));

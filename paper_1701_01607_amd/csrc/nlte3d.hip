@@ -74,6 +74,7 @@ struct nlte_ctx {
     std::vector<std::thread> workers;
     int max_running = 0, running = 0;
     bool stopping = false;
+    size_t lds_max = 65536;                  // dynamic LDS a workgroup may use
 };
 
 namespace {
@@ -240,7 +241,40 @@ struct Level {
     int nslot = 2;   // direction-group slots in acc written by the last formal solution
     int fc = 1;      // frequency chunks per (direction, tile): fixed by the level shape
     int maxslot = 8; // direction-group slots allocated in acc (8 allows every block shape)
+    struct MarchPlan {
+        int ppt = 0, threads = 0, F = 0, nchunk = 0;   // F = 0: plane-step sweep
+        size_t lds = 0;
+    } march;
 };
+
+// Plane-resident sweep plan for a plane of nxy points (FP32 only, on request): points
+// per thread, threads per workgroup, frequencies per chunk F (as many as the LDS holds, up
+// to 3 / 6 / 16 by points per thread, but no more than keep >= 1024 workgroups busy) and
+// chunks per line.  F = 0 where the plane does not fit, in FP64, or unless requested: on
+// the workloads measured it is slower than the plane-step sweep except on the smallest
+// grids (its partial sums per (direction, chunk) and its four waves per SIMD cost more
+// than the plane state's HBM round trip saves).
+template <typename P>
+inline void march_plan(P& m, size_t nxy, int nline, int maxfreq, size_t rbytes, size_t lds_max, int mode) {
+    m.ppt = m.threads = m.F = m.nchunk = 0;
+    m.lds = 0;
+    if (rbytes != 4 || mode != NLTE_SWEEP_RESIDENT || maxfreq < 1) return;
+    int ppt, fmax;
+    if (nxy <= 1024) { ppt = 1; fmax = 16; }
+    else if (nxy <= 2048) { ppt = 2; fmax = 6; }
+    else if (nxy <= 4096) { ppt = 4; fmax = 3; }
+    else return;
+    const size_t per_f = 3 * sizeof(float) * nxy;   // one LDS buffer; F frequencies need F + 1
+    int F = std::min(fmax, int(lds_max / per_f) - 1);
+    const int fpar = std::max(1, int(double(kNDir) * nline * maxfreq / 1024.0));
+    F = std::min(std::min(F, maxfreq), fpar);
+    if (F < 1) return;
+    m.ppt = ppt;
+    m.F = F;
+    m.threads = ppt == 1 ? int((nxy + 63) / 64 * 64) : 1024;
+    m.nchunk = (maxfreq + F - 1) / F;
+    m.lds = per_f * size_t(F + 1);
+}
 
 // Accumulator slots for a level: every block shape (down to 3 directions, 8 slots) on
 // levels whose 8-slot accumulators stay under 4 GiB; larger levels keep 2 slots and
@@ -356,6 +390,8 @@ struct Job : JobBase {
         HIPCHK(hipMemsetAsync(repairs.p, 0, sizeof(unsigned long long), st()));
 
         const int nprim = 7 + atm->nline_chic;
+        maxfreq = 0;
+        for (int l = 0; l < nline; ++l) maxfreq = std::max(maxfreq, info.line[l].nfreq);
         lev.resize(nlev);
         for (int k = nlev - 1; k >= 0; --k) {
             lev[k].reset(new Level());
@@ -392,7 +428,11 @@ struct Job : JobBase {
             dalloc(L.nb, sizeof(double) * N * L.nvox);
             dalloc(L.tmp, sizeof(double) * N * L.nvox);
             L.maxslot = acc_slots(L.nvox, nline, sizeof(R));
-            dalloc(L.acc, sizeof(R) * 2 * L.maxslot * nline * L.nvox);
+            march_plan(L.march, L.nxy, nline, maxfreq, sizeof(R), ctx->lds_max, p->sweep_kernel);
+            if (p->sweep_kernel == NLTE_SWEEP_RESIDENT)
+                REQUIRE(L.march.F > 0, "the plane-resident sweep needs FP32 and planes of at most 4096 points");
+            const size_t slots = L.march.F ? size_t(kNDir) * L.march.nchunk : size_t(L.maxslot);
+            dalloc(L.acc, sizeof(R) * 2 * slots * nline * L.nvox);
             dalloc(L.lc, sizeof(R) * 2 * nline * L.nvox);
             dalloc(L.partial, sizeof(double) * std::max<size_t>(blocks_for(L.nvox, 256), 1024));
             SetupArgs<R> sa;
@@ -418,8 +458,6 @@ struct Job : JobBase {
         // default; the plane state (2 x 24 x nline x Q cells per plane point) is split into
         // more passes only when a single pass would take more than a quarter of the
         // context's HBM budget (NLTE3D_SWEEP_STATE_MB overrides the state size cap).
-        maxfreq = 0;
-        for (int l = 0; l < nline; ++l) maxfreq = std::max(maxfreq, info.line[l].nfreq);
         const char* envb = std::getenv("NLTE3D_SWEEP_STATE_MB");
         const double cap_bytes = envb ? std::atof(envb) * 1048576.0 : 0.25 * double(ctx->budget);
         const double per_q = double(sizeof(Cell<R>)) * 2 * kNDir * nline * Fz.nxy;
@@ -427,7 +465,9 @@ struct Job : JobBase {
         // a pass's (direction, line) column is addressed by 32-bit buffer offsets
         const double colmax = 4294967295.0 / (double(sizeof(Cell<R>)) * double(Fz.nxy));
         Qpass = std::max(1, std::min(Qpass, int(colmax)));
-        dalloc(state, sizeof(Cell<R>) * 2 * kNDir * size_t(nline) * Qpass * Fz.nxy);
+        // the plane state is needed only where a level sweeps plane by plane (planes shrink
+        // towards the coarse levels, so the finest level decides)
+        if (!Fz.march.F) dalloc(state, sizeof(Cell<R>) * 2 * kNDir * size_t(nline) * Qpass * Fz.nxy);
         dalloc(nprev, sizeof(double) * N * Fz.nvox);
         if (p->top_I) {
             dalloc(topI, sizeof(R) * size_t(nf) * Fz.nxy);
@@ -452,6 +492,16 @@ struct Job : JobBase {
         }
         HIPCHK(hipStreamSynchronize(st()));
         for (auto& Lp : lev) Lp->fc = freq_chunks(*Lp);
+        if (log_enabled())
+            for (int k = 0; k < nlev; ++k) {
+                const Level& L = *lev[k];
+                if (L.march.F)
+                    log_line("level %d (%dx%dx%d): plane-resident sweep, %d frequencies x %d chunks, %d threads, %zu B LDS",
+                             k, L.nx, L.ny, L.nz, L.march.F, L.march.nchunk, L.march.threads, L.march.lds);
+                else
+                    log_line("level %d (%dx%dx%d): plane-step sweep, %d frequency chunks per wave group", k, L.nx,
+                             L.ny, L.nz, L.fc);
+            }
         choose_tile();
         ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
     }
@@ -564,6 +614,8 @@ struct Job : JobBase {
         ra.pfix = L.pfix.as<double>();
         ra.acc = L.acc.as<R>();
         ra.nslot = L.nslot;
+        ra.march_F = L.march.F;
+        ra.nchunk = L.march.nchunk;
         ra.n = L.n.as<double>();
         ra.f = L.f.as<double>();
         ra.base = base;
@@ -608,25 +660,62 @@ struct Job : JobBase {
         a.topI = (k == nlev - 1 && topI.p) ? topI.as<R>() : nullptr;
         a.state = state.as<Cell<R>>();
         a.acc = L.acc.as<R>();
-        const int db = tile_for(k, a);
-        if (k == nlev - 1) fine_db = db;
-        const dim3 grid = sweep_grid(L, nline, db);
-        ev_begin(EV_SWEEP);
-        for (int m0 = 0; m0 < maxfreq; m0 += Qpass) {
-            a.m0 = m0;
-            a.Q = Qpass;
-            a.add = m0 > 0 ? 1 : 0;
-            for (int s = 0; s < L.nz; ++s) launch_step(a, grid, db, L.fc, s);
-            sweep_launches += L.nz;
+        if (L.march.F) {
+            march_launch(k);
+        } else {
+            const int db = tile_for(k, a);
+            if (k == nlev - 1) fine_db = db;
+            const dim3 grid = sweep_grid(L, nline, db);
+            ev_begin(EV_SWEEP);
+            for (int m0 = 0; m0 < maxfreq; m0 += Qpass) {
+                a.m0 = m0;
+                a.Q = Qpass;
+                a.add = m0 > 0 ? 1 : 0;
+                for (int s = 0; s < L.nz; ++s) launch_step(a, grid, db, L.fc, s);
+                sweep_launches += L.nz;
+            }
+            HIPCHK(hipGetLastError());
+            ev_end();
+            L.nslot = kNDir / db;
         }
-        HIPCHK(hipGetLastError());
-        ev_end();
-        L.nslot = kNDir / db;
         L.fs_valid = true;
         ++L.fs_count;
         const Level& F = *lev[nlev - 1];
         cost_units += double(L.nvox) / double(F.nvox);
         updates += double(L.nvox) * kNDir * nf;
+    }
+
+    void march_launch(int k) {
+        Level& L = *lev[k];
+        if constexpr (sizeof(R) == 4) {
+            MarchArgs<float> m;
+            m.atom = atom_d.as<AtomInfo>();
+            m.nx = L.nx; m.ny = L.ny; m.nz = L.nz;
+            m.nxy = unsigned(L.nxy); m.nvox = L.nvox;
+            m.dx = L.dx; m.dy = L.dy;
+            m.z = L.dz.as<double>();
+            m.sc = L.sc.as<float>(); m.sv = L.sv.as<float>(); m.lc = L.lc.as<float>();
+            m.qf = qf.as<float>(); m.wf = wf.as<float>();
+            m.topI = (k == nlev - 1 && topI.p) ? topI.as<float>() : nullptr;
+            m.acc = L.acc.as<float>();
+            m.F = L.march.F;
+            m.nchunk = L.march.nchunk;
+            const dim3 grid(unsigned(L.march.nchunk), unsigned(nline), unsigned(kNDir));
+            const unsigned thr = unsigned(L.march.threads);
+            const size_t lds = L.march.lds;
+            ev_begin(EV_SWEEP);
+            switch (L.march.ppt) {
+                case 4: march_kernel<4><<<grid, thr, lds, st()>>>(m); break;
+                case 2: march_kernel<2><<<grid, thr, lds, st()>>>(m); break;
+                default: march_kernel<1><<<grid, thr, lds, st()>>>(m); break;
+            }
+            HIPCHK(hipGetLastError());
+            ev_end();
+            ++sweep_launches;
+        } else {
+            (void)L;
+            throw Error(NLTE_E_INVALID, "plane-resident sweep is FP32 only");
+        }
     }
 
     double read_scalar() {
@@ -868,6 +957,7 @@ struct Job : JobBase {
         r.ms_transfer = ms_phase[EV_TRANSFER];
         r.sweep_launches = sweep_launches;
         r.dirs_per_block = fine_db;
+        r.sweep_kernel = lev[nlev - 1]->march.F ? NLTE_SWEEP_RESIDENT : NLTE_SWEEP_PLANE_STEP;
         res = r;
         if (out) *out = r;
     }
@@ -887,13 +977,31 @@ struct Job : JobBase {
         // direction-group slots summed on the host side of the copy, by the same tree
         // as the rate equations
         const size_t m = size_t(nline) * L.nvox;
-        std::vector<R> a(size_t(2) * L.nslot * m);
+        const size_t ns = L.march.F ? size_t(kNDir) * L.march.nchunk : size_t(L.nslot);
+        std::vector<R> a(size_t(2) * ns * m);
         HIPCHK(hipMemcpyAsync(a.data(), L.acc.p, sizeof(R) * a.size(), hipMemcpyDeviceToHost, st()));
         HIPCHK(hipStreamSynchronize(st()));
         std::vector<R> j(m), o(m);
-        for (size_t i = 0; i < m; ++i) {
-            j[i] = tree_slots(a.data() + i, m, L.nslot);
-            o[i] = tree_slots(a.data() + size_t(L.nslot) * m + i, m, L.nslot);
+        if (L.march.F) {
+            for (int l = 0; l < nline; ++l) {
+                const int nch = (info.line[l].nfreq + L.march.F - 1) / L.march.F;
+                for (size_t v = 0; v < L.nvox; ++v) {
+                    double sj = 0.0, so = 0.0;
+                    for (int d = 0; d < kNDir; ++d)
+                        for (int c = 0; c < nch; ++c) {
+                            const size_t slot = size_t(d) * L.march.nchunk + c;
+                            sj += double(a[(slot * nline + l) * L.nvox + v]);
+                            so += double(a[((ns + slot) * nline + l) * L.nvox + v]);
+                        }
+                    j[size_t(l) * L.nvox + v] = R(sj);
+                    o[size_t(l) * L.nvox + v] = R(so);
+                }
+            }
+        } else {
+            for (size_t i = 0; i < m; ++i) {
+                j[i] = tree_slots(a.data() + i, m, L.nslot);
+                o[i] = tree_slots(a.data() + size_t(L.nslot) * m + i, m, L.nslot);
+            }
         }
         if (mem == NLTE_MEM_DEVICE) {
             HIPCHK(hipMemcpyAsync(jeff, j.data(), sizeof(R) * m, hipMemcpyHostToDevice, st()));
@@ -1015,21 +1123,26 @@ size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom
     size_t bytes = sizeof(AtomInfo) + (2 * R + 4) * size_t(nf) + 64;
     int nx = atm->nx, ny = atm->ny, nz = atm->nz;
     size_t fine_nxy = size_t(nx) * ny, fine_nvox = fine_nxy * nz;
+    int maxfreq = 0;
+    for (int l = 0; l < nline; ++l) maxfreq = std::max(maxfreq, atom->info.line[l].nfreq);
+    bool fine_resident = false;
     for (int k = nlev - 1; k >= 0; --k) {
         const size_t nvox = size_t(nx) * ny * nz;
+        Level::MarchPlan mp;
+        march_plan(mp, size_t(nx) * ny, nline, maxfreq, R, ctx->lds_max, p->sweep_kernel);
+        if (k == nlev - 1) fine_resident = mp.F > 0;
+        const size_t slots = mp.F ? size_t(kNDir) * mp.nchunk : size_t(acc_slots(nvox, nline, R));
         bytes += 8 * size_t(nz) + 8 * size_t(nprim) * nvox + R * (6 * nline + 4) * nvox;
-        bytes += 8 * (size_t(N) * 6 + size_t(N) * N + 1) * nvox + R * (2 * acc_slots(nvox, nline, R) + 2) * nline * nvox;
+        bytes += 8 * (size_t(N) * 6 + size_t(N) * N + 1) * nvox + R * (2 * slots + 2) * nline * nvox;
         bytes += 8 * std::max<size_t>((nvox + 255) / 256, 1024);
         nx /= 2; ny /= 2; nz = (nz - 1) / 2 + 1;
     }
-    int maxfreq = 0;
-    for (int l = 0; l < nline; ++l) maxfreq = std::max(maxfreq, atom->info.line[l].nfreq);
     const char* envb = std::getenv("NLTE3D_SWEEP_STATE_MB");
     const double cap = envb ? std::atof(envb) * 1048576.0 : 0.25 * double(ctx->budget);
     const double per_q = double(3 * R) * 2 * kNDir * nline * fine_nxy;
     int Q = std::max(1, std::min(maxfreq, int(cap / per_q)));
     Q = std::max(1, std::min(Q, int(4294967295.0 / (double(3 * R) * double(fine_nxy)))));
-    bytes += size_t(3 * R) * 2 * kNDir * size_t(nline) * Q * fine_nxy;
+    if (!fine_resident) bytes += size_t(3 * R) * 2 * kNDir * size_t(nline) * Q * fine_nxy;
     bytes += 8 * size_t(N) * fine_nvox;
     if (p->top_I) bytes += R * size_t(nf) * fine_nxy;
     bytes += 8 * 6 * size_t(nf) * fine_nxy;             // emergent-intensity state
@@ -1162,6 +1275,24 @@ nlte_status nlte_ctx_create(int device, void* hip_stream, size_t hbm_budget, nlt
         size_t fr = 0, tot = 0;
         HIPCHK(hipMemGetInfo(&fr, &tot));
         c->budget = hbm_budget ? hbm_budget : size_t(0.9 * double(fr));
+        // dynamic LDS for the plane-resident sweep: what the device grants a workgroup
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+            c->lds_max = size_t(lds);
+        if (c->lds_max > 65536) {
+            const int v = int(c->lds_max);
+            const bool ok =
+                hipFuncSetAttribute(reinterpret_cast<const void*>(&march_kernel<4>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess &&
+                hipFuncSetAttribute(reinterpret_cast<const void*>(&march_kernel<2>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess &&
+                hipFuncSetAttribute(reinterpret_cast<const void*>(&march_kernel<1>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess;
+            if (!ok) {
+                (void)hipGetLastError();
+                c->lds_max = 65536;
+            }
+        }
     } catch (const Error& e) {
         delete c;
         return e.code;

@@ -21,6 +21,7 @@ W_NOT_CONVERGED, W_QUEUED = 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 MALI, FAS, FMG = 0, 1, 2
 FP64, MIXED = 0, 1
+SWEEP_AUTO, SWEEP_PLANE_STEP, SWEEP_RESIDENT = 0, 1, 2
 INIT_ZERO_RAD, INIT_LTE, INIT_USER = 0, 1, 2
 
 SYMBOLS = (
@@ -85,7 +86,7 @@ class Params(ct.Structure):
                 ("tol_C", ct.c_double), ("E_target", ct.c_double), ("max_iter", ct.c_int),
                 ("repair_frac", ct.c_double), ("fallback_mali", ct.c_int),
                 ("top_I", ct.POINTER(ct.c_double)), ("dirs_per_block", ct.c_int), ("timing", ct.c_int),
-                ("graph", ct.c_int)]
+                ("graph", ct.c_int), ("sweep_kernel", ct.c_int)]
 
 
 class Result(ct.Structure):
@@ -95,7 +96,7 @@ class Result(ct.Structure):
                 ("fine_fs_equiv", ct.c_double), ("updates", ct.c_double),
                 ("ms_total", ct.c_double), ("ms_setup", ct.c_double), ("ms_sweep", ct.c_double),
                 ("ms_rates", ct.c_double), ("ms_transfer", ct.c_double), ("sweep_launches", ct.c_longlong),
-                ("dirs_per_block", ct.c_int)]
+                ("dirs_per_block", ct.c_int), ("sweep_kernel", ct.c_int)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "formal_solutions"}
@@ -186,6 +187,7 @@ class SolveParams:
     dirs_per_block: int = 0
     timing: int = 0
     graph: int = 0
+    sweep_kernel: int = 0
     init_pops: np.ndarray | None = None
     top_I: np.ndarray | None = None
     _keep: list = field(default_factory=list, repr=False)
@@ -193,7 +195,7 @@ class SolveParams:
     def to_c(self):
         p = Params()
         for k in ("method", "precision", "nlev", "nu_fmg", "nu0", "nu1", "nu2", "nu3", "init",
-                  "max_iter", "fallback_mali", "dirs_per_block", "timing", "graph"):
+                  "max_iter", "fallback_mali", "dirs_per_block", "timing", "graph", "sweep_kernel"):
             setattr(p, k, int(getattr(self, k)))
         for k in ("tol_C", "E_target", "repair_frac"):
             setattr(p, k, float(getattr(self, k)))

@@ -62,25 +62,32 @@ def ragged():
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
 @pytest.mark.parametrize("dpb", [0, 3, 12])
-def test_formal_solution_parity(nl, ctx, ragged, prec, tol, dpb):
+@pytest.mark.parametrize("kern", [1, 2], ids=["plane_step", "resident"])
+def test_formal_solution_parity(nl, ctx, ragged, prec, tol, dpb, kern):
+    if kern == 2 and prec == 0:
+        pytest.skip("the plane-resident sweep is FP32 only")
     atom, atm, lev, n0 = ragged
     npop, nln = shapes(atom, atm)
     job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1,
-                                                                 dirs_per_block=dpb))
+                                                                 dirs_per_block=dpb, sweep_kernel=kern))
     g0 = job.populations(0, npop)
     assert relerr(g0, n0) < 1e-11
     jg, og = job.formal_solution(0, nln)
     jo, oo = formal_solution(lev, n0)
     ej, eo = relerr(jg, jo), relerr(og, oo)
-    print(f"prec={prec} dirs_per_block={dpb} Jeff err {ej:.2e}  1-L* err {eo:.2e}")
+    print(f"prec={prec} dirs_per_block={dpb} kernel={kern} Jeff err {ej:.2e}  1-L* err {eo:.2e}")
     assert ej < tol and eo < tol
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-3)])
-def test_mali_iterations_parity(nl, ctx, ragged, prec, tol):
+@pytest.mark.parametrize("kern", [1, 2], ids=["plane_step", "resident"])
+def test_mali_iterations_parity(nl, ctx, ragged, prec, tol, kern):
+    if kern == 2 and prec == 0:
+        pytest.skip("the plane-resident sweep is FP32 only")
     atom, atm, lev, n0 = ragged
     npop, _ = shapes(atom, atm)
-    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1))
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1,
+                                                                 sweep_kernel=kern))
     Cg = job.mali(0, 3)
     n3, Co = mali(lev, 1, n0, fine_rhs(lev), 3)
     e = relerr(job.populations(0, npop), n3)
@@ -128,7 +135,10 @@ def mg_case(nfreq=7):
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-3)])
-def test_vcycle_parity(nl, ctx, prec, tol):
+@pytest.mark.parametrize("kern", [1, 2], ids=["plane_step", "resident"])
+def test_vcycle_parity(nl, ctx, prec, tol, kern):
+    if kern == 2 and prec == 0:
+        pytest.skip("the plane-resident sweep is FP32 only")
     atom, atm = mg_case()
     p = OParams(nlev=3, nu0=3, nu1=2, nu2=2, nu3=6)
     levels = build_hierarchy(atom, atm, 3)
@@ -136,7 +146,7 @@ def test_vcycle_parity(nl, ctx, prec, tol):
     n = zero_radiation(fine)
     n = vcycle(levels, 3, n, fine_rhs(fine), p, first=True)
     job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
-                  nl.SolveParams(method=nl.FAS, precision=prec, nlev=3, nu0=3, nu1=2, nu2=2, nu3=6))
+                  nl.SolveParams(method=nl.FAS, precision=prec, nlev=3, nu0=3, nu1=2, nu2=2, nu3=6, sweep_kernel=kern))
     job.vcycle(2, first=True)
     npop, _ = shapes(atom, atm)
     e = relerr(job.populations(2, npop), n)
@@ -146,13 +156,16 @@ def test_vcycle_parity(nl, ctx, prec, tol):
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-3)])
 @pytest.mark.parametrize("fmg", [False, True])
-def test_fas_fmg_fixed_cycles_parity(nl, ctx, prec, tol, fmg):
+@pytest.mark.parametrize("kern", [1, 2], ids=["plane_step", "resident"])
+def test_fas_fmg_fixed_cycles_parity(nl, ctx, prec, tol, fmg, kern):
+    if kern == 2 and prec == 0:
+        pytest.skip("the plane-resident sweep is FP32 only")
     atom, atm = mg_case()
     p = OParams(nlev=3, nu1=2, nu2=2, nu3=6, nu_fmg=4)
     n_or, st, _ = solve_fas(atom, atm, p, fmg=fmg, cycles=2)
     job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
                   nl.SolveParams(method=nl.FMG if fmg else nl.FAS, precision=prec, nlev=3, nu1=2, nu2=2, nu3=6,
-                                 nu_fmg=4, E_target=0.0, tol_C=0.0, max_iter=2))
+                                 nu_fmg=4, E_target=0.0, tol_C=0.0, max_iter=2, sweep_kernel=kern))
     rc, r = job.run()
     npop, _ = shapes(atom, atm)
     e = relerr(job.populations(2, npop), n_or)
@@ -272,7 +285,8 @@ def test_block_shape_does_not_change_results(nl, ctx, prec, nx, ny, shapes_):
     A, M = ctx.atmos(atm), ctx.atom(atom)
     outs = []
     for dpb in shapes_:
-        job = ctx.job(A, M, nl.SolveParams(method=nl.MALI, precision=prec, nlev=1, dirs_per_block=dpb, timing=1))
+        job = ctx.job(A, M, nl.SolveParams(method=nl.MALI, precision=prec, nlev=1, dirs_per_block=dpb, timing=1,
+                                           sweep_kernel=nl.SWEEP_PLANE_STEP))
         jg, og = job.formal_solution(0, nln)
         job.mali(0, 3)
         outs.append((jg, og, job.populations(0, npop)))
@@ -282,7 +296,10 @@ def test_block_shape_does_not_change_results(nl, ctx, prec, nx, ny, shapes_):
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
-def test_formal_solution_parity_one_chunk_per_wave(nl, ctx, prec, tol):
+@pytest.mark.parametrize("kern", [1, 2], ids=["plane_step", "resident"])
+def test_formal_solution_parity_one_chunk_per_wave(nl, ctx, prec, tol, kern):
+    if kern == 2 and prec == 0:
+        pytest.skip("the plane-resident sweep is FP32 only")
     """A plane large enough for one frequency chunk per wave (the layout of the bench's
     finest grid), against the oracle."""
     atom = synth.caii_like_atom(9)
@@ -290,16 +307,20 @@ def test_formal_solution_parity_one_chunk_per_wave(nl, ctx, prec, tol):
     lev = Level(atom, atm)
     n0 = zero_radiation(lev)
     npop, nln = shapes(atom, atm)
-    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1))
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1,
+                                                                 sweep_kernel=kern))
     jg, og = job.formal_solution(0, nln)
     jo, oo = formal_solution(lev, n0)
     ej, eo = relerr(jg, jo), relerr(og, oo)
-    print(f"prec={prec} Jeff err {ej:.2e}  1-L* err {eo:.2e}")
+    print(f"prec={prec} kernel={kern} Jeff err {ej:.2e}  1-L* err {eo:.2e}")
     assert ej < tol and eo < tol
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
-def test_strongly_damped_line_parity(nl, ctx, prec, tol):
+@pytest.mark.parametrize("kern", [1, 2], ids=["plane_step", "resident"])
+def test_strongly_damped_line_parity(nl, ctx, prec, tol, kern):
+    if kern == 2 and prec == 0:
+        pytest.skip("the plane-resident sweep is FP32 only")
     """Damping well above the Doppler width (a ~ 40), so that the profile wings beyond
     |u| = 5 lie far off the real axis of the Faddeeva function."""
     atom = synth.two_level_atom(1e-2, q_max=16 * synth.KM, nfreq=33)
@@ -308,10 +329,29 @@ def test_strongly_damped_line_parity(nl, ctx, prec, tol):
     lev = Level(atom, atm)
     n0 = zero_radiation(lev)
     npop, nln = shapes(atom, atm)
-    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1))
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1,
+                                                                 sweep_kernel=kern))
     jg, og = job.formal_solution(0, nln)
     jo, oo = formal_solution(lev, n0)
     assert np.isfinite(jg).all() and np.isfinite(og).all()
     ej, eo = relerr(jg, jo), relerr(og, oo)
     print(f"prec={prec} Jeff err {ej:.2e}  1-L* err {eo:.2e}")
     assert ej < tol and eo < tol
+
+
+def test_plane_resident_sweep_requests(nl, ctx):
+    """The plane-resident sweep runs where asked and applies; it refuses FP64 and planes
+    too large for LDS instead of silently switching kernels."""
+    atom, atm = ragged_case(nfreq=9, seed=37)
+    A, M = ctx.atmos(atm), ctx.atom(atom)
+    job = ctx.job(A, M, nl.SolveParams(method=nl.MALI, precision=nl.MIXED, nlev=1, max_iter=2, E_target=0.0,
+                                       sweep_kernel=nl.SWEEP_RESIDENT))
+    rc, r = job.run()
+    assert r.sweep_kernel == nl.SWEEP_RESIDENT
+    job.close()
+    with pytest.raises(nl.NlteError):
+        ctx.job(A, M, nl.SolveParams(method=nl.MALI, precision=nl.FP64, nlev=1, sweep_kernel=nl.SWEEP_RESIDENT))
+    big = synth.atmos_stratified(nx=96, ny=96, nz=3, dx=120 * synth.KM, seed=37)
+    with pytest.raises(nl.NlteError):
+        ctx.job(ctx.atmos(big), M, nl.SolveParams(method=nl.MALI, precision=nl.MIXED, nlev=1,
+                                                  sweep_kernel=nl.SWEEP_RESIDENT))
