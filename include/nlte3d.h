@@ -51,6 +51,7 @@ typedef int nlte_status;
 #define NLTE_SWEEP_AUTO        0    /* sweep kernel chosen per grid level */
 #define NLTE_SWEEP_PLANE_STEP  1
 #define NLTE_SWEEP_RESIDENT    2
+#define NLTE_SWEEP_PAIR        3    /* two plane steps per launch (FP32) */
 
 #define NLTE_FP64  0                /* formal solution in FP64 */
 #define NLTE_MIXED 1                /* formal solution and accumulation in FP32; rate
@@ -135,11 +136,16 @@ typedef struct {
                                   cycle (nu0) runs eagerly.  Phase timing is not available
                                   for replayed work. */
     int sweep_kernel;          /* NLTE_SWEEP_AUTO, NLTE_SWEEP_PLANE_STEP (plane state in HBM,
-                                  one launch per plane) or NLTE_SWEEP_RESIDENT (FP32 only:
-                                  each workgroup marches a few frequencies of one direction
-                                  through all planes with the plane in LDS; planes of up to
-                                  4096 points; measured slower except on the smallest
-                                  grids).  AUTO takes PLANE_STEP. */
+                                  one launch per plane), NLTE_SWEEP_PAIR (FP32: two plane
+                                  steps per launch, the intermediate plane kept in LDS per
+                                  16x16 tile; same results as PLANE_STEP bit for bit; needs
+                                  planes that fill the GPU with one frequency chunk per wave;
+                                  measured slower than PLANE_STEP)
+                                  or NLTE_SWEEP_RESIDENT (FP32 only: each workgroup marches a
+                                  few frequencies of one direction through all planes with
+                                  the plane in LDS; planes of up to 4096 points; measured
+                                  slower except on the smallest grids).  AUTO takes
+                                  PLANE_STEP. */
 } nlte_params;
 
 typedef struct {
@@ -156,7 +162,7 @@ typedef struct {
     double ms_total, ms_setup, ms_sweep, ms_rates, ms_transfer;   /* phase times need params.timing */
     long long sweep_launches;  /* plane-step sweep kernel launches (formal solutions x planes) */
     int dirs_per_block;        /* sweep block shape used on the finest level (3, 6 or 12; 0 if none ran) */
-    int sweep_kernel;          /* NLTE_SWEEP_PLANE_STEP or NLTE_SWEEP_RESIDENT on the finest level */
+    int sweep_kernel;          /* NLTE_SWEEP_PLANE_STEP, _PAIR or _RESIDENT on the finest level */
 } nlte_result;
 
 /* ---------------------------------------------------------------- lifecycle */

@@ -243,6 +243,11 @@ constexpr int kMaxSlots = 8;
 
 template <typename R>
 __device__ __host__ inline R tree_slots(const R* x, size_t stride, int nslot) {
+    if (nslot == kNDir) {   // one slot per direction: groups of three first
+        R g[8];
+        for (int q = 0; q < 8; ++q) g[q] = (x[(3 * q) * stride] + x[(3 * q + 1) * stride]) + x[(3 * q + 2) * stride];
+        return ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]));
+    }
     if (nslot == 2) return x[0] + x[stride];
     if (nslot == 4) return (x[0] + x[stride]) + (x[2 * stride] + x[3 * stride]);
     return ((x[0] + x[stride]) + (x[2 * stride] + x[3 * stride])) +
@@ -260,6 +265,58 @@ __device__ __host__ inline R tree_slots(const R* x, size_t stride, int nslot) {
 // access is a scalar base plus a fixed 32-bit lane offset.  A wave sums its chunk in
 // frequency order; chunks are added in order, then directions by the fixed tree.  FC
 // changes the rounding of the frequency sum, so it is fixed by the level shape alone.
+// One short-characteristics update of a cell for one direction and frequency, shared by
+// every sweep kernel so that they compute bit-identical cells and sums: the local opacity
+// and source function from the profile, the segment from the (already interpolated)
+// upwind values, the new cell, and the two positive accumulation terms.
+template <typename R>
+struct PointConst {
+    R chic, etac, adamp, pn, pw, kpl, el, ivD, vn;
+};
+
+template <typename R>
+__device__ inline PointConst<R> point_const(const R* sc, const R* sv, const R* lc, int L, int l, size_t nv,
+                                            size_t v, double mux, double muy, double muz) {
+    PointConst<R> c;
+    c.chic = sc[(SC_CHIC * L + l) * nv + v];
+    c.etac = sc[(SC_ETAC * L + l) * nv + v];
+    c.adamp = sc[(SC_ADAMP * L + l) * nv + v];
+    c.pn = sc[(SC_PN * L + l) * nv + v];
+    c.pw = sc[(SC_PW * L + l) * nv + v] * R(1.0 / kNDir);
+    c.kpl = lc[size_t(l) * nv + v];
+    c.el = lc[size_t(L + l) * nv + v];
+    c.ivD = sv[SV_INVVD * nv + v];
+    c.vn = sv[SV_VX * nv + v] * R(mux) + sv[SV_VY * nv + v] * R(muy) + sv[SV_VZ * nv + v] * R(muz);
+    return c;
+}
+
+template <typename R>
+__device__ inline R interp4(R w00, R w01, R w10, R w11, R a00, R a01, R a10, R a11) {
+    return fma(w00, a00, fma(w01, a01, fma(w10, a10, w11 * a11)));
+}
+
+template <typename R>
+__device__ inline void sc_point(const PointConst<R>& c, R q, R w, bool gauss, R Iu, R Su, R Cu, R rds,
+                                Cell<R>& cell, R& jacc, R& lacc) {
+    const R u = q * c.ivD - c.vn;
+    const R H = profile_H<R>(c.adamp, u, gauss);
+    const R phi = H * c.pn;
+    const R chi = fma(c.kpl, phi, c.chic);
+    R rchi;
+    const R S = source_fn(chi, c.chic, c.etac, c.kpl, c.el, phi, rchi);
+    const R dtau = R(0.5) * (Cu + chi) * rds;
+    R ex, pu, po, omp;
+    sc_coeffs(dtau, ex, pu, po, omp);
+    const R Ith = fma(Iu, ex, pu * Su);
+    cell.I = fma(po, S, Ith);
+    cell.S = S;
+    cell.C = chi;
+    const R wphi = w * H * c.pw;
+    const R por = po * rchi;
+    jacc = fma(wphi, fma(por, c.etac, Ith), jacc);
+    lacc = fma(wphi, fma(por, c.chic, omp), lacc);
+}
+
 template <typename R>
 struct SweepArgs {
     const AtomInfo* atom;
@@ -278,6 +335,8 @@ struct SweepArgs {
     R* acc;              // [2 qty][24/DB slots][nline][nvox]
     int m0, Q;           // this pass covers frequencies m0 .. m0+Q-1 of every line
     int add;             // 1: add this pass's sums to acc; 0: overwrite
+    int nstate;          // plane-state slots (2, or 3 with the two-plane kernel), used by step % nstate
+    int dslots;          // 1: one acc slot per direction (24) instead of one per block
 };
 
 constexpr int kMaxSweepWaves = 12;
@@ -320,16 +379,7 @@ __global__ __launch_bounds__((sizeof(R) == 4 ? kMaxSweepWaves : DB) * 64) void s
     const int clen = (mend - a.m0 + FC - 1) / FC;
     const int mb = min(mend, a.m0 + c * clen), me = min(mend, mb + clen);   // this wave's chunk
     const double mux = c_mu[3 * d], muy = c_mu[3 * d + 1], muz = c_mu[3 * d + 2];
-    const R chic = a.sc[(SC_CHIC * L + l) * nv + v];
-    const R etac = a.sc[(SC_ETAC * L + l) * nv + v];
-    const R adamp = a.sc[(SC_ADAMP * L + l) * nv + v];
-    const R pn = a.sc[(SC_PN * L + l) * nv + v];
-    const R pw = a.sc[(SC_PW * L + l) * nv + v] * R(1.0 / kNDir);
-    const R kpl = a.lc[size_t(l) * nv + v];
-    const R el = a.lc[size_t(L + l) * nv + v];
-    const R ivD = a.sv[SV_INVVD * nv + v];
-    const R vn = a.sv[SV_VX * nv + v] * R(mux) + a.sv[SV_VY * nv + v] * R(muy) +
-                 a.sv[SV_VZ * nv + v] * R(muz);
+    const PointConst<R> pc = point_const<R>(a.sc, a.sv, a.lc, L, l, nv, v, mux, muy, muz);
     const bool gauss = ln.gauss != 0;
     const const_as<R>* qf = (const const_as<R>*)(a.qf + ln.fstart);
     const const_as<R>* wf = (const const_as<R>*)(a.wf + ln.fstart);
@@ -337,24 +387,24 @@ __global__ __launch_bounds__((sizeof(R) == 4 ? kMaxSweepWaves : DB) * 64) void s
     const unsigned csz = sizeof(Cell<R>);
     const unsigned rowb = nxy * csz;                                  // bytes per frequency row
     const unsigned colb = unsigned(mend - a.m0) * rowb;
-    const auto rcur = cell_rsrc(a.state + size_t(s & 1) * slot_stride + col, colb);
+    const auto rcur = cell_rsrc(a.state + size_t(s % a.nstate) * slot_stride + col, colb);
     R jacc = R(0), lacc = R(0);
     const unsigned oc = g * csz;
     if (s == 0) {
         const R Bb = a.sc[(SC_B * L + l) * nv + v];
         const R* top = a.topI ? a.topI + size_t(ln.fstart) * nxy + g : nullptr;
         for (int m = mb; m < me; ++m) {
-            const R u = qf[m] * ivD - vn;
-            const R H = profile_H<R>(adamp, u, gauss);
-            const R phi = H * pn;
-            const R chi = chic + kpl * phi;
+            const R u = qf[m] * pc.ivD - pc.vn;
+            const R H = profile_H<R>(pc.adamp, u, gauss);
+            const R phi = H * pc.pn;
+            const R chi = pc.chic + pc.kpl * phi;
             R rchi_b;
-            const R S = source_fn(chi, chic, etac, kpl, el, phi, rchi_b);
+            const R S = source_fn(chi, pc.chic, pc.etac, pc.kpl, pc.el, phi, rchi_b);
             const R I = (h == 0) ? Bb : (top ? top[size_t(m) * nxy] : R(0));
             Cell<R> cell;
             cell.I = I; cell.S = S; cell.C = chi;
             if (valid) cell_put(rcur, oc, unsigned(m - a.m0) * rowb, cell);
-            const R wphi = wf[m] * H * pw;
+            const R wphi = wf[m] * H * pc.pw;
             jacc += wphi * I;
             lacc += wphi;
         }
@@ -374,33 +424,17 @@ __global__ __launch_bounds__((sizeof(R) == 4 ? kMaxSweepWaves : DB) * 64) void s
         const R w00 = (R(1) - fx) * (R(1) - fy), w01 = fx * (R(1) - fy);
         const R w10 = (R(1) - fx) * fy, w11 = fx * fy;
         const R rds = R(ds);
-        const auto rprv = cell_rsrc(a.state + size_t((s - 1) & 1) * slot_stride + col, colb);
+        const auto rprv = cell_rsrc(a.state + size_t((s - 1) % a.nstate) * slot_stride + col, colb);
         for (int m = mb; m < me; ++m) {
             const unsigned so = unsigned(m - a.m0) * rowb;
             const Cell<R> c00 = cell_get<R>(rprv, o00, so), c01 = cell_get<R>(rprv, o01, so);
             const Cell<R> c10 = cell_get<R>(rprv, o10, so), c11 = cell_get<R>(rprv, o11, so);
-            const R u = qf[m] * ivD - vn;
-            const R H = profile_H<R>(adamp, u, gauss);
-            const R phi = H * pn;
-            const R chi = fma(kpl, phi, chic);
-            R rchi;
-            const R S = source_fn(chi, chic, etac, kpl, el, phi, rchi);
-            const R Iu = fma(w00, c00.I, fma(w01, c01.I, fma(w10, c10.I, w11 * c11.I)));
-            const R Su = fma(w00, c00.S, fma(w01, c01.S, fma(w10, c10.S, w11 * c11.S)));
-            const R Cu = fma(w00, c00.C, fma(w01, c01.C, fma(w10, c10.C, w11 * c11.C)));
-            const R dtau = R(0.5) * (Cu + chi) * rds;
-            R ex, pu, po, omp;
-            sc_coeffs(dtau, ex, pu, po, omp);
-            const R Ith = fma(Iu, ex, pu * Su);
+            const R Iu = interp4(w00, w01, w10, w11, c00.I, c01.I, c10.I, c11.I);
+            const R Su = interp4(w00, w01, w10, w11, c00.S, c01.S, c10.S, c11.S);
+            const R Cu = interp4(w00, w01, w10, w11, c00.C, c01.C, c10.C, c11.C);
             Cell<R> cell;
-            cell.I = fma(po, S, Ith);
-            cell.S = S;
-            cell.C = chi;
+            sc_point(pc, R(qf[m]), R(wf[m]), gauss, Iu, Su, Cu, rds, cell, jacc, lacc);
             if (valid) cell_put(rcur, oc, so, cell);
-            const R wphi = wf[m] * H * pw;
-            const R por = po * rchi;
-            jacc = fma(wphi, fma(por, etac, Ith), jacc);
-            lacc = fma(wphi, fma(por, chic, omp), lacc);
         }
     }
     __shared__ R sj[kMaxSweepWaves * kW];
@@ -419,6 +453,15 @@ __global__ __launch_bounds__((sizeof(R) == 4 ? kMaxSweepWaves : DB) * 64) void s
                 dj[q] += sj[(cc * DB + q) * kW + lane];
                 dl[q] += sl[(cc * DB + q) * kW + lane];
             }
+        }
+        if (a.dslots) {
+            // one slot per direction; the readers apply the whole tree
+#pragma unroll
+            for (int q = 0; q < DB; ++q) {
+                a.acc[((size_t(0) * kNDir + grp * DB + q) * L + l) * nv + v] = dj[q];
+                a.acc[((size_t(1) * kNDir + grp * DB + q) * L + l) * nv + v] = dl[q];
+            }
+            return;
         }
         // groups of three directions, then pairs of groups (the fixed tree)
         R gj[DB / 3], gl[DB / 3];
@@ -442,6 +485,130 @@ __global__ __launch_bounds__((sizeof(R) == 4 ? kMaxSweepWaves : DB) * 64) void s
         if (a.add) { jt += *aj; lt += *al; }
         *aj = jt;
         *al = lt;
+    }
+}
+
+// Two plane steps per launch (steps s and s+1, s >= 1), FP32.  Workgroup: one direction,
+// one line, one 16x16 tile of the output plane (step s+1).  Its upwind corners lie in a
+// 17x17 region of the intermediate plane (step s), shifted by the integer part of the
+// step-(s+1) offset; the workgroup computes that region from the stored plane of step
+// s-1 into LDS (five waves, 289 cells), then the tile from LDS (four waves), and stores
+// only the tile.  The plane of step s never goes to HBM: per two planes the state moves
+// once each way instead of twice.  The regions overlap by one row and column; each
+// intermediate voxel is accumulated once, by the workgroup whose tile shifted by the
+// same offset (its "core") contains it - the shifted tiles partition the plane.  Sums go
+// to one slot per direction, cells and sums are computed by the same code as the
+// plane-step kernel (bit-identical results).  State slots rotate by step % 3.
+constexpr int kPairT = 16;
+constexpr int kPairR = kPairT + 1;
+constexpr int kPairThreads = 320;   // 5 waves: 289 region cells, then 256 tile points
+
+__device__ inline int wrap_idx(long long i, int n) {
+    long long r = i % n;
+    return int(r < 0 ? r + n : r);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kPairThreads) void sweep_pair_kernel(SweepArgs<R> a, int s) {
+    const int tid = int(threadIdx.x);
+    const int ntx = (a.nx + kPairT - 1) / kPairT, nty = (a.ny + kPairT - 1) / kPairT;
+    const unsigned T = gridDim.x, nb = T * gridDim.y * gridDim.z;
+    const unsigned lin = blockIdx.x + T * (blockIdx.y + gridDim.y * blockIdx.z);
+    const unsigned work = (nb % 8u == 0u) ? (lin % 8u) * (nb / 8u) + lin / 8u : lin;
+    const int tile = int(work % T);
+    const int l = int((work / T) % gridDim.y);
+    const int d = int(work / (T * gridDim.y));
+    const int tx = tile % ntx, ty = tile / ntx;
+    (void)nty;
+    const int X0 = tx * kPairT, Y0 = ty * kPairT;
+    const AtomInfo& at = *a.atom;
+    const LineInfo& ln = at.line[l];
+    const int L = at.nline;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const unsigned nxy = a.nxy;
+    const size_t nv = a.nvox;
+    const bool up = d < kNHemi;
+    const int k0 = up ? s - 1 : nz - s, k1 = up ? s : nz - 1 - s, k2 = up ? s + 1 : nz - 2 - s;
+    const double mux = c_mu[3 * d], muy = c_mu[3 * d + 1], muz = c_mu[3 * d + 2];
+    // offsets of the two steps
+    const double ds1 = fabs(a.z[k1] - a.z[k0]) / fabs(muz), ds2 = fabs(a.z[k2] - a.z[k1]) / fabs(muz);
+    const double sx1 = -ds1 * mux / a.dx, sy1 = -ds1 * muy / a.dy;
+    const double sx2 = -ds2 * mux / a.dx, sy2 = -ds2 * muy / a.dy;
+    const double fsx1 = floor(sx1), fsy1 = floor(sy1), fsx2 = floor(sx2), fsy2 = floor(sy2);
+    const R fx1 = R(sx1 - fsx1), fy1 = R(sy1 - fsy1), fx2 = R(sx2 - fsx2), fy2 = R(sy2 - fsy2);
+    const R a00 = (R(1) - fx1) * (R(1) - fy1), a01 = fx1 * (R(1) - fy1);
+    const R a10 = (R(1) - fx1) * fy1, a11 = fx1 * fy1;
+    const R b00 = (R(1) - fx2) * (R(1) - fy2), b01 = fx2 * (R(1) - fy2);
+    const R b10 = (R(1) - fx2) * fy2, b11 = fx2 * fy2;
+    const R rds1 = R(ds1), rds2 = R(ds2);
+    const long long ix1 = (long long)fsx1, iy1 = (long long)fsy1;
+    const long long ix2 = (long long)fsx2, iy2 = (long long)fsy2;
+    // this thread's intermediate cell (phase 1) and tile point (phase 2)
+    const bool p1 = tid < kPairR * kPairR;
+    const int ri = p1 ? tid % kPairR : 0, rj = p1 ? tid / kPairR : 0;
+    const int x1 = wrap_idx(X0 + ix2 + ri, nx), y1 = wrap_idx(Y0 + iy2 + rj, ny);
+    const bool core1 = p1 && ri < kPairT && rj < kPairT && X0 + ri < nx && Y0 + rj < ny;
+    const bool p2 = tid < kPairT * kPairT;
+    const int oi = tid % kPairT, oj = tid / kPairT;
+    const bool valid2 = p2 && X0 + oi < nx && Y0 + oj < ny;
+    const int x2 = valid2 ? X0 + oi : 0, y2 = valid2 ? Y0 + oj : 0;
+    const size_t v1 = size_t(k1) * nxy + size_t(y1) * nx + x1;
+    const size_t v2 = size_t(k2) * nxy + size_t(y2) * nx + x2;
+    const PointConst<R> c1 = point_const<R>(a.sc, a.sv, a.lc, L, l, nv, v1, mux, muy, muz);
+    const PointConst<R> c2 = point_const<R>(a.sc, a.sv, a.lc, L, l, nv, v2, mux, muy, muz);
+    // upwind corners of the intermediate cell on the stored plane (byte offsets in a row)
+    const unsigned csz = sizeof(Cell<R>);
+    const int xa = wrap_idx(x1 + ix1, nx), ya = wrap_idx(y1 + iy1, ny);
+    const int xb = xa + 1 == nx ? 0 : xa + 1, yb = ya + 1 == ny ? 0 : ya + 1;
+    const unsigned o00 = unsigned(ya * nx + xa) * csz, o01 = unsigned(ya * nx + xb) * csz;
+    const unsigned o10 = unsigned(yb * nx + xa) * csz, o11 = unsigned(yb * nx + xb) * csz;
+    const unsigned oc = unsigned(y2 * nx + x2) * csz;
+    const int nf = ln.nfreq;                        // single pass: a.m0 = 0, a.Q >= nf
+    const size_t dstride = size_t(L) * a.Q * nxy;
+    const size_t slot_stride = size_t(kNDir) * dstride;
+    const size_t col = size_t(d) * dstride + size_t(l) * a.Q * nxy;
+    const unsigned rowb = nxy * csz;
+    const unsigned colb = unsigned(nf) * rowb;
+    const auto rprv = cell_rsrc(a.state + size_t((s - 1) % a.nstate) * slot_stride + col, colb);
+    const auto rout = cell_rsrc(a.state + size_t((s + 1) % a.nstate) * slot_stride + col, colb);
+    const bool gauss = ln.gauss != 0;
+    const const_as<R>* qf = (const const_as<R>*)(a.qf + ln.fstart);
+    const const_as<R>* wf = (const const_as<R>*)(a.wf + ln.fstart);
+    __shared__ R rI[2][kPairR * kPairR], rS[2][kPairR * kPairR], rC[2][kPairR * kPairR];
+    R j1 = R(0), l1 = R(0), j2 = R(0), l2 = R(0);
+    for (int m = 0; m < nf; ++m) {
+        const int b = m & 1;
+        const unsigned so = unsigned(m) * rowb;
+        if (p1) {
+            const Cell<R> e00 = cell_get<R>(rprv, o00, so), e01 = cell_get<R>(rprv, o01, so);
+            const Cell<R> e10 = cell_get<R>(rprv, o10, so), e11 = cell_get<R>(rprv, o11, so);
+            const R Iu = interp4(a00, a01, a10, a11, e00.I, e01.I, e10.I, e11.I);
+            const R Su = interp4(a00, a01, a10, a11, e00.S, e01.S, e10.S, e11.S);
+            const R Cu = interp4(a00, a01, a10, a11, e00.C, e01.C, e10.C, e11.C);
+            Cell<R> cell;
+            sc_point(c1, R(qf[m]), R(wf[m]), gauss, Iu, Su, Cu, rds1, cell, j1, l1);
+            rI[b][tid] = cell.I;
+            rS[b][tid] = cell.S;
+            rC[b][tid] = cell.C;
+        }
+        __syncthreads();   // the region of frequency m is complete (buffer b is next written at m+2)
+        if (p2) {
+            const int q00 = oj * kPairR + oi, q01 = q00 + 1, q10 = q00 + kPairR, q11 = q10 + 1;
+            const R Iu = interp4(b00, b01, b10, b11, rI[b][q00], rI[b][q01], rI[b][q10], rI[b][q11]);
+            const R Su = interp4(b00, b01, b10, b11, rS[b][q00], rS[b][q01], rS[b][q10], rS[b][q11]);
+            const R Cu = interp4(b00, b01, b10, b11, rC[b][q00], rC[b][q01], rC[b][q10], rC[b][q11]);
+            Cell<R> cell;
+            sc_point(c2, R(qf[m]), R(wf[m]), gauss, Iu, Su, Cu, rds2, cell, j2, l2);
+            if (valid2) cell_put(rout, oc, so, cell);
+        }
+    }
+    if (core1) {
+        a.acc[((size_t(0) * kNDir + d) * L + l) * nv + v1] = j1;
+        a.acc[((size_t(1) * kNDir + d) * L + l) * nv + v1] = l1;
+    }
+    if (valid2) {
+        a.acc[((size_t(0) * kNDir + d) * L + l) * nv + v2] = j2;
+        a.acc[((size_t(1) * kNDir + d) * L + l) * nv + v2] = l2;
     }
 }
 

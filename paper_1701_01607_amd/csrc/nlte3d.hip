@@ -241,6 +241,7 @@ struct Level {
     int nslot = 2;   // direction-group slots in acc written by the last formal solution
     int fc = 1;      // frequency chunks per (direction, tile): fixed by the level shape
     int maxslot = 8; // direction-group slots allocated in acc (8 allows every block shape)
+    bool pair = false;   // two plane steps per launch (FP32, one frequency chunk, 24 acc slots)
     struct MarchPlan {
         int ppt = 0, threads = 0, F = 0, nchunk = 0;   // F = 0: plane-step sweep
         size_t lds = 0;
@@ -276,6 +277,28 @@ inline void march_plan(P& m, size_t nxy, int nline, int maxfreq, size_t rbytes, 
     m.lds = per_f * size_t(F + 1);
 }
 
+// Frequency chunks per (direction, tile) wave group of the plane-step sweep: small planes
+// give too few waves to fill the GPU with one wave per (direction, tile, line), so their
+// frequencies are split over 2 or 4 waves.  FP32 only (the FP64 kernel's registers allow
+// one).
+inline int freq_chunks_for(size_t nxy, int nline, size_t rbytes) {
+    if (rbytes != 4) return 1;
+    const double waves = double((nxy + 63) / 64) * nline * kNDir;
+    int fc = 1;
+    while (fc < 4 && waves * fc < 4096.0) fc *= 2;
+    return fc;
+}
+
+// Two plane steps per launch, on request, where it applies: FP32, nz >= 3, one frequency
+// chunk per wave (planes that fill the GPU) and 24 accumulator slots under 8 GiB.  It
+// moves half the plane state but measured slower than the plane-step sweep (its barrier
+// per frequency and five-wave blocks hide less latency), so it is not the default.
+inline bool pair_ok(size_t nxy, int nz, int nline, size_t rbytes, int mode) {
+    if (rbytes != 4 || nz < 3 || freq_chunks_for(nxy, nline, rbytes) != 1) return false;
+    if (mode != NLTE_SWEEP_PAIR) return false;
+    return double(2 * kNDir) * nline * double(nxy) * nz * double(rbytes) <= 8.0 * 1073741824.0;
+}
+
 // Accumulator slots for a level: every block shape (down to 3 directions, 8 slots) on
 // levels whose 8-slot accumulators stay under 4 GiB; larger levels keep 2 slots and
 // sweep with 12-direction blocks.
@@ -290,6 +313,7 @@ struct Job : JobBase {
     DevBuf atom_d, qf, wf, line_of_d, state, topI, scalar, repairs, estate, eout, flag, nprev;
     AtomInfo info{};
     int DB = 0;   // directions per sweep block (0: autotuned per level)
+    int nstate = 2;   // plane-state slots (3 when a level sweeps two planes per launch)
     int fine_db = 0;   // block shape of the last finest-level formal solution
     std::vector<double> hz_top;
     double updates_per_fs_fine = 0;
@@ -406,6 +430,11 @@ struct Job : JobBase {
             }
             L.nxy = size_t(L.nx) * L.ny;
             L.nvox = L.nxy * L.nz;
+            L.fc = freq_chunks(L);
+            L.pair = pair_eligible(L, p->sweep_kernel);
+            if (p->sweep_kernel == NLTE_SWEEP_PAIR)
+                REQUIRE(L.pair, "the two-plane sweep needs FP32, nz >= 3 and planes large enough for one "
+                                "frequency chunk per wave");
             dalloc(L.dz, sizeof(double) * L.nz);
             HIPCHK(hipMemcpyAsync(L.dz.p, L.z.data(), sizeof(double) * L.nz, hipMemcpyHostToDevice, st()));
             dalloc(L.prim, sizeof(double) * nprim * L.nvox);
@@ -431,7 +460,7 @@ struct Job : JobBase {
             march_plan(L.march, L.nxy, nline, maxfreq, sizeof(R), ctx->lds_max, p->sweep_kernel);
             if (p->sweep_kernel == NLTE_SWEEP_RESIDENT)
                 REQUIRE(L.march.F > 0, "the plane-resident sweep needs FP32 and planes of at most 4096 points");
-            const size_t slots = L.march.F ? size_t(kNDir) * L.march.nchunk : size_t(L.maxslot);
+            const size_t slots = L.march.F ? size_t(kNDir) * L.march.nchunk : (L.pair ? size_t(kNDir) : size_t(L.maxslot));
             dalloc(L.acc, sizeof(R) * 2 * slots * nline * L.nvox);
             dalloc(L.lc, sizeof(R) * 2 * nline * L.nvox);
             dalloc(L.partial, sizeof(double) * std::max<size_t>(blocks_for(L.nvox, 256), 1024));
@@ -460,14 +489,25 @@ struct Job : JobBase {
         // context's HBM budget (NLTE3D_SWEEP_STATE_MB overrides the state size cap).
         const char* envb = std::getenv("NLTE3D_SWEEP_STATE_MB");
         const double cap_bytes = envb ? std::atof(envb) * 1048576.0 : 0.25 * double(ctx->budget);
-        const double per_q = double(sizeof(Cell<R>)) * 2 * kNDir * nline * Fz.nxy;
-        Qpass = std::max(1, std::min(maxfreq, int(cap_bytes / per_q)));
         // a pass's (direction, line) column is addressed by 32-bit buffer offsets
         const double colmax = 4294967295.0 / (double(sizeof(Cell<R>)) * double(Fz.nxy));
-        Qpass = std::max(1, std::min(Qpass, int(colmax)));
+        bool any_pair = false;
+        for (auto& Lp : lev) any_pair = any_pair || Lp->pair;
+        nstate = any_pair ? 3 : 2;
+        for (;;) {
+            const double per_q = double(sizeof(Cell<R>)) * nstate * kNDir * nline * Fz.nxy;
+            Qpass = std::max(1, std::min(maxfreq, int(cap_bytes / per_q)));
+            Qpass = std::max(1, std::min(Qpass, int(colmax)));
+            if (nstate == 2 || Qpass >= maxfreq) break;
+            // the two-plane sweep needs every frequency in one pass: fall back
+            REQUIRE(p->sweep_kernel != NLTE_SWEEP_PAIR, "the two-plane sweep needs the plane state of all "
+                                                        "frequencies in one pass");
+            for (auto& Lp : lev) Lp->pair = false;
+            nstate = 2;
+        }
         // the plane state is needed only where a level sweeps plane by plane (planes shrink
         // towards the coarse levels, so the finest level decides)
-        if (!Fz.march.F) dalloc(state, sizeof(Cell<R>) * 2 * kNDir * size_t(nline) * Qpass * Fz.nxy);
+        if (!Fz.march.F) dalloc(state, sizeof(Cell<R>) * nstate * kNDir * size_t(nline) * Qpass * Fz.nxy);
         dalloc(nprev, sizeof(double) * N * Fz.nvox);
         if (p->top_I) {
             dalloc(topI, sizeof(R) * size_t(nf) * Fz.nxy);
@@ -491,13 +531,14 @@ struct Job : JobBase {
             zero_radiation(k0);
         }
         HIPCHK(hipStreamSynchronize(st()));
-        for (auto& Lp : lev) Lp->fc = freq_chunks(*Lp);
         if (log_enabled())
             for (int k = 0; k < nlev; ++k) {
                 const Level& L = *lev[k];
                 if (L.march.F)
                     log_line("level %d (%dx%dx%d): plane-resident sweep, %d frequencies x %d chunks, %d threads, %zu B LDS",
                              k, L.nx, L.ny, L.nz, L.march.F, L.march.nchunk, L.march.threads, L.march.lds);
+                else if (L.pair)
+                    log_line("level %d (%dx%dx%d): two-plane sweep (16x16 tiles)", k, L.nx, L.ny, L.nz);
                 else
                     log_line("level %d (%dx%dx%d): plane-step sweep, %d frequency chunks per wave group", k, L.nx,
                              L.ny, L.nz, L.fc);
@@ -523,16 +564,15 @@ struct Job : JobBase {
         return dim3(blocks_for(L.nxy, 64), nline, kNDir / db);
     }
 
+    // Two plane steps per launch when requested and the level qualifies (see pair_ok).
+    bool pair_eligible(const Level& L, int mode) const {
+        return pair_ok(L.nxy, L.nz, nline, sizeof(R), mode);
+    }
+
     // Frequency chunks per (direction, tile) wave group: small planes give too few waves
     // to fill the GPU with one wave per (direction, tile, line), so their frequencies
     // are split over 2 or 4 waves.  FP32 only (the FP64 kernel's registers allow one).
-    int freq_chunks(const Level& L) const {
-        if (sizeof(R) != 4) return 1;
-        const double waves = double(blocks_for(L.nxy, 64)) * nline * kNDir;
-        int fc = 1;
-        while (fc < 4 && waves * fc < 4096.0) fc *= 2;
-        return fc;
-    }
+    int freq_chunks(const Level& L) const { return freq_chunks_for(L.nxy, nline, sizeof(R)); }
 
     void launch_step(const SweepArgs<R>& a, dim3 grid, int db, int fc, int s) {
         const unsigned threads = unsigned(db * fc * 64);
@@ -660,8 +700,35 @@ struct Job : JobBase {
         a.topI = (k == nlev - 1 && topI.p) ? topI.as<R>() : nullptr;
         a.state = state.as<Cell<R>>();
         a.acc = L.acc.as<R>();
+        a.nstate = nstate;
+        a.dslots = L.pair ? 1 : 0;
         if (L.march.F) {
             march_launch(k);
+        } else if (L.pair) {
+            // boundary step and, for an even number of planes, the last step plane by
+            // plane; every other pair of steps in one launch
+            a.m0 = 0;
+            a.Q = Qpass;
+            a.add = 0;
+            const int db = tile_for(k, a);
+            if (k == nlev - 1) fine_db = db;
+            const dim3 grid = sweep_grid(L, nline, db);
+            const dim3 pgrid(unsigned(((L.nx + kPairT - 1) / kPairT) * ((L.ny + kPairT - 1) / kPairT)),
+                             unsigned(nline), unsigned(kNDir));
+            ev_begin(EV_SWEEP);
+            launch_step(a, grid, db, L.fc, 0);
+            int s = 1;
+            if constexpr (sizeof(R) == 4) {
+                for (; s + 1 < L.nz; s += 2) {
+                    sweep_pair_kernel<float><<<pgrid, kPairThreads, 0, st()>>>(a, s);
+                    ++sweep_launches;
+                }
+            }
+            for (; s < L.nz; ++s) launch_step(a, grid, db, L.fc, s);
+            sweep_launches += 1 + (L.nz % 2 == 0 ? 1 : 0);
+            HIPCHK(hipGetLastError());
+            ev_end();
+            L.nslot = kNDir;
         } else {
             const int db = tile_for(k, a);
             if (k == nlev - 1) fine_db = db;
@@ -957,7 +1024,8 @@ struct Job : JobBase {
         r.ms_transfer = ms_phase[EV_TRANSFER];
         r.sweep_launches = sweep_launches;
         r.dirs_per_block = fine_db;
-        r.sweep_kernel = lev[nlev - 1]->march.F ? NLTE_SWEEP_RESIDENT : NLTE_SWEEP_PLANE_STEP;
+        r.sweep_kernel = lev[nlev - 1]->march.F ? NLTE_SWEEP_RESIDENT
+                         : lev[nlev - 1]->pair ? NLTE_SWEEP_PAIR : NLTE_SWEEP_PLANE_STEP;
         res = r;
         if (out) *out = r;
     }
@@ -1125,13 +1193,15 @@ size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom
     size_t fine_nxy = size_t(nx) * ny, fine_nvox = fine_nxy * nz;
     int maxfreq = 0;
     for (int l = 0; l < nline; ++l) maxfreq = std::max(maxfreq, atom->info.line[l].nfreq);
-    bool fine_resident = false;
+    bool fine_resident = false, any_pair = false;
     for (int k = nlev - 1; k >= 0; --k) {
         const size_t nvox = size_t(nx) * ny * nz;
         Level::MarchPlan mp;
         march_plan(mp, size_t(nx) * ny, nline, maxfreq, R, ctx->lds_max, p->sweep_kernel);
         if (k == nlev - 1) fine_resident = mp.F > 0;
-        const size_t slots = mp.F ? size_t(kNDir) * mp.nchunk : size_t(acc_slots(nvox, nline, R));
+        const bool pr = !mp.F && pair_ok(size_t(nx) * ny, nz, nline, R, p->sweep_kernel);
+        any_pair = any_pair || pr;
+        const size_t slots = mp.F ? size_t(kNDir) * mp.nchunk : (pr ? size_t(kNDir) : size_t(acc_slots(nvox, nline, R)));
         bytes += 8 * size_t(nz) + 8 * size_t(nprim) * nvox + R * (6 * nline + 4) * nvox;
         bytes += 8 * (size_t(N) * 6 + size_t(N) * N + 1) * nvox + R * (2 * slots + 2) * nline * nvox;
         bytes += 8 * std::max<size_t>((nvox + 255) / 256, 1024);
@@ -1139,10 +1209,16 @@ size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom
     }
     const char* envb = std::getenv("NLTE3D_SWEEP_STATE_MB");
     const double cap = envb ? std::atof(envb) * 1048576.0 : 0.25 * double(ctx->budget);
-    const double per_q = double(3 * R) * 2 * kNDir * nline * fine_nxy;
-    int Q = std::max(1, std::min(maxfreq, int(cap / per_q)));
-    Q = std::max(1, std::min(Q, int(4294967295.0 / (double(3 * R) * double(fine_nxy)))));
-    if (!fine_resident) bytes += size_t(3 * R) * 2 * kNDir * size_t(nline) * Q * fine_nxy;
+    int nstate = any_pair ? 3 : 2;
+    int Q = 1;
+    for (;;) {
+        const double per_q = double(3 * R) * nstate * kNDir * nline * fine_nxy;
+        Q = std::max(1, std::min(maxfreq, int(cap / per_q)));
+        Q = std::max(1, std::min(Q, int(4294967295.0 / (double(3 * R) * double(fine_nxy)))));
+        if (nstate == 2 || Q >= maxfreq) break;
+        nstate = 2;
+    }
+    if (!fine_resident) bytes += size_t(3 * R) * nstate * kNDir * size_t(nline) * Q * fine_nxy;
     bytes += 8 * size_t(N) * fine_nvox;
     if (p->top_I) bytes += R * size_t(nf) * fine_nxy;
     bytes += 8 * 6 * size_t(nf) * fine_nxy;             // emergent-intensity state

@@ -21,7 +21,7 @@ W_NOT_CONVERGED, W_QUEUED = 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 MALI, FAS, FMG = 0, 1, 2
 FP64, MIXED = 0, 1
-SWEEP_AUTO, SWEEP_PLANE_STEP, SWEEP_RESIDENT = 0, 1, 2
+SWEEP_AUTO, SWEEP_PLANE_STEP, SWEEP_RESIDENT, SWEEP_PAIR = 0, 1, 2, 3
 INIT_ZERO_RAD, INIT_LTE, INIT_USER = 0, 1, 2
 
 SYMBOLS = (

@@ -52,8 +52,9 @@ def homogeneous(nx, ny):
     return atm
 
 
-@pytest.mark.parametrize("prec,tol_fs,tol_n,kern", [(0, 1e-9, 1e-9, 1), (1, 2e-4, 1e-3, 1), (1, 2e-4, 1e-3, 2)],
-                         ids=["fp64", "fp32_plane_step", "fp32_resident"])
+@pytest.mark.parametrize("prec,tol_fs,tol_n,kern", [(0, 1e-9, 1e-9, 1), (1, 2e-4, 1e-3, 1), (1, 2e-4, 1e-3, 2),
+                                                     (1, 2e-4, 1e-3, 3)],
+                         ids=["fp64", "fp32_plane_step", "fp32_resident", "fp32_two_plane"])
 def test_full_size_homogeneous_equals_1d_oracle(nl, ctx, prec, tol_fs, tol_n, kern):
     atom = synth.caii_like_atom(101)
     atm3, atm1 = homogeneous(64, 64), homogeneous(1, 1)

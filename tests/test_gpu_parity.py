@@ -296,10 +296,10 @@ def test_block_shape_does_not_change_results(nl, ctx, prec, nx, ny, shapes_):
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
-@pytest.mark.parametrize("kern", [1, 2], ids=["plane_step", "resident"])
+@pytest.mark.parametrize("kern", [1, 2, 3], ids=["plane_step", "resident", "two_plane"])
 def test_formal_solution_parity_one_chunk_per_wave(nl, ctx, prec, tol, kern):
-    if kern == 2 and prec == 0:
-        pytest.skip("the plane-resident sweep is FP32 only")
+    if kern >= 2 and prec == 0:
+        pytest.skip("the plane-resident and two-plane sweeps are FP32 only")
     """A plane large enough for one frequency chunk per wave (the layout of the bench's
     finest grid), against the oracle."""
     atom = synth.caii_like_atom(9)
@@ -355,3 +355,26 @@ def test_plane_resident_sweep_requests(nl, ctx):
     with pytest.raises(nl.NlteError):
         ctx.job(ctx.atmos(big), M, nl.SolveParams(method=nl.MALI, precision=nl.MIXED, nlev=1,
                                                   sweep_kernel=nl.SWEEP_RESIDENT))
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(48, 48, 9), (56, 48, 10)])
+def test_two_plane_sweep_equals_plane_step_bitwise(nl, ctx, nx, ny, nz):
+    """The two-plane sweep computes the same cells and sums as the plane-step sweep with the
+    same code, so formal solutions and MALI iterations agree bit for bit (56 = 3.5 tiles of
+    16 and an even nz exercise ragged tiles and the closing single step)."""
+    atom = synth.caii_like_atom(9)
+    atm = synth.atmos_stratified(nx=nx, ny=ny, nz=nz, dx=120 * synth.KM, seed=41)
+    npop, nln = shapes(atom, atm)
+    A, M = ctx.atmos(atm), ctx.atom(atom)
+    outs = []
+    for kern in (nl.SWEEP_PLANE_STEP, nl.SWEEP_PAIR):
+        job = ctx.job(A, M, nl.SolveParams(method=nl.MALI, precision=nl.MIXED, nlev=1, max_iter=3, E_target=0.0,
+                                           sweep_kernel=kern))
+        jg, og = job.formal_solution(0, nln)
+        job.mali(0, 3)
+        rc, r = job.run()
+        assert r.sweep_kernel == kern
+        outs.append((jg, og, job.populations(0, npop)))
+        job.close()
+    for x, y in zip(*outs):
+        assert np.array_equal(x, y)
