@@ -34,7 +34,7 @@ STATE_BYTES_PER_UPDATE = 24.0        # FP32 cells; FP64 cells are twice that
 # counter runs of `bench.py --kernel-probe` (each scaled by the counter's reading for a
 # plain device copy of known size), keyed by (workload, directions per block).  Only for
 # the kernel as it was when the counters were taken.
-MEASURED_BYTES_PER_UPDATE = {("caii6_64x64x129", 3): 25.23}
+MEASURED_BYTES_PER_UPDATE = {("caii6_64x64x129", 3): 25.19}
 VOXEL_BYTES_PER_GROUP = (11 + 2) * 4.0   # FP32; twice that in FP64
 
 # FP32 flops per update (FMA = 2) for the ALU side of the roofline: profile argument
@@ -194,7 +194,7 @@ def main():
     log(f"generating {args.workload} ...")
     atom, atm = synth.workload(args.workload)
     sample = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.kernel_probe:
         log("cpu baseline (oracle sample, before the GPU is initialised) ...")
         sample = cpu_baseline_sample(atom, atm)
 
