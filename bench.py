@@ -25,24 +25,28 @@ PEAK_HBM_GBS = 8000.0           # MI355X HBM3E (published)
 PEAK_FP64_TFLOPS = 78.6         # MI355X vector FP64 (published)
 
 # Algorithmic HBM bytes per voxel-direction-frequency update of the sweep.  The plane
-# state (I, S, chi per direction, frequency and plane point, 12 B in FP32) lives in HBM
-# between plane steps: each cell is written once and read back once by the next step
-# (its four upwind readers share it through L2).  Per (voxel, line, direction group)
-# the block also reads 11 per-voxel constants and writes 2 partial sums.
-STATE_BYTES_PER_UPDATE = 24.0        # FP32 cells; FP64 cells are twice that
+# state (one cell per direction, frequency and plane point: I and phi, 8 B, in FP32;
+# I, S and chi, 24 B, in FP64) lives in HBM between plane steps: each cell is written
+# once and read back once by the next step (its four upwind readers share it through
+# L2).  Per (voxel, line, direction group) the block also reads 11 per-voxel constants
+# and writes 2 partial sums.
+STATE_BYTES_PER_UPDATE = {False: 16.0, True: 48.0}   # keyed by "FP64 sweep"
 # HBM bytes per update of the finest-grid sweep launches from FETCH_SIZE + WRITE_SIZE
 # counter runs of `bench.py --kernel-probe` (each scaled by the counter's reading for a
 # plain device copy of known size), keyed by (workload, directions per block).  Only for
 # the kernel as it was when the counters were taken.
-MEASURED_BYTES_PER_UPDATE = {("caii6_64x64x129", 3): 25.19}
+MEASURED_BYTES_PER_UPDATE = {("caii6_64x64x129", 3): 16.60}
 VOXEL_BYTES_PER_GROUP = (11 + 2) * 4.0   # FP32; twice that in FP64
 
-# FP32 flops per update (FMA = 2) for the ALU side of the roofline: profile argument
-# 2, opacity/source function 7, three bilinear interpolations 21, optical depth 3,
-# segment coefficients 7, intensity 5, quadrature weight 2, accumulations 10 (57),
-# plus the profile: Weideman N=16 core (|u| < 6) 88, asymptotic wing 46, Gaussian 3.
-FLOPS_PER_UPDATE_BASE = 57
-FLOPS_VOIGT_CORE, FLOPS_VOIGT_WING, FLOPS_GAUSS = 88, 46, 3
+# Flops per update (FMA = 2, a reciprocal, exponential or cosine = 1) for the ALU side
+# of the roofline: profile argument 2, opacity/source function 7, three bilinear
+# interpolations 21, optical depth 3, segment coefficients 7, intensity 5, quadrature
+# weight 2, accumulations 10 (57); FP32 cells add the opacity and source function of
+# the four upwind corners rebuilt from phi (4 x 6); plus the profile: the Weideman N=32
+# series (|u| < 5, evaluated in FP64) 154, the FP32 asymptotic wing with its Gaussian
+# term 64, a pure Gaussian 3.
+FLOPS_PER_UPDATE_BASE = {False: 57 + 24, True: 57}
+FLOPS_VOIGT_CORE, FLOPS_VOIGT_WING, FLOPS_GAUSS = 154, 64, 3
 
 WORKLOADS = {
     "caii6_64x64x129": dict(nlev=3, nu0=20, nu1=4, nu2=8, nu3=32, nu_fmg=16, method="FAS", fp64=False,
@@ -61,10 +65,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def flops_per_update(atom, atm, stride=61):
-    """Mean FP32 flops per update on the finest grid: the profile costs the Weideman
-    core where |u| < 6 and the asymptotic wing elsewhere, so the fraction of core
-    evaluations is counted on a sample of voxels over all directions and frequencies."""
+def flops_per_update(atom, atm, fp64, stride=61):
+    """Mean flops per update on the finest grid: the profile costs the Weideman series
+    where |u| < 5 (everywhere in FP64 sweeps) and the asymptotic wing elsewhere, so the
+    fraction of series evaluations is counted on a sample of voxels over all directions
+    and frequencies."""
     import numpy as np
     kb, amu = 1.380649e-16, 1.66053906660e-24
     sl = slice(None, None, stride)
@@ -78,17 +83,18 @@ def flops_per_update(atom, atm, stride=61):
     vn = mus @ v                                                   # [24][sample]
     total = core = 0.0
     flops = 0.0
+    base = FLOPS_PER_UPDATE_BASE[fp64]
     for ln in atom["lines"]:
         q = np.asarray(ln["q"], dtype=np.float64)
         n = q.size * vn.size
         total += n
         if not (ln["gamma_rad"] or ln["gamma_vdw"]):
-            flops += n * (FLOPS_PER_UPDATE_BASE + FLOPS_GAUSS)
+            flops += n * (base + FLOPS_GAUSS)
             continue
         u = (q[:, None, None] - vn[None]) / vD[None, None]
-        c = float(np.count_nonzero(np.abs(u) < 6.0))
+        c = float(n) if fp64 else float(np.count_nonzero(np.abs(u) < 5.0))
         core += c
-        flops += n * FLOPS_PER_UPDATE_BASE + c * FLOPS_VOIGT_CORE + (n - c) * FLOPS_VOIGT_WING
+        flops += n * base + c * FLOPS_VOIGT_CORE + (n - c) * FLOPS_VOIGT_WING
     return flops / total, core / total
 
 
@@ -260,11 +266,11 @@ def main():
     upd = sum(x.updates for _, x in results)
     sweep_ms = sum(x.ms_sweep for _, x in results)
     launches = sum(x.sweep_launches for _, x in results)
-    fl, core_frac = flops_per_update(atom, atm)
+    fl, core_frac = flops_per_update(atom, atm, wl["fp64"])
     nslot = 24 // r.dirs_per_block if r.dirs_per_block else 8
     nfl = nf / len(atom["lines"])
     wbytes = 2.0 if wl["fp64"] else 1.0
-    bytes_upd = wbytes * (STATE_BYTES_PER_UPDATE + VOXEL_BYTES_PER_GROUP * nslot / (24.0 * nfl))
+    bytes_upd = STATE_BYTES_PER_UPDATE[wl["fp64"]] + wbytes * VOXEL_BYTES_PER_GROUP * nslot / (24.0 * nfl)
     peak_alu = PEAK_FP64_TFLOPS if wl["fp64"] else PEAK_FP32_TFLOPS
     measured = MEASURED_BYTES_PER_UPDATE.get((args.workload, r.dirs_per_block))
     traffic = None

@@ -63,15 +63,20 @@ __device__ inline bool opaque(double chi) { return chi >= 1e-150; }
 // the line source function e/k, else 0; rchi is 0 there (the point's own weight
 // w phi~ vanishes with phi, but a segment from an opaque upwind point still sees S).
 template <typename R>
+__device__ inline R source_limit(R chic, R etac, R kpl, R el) {
+    if (opaque(chic)) return etac * dev_rcp(chic);
+    if (opaque(kpl)) return el * dev_rcp(kpl);
+    return R(0);
+}
+
+template <typename R>
 __device__ inline R source_fn(R chi, R chic, R etac, R kpl, R el, R phi, R& rchi) {
     if (opaque(chi)) {
         rchi = dev_rcp(chi);
         return fma(el, phi, etac) * rchi;
     }
     rchi = R(0);
-    if (opaque(chic)) return etac * dev_rcp(chic);
-    if (opaque(kpl)) return el * dev_rcp(kpl);
-    return R(0);
+    return source_limit(chic, etac, kpl, el);
 }
 
 // H(a, u) for a >= 0 (Weideman rational series).  p has real coefficients, so p(Z) is

@@ -183,12 +183,32 @@ __global__ void line_coef_kernel(const AtomInfo* atom, const double* n, R* lc, s
 }
 
 // ------------------------------------------------------------------ sweep
-// Plane state of one (direction, frequency, point): intensity, source function and
-// opacity, stored together so one 12-byte load fetches an upwind corner.
+// Plane state of one (direction, frequency, point).  FP32 stores the intensity and the
+// profile value phi (8 bytes): a reader rebuilds an upwind corner's opacity and source
+// function from phi and that voxel's line constants with the writer's own expressions
+// (corner_SC), so it sees exactly the values the writer computed while a third less state
+// moves through HBM.  FP64, bound by its arithmetic, where the rebuild's divisions would
+// cost more than the bytes save, stores the intensity, source function and opacity.
 template <typename R>
-struct Cell {
-    R I, S, C;
+struct Cell;
+template <>
+struct Cell<float> {
+    float I, P;
 };
+template <>
+struct Cell<double> {
+    double I, S, C;
+};
+template <typename R>
+constexpr bool kPhiCell = sizeof(R) == 4;
+
+// Everything one update produces at a point: intensity, source function, opacity, phi.
+template <typename R>
+struct CellVals {
+    R I, S, C, P;
+};
+__device__ inline Cell<float> make_cell(const CellVals<float>& v) { return Cell<float>{v.I, v.P}; }
+__device__ inline Cell<double> make_cell(const CellVals<double>& v) { return Cell<double>{v.I, v.S, v.C}; }
 
 // Cells move through raw buffer instructions: the resource holds the wave-uniform base
 // of one (direction, line) column and its size, the lane supplies a fixed byte offset
@@ -199,12 +219,13 @@ __device__ inline __amdgpu_buffer_rsrc_t cell_rsrc(const void* base, unsigned by
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, int(bytes), 0x00020000);
 }
 
-typedef float f32x3 __attribute__((ext_vector_type(3)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 
 __device__ inline Cell<float> cell_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-    const f32x3 x = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
-    return Cell<float>{x.x, x.y, x.z};
+    const f32x2 x = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    return Cell<float>{x.x, x.y};
 }
 __device__ inline Cell<double> cell_load_d(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
     const f64x2 a = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
@@ -219,7 +240,7 @@ template <> __device__ inline Cell<double> cell_get<double>(__amdgpu_buffer_rsrc
     return cell_load_d(r, voff, soff);
 }
 __device__ inline void cell_put(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, const Cell<float>& c) {
-    __builtin_amdgcn_raw_buffer_store_b96(f32x3{c.I, c.S, c.C}, r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, f32x2{c.I, c.P}), r, voff, soff, 0);
 }
 __device__ inline void cell_put(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, const Cell<double>& c) {
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned,
@@ -295,9 +316,74 @@ __device__ inline R interp4(R w00, R w01, R w10, R w11, R a00, R a01, R a10, R a
     return fma(w00, a00, fma(w01, a01, fma(w10, a10, w11 * a11)));
 }
 
+// Line constants of an upwind corner voxel, to rebuild its opacity and source function
+// from a stored phi; sfb is the source function where the opacity is negligible, which
+// does not depend on phi.
+template <typename R>
+struct CornerConst {
+    R kpl, chic, el, etac, sfb;
+};
+template <typename R>
+struct Corners {
+    CornerConst<R> q00, q01, q10, q11;
+};
+
+template <typename R>
+__device__ inline CornerConst<R> corner_const(const R* sc, const R* lc, int L, int l, size_t nv, size_t v) {
+    CornerConst<R> q;
+    q.chic = sc[(SC_CHIC * L + l) * nv + v];
+    q.etac = sc[(SC_ETAC * L + l) * nv + v];
+    q.kpl = lc[size_t(l) * nv + v];
+    q.el = lc[size_t(L + l) * nv + v];
+    q.sfb = source_limit(q.chic, q.etac, q.kpl, q.el);
+    return q;
+}
+
+// The corners' constants where cells carry phi (FP32); nothing to load otherwise.
+template <typename R>
+__device__ inline Corners<R> corners_at(const R* sc, const R* lc, int L, int l, size_t nv, size_t v00, size_t v01,
+                                        size_t v10, size_t v11) {
+    Corners<R> q{};
+    if constexpr (kPhiCell<R>) {
+        q.q00 = corner_const<R>(sc, lc, L, l, nv, v00);
+        q.q01 = corner_const<R>(sc, lc, L, l, nv, v01);
+        q.q10 = corner_const<R>(sc, lc, L, l, nv, v10);
+        q.q11 = corner_const<R>(sc, lc, L, l, nv, v11);
+    }
+    return q;
+}
+
+// Opacity and source function of a point from phi: the expressions of sc_point.
+template <typename R>
+__device__ inline void corner_SC(const CornerConst<R>& q, R phi, R& S, R& chi) {
+    chi = fma(q.kpl, phi, q.chic);
+    S = opaque(chi) ? fma(q.el, phi, q.etac) * dev_rcp(chi) : q.sfb;
+}
+
+// Upwind intensity, source function and opacity: bilinear in the four corner cells.
+__device__ inline void upwind_values(const Corners<float>& q, float w00, float w01, float w10, float w11,
+                                     const Cell<float>& c00, const Cell<float>& c01, const Cell<float>& c10,
+                                     const Cell<float>& c11, float& Iu, float& Su, float& Cu) {
+    float S00, S01, S10, S11, X00, X01, X10, X11;
+    corner_SC(q.q00, c00.P, S00, X00);
+    corner_SC(q.q01, c01.P, S01, X01);
+    corner_SC(q.q10, c10.P, S10, X10);
+    corner_SC(q.q11, c11.P, S11, X11);
+    Iu = interp4(w00, w01, w10, w11, c00.I, c01.I, c10.I, c11.I);
+    Su = interp4(w00, w01, w10, w11, S00, S01, S10, S11);
+    Cu = interp4(w00, w01, w10, w11, X00, X01, X10, X11);
+}
+__device__ inline void upwind_values(const Corners<double>&, double w00, double w01, double w10, double w11,
+                                     const Cell<double>& c00, const Cell<double>& c01, const Cell<double>& c10,
+                                     const Cell<double>& c11, double& Iu, double& Su, double& Cu) {
+    Iu = interp4(w00, w01, w10, w11, c00.I, c01.I, c10.I, c11.I);
+    Su = interp4(w00, w01, w10, w11, c00.S, c01.S, c10.S, c11.S);
+    Cu = interp4(w00, w01, w10, w11, c00.C, c01.C, c10.C, c11.C);
+}
+
 template <typename R>
 __device__ inline void sc_point(const PointConst<R>& c, R q, R w, bool gauss, R Iu, R Su, R Cu, R rds,
-                                Cell<R>& cell, R& jacc, R& lacc) {
+                                CellVals<R>& cell, R& jacc, R& lacc) {
     const R u = q * c.ivD - c.vn;
     const R H = profile_H<R>(c.adamp, u, gauss);
     const R phi = H * c.pn;
@@ -311,6 +397,7 @@ __device__ inline void sc_point(const PointConst<R>& c, R q, R w, bool gauss, R 
     cell.I = fma(po, S, Ith);
     cell.S = S;
     cell.C = chi;
+    cell.P = phi;
     const R wphi = w * H * c.pw;
     const R por = po * rchi;
     jacc = fma(wphi, fma(por, c.etac, Ith), jacc);
@@ -340,10 +427,14 @@ struct SweepArgs {
 };
 
 constexpr int kMaxSweepWaves = 12;
+// FP32: at most 80 VGPRs, so six waves share each SIMD (the sweep hides its HBM latency
+// with waves); FP64 needs its ~175 registers.
+constexpr int kSweepWavesPerSimdF32 = 6;
 
 template <typename R, int DB>
-__global__ __launch_bounds__((sizeof(R) == 4 ? kMaxSweepWaves : DB) * 64) void sweep_step_kernel(SweepArgs<R> a,
-                                                                                                   int s) {
+__global__ __launch_bounds__((sizeof(R) == 4 ? kMaxSweepWaves : DB) * 64)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? kSweepWavesPerSimdF32 : 1))) void sweep_step_kernel(
+    SweepArgs<R> a, int s) {
     static_assert(DB == 3 || DB == 6 || DB == 12, "direction groups follow the fixed tree");
     constexpr int kW = 64;
     const int lane = int(threadIdx.x) & (kW - 1);
@@ -397,13 +488,11 @@ __global__ __launch_bounds__((sizeof(R) == 4 ? kMaxSweepWaves : DB) * 64) void s
             const R u = qf[m] * pc.ivD - pc.vn;
             const R H = profile_H<R>(pc.adamp, u, gauss);
             const R phi = H * pc.pn;
-            const R chi = pc.chic + pc.kpl * phi;
+            const R chi = fma(pc.kpl, phi, pc.chic);
             R rchi_b;
             const R S = source_fn(chi, pc.chic, pc.etac, pc.kpl, pc.el, phi, rchi_b);
             const R I = (h == 0) ? Bb : (top ? top[size_t(m) * nxy] : R(0));
-            Cell<R> cell;
-            cell.I = I; cell.S = S; cell.C = chi;
-            if (valid) cell_put(rcur, oc, unsigned(m - a.m0) * rowb, cell);
+            if (valid) cell_put(rcur, oc, unsigned(m - a.m0) * rowb, make_cell(CellVals<R>{I, S, chi, phi}));
             const R wphi = wf[m] * H * pc.pw;
             jacc += wphi * I;
             lacc += wphi;
@@ -421,6 +510,9 @@ __global__ __launch_bounds__((sizeof(R) == 4 ? kMaxSweepWaves : DB) * 64) void s
         const int y1 = (y0 + 1 == a.ny) ? 0 : y0 + 1;
         const unsigned o00 = unsigned(y0 * a.nx + x0) * csz, o01 = unsigned(y0 * a.nx + x1) * csz;
         const unsigned o10 = unsigned(y1 * a.nx + x0) * csz, o11 = unsigned(y1 * a.nx + x1) * csz;
+        const size_t vp = size_t(kp) * nxy;
+        const Corners<R> qc = corners_at<R>(a.sc, a.lc, L, l, nv, vp + o00 / csz, vp + o01 / csz,
+                                            vp + o10 / csz, vp + o11 / csz);
         const R w00 = (R(1) - fx) * (R(1) - fy), w01 = fx * (R(1) - fy);
         const R w10 = (R(1) - fx) * fy, w11 = fx * fy;
         const R rds = R(ds);
@@ -429,12 +521,11 @@ __global__ __launch_bounds__((sizeof(R) == 4 ? kMaxSweepWaves : DB) * 64) void s
             const unsigned so = unsigned(m - a.m0) * rowb;
             const Cell<R> c00 = cell_get<R>(rprv, o00, so), c01 = cell_get<R>(rprv, o01, so);
             const Cell<R> c10 = cell_get<R>(rprv, o10, so), c11 = cell_get<R>(rprv, o11, so);
-            const R Iu = interp4(w00, w01, w10, w11, c00.I, c01.I, c10.I, c11.I);
-            const R Su = interp4(w00, w01, w10, w11, c00.S, c01.S, c10.S, c11.S);
-            const R Cu = interp4(w00, w01, w10, w11, c00.C, c01.C, c10.C, c11.C);
-            Cell<R> cell;
+            R Iu, Su, Cu;
+            upwind_values(qc, w00, w01, w10, w11, c00, c01, c10, c11, Iu, Su, Cu);
+            CellVals<R> cell;
             sc_point(pc, R(qf[m]), R(wf[m]), gauss, Iu, Su, Cu, rds, cell, jacc, lacc);
-            if (valid) cell_put(rcur, oc, so, cell);
+            if (valid) cell_put(rcur, oc, so, make_cell(cell));
         }
     }
     __shared__ R sj[kMaxSweepWaves * kW];
@@ -563,6 +654,9 @@ __global__ __launch_bounds__(kPairThreads) void sweep_pair_kernel(SweepArgs<R> a
     const unsigned o00 = unsigned(ya * nx + xa) * csz, o01 = unsigned(ya * nx + xb) * csz;
     const unsigned o10 = unsigned(yb * nx + xa) * csz, o11 = unsigned(yb * nx + xb) * csz;
     const unsigned oc = unsigned(y2 * nx + x2) * csz;
+    const size_t vp = size_t(k0) * nxy;
+    const Corners<R> qc = corners_at<R>(a.sc, a.lc, L, l, nv, vp + size_t(ya) * nx + xa, vp + size_t(ya) * nx + xb,
+                                        vp + size_t(yb) * nx + xa, vp + size_t(yb) * nx + xb);
     const int nf = ln.nfreq;                        // single pass: a.m0 = 0, a.Q >= nf
     const size_t dstride = size_t(L) * a.Q * nxy;
     const size_t slot_stride = size_t(kNDir) * dstride;
@@ -582,10 +676,9 @@ __global__ __launch_bounds__(kPairThreads) void sweep_pair_kernel(SweepArgs<R> a
         if (p1) {
             const Cell<R> e00 = cell_get<R>(rprv, o00, so), e01 = cell_get<R>(rprv, o01, so);
             const Cell<R> e10 = cell_get<R>(rprv, o10, so), e11 = cell_get<R>(rprv, o11, so);
-            const R Iu = interp4(a00, a01, a10, a11, e00.I, e01.I, e10.I, e11.I);
-            const R Su = interp4(a00, a01, a10, a11, e00.S, e01.S, e10.S, e11.S);
-            const R Cu = interp4(a00, a01, a10, a11, e00.C, e01.C, e10.C, e11.C);
-            Cell<R> cell;
+            R Iu, Su, Cu;
+            upwind_values(qc, a00, a01, a10, a11, e00, e01, e10, e11, Iu, Su, Cu);
+            CellVals<R> cell;
             sc_point(c1, R(qf[m]), R(wf[m]), gauss, Iu, Su, Cu, rds1, cell, j1, l1);
             rI[b][tid] = cell.I;
             rS[b][tid] = cell.S;
@@ -597,9 +690,9 @@ __global__ __launch_bounds__(kPairThreads) void sweep_pair_kernel(SweepArgs<R> a
             const R Iu = interp4(b00, b01, b10, b11, rI[b][q00], rI[b][q01], rI[b][q10], rI[b][q11]);
             const R Su = interp4(b00, b01, b10, b11, rS[b][q00], rS[b][q01], rS[b][q10], rS[b][q11]);
             const R Cu = interp4(b00, b01, b10, b11, rC[b][q00], rC[b][q01], rC[b][q10], rC[b][q11]);
-            Cell<R> cell;
+            CellVals<R> cell;
             sc_point(c2, R(qf[m]), R(wf[m]), gauss, Iu, Su, Cu, rds2, cell, j2, l2);
-            if (valid2) cell_put(rout, oc, so, cell);
+            if (valid2) cell_put(rout, oc, so, make_cell(cell));
         }
     }
     if (core1) {

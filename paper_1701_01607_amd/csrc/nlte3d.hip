@@ -1188,6 +1188,7 @@ size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom
     const int nline = atom->info.nline, N = atom->info.N, nf = atom->nf;
     const int nlev = std::max(1, p->method == NLTE_MALI ? 1 : p->nlev);
     const int nprim = 7 + atm->nline_chic;
+    const size_t cell = R == 8 ? sizeof(Cell<double>) : sizeof(Cell<float>);
     size_t bytes = sizeof(AtomInfo) + (2 * R + 4) * size_t(nf) + 64;
     int nx = atm->nx, ny = atm->ny, nz = atm->nz;
     size_t fine_nxy = size_t(nx) * ny, fine_nvox = fine_nxy * nz;
@@ -1212,13 +1213,13 @@ size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom
     int nstate = any_pair ? 3 : 2;
     int Q = 1;
     for (;;) {
-        const double per_q = double(3 * R) * nstate * kNDir * nline * fine_nxy;
+        const double per_q = double(cell) * nstate * kNDir * nline * fine_nxy;
         Q = std::max(1, std::min(maxfreq, int(cap / per_q)));
-        Q = std::max(1, std::min(Q, int(4294967295.0 / (double(3 * R) * double(fine_nxy)))));
+        Q = std::max(1, std::min(Q, int(4294967295.0 / (double(cell) * double(fine_nxy)))));
         if (nstate == 2 || Q >= maxfreq) break;
         nstate = 2;
     }
-    if (!fine_resident) bytes += size_t(3 * R) * nstate * kNDir * size_t(nline) * Q * fine_nxy;
+    if (!fine_resident) bytes += cell * nstate * kNDir * size_t(nline) * Q * fine_nxy;
     bytes += 8 * size_t(N) * fine_nvox;
     if (p->top_I) bytes += R * size_t(nf) * fine_nxy;
     bytes += 8 * 6 * size_t(nf) * fine_nxy;             // emergent-intensity state
