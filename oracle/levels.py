@@ -14,7 +14,8 @@ Readings:
   isotropic I = B gives Jbar = B exactly.  Used only inside the Jbar and Lambda*
   quadratures.
 * Grid hierarchy (Sect. 4.1, 4.2, 4.7): the coarse level keeps every second point;
-  its atmosphere is the full-weighting restriction of the finer one.  Level index
+  its atmosphere is the restriction of the finer one (full weighting unless another
+  operator is asked for).  Level index
   k = 1 is the coarsest, k = nlev the finest (Sect. 2.2).
 """
 from __future__ import annotations
@@ -109,15 +110,16 @@ class Level:
         return kk, ee
 
 
-def build_hierarchy(atom, atmos, nlev, top_I=None):
-    """Levels [k=1 (coarsest), ..., k=nlev (finest)] as a list indexed k-1."""
+def build_hierarchy(atom, atmos, nlev, top_I=None, coarse_op="full"):
+    """Levels [k=1 (coarsest), ..., k=nlev (finest)] as a list indexed k-1; each coarser
+    atmosphere is the restriction (`coarse_op`) of the next finer one."""
     nx, ny, nz = atmos["nx"], atmos["ny"], atmos["nz"]
     step = 2 ** (nlev - 1)
     if nx % step or ny % step or (nz - 1) % step:
         raise ValueError("grid %dx%dx%d does not admit %d levels" % (nx, ny, nz, nlev))
     atms = [atmos]
     for _ in range(nlev - 1):
-        atms.append(coarsen_atmosphere(atms[-1]))
+        atms.append(coarsen_atmosphere(atms[-1], coarse_op))
     levels = [Level(atom, a) for a in reversed(atms)]
     if top_I is not None:
         levels[-1].top_I = top_I

@@ -54,6 +54,8 @@ class Params:
     max_iter: int = 2000
     tol_C: float | None = None
     E_target: float | None = 1.0e-3
+    restriction: str = "full"      # populations and residuals (Sect. 4.4)
+    coarse_atmos: str = "full"     # coarse model atmospheres (Sect. 4.7)
 
 
 @dataclass
@@ -108,8 +110,8 @@ def vcycle(levels, k, n, f, p, first=False, stats=None, fs0=None):
     fs_n = fs0 if (nu_pre == 0 and fs0 is not None) else _fs(lev, k, n, stats)
     r = f - apply_W(lev, n, *fs_n)
     levc = levels[k - 2]
-    nc = restrict(n)
-    rc = restrict(r)
+    nc = restrict(n, p.restriction)
+    rc = restrict(r, p.restriction)
     fs_c = _fs(levc, k - 1, nc, stats)
     fc = rc + apply_W(levc, nc, *fs_c)
     n_before = nc.copy()
@@ -167,7 +169,7 @@ def solve_mali(atom, atmos, p, stats=None, n0=None, iters=None, top_I=None):
 def solve_fas(atom, atmos, p, fmg=False, stats=None, cycles=None, levels=None):
     """FAS V-cycles (optionally preceded by full multigrid) until the stop rule."""
     stats = stats if stats is not None else Stats()
-    levels = levels if levels is not None else build_hierarchy(atom, atmos, p.nlev)
+    levels = levels if levels is not None else build_hierarchy(atom, atmos, p.nlev, coarse_op=p.coarse_atmos)
     L = len(levels)
     fine = levels[-1]
     f = fine_rhs(fine)

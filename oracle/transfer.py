@@ -2,11 +2,18 @@
 
 * Coarsening (Sect. 4.1): the coarse grid keeps every second point along x, y and z,
   both vertical boundaries included (Sect. 4.2: odd N_z at every level).
-* Restriction (Sect. 4.4): full weighting, the 27-point tensor product of the 1D
-  weights [1/4, 1/2, 1/4] centred on fine index 2c.  Periodic in x and y.  At the two
-  vertical boundary planes the reading is [1/2 self, 1/2 inward neighbour], which keeps
-  the trapezoid sum of a field exactly (the paper states full weighting conserves the
-  domain integral).  Weights are in index space.
+* Restriction (Sect. 4.4), three operators, all centred on fine index 2c, periodic in x
+  and y, weights in index space:
+  - full weighting: the 27-point tensor product of the 1D weights [1/4, 1/2, 1/4].  At
+    the two vertical boundary planes the reading is [1/2 self, 1/2 inward neighbour],
+    which keeps the trapezoid sum of a field exactly (the paper states full weighting
+    conserves the domain integral);
+  - half weighting: the point itself and its six neighbours along the axes, with the
+    standard 7-point weights of the multigrid literature the paper cites (1/2 for the
+    point, 1/12 for each neighbour).  At a vertical boundary plane the missing outward
+    neighbour's 1/12 goes to the inward one, the same fold as full weighting's boundary
+    rows (a mirror of the stencil);
+  - injection: the coarse value is the fine value at the same point.
 * Prolongation (Sect. 4.5): trilinear, the 8-point tensor product of 1D linear
   interpolation.  In x and y (uniform, periodic) an odd fine point is the mean of its
   two coarse neighbours; in z the weights are linear in the physical height.
@@ -35,10 +42,28 @@ def _restrict_z(q, axis):
     return np.moveaxis(out, 0, axis)
 
 
-def restrict(q):
-    """Full-weighting restriction of q[..., nz, ny, nx] to [..., (nz+1)/2, ny/2, nx/2]."""
+def _half_weighting(q):
+    zd = np.concatenate([q[..., 1:2, :, :], q[..., :-1, :, :]], axis=-3)   # value below (mirrored at the bottom)
+    zu = np.concatenate([q[..., 1:, :, :], q[..., -2:-1, :, :]], axis=-3)  # value above (mirrored at the top)
+    nb = (np.roll(q, 1, axis=-1) + np.roll(q, -1, axis=-1) + np.roll(q, 1, axis=-2) + np.roll(q, -1, axis=-2)
+          + zd + zu)
+    return (0.5 * q + nb / 12.0)[..., ::2, ::2, ::2]
+
+
+RESTRICTIONS = ("full", "half", "inject")
+
+
+def restrict(q, op="full"):
+    """Restriction of q[..., nz, ny, nx] to [..., (nz+1)/2, ny/2, nx/2] by full weighting,
+    half weighting or injection."""
     q = np.asarray(q, dtype=np.float64)
     assert q.shape[-1] % 2 == 0 and q.shape[-2] % 2 == 0 and q.shape[-3] % 2 == 1
+    if op == "inject":
+        return q[..., ::2, ::2, ::2].copy()
+    if op == "half":
+        return _half_weighting(q)
+    if op != "full":
+        raise ValueError("unknown restriction %r" % (op,))
     q = _restrict_periodic(q, q.ndim - 1)
     q = _restrict_periodic(q, q.ndim - 2)
     return _restrict_z(q, q.ndim - 3)
@@ -77,13 +102,14 @@ def prolong(qc, zf):
 PRIMITIVES = ("T", "ne", "nH", "ntot", "vx", "vy", "vz")
 
 
-def coarsen_atmosphere(atmos):
-    """Coarse-grid model atmosphere by full weighting of the primitives (Sect. 4.7)."""
+def coarsen_atmosphere(atmos, op="full"):
+    """Coarse-grid model atmosphere by restriction of the primitives (Sect. 4.7: full
+    weighting by default; injection was the paper's alternative)."""
     out = {
         "nx": atmos["nx"] // 2, "ny": atmos["ny"] // 2, "nz": (atmos["nz"] - 1) // 2 + 1,
         "dx": 2.0 * atmos["dx"], "dy": 2.0 * atmos["dy"], "z": np.asarray(atmos["z"])[::2].copy(),
     }
     for k in PRIMITIVES:
-        out[k] = restrict(atmos[k])
-    out["chi_c"] = None if atmos.get("chi_c") is None else restrict(atmos["chi_c"])
+        out[k] = restrict(atmos[k], op)
+    out["chi_c"] = None if atmos.get("chi_c") is None else restrict(atmos["chi_c"], op)
     return out
