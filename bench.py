@@ -221,6 +221,7 @@ def main():
                               dirs_per_block=args.dirs_per_block,
                               graph=args.graph)
     nf = sum(len(l["q"]) for l in atom["lines"])
+    log(f"device footprint of one solve: {ctx.footprint(M, A, params) / 1e9:.2f} GB")
     mu_out = np.array([[0.0, 0.0, 1.0]])
     N = len(atom["levels"])
 

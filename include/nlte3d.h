@@ -58,6 +58,10 @@ typedef int nlte_status;
                                        solves, normalisation, residual and coarse-grid
                                        right-hand side in FP64 */
 
+#define NLTE_RESTRICT_FULL   0      /* full weighting, 27 points (Sect. 4.4) */
+#define NLTE_RESTRICT_HALF   1      /* half weighting: the point 1/2, its six axis neighbours 1/12 each */
+#define NLTE_RESTRICT_INJECT 2      /* injection: the fine value at the coarse point */
+
 #define NLTE_INIT_ZERO_RAD 0        /* zero-radiation populations (Sect. 4.11) */
 #define NLTE_INIT_LTE      1        /* Saha-Boltzmann populations */
 #define NLTE_INIT_USER     2        /* params.init_pops */
@@ -146,6 +150,12 @@ typedef struct {
                                   the plane in LDS; planes of up to 4096 points; measured
                                   slower except on the smallest grids).  AUTO takes
                                   PLANE_STEP. */
+    int restriction;           /* NLTE_RESTRICT_*: restriction of populations and residuals
+                                  in FAS/FMG (Sect. 4.4); the paper's choice, and the
+                                  zero default, is full weighting */
+    int coarse_atmos;          /* NLTE_RESTRICT_*: how the coarse model atmospheres are made
+                                  from the finer ones (Sect. 4.7); full weighting by default,
+                                  injection the paper's alternative */
 } nlte_params;
 
 typedef struct {

@@ -55,6 +55,7 @@ class Params:
     tol_C: float | None = None
     E_target: float | None = 1.0e-3
     restriction: str = "full"      # populations and residuals (Sect. 4.4)
+    interpolation: str = "trilinear"   # corrections and FMG full approximations (Sect. 4.5)
     coarse_atmos: str = "full"     # coarse model atmospheres (Sect. 4.7)
 
 
@@ -121,7 +122,7 @@ def vcycle(levels, k, n, f, p, first=False, stats=None, fs0=None):
         nc = vcycle(levels, k - 1, nc, fc, p, False, stats, fs_c)
     e = (nc - n_before) / n_before
     n_old = n
-    n = n_old * (1.0 + prolong(e, lev.z))
+    n = n_old * (1.0 + prolong(e, lev.z, p.interpolation))
     bad = n <= 0.0
     if np.any(bad):
         n[bad] = p.repair_frac * n_old[bad]
@@ -178,7 +179,7 @@ def solve_fas(atom, atmos, p, fmg=False, stats=None, cycles=None, levels=None):
         n = zero_radiation(lev1)
         n, _ = mali(lev1, 1, n, fine_rhs(lev1), p.nu_fmg, stats)
         for k in range(2, L + 1):
-            n = prolong(n, levels[k - 1].z)
+            n = prolong(n, levels[k - 1].z, p.interpolation)
             if k < L:
                 n = vcycle(levels, k, n, fine_rhs(levels[k - 1]), p, False, stats)
         first = False

@@ -1158,9 +1158,15 @@ __global__ void source_function_kernel(const AtomInfo* atom, const double* n, do
 }
 
 // ------------------------------------------------------------------ grid transfer
-// Full weighting (27-point tensor product of [1/4, 1/2, 1/4], periodic in x and y,
-// [1/2, 1/2] at the vertical boundary planes) from the fine grid to the coarse grid.
-__global__ void restrict_kernel(const double* src, double* dst, int nq, int nxf, int nyf, int nzf) {
+// Restriction from the fine grid to the coarse grid (coarse point = fine index 2c),
+// periodic in x and y:
+//  * full weighting: 27-point tensor product of [1/4, 1/2, 1/4], [1/2, 1/2] at the
+//    vertical boundary planes;
+//  * half weighting: 1/2 for the point and 1/12 for each of its six axis neighbours;
+//    at a vertical boundary plane the missing outward neighbour is replaced by the
+//    inward one (the stencil mirrored);
+//  * injection: the fine value at the coarse point.
+__global__ void restrict_kernel(const double* src, double* dst, int nq, int nxf, int nyf, int nzf, int op) {
     const int nxc = nxf / 2, nyc = nyf / 2, nzc = (nzf - 1) / 2 + 1;
     const size_t ncv = size_t(nxc) * nyc * nzc;
     const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1170,6 +1176,22 @@ __global__ void restrict_kernel(const double* src, double* dst, int nq, int nxf,
     const int xc = int(r % nxc), yc = int((r / nxc) % nyc), zc = int(r / (size_t(nxc) * nyc));
     const size_t nfv = size_t(nxf) * nyf * nzf;
     const double* s = src + size_t(q) * nfv;
+    const size_t pxy = size_t(nxf) * nyf;
+    if (op == NLTE_RESTRICT_INJECT) {
+        dst[idx] = s[size_t(2 * zc) * pxy + size_t(2 * yc) * nxf + 2 * xc];
+        return;
+    }
+    if (op == NLTE_RESTRICT_HALF) {
+        const int k = 2 * zc, y = 2 * yc, x = 2 * xc;
+        const int kd = k > 0 ? k - 1 : k + 1, ku = k < nzf - 1 ? k + 1 : k - 1;
+        const int xm = x > 0 ? x - 1 : nxf - 1, xp = x + 1 < nxf ? x + 1 : 0;
+        const int ym = y > 0 ? y - 1 : nyf - 1, yp = y + 1 < nyf ? y + 1 : 0;
+        const double nb = ((s[size_t(k) * pxy + size_t(y) * nxf + xm] + s[size_t(k) * pxy + size_t(y) * nxf + xp]) +
+                           (s[size_t(k) * pxy + size_t(ym) * nxf + x] + s[size_t(k) * pxy + size_t(yp) * nxf + x])) +
+                          (s[size_t(kd) * pxy + size_t(y) * nxf + x] + s[size_t(ku) * pxy + size_t(y) * nxf + x]);
+        dst[idx] = 0.5 * s[size_t(k) * pxy + size_t(y) * nxf + x] + nb / 12.0;
+        return;
+    }
     double wz[3];
     int kz[3];
     const int kc = 2 * zc;

@@ -444,7 +444,7 @@ struct Job : JobBase {
             } else {
                 const Level& F = *lev[k + 1];
                 restrict_kernel<<<blocks_for(L.nvox * nprim, 256), 256, 0, st()>>>(
-                    F.prim.as<double>(), L.prim.as<double>(), nprim, F.nx, F.ny, F.nz);
+                    F.prim.as<double>(), L.prim.as<double>(), nprim, F.nx, F.ny, F.nz, p->coarse_atmos);
                 HIPCHK(hipGetLastError());
             }
             dalloc(L.sc, sizeof(R) * SC_NQ * nline * L.nvox);
@@ -815,7 +815,8 @@ struct Job : JobBase {
         const Level& F = *lev[kf];
         const Level& C = *lev[kf - 1];
         ev_begin(EV_TRANSFER);
-        restrict_kernel<<<blocks_for(C.nvox * nq, 256), 256, 0, st()>>>(src, dst, nq, F.nx, F.ny, F.nz);
+        restrict_kernel<<<blocks_for(C.nvox * nq, 256), 256, 0, st()>>>(src, dst, nq, F.nx, F.ny, F.nz,
+                                                                          params.restriction);
         HIPCHK(hipGetLastError());
         ev_end();
     }
@@ -1525,6 +1526,11 @@ void nlte_atmos_destroy(nlte_ctx* ctx, nlte_atmos* atmos) {
 
 }  // extern "C"
 
+static bool transfer_ops_ok(const nlte_params* p) {
+    auto ok = [](int op) { return op == NLTE_RESTRICT_FULL || op == NLTE_RESTRICT_HALF || op == NLTE_RESTRICT_INJECT; };
+    return ok(p->restriction) && ok(p->coarse_atmos);
+}
+
 extern "C" {
 
 nlte_status nlte_job_create(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom* atom,
@@ -1533,6 +1539,7 @@ nlte_status nlte_job_create(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_a
         REQUIRE(atmos && atom && params && job, "null argument");
         REQUIRE(params->method >= NLTE_MALI && params->method <= NLTE_FMG, "unknown method");
         REQUIRE(params->precision == NLTE_FP64 || params->precision == NLTE_MIXED, "unknown precision");
+        REQUIRE(transfer_ops_ok(params), "unknown restriction operator");
         REQUIRE(params->nu0 >= 0 && params->nu1 >= 0 && params->nu2 >= 0 && params->nu3 >= 0 && params->nu_fmg >= 0,
                 "iteration counts must be >= 0");
         REQUIRE(params->repair_frac > 0 && params->repair_frac < 1, "repair_frac must lie in (0, 1)");
@@ -1728,6 +1735,7 @@ nlte_status nlte_submit(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom*
         REQUIRE(atmos && atom && params && job, "null argument");
         REQUIRE(params->method >= NLTE_MALI && params->method <= NLTE_FMG, "unknown method");
         REQUIRE(params->precision == NLTE_FP64 || params->precision == NLTE_MIXED, "unknown precision");
+        REQUIRE(transfer_ops_ok(params), "unknown restriction operator");
         REQUIRE(params->init != NLTE_INIT_USER && params->top_I == nullptr,
                 "served jobs take no host arrays in params");
         const int nlev = std::max(1, params->method == NLTE_MALI ? 1 : params->nlev);

@@ -212,6 +212,49 @@ def test_restrict_and_prolong_parity(nl, ctx):
     assert np.allclose(dstf.cpu().numpy(), prolong(c, atm["z"]), rtol=1e-14, atol=0)
 
 
+@pytest.mark.parametrize("op,name", [(1, "half"), (2, "inject"), (0, "full")])
+def test_restriction_operator_parity(nl, ctx, op, name):
+    import torch
+    atom, atm = mg_case()
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.FAS, precision=0, nlev=3, restriction=op))
+    f = np.random.default_rng(30 + op).random((3, 17, 8, 8))
+    src = torch.tensor(f, dtype=torch.float64, device="cuda")
+    dst = torch.empty((3, 9, 4, 4), dtype=torch.float64, device="cuda")
+    job.restrict(2, src.data_ptr(), dst.data_ptr(), 3)
+    torch.cuda.synchronize()
+    assert np.allclose(dst.cpu().numpy(), restrict(f, name), rtol=1e-15, atol=0)
+    # one level further down: 9x4x4 -> 5x2x2
+    src2 = torch.tensor(f[:, ::2, ::2, ::2].copy(), dtype=torch.float64, device="cuda")
+    dst2 = torch.empty((3, 5, 2, 2), dtype=torch.float64, device="cuda")
+    job.restrict(1, src2.data_ptr(), dst2.data_ptr(), 3)
+    torch.cuda.synchronize()
+    assert np.allclose(dst2.cpu().numpy(), restrict(f[:, ::2, ::2, ::2], name), rtol=1e-15, atol=0)
+    job.close()
+    with pytest.raises(nl.NlteError):
+        ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.FAS, nlev=3, restriction=3))
+    with pytest.raises(nl.NlteError):
+        ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.FAS, nlev=3, coarse_atmos=-1))
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-3)])
+@pytest.mark.parametrize("restr,coarse", [(1, 0), (2, 0), (0, 2)], ids=["half", "inject", "inject_atmos"])
+def test_fas_transfer_operators_parity(nl, ctx, prec, tol, restr, coarse):
+    names = ("full", "half", "inject")
+    atom, atm = mg_case()
+    p = OParams(nlev=3, nu1=2, nu2=2, nu3=6, restriction=names[restr], coarse_atmos=names[coarse])
+    n_or, st, _ = solve_fas(atom, atm, p, cycles=2)
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
+                  nl.SolveParams(method=nl.FAS, precision=prec, nlev=3, nu1=2, nu2=2, nu3=6, E_target=0.0, tol_C=0.0,
+                                 max_iter=2, restriction=restr, coarse_atmos=coarse))
+    rc, r = job.run()
+    npop, _ = shapes(atom, atm)
+    e = relerr(job.populations(2, npop), n_or)
+    print(f"prec={prec} restriction={names[restr]} atmos={names[coarse]} 2 cycles err {e:.2e}")
+    assert r.cycles == 2
+    assert e < tol
+    assert abs(r.C / st.C[-1] - 1) < 0.05
+
+
 def test_determinism_and_invalid_inputs(nl, ctx):
     atom, atm = mg_case()
     outs = []

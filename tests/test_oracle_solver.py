@@ -143,13 +143,15 @@ def test_fas_fixed_point_and_convergence_to_discrete_solution(exact_column):
     assert np.max(np.abs(nfmg / n - 1)) < 4 * st2.E_est[-1] + 1e-9
 
 
-@pytest.mark.parametrize("restriction,coarse", [("half", "full"), ("inject", "full"), ("full", "inject")])
-def test_other_transfer_operators_keep_the_fixed_point(exact_column, restriction, coarse):
-    # The restriction of populations and residuals and the coarse atmospheres only
-    # shape the coarse-grid correction: the discrete fine-grid solution stays a fixed
+@pytest.mark.parametrize("restriction,coarse,interp", [("half", "full", "trilinear"), ("inject", "full", "trilinear"),
+                                                        ("full", "inject", "trilinear"), ("full", "full", "hermite")])
+def test_other_transfer_operators_keep_the_fixed_point(exact_column, restriction, coarse, interp):
+    # The restriction of populations and residuals, the coarse atmospheres and the
+    # interpolation only shape the coarse-grid correction: the discrete fine-grid solution stays a fixed
     # point of the V-cycle, and FAS converges to it with any of them (Sect. 4.4, 4.7).
     atom, atm, S, n, lev = exact_column
-    p = Params(nlev=3, nu1=2, nu2=2, nu3=6, E_target=1e-7, restriction=restriction, coarse_atmos=coarse)
+    p = Params(nlev=3, nu1=2, nu2=2, nu3=6, E_target=1e-7, restriction=restriction, coarse_atmos=coarse,
+               interpolation=interp)
     levels = build_hierarchy(atom, atm, 3, coarse_op=coarse)
     n_after = vcycle(levels, 3, n.copy(), fine_rhs(levels[-1]), p)
     assert np.max(np.abs(n_after / n - 1)) < 1e-9

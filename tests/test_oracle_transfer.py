@@ -166,3 +166,91 @@ def test_coarsen_atmosphere_by_injection():
     assert np.array_equal(c["chi_c"], atm["chi_c"][:, ::2, ::2, ::2])
     f = coarsen_atmosphere(atm)
     assert not np.array_equal(f["T"], c["T"])
+
+
+def _fb_derivative(sl, sr, hl, hr):
+    """Fritsch-Butland derivative at a node, written out for one node."""
+    if sl * sr <= 0.0:
+        return 0.0
+    a = (1.0 + hr / (hl + hr)) / 3.0
+    return sl * sr / (a * sr + (1.0 - a) * sl)
+
+
+def _cubic_through(x0, x1, y0, y1, d0, d1, x):
+    """Value at x of the cubic with the given values and derivatives at x0 and x1,
+    from the 4x4 linear system of its coefficients."""
+    A = np.array([[1, x0, x0 ** 2, x0 ** 3], [1, x1, x1 ** 2, x1 ** 3],
+                  [0, 1, 2 * x0, 3 * x0 ** 2], [0, 1, 2 * x1, 3 * x1 ** 2]], dtype=float)
+    c = np.linalg.solve(A, np.array([y0, y1, d0, d1]))
+    return c[0] + c[1] * x + c[2] * x ** 2 + c[3] * x ** 3
+
+
+def test_hermite_z_matches_the_cubic_through_values_and_monotone_slopes():
+    rng = np.random.default_rng(21)
+    zf = np.cumsum(np.concatenate([[0.0], rng.uniform(0.5, 2.0, 8)]))
+    zc = zf[::2]
+    qc = rng.normal(size=(5, 1, 2))
+    qf = prolong(qc, zf, "hermite")
+    for j in range(2):
+        y = qc[:, 0, j]
+        s = np.diff(y) / np.diff(zc)
+        d = [s[0]] + [_fb_derivative(s[i - 1], s[i], zc[i] - zc[i - 1], zc[i + 1] - zc[i])
+                      for i in range(1, 4)] + [s[-1]]
+        for K in range(4):
+            exp = _cubic_through(zc[K], zc[K + 1], y[K], y[K + 1], d[K], d[K + 1], zf[2 * K + 1])
+            assert qf[2 * K + 1, 0, 2 * j] == pytest.approx(exp, rel=1e-11, abs=1e-12)
+        assert np.array_equal(qf[::2, 0, 2 * j], y)
+
+
+def test_hermite_xy_periodic_midpoints():
+    rng = np.random.default_rng(22)
+    qc = rng.normal(size=(1, 3, 6))
+    qf = prolong(qc, np.array([0.0]), "hermite")
+    y = qc[0, 0]
+    n = len(y)
+    for i in range(n):
+        sl, sr, srr = y[i] - y[i - 1], y[(i + 1) % n] - y[i], y[(i + 2) % n] - y[(i + 1) % n]
+        d0, d1 = _fb_derivative(sl, sr, 1.0, 1.0), _fb_derivative(sr, srr, 1.0, 1.0)
+        exp = _cubic_through(0.0, 1.0, y[i], y[(i + 1) % n], d0, d1, 0.5)
+        assert qf[0, 0, 2 * i + 1] == pytest.approx(exp, rel=1e-12, abs=1e-13)
+    assert np.array_equal(qf[0, ::2, ::2], qc[0])
+
+
+def test_hermite_reproduces_linear_and_keeps_monotone_data_in_range():
+    zf = np.cumsum(np.concatenate([[0.0], np.random.default_rng(23).uniform(1, 3, 16)]))
+    qc = np.broadcast_to((1.5 - 0.25 * zf[::2])[:, None, None], (9, 2, 4))
+    assert np.allclose(prolong(qc, zf, "hermite"), (1.5 - 0.25 * zf)[:, None, None], rtol=1e-13)
+    # a steep monotone step: no value leaves its interval's range (a cubic through
+    # centred differences overshoots here)
+    zc = zf[::2]
+    step = np.tanh((zc - zc.mean()) / 2.0)
+    qc = np.broadcast_to(step[:, None, None], (9, 2, 2))
+    qf = prolong(qc, zf, "hermite")[:, 0, 0]
+    for K in range(8):
+        lo, hi = sorted((step[K], step[K + 1]))
+        assert lo - 1e-15 <= qf[2 * K + 1] <= hi + 1e-15
+    assert np.all(np.diff(qf) >= 0)
+    # at a local maximum the derivative is zero: the neighbours' midpoints stay below it
+    y = np.array([0.0, 1.0, 3.0, 1.0, 0.0])
+    d = [float(v) for v in np.ravel(__import__("oracle.transfer", fromlist=["x"]).monotone_slopes(y))]
+    assert d[2] == 0.0
+
+
+def test_hermite_is_third_order_on_smooth_monotone_data():
+    # interior intervals: harmonic-mean derivatives make the interpolant at least third
+    # order (error ratio >= 8 per halving; trilinear is second order, ratio 4); the two
+    # end intervals use the one-sided slope and stay at least second order
+    err = {"hermite": [], "trilinear": [], "ends": []}
+    for n in (17, 33, 65):
+        zf = np.linspace(0.0, 1.0, 2 * n - 1)
+        f = np.tanh((zf - 0.4) / 0.15)
+        qc = np.broadcast_to(f[::2][:, None, None], (n, 2, 2))
+        for op in ("hermite", "trilinear"):
+            e = np.abs(prolong(qc, zf, op)[:, 0, 0] - f)
+            err[op].append(e[2:-2].max())
+            if op == "hermite":
+                err["ends"].append(max(e[1], e[-2]))
+    assert err["hermite"][1] / err["hermite"][2] > 8.0
+    assert 3.5 < err["trilinear"][1] / err["trilinear"][2] < 4.5
+    assert err["ends"][1] / err["ends"][2] > 3.5
+    assert err["hermite"][2] < 0.01 * err["trilinear"][2]
