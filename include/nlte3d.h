@@ -62,6 +62,9 @@ typedef int nlte_status;
 #define NLTE_RESTRICT_HALF   1      /* half weighting: the point 1/2, its six axis neighbours 1/12 each */
 #define NLTE_RESTRICT_INJECT 2      /* injection: the fine value at the coarse point */
 
+#define NLTE_INTERP_TRILINEAR 0     /* trilinear prolongation (Sect. 4.5) */
+#define NLTE_INTERP_HERMITE   1     /* monotone cubic Hermite on the 4x4x4 coarse stencil */
+
 #define NLTE_INIT_ZERO_RAD 0        /* zero-radiation populations (Sect. 4.11) */
 #define NLTE_INIT_LTE      1        /* Saha-Boltzmann populations */
 #define NLTE_INIT_USER     2        /* params.init_pops */
@@ -156,6 +159,9 @@ typedef struct {
     int coarse_atmos;          /* NLTE_RESTRICT_*: how the coarse model atmospheres are made
                                   from the finer ones (Sect. 4.7); full weighting by default,
                                   injection the paper's alternative */
+    int interpolation;         /* NLTE_INTERP_*: prolongation of corrections and of FMG full
+                                  approximations (Sect. 4.5); trilinear by default, as in
+                                  the paper's 3D runs */
 } nlte_params;
 
 typedef struct {

@@ -1247,8 +1247,57 @@ __device__ inline double tri_eval(const double* c, const Tri& t, int nxc, int ny
     return (1.0 - t.wz) * a + t.wz * b;
 }
 
+// Monotone cubic Hermite prolongation on the 4x4x4 coarse stencil, one axis at a time
+// (x, then y, then z).  Along an axis a fine point between coarse nodes i and i+1 takes
+// the cubic Hermite interpolant of the values and derivatives at those nodes; the
+// derivatives are Fritsch & Butland's: zero unless the two adjacent slopes s_l, s_r
+// have one sign, else s_l s_r / (a s_r + (1 - a) s_l), a = (1 + h_r / (h_l + h_r)) / 3.
+// x and y are periodic with unit spacing (a = 1/2); z uses the physical heights, and
+// its two boundary nodes take the slope of their one interval.
+__device__ inline double fb_derivative(double sl, double sr, double a) {
+    return (sl * sr > 0.0) ? sl * sr / (a * sr + (1.0 - a) * sl) : 0.0;
+}
+__device__ inline double hermite(double y0, double y1, double d0, double d1, double h, double t) {
+    const double t2 = t * t, t3 = t * t * t;
+    return ((2 * t3 - 3 * t2 + 1) * y0 + (t3 - 2 * t2 + t) * h * d0) + (-2 * t3 + 3 * t2) * y1 + (t3 - t2) * h * d1;
+}
+// midpoint between v1 and v2 of a periodic unit-spaced window v0..v3
+__device__ inline double hermite_mid(double v0, double v1, double v2, double v3) {
+    const double s0 = v1 - v0, s1 = v2 - v1, s2 = v3 - v2;
+    return hermite(v1, v2, fb_derivative(s0, s1, 0.5), fb_derivative(s1, s2, 0.5), 1.0, 0.5);
+}
+__device__ inline double hermite_at(const double* c, int x, int y, int k, int nxc, int nyc, int nzc,
+                                    const double* zf) {
+    auto gx = [&](int K, int J) -> double {   // x pass at fine x on coarse row (K, J)
+        const double* row = c + (size_t(K) * nyc + J) * nxc;
+        const int I = x >> 1;
+        if (!(x & 1)) return row[I];
+        return hermite_mid(row[I == 0 ? nxc - 1 : I - 1], row[I], row[(I + 1) % nxc], row[(I + 2) % nxc]);
+    };
+    auto gy = [&](int K) -> double {          // then y at fine y on coarse plane K
+        const int J = y >> 1;
+        if (!(y & 1)) return gx(K, J);
+        return hermite_mid(gx(K, J == 0 ? nyc - 1 : J - 1), gx(K, J), gx(K, (J + 1) % nyc), gx(K, (J + 2) % nyc));
+    };
+    const int K = k >> 1;                      // then z at fine plane k
+    if (!(k & 1)) return gy(K);
+    const double z0 = zf[2 * K], z1 = zf[2 * K + 2];
+    const double h0 = gy(K), h1 = gy(K + 1);
+    const double hm = z1 - z0, sm = (h1 - h0) / hm;
+    double d0 = sm, d1 = sm;
+    if (K > 0) {
+        const double hl = z0 - zf[2 * K - 2];
+        d0 = fb_derivative((h0 - gy(K - 1)) / hl, sm, (1.0 + hm / (hl + hm)) / 3.0);
+    }
+    if (K + 1 < nzc - 1) {
+        const double hr = zf[2 * K + 4] - z1;
+        d1 = fb_derivative(sm, (gy(K + 2) - h1) / hr, (1.0 + hr / (hm + hr)) / 3.0);
+    }
+    return hermite(h0, h1, d0, d1, hm, (zf[k] - z0) / hm);
+}
+
 __global__ void prolong_kernel(const double* src, double* dst, int nq, int nxf, int nyf, int nzf,
-                               const double* zf) {
+                               const double* zf, int op) {
     const size_t nfv = size_t(nxf) * nyf * nzf;
     const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= nfv * nq) return;
@@ -1256,15 +1305,28 @@ __global__ void prolong_kernel(const double* src, double* dst, int nq, int nxf, 
     const size_t r = idx % nfv;
     const int x = int(r % nxf), y = int((r / nxf) % nyf), k = int(r / (size_t(nxf) * nyf));
     const int nxc = nxf / 2, nyc = nyf / 2, nzc = (nzf - 1) / 2 + 1;
+    const double* c = src + size_t(q) * nxc * nyc * nzc;
+    if (op == NLTE_INTERP_HERMITE) {
+        dst[idx] = hermite_at(c, x, y, k, nxc, nyc, nzc, zf);
+        return;
+    }
     const Tri t = tri_weights(x, y, k, nxc, nyc, zf);
-    dst[idx] = tri_eval(src + size_t(q) * nxc * nyc * nzc, t, nxc, nyc);
+    dst[idx] = tri_eval(c, t, nxc, nyc);
+}
+
+// Coarse relative correction e = (n_after - n_before) / n_before (Eq. 11).
+__global__ void rel_correction_kernel(const double* na, const double* nb, double* e, size_t n) {
+    const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) e[i] = (na[i] - nb[i]) / nb[i];
 }
 
 // Relative coarse-grid correction (Eqs. 11, 12) with the negative-population repair:
 // e = (n_after - n_before) / n_before on the coarse grid, interpolated trilinearly;
 // n <- n (1 + I e), and n <- frac * n where that is <= 0.  Repairs counted per block.
+// With Hermite interpolation the coarse e comes precomputed in ec (na, nb unused).
 __global__ void correct_kernel(double* n, const double* na, const double* nb, int nq, int nxf, int nyf,
-                               int nzf, const double* zf, double frac, unsigned long long* repairs) {
+                               int nzf, const double* zf, double frac, unsigned long long* repairs,
+                               const double* ec, int op) {
     const size_t nfv = size_t(nxf) * nyf * nzf;
     const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
     int rep = 0;
@@ -1274,18 +1336,23 @@ __global__ void correct_kernel(double* n, const double* na, const double* nb, in
         const int x = int(r % nxf), y = int((r / nxf) % nyf), k = int(r / (size_t(nxf) * nyf));
         const int nxc = nxf / 2, nyc = nyf / 2, nzc = (nzf - 1) / 2 + 1;
         const size_t ncv = size_t(nxc) * nyc * nzc;
-        const Tri t = tri_weights(x, y, k, nxc, nyc, zf);
-        const double* A = na + size_t(q) * ncv;
-        const double* B = nb + size_t(q) * ncv;
-        auto e = [&](int kk, int yy, int xx) {
-            const size_t o = (size_t(kk) * nyc + yy) * nxc + xx;
-            return (A[o] - B[o]) / B[o];
-        };
-        const double a0 = (1.0 - t.wx) * e(t.k0, t.y0, t.x0) + t.wx * e(t.k0, t.y0, t.x1);
-        const double a1 = (1.0 - t.wx) * e(t.k0, t.y1, t.x0) + t.wx * e(t.k0, t.y1, t.x1);
-        const double b0 = (1.0 - t.wx) * e(t.k1, t.y0, t.x0) + t.wx * e(t.k1, t.y0, t.x1);
-        const double b1 = (1.0 - t.wx) * e(t.k1, t.y1, t.x0) + t.wx * e(t.k1, t.y1, t.x1);
-        const double ie = (1.0 - t.wz) * ((1.0 - t.wy) * a0 + t.wy * a1) + t.wz * ((1.0 - t.wy) * b0 + t.wy * b1);
+        double ie;
+        if (op == NLTE_INTERP_HERMITE) {
+            ie = hermite_at(ec + size_t(q) * ncv, x, y, k, nxc, nyc, nzc, zf);
+        } else {
+            const Tri t = tri_weights(x, y, k, nxc, nyc, zf);
+            const double* A = na + size_t(q) * ncv;
+            const double* B = nb + size_t(q) * ncv;
+            auto e = [&](int kk, int yy, int xx) {
+                const size_t o = (size_t(kk) * nyc + yy) * nxc + xx;
+                return (A[o] - B[o]) / B[o];
+            };
+            const double a0 = (1.0 - t.wx) * e(t.k0, t.y0, t.x0) + t.wx * e(t.k0, t.y0, t.x1);
+            const double a1 = (1.0 - t.wx) * e(t.k0, t.y1, t.x0) + t.wx * e(t.k0, t.y1, t.x1);
+            const double b0 = (1.0 - t.wx) * e(t.k1, t.y0, t.x0) + t.wx * e(t.k1, t.y0, t.x1);
+            const double b1 = (1.0 - t.wx) * e(t.k1, t.y1, t.x0) + t.wx * e(t.k1, t.y1, t.x1);
+            ie = (1.0 - t.wz) * ((1.0 - t.wy) * a0 + t.wy * a1) + t.wz * ((1.0 - t.wy) * b0 + t.wy * b1);
+        }
         const double nold = n[idx];
         double nn = nold * (1.0 + ie);
         if (!(nn > 0.0)) {

@@ -824,7 +824,7 @@ struct Job : JobBase {
     void prolong_fields(int kf, int nq, const double* src, double* dst) {
         const Level& F = *lev[kf];
         prolong_kernel<<<blocks_for(F.nvox * nq, 256), 256, 0, st()>>>(src, dst, nq, F.nx, F.ny, F.nz,
-                                                                      F.dz.as<double>());
+                                                                      F.dz.as<double>(), params.interpolation);
         HIPCHK(hipGetLastError());
     }
 
@@ -849,9 +849,16 @@ struct Job : JobBase {
         dcopy(C.n.as<double>(), C.nb.as<double>(), size_t(N) * C.nvox);
         if (k - 1 == 0) mali(0, params.nu3);
         else vcycle(k - 1, false);
+        if (params.interpolation == NLTE_INTERP_HERMITE) {
+            // e on the coarse grid first (C.tmp is free once the coarse right-hand side is formed)
+            const size_t nc = size_t(N) * C.nvox;
+            rel_correction_kernel<<<blocks_for(nc, 256), 256, 0, st()>>>(C.n.as<double>(), C.nb.as<double>(),
+                                                                          C.tmp.as<double>(), nc);
+            HIPCHK(hipGetLastError());
+        }
         correct_kernel<<<blocks_for(L.nvox * N, 256), 256, 0, st()>>>(
             L.n.as<double>(), C.n.as<double>(), C.nb.as<double>(), N, L.nx, L.ny, L.nz, L.dz.as<double>(),
-            params.repair_frac, repairs.as<unsigned long long>());
+            params.repair_frac, repairs.as<unsigned long long>(), C.tmp.as<double>(), params.interpolation);
         HIPCHK(hipGetLastError());
         L.fs_valid = false;
         mali(k, params.nu2);
@@ -1528,7 +1535,8 @@ void nlte_atmos_destroy(nlte_ctx* ctx, nlte_atmos* atmos) {
 
 static bool transfer_ops_ok(const nlte_params* p) {
     auto ok = [](int op) { return op == NLTE_RESTRICT_FULL || op == NLTE_RESTRICT_HALF || op == NLTE_RESTRICT_INJECT; };
-    return ok(p->restriction) && ok(p->coarse_atmos);
+    return ok(p->restriction) && ok(p->coarse_atmos) &&
+           (p->interpolation == NLTE_INTERP_TRILINEAR || p->interpolation == NLTE_INTERP_HERMITE);
 }
 
 extern "C" {
@@ -1539,7 +1547,7 @@ nlte_status nlte_job_create(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_a
         REQUIRE(atmos && atom && params && job, "null argument");
         REQUIRE(params->method >= NLTE_MALI && params->method <= NLTE_FMG, "unknown method");
         REQUIRE(params->precision == NLTE_FP64 || params->precision == NLTE_MIXED, "unknown precision");
-        REQUIRE(transfer_ops_ok(params), "unknown restriction operator");
+        REQUIRE(transfer_ops_ok(params), "unknown restriction or interpolation operator");
         REQUIRE(params->nu0 >= 0 && params->nu1 >= 0 && params->nu2 >= 0 && params->nu3 >= 0 && params->nu_fmg >= 0,
                 "iteration counts must be >= 0");
         REQUIRE(params->repair_frac > 0 && params->repair_frac < 1, "repair_frac must lie in (0, 1)");
@@ -1735,7 +1743,7 @@ nlte_status nlte_submit(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom*
         REQUIRE(atmos && atom && params && job, "null argument");
         REQUIRE(params->method >= NLTE_MALI && params->method <= NLTE_FMG, "unknown method");
         REQUIRE(params->precision == NLTE_FP64 || params->precision == NLTE_MIXED, "unknown precision");
-        REQUIRE(transfer_ops_ok(params), "unknown restriction operator");
+        REQUIRE(transfer_ops_ok(params), "unknown restriction or interpolation operator");
         REQUIRE(params->init != NLTE_INIT_USER && params->top_I == nullptr,
                 "served jobs take no host arrays in params");
         const int nlev = std::max(1, params->method == NLTE_MALI ? 1 : params->nlev);

@@ -11,6 +11,7 @@ atmospheres, through the library (every solve on the GPU):
   number rho_L(i) = max |D2[n_i - n_inf]| after i MALI iterations (Fig. 7);
 * post-smoothing counts nu_2 with the number of negative-population repairs
   (Sect. 4.10, Fig. 6);
+* trilinear against monotone cubic Hermite prolongation (Sect. 4.5);
 * plain MALI as the reference curve.
 
 The true error E_i = max |n_i - n_ref| / n_ref (Sect. 3.3) is measured against a tightly
@@ -50,6 +51,7 @@ VARIANTS = {
     "fas4_full": dict(nlev=4),
     "fas3_lte_init": dict(init=nlte.INIT_LTE),
     "fas3_nu2_8": dict(nu2=8),
+    "fas3_hermite": dict(interpolation=nlte.INTERP_HERMITE),
 }
 
 

@@ -234,22 +234,57 @@ def test_restriction_operator_parity(nl, ctx, op, name):
         ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.FAS, nlev=3, restriction=3))
     with pytest.raises(nl.NlteError):
         ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.FAS, nlev=3, coarse_atmos=-1))
+    with pytest.raises(nl.NlteError):
+        ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.FAS, nlev=3, interpolation=2))
+
+
+def test_hermite_prolongation_parity(nl, ctx):
+    import torch
+    atom, atm = mg_case()
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
+                  nl.SolveParams(method=nl.FAS, precision=0, nlev=3, interpolation=nl.INTERP_HERMITE))
+    rng = np.random.default_rng(41)
+    # random data, and smooth positive data with a steep front (where the limiter acts)
+    z = np.asarray(atm["z"])
+    zz = z[::2][:, None, None]
+    front = 1.0 + np.tanh((zz - zz.mean()) / (0.05 * np.ptp(zz)))
+    c = np.stack([rng.random((9, 4, 4)), np.broadcast_to(front, (9, 4, 4))])
+    srcc = torch.tensor(c, dtype=torch.float64, device="cuda")
+    dstf = torch.empty((2, 17, 8, 8), dtype=torch.float64, device="cuda")
+    job.prolong(2, srcc.data_ptr(), dstf.data_ptr(), 2)
+    torch.cuda.synchronize()
+    ref = prolong(c, z, "hermite")
+    assert np.allclose(dstf.cpu().numpy(), ref, rtol=1e-13, atol=1e-15)
+    # one level further down (5x2x2 -> 9x4x4; two coarse points per periodic axis)
+    c2 = rng.random((2, 5, 2, 2))
+    src2 = torch.tensor(c2, dtype=torch.float64, device="cuda")
+    dst2 = torch.empty((2, 9, 4, 4), dtype=torch.float64, device="cuda")
+    job.prolong(1, src2.data_ptr(), dst2.data_ptr(), 2)
+    torch.cuda.synchronize()
+    assert np.allclose(dst2.cpu().numpy(), prolong(c2, z[::2], "hermite"), rtol=1e-13, atol=1e-15)
+    job.close()
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-3)])
-@pytest.mark.parametrize("restr,coarse", [(1, 0), (2, 0), (0, 2)], ids=["half", "inject", "inject_atmos"])
-def test_fas_transfer_operators_parity(nl, ctx, prec, tol, restr, coarse):
+@pytest.mark.parametrize("restr,coarse,interp,fmg", [(1, 0, 0, False), (2, 0, 0, False), (0, 2, 0, False),
+                                                     (0, 0, 1, False), (0, 0, 1, True)],
+                         ids=["half", "inject", "inject_atmos", "hermite", "hermite_fmg"])
+def test_fas_transfer_operators_parity(nl, ctx, prec, tol, restr, coarse, interp, fmg):
     names = ("full", "half", "inject")
+    inames = ("trilinear", "hermite")
     atom, atm = mg_case()
-    p = OParams(nlev=3, nu1=2, nu2=2, nu3=6, restriction=names[restr], coarse_atmos=names[coarse])
-    n_or, st, _ = solve_fas(atom, atm, p, cycles=2)
+    p = OParams(nlev=3, nu1=2, nu2=2, nu3=6, nu_fmg=4, restriction=names[restr], coarse_atmos=names[coarse],
+                interpolation=inames[interp])
+    n_or, st, _ = solve_fas(atom, atm, p, fmg=fmg, cycles=2)
     job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
-                  nl.SolveParams(method=nl.FAS, precision=prec, nlev=3, nu1=2, nu2=2, nu3=6, E_target=0.0, tol_C=0.0,
-                                 max_iter=2, restriction=restr, coarse_atmos=coarse))
+                  nl.SolveParams(method=nl.FMG if fmg else nl.FAS, precision=prec, nlev=3, nu1=2, nu2=2, nu3=6,
+                                 nu_fmg=4, E_target=0.0, tol_C=0.0, max_iter=2, restriction=restr,
+                                 coarse_atmos=coarse, interpolation=interp))
     rc, r = job.run()
     npop, _ = shapes(atom, atm)
     e = relerr(job.populations(2, npop), n_or)
-    print(f"prec={prec} restriction={names[restr]} atmos={names[coarse]} 2 cycles err {e:.2e}")
+    print(f"prec={prec} restriction={names[restr]} atmos={names[coarse]} interp={inames[interp]} fmg={fmg} "
+          f"2 cycles err {e:.2e}")
     assert r.cycles == 2
     assert e < tol
     assert abs(r.C / st.C[-1] - 1) < 0.05
