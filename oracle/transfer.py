@@ -21,8 +21,9 @@
   - cubic Hermite on the 4x4x4 coarse stencil, applied one axis at a time (x, then y,
     then z).  Along an axis a fine point between coarse nodes i and i+1 takes the cubic
     Hermite interpolant of the values and derivatives at those two nodes.  The paper
-    cites Auer (2003) for it; its derivatives are the monotone ones of Fritsch & Butland
-    (1984): zero where the slopes s_l, s_r of the two adjacent intervals differ in sign
+    cites Auer (2003) for it and gives no derivative formula; the derivatives here are
+    the monotone ones of Fritsch & Butland (1984): zero where the slopes s_l, s_r of the
+    two adjacent intervals differ in sign
     or one vanishes, else the weighted harmonic mean s_l s_r / (a s_r + (1 - a) s_l) with
     a = (1 + h_r / (h_l + h_r)) / 3 (the plain harmonic mean on a uniform axis).  At the
     two vertical boundary nodes the derivative is the slope of the one adjacent interval.
