@@ -16,8 +16,12 @@ into Jeff and 1 into 1-L*.
 Readings of the geometry and boundaries:
 * The upwind point of a voxel lies on the adjacent z-plane at horizontal offset
   -ds (mu_x, mu_y), ds = dz / |mu_z|.  I, S and chi there come from bilinear
-  interpolation with periodic wrap.  S varies linearly along the segment and
-  dtau = (chi_u + chi_o) ds / 2.
+  interpolation with periodic wrap, or (the paper's alternative, Sect. 3) from monotone
+  bicubic Hermite interpolation on the 4x4 surrounding points: along x on the four
+  rows, then along y, each 1D step the cubic Hermite interpolant between the two middle
+  points with the Fritsch-Butland derivatives (zero where the adjacent slopes differ in
+  sign, else their harmonic mean), so every value stays within the range of its 2x2
+  cell.  S varies linearly along the segment and dtau = (chi_u + chi_o) ds / 2.
 * Lower boundary (upward rays): I = B_nu0(T) at the local gas temperature.  Upper
   boundary (downward rays): I = 0, or a prescribed array (Sect. 4.2).
 * Where the total opacity vanishes (the profile underflows far out in a wing, or a
@@ -63,12 +67,31 @@ def psi_coefficients(dtau):
     return ex, psi_u, psi_o
 
 
-def upwind_interp(Q, sx, sy):
-    """Bilinear periodic interpolation of Q[..., ny, nx] at (i + sx, j + sy)."""
+def _hermite_between(v0, v1, v2, v3, t):
+    """Monotone cubic Hermite interpolant between v1 and v2 (unit spacing) at fraction t."""
+    def slope(sl, sr):
+        same = sl * sr > 0.0
+        return np.where(same, sl * sr / np.where(same, 0.5 * sr + 0.5 * sl, 1.0), 0.0)
+    d1 = slope(v1 - v0, v2 - v1)
+    d2 = slope(v2 - v1, v3 - v2)
+    t2, t3 = t * t, t * t * t
+    return (2 * t3 - 3 * t2 + 1) * v1 + (t3 - 2 * t2 + t) * d1 + (-2 * t3 + 3 * t2) * v2 + (t3 - t2) * d2
+
+
+def upwind_interp(Q, sx, sy, op="bilinear"):
+    """Periodic interpolation of Q[..., ny, nx] at (i + sx, j + sy), bilinear or monotone
+    bicubic Hermite."""
     ix = int(np.floor(sx))
     iy = int(np.floor(sy))
     fx = sx - ix
     fy = sy - iy
+    if op == "hermite":
+        def at(dr, dc):
+            return np.roll(Q, (-iy - dr, -ix - dc), axis=(-2, -1))
+        rows = [_hermite_between(at(r, -1), at(r, 0), at(r, 1), at(r, 2), fx) for r in (-1, 0, 1, 2)]
+        return _hermite_between(rows[0], rows[1], rows[2], rows[3], fy)
+    if op != "bilinear":
+        raise ValueError("unknown upwind interpolation %r" % (op,))
     q00 = np.roll(Q, (-iy, -ix), axis=(-2, -1))
     q01 = np.roll(Q, (-iy, -ix - 1), axis=(-2, -1))
     q10 = np.roll(Q, (-iy - 1, -ix), axis=(-2, -1))
@@ -96,7 +119,7 @@ def plane_order(nz, mu_z):
 def sweep(geom, mu, local, boundary, accumulate=None, keep_top=False):
     """Sweep one direction through all z-planes.
 
-    geom: object with nz, dx, dy, z.  local(k) -> (chi, S, extra) at plane k,
+    geom: object with nz, dx, dy, z and optionally sc_interp ("bilinear" by default).  local(k) -> (chi, S, extra) at plane k,
     arrays (nf, ny, nx).  boundary(k) -> I at the boundary plane k.
     accumulate(k, kind, data) is called per plane with kind 'bc' (data = (I, extra))
     or 'seg' (data = (I_u, S_u, ex, psi_u, psi_o, I_o, chi, S, extra)).
@@ -113,9 +136,10 @@ def sweep(geom, mu, local, boundary, accumulate=None, keep_top=False):
         ds = dz / abs(mu[2])
         sx = -ds * mu[0] / geom.dx
         sy = -ds * mu[1] / geom.dy
-        I_u = upwind_interp(I_p, sx, sy)
-        S_u = upwind_interp(S_p, sx, sy)
-        chi_u = upwind_interp(chi_p, sx, sy)
+        op = getattr(geom, "sc_interp", "bilinear")
+        I_u = upwind_interp(I_p, sx, sy, op)
+        S_u = upwind_interp(S_p, sx, sy, op)
+        chi_u = upwind_interp(chi_p, sx, sy, op)
         chi_o, S_o, extra = local(k)
         dtau = 0.5 * (chi_u + chi_o) * ds
         ex, psi_u, psi_o = psi_coefficients(dtau)

@@ -28,7 +28,7 @@ from .transfer import coarsen_atmosphere
 
 
 class Level:
-    def __init__(self, atom, atmos, top_I=None):
+    def __init__(self, atom, atmos, top_I=None, sc_interp="bilinear"):
         self.atom = atom
         self.atmos = atmos
         self.nx, self.ny, self.nz = atmos["nx"], atmos["ny"], atmos["nz"]
@@ -69,6 +69,7 @@ class Level:
         self.fixed = ph.collision_matrix(atom, T, atmos["ne"], self.nstar) \
             + ph.fixed_bf_rates(atom, T, self.nstar)
         self.top_I = top_I
+        self.sc_interp = sc_interp   # upwind interpolation of the formal solution
         self._norm = None
 
     # ---- profile -----------------------------------------------------------
@@ -110,7 +111,7 @@ class Level:
         return kk, ee
 
 
-def build_hierarchy(atom, atmos, nlev, top_I=None, coarse_op="full"):
+def build_hierarchy(atom, atmos, nlev, top_I=None, coarse_op="full", sc_interp="bilinear"):
     """Levels [k=1 (coarsest), ..., k=nlev (finest)] as a list indexed k-1; each coarser
     atmosphere is the restriction (`coarse_op`) of the next finer one."""
     nx, ny, nz = atmos["nx"], atmos["ny"], atmos["nz"]
@@ -120,7 +121,7 @@ def build_hierarchy(atom, atmos, nlev, top_I=None, coarse_op="full"):
     atms = [atmos]
     for _ in range(nlev - 1):
         atms.append(coarsen_atmosphere(atms[-1], coarse_op))
-    levels = [Level(atom, a) for a in reversed(atms)]
+    levels = [Level(atom, a, sc_interp=sc_interp) for a in reversed(atms)]
     if top_I is not None:
         levels[-1].top_I = top_I
     return levels

@@ -56,6 +56,7 @@ class Params:
     E_target: float | None = 1.0e-3
     restriction: str = "full"      # populations and residuals (Sect. 4.4)
     interpolation: str = "trilinear"   # corrections and FMG full approximations (Sect. 4.5)
+    sc_interp: str = "bilinear"        # upwind interpolation of the formal solution (Sect. 3)
     coarse_atmos: str = "full"     # coarse model atmospheres (Sect. 4.7)
 
 
@@ -154,7 +155,7 @@ def _record(stats, hist):
 def solve_mali(atom, atmos, p, stats=None, n0=None, iters=None, top_I=None):
     """Plain MALI from zero-radiation populations until the stop rule (or ``iters``)."""
     stats = stats if stats is not None else Stats()
-    lev = Level(atom, atmos, top_I=top_I)
+    lev = Level(atom, atmos, top_I=top_I, sc_interp=p.sc_interp)
     f = fine_rhs(lev)
     n = zero_radiation(lev) if n0 is None else np.array(n0, dtype=np.float64)
     count = iters if iters is not None else p.max_iter
@@ -170,7 +171,8 @@ def solve_mali(atom, atmos, p, stats=None, n0=None, iters=None, top_I=None):
 def solve_fas(atom, atmos, p, fmg=False, stats=None, cycles=None, levels=None):
     """FAS V-cycles (optionally preceded by full multigrid) until the stop rule."""
     stats = stats if stats is not None else Stats()
-    levels = levels if levels is not None else build_hierarchy(atom, atmos, p.nlev, coarse_op=p.coarse_atmos)
+    levels = levels if levels is not None else build_hierarchy(atom, atmos, p.nlev, coarse_op=p.coarse_atmos,
+                                                               sc_interp=p.sc_interp)
     L = len(levels)
     fine = levels[-1]
     f = fine_rhs(fine)

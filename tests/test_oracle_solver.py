@@ -101,6 +101,16 @@ def test_homogeneous_3d_equals_1d_column():
     assert np.allclose(n3, np.broadcast_to(n1, n3.shape), rtol=1e-12)
 
 
+def test_homogeneous_3d_equals_1d_column_with_hermite_upwind_interpolation():
+    # interpolating a horizontally constant field is exact for the monotone cubic too
+    atom = synth.two_level_atom()
+    atm3 = synth.atmos_isothermal(nx=8, ny=8, nz=32)
+    atm1 = synth.atmos_isothermal(nx=1, ny=1, nz=32)
+    n3, _, _ = solve_mali(atom, atm3, Params(sc_interp="hermite"), iters=3)
+    n1, _, _ = solve_mali(atom, atm1, Params(), iters=3)
+    assert np.allclose(n3, np.broadcast_to(n1, n3.shape), rtol=1e-12)
+
+
 def test_one_grid_fas_is_mali_bitwise():
     atom, atm = six_level_small(nx=4, ny=4, nz=9)
     p = Params(nlev=1, nu1=2, nu2=1)
