@@ -65,6 +65,9 @@ typedef int nlte_status;
 #define NLTE_INTERP_TRILINEAR 0     /* trilinear prolongation (Sect. 4.5) */
 #define NLTE_INTERP_HERMITE   1     /* monotone cubic Hermite on the 4x4x4 coarse stencil */
 
+#define NLTE_SC_BILINEAR 0          /* upwind I, S, chi by bilinear interpolation (Sect. 3) */
+#define NLTE_SC_HERMITE  1          /* ... by monotone bicubic Hermite interpolation on 4x4 points */
+
 #define NLTE_INIT_ZERO_RAD 0        /* zero-radiation populations (Sect. 4.11) */
 #define NLTE_INIT_LTE      1        /* Saha-Boltzmann populations */
 #define NLTE_INIT_USER     2        /* params.init_pops */
@@ -162,6 +165,13 @@ typedef struct {
     int interpolation;         /* NLTE_INTERP_*: prolongation of corrections and of FMG full
                                   approximations (Sect. 4.5); trilinear by default, as in
                                   the paper's 3D runs */
+    int sc_interp;             /* NLTE_SC_*: interpolation of the upwind intensity, source
+                                  function and opacity in the short-characteristics formal
+                                  solution (Sect. 3 names linear and Hermite-spline);
+                                  bilinear by default.  Hermite runs the plane-step sweep
+                                  with three directions per block and needs levels whose
+                                  8-slot accumulators fit in 4 GiB; it applies to the
+                                  emergent intensity too. */
 } nlte_params;
 
 typedef struct {

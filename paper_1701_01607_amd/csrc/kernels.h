@@ -381,6 +381,33 @@ __device__ inline void upwind_values(const Corners<double>&, double w00, double 
     Cu = interp4(w00, w01, w10, w11, c00.C, c01.C, c10.C, c11.C);
 }
 
+// Monotone cubic Hermite interpolation between v1 and v2 (unit spacing) at fraction t,
+// with the Fritsch-Butland slopes: the harmonic mean of the adjacent differences, zero
+// where they differ in sign.  The result stays within [v1, v2].
+template <typename R>
+__device__ inline R mono_slope(R sl, R sr) {
+    return (sl * sr > R(0)) ? sl * sr / (R(0.5) * sr + R(0.5) * sl) : R(0);
+}
+template <typename R>
+__device__ inline R hermite_between(R v0, R v1, R v2, R v3, R t) {
+    const R d1 = mono_slope(v1 - v0, v2 - v1), d2 = mono_slope(v2 - v1, v3 - v2);
+    const R t2 = t * t, t3 = t * t * t;
+    return ((R(2) * t3 - R(3) * t2 + R(1)) * v1 + (t3 - R(2) * t2 + t) * d1) + (R(-2) * t3 + R(3) * t2) * v2 +
+           (t3 - t2) * d2;
+}
+
+// I, S and chi of a stored cell (FP32 cells rebuild S and chi from phi).
+__device__ inline void cell_values(const Cell<float>& c, const CornerConst<float>& q, float& I, float& S, float& X) {
+    I = c.I;
+    corner_SC(q, c.P, S, X);
+}
+__device__ inline void cell_values(const Cell<double>& c, const CornerConst<double>&, double& I, double& S,
+                                   double& X) {
+    I = c.I;
+    S = c.S;
+    X = c.C;
+}
+
 template <typename R>
 __device__ inline void sc_point(const PointConst<R>& c, R q, R w, bool gauss, R Iu, R Su, R Cu, R rds,
                                 CellVals<R>& cell, R& jacc, R& lacc) {
@@ -431,11 +458,15 @@ constexpr int kMaxSweepWaves = 12;
 // with waves); FP64 needs its ~175 registers.
 constexpr int kSweepWavesPerSimdF32 = 6;
 
-template <typename R, int DB>
-__global__ __launch_bounds__((sizeof(R) == 4 ? kMaxSweepWaves : DB) * 64)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? kSweepWavesPerSimdF32 : 1))) void sweep_step_kernel(
+// HERM: upwind values by monotone bicubic Hermite interpolation on the 4x4 surrounding
+// points (x along the four rows, then y) instead of bilinear; one frequency chunk per
+// wave, three directions per block.
+template <typename R, int DB, bool HERM = false>
+__global__ __launch_bounds__((sizeof(R) == 4 && !HERM ? kMaxSweepWaves : DB) * 64)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !HERM ? kSweepWavesPerSimdF32 : 1))) void sweep_step_kernel(
     SweepArgs<R> a, int s) {
     static_assert(DB == 3 || DB == 6 || DB == 12, "direction groups follow the fixed tree");
+    static_assert(!HERM || DB == 3, "the Hermite variant runs three directions per block");
     constexpr int kW = 64;
     const int lane = int(threadIdx.x) & (kW - 1);
     const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kW);
@@ -517,6 +548,39 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? kSweepWavesPerSimdF32 : 1)))
         const R w10 = (R(1) - fx) * fy, w11 = fx * fy;
         const R rds = R(ds);
         const auto rprv = cell_rsrc(a.state + size_t((s - 1) % a.nstate) * slot_stride + col, colb);
+        if constexpr (HERM) {
+            // the 4x4 stencil: columns x0-1 .. x0+2 and rows y0-1 .. y0+2, periodic
+            const int xs[4] = {x0 == 0 ? a.nx - 1 : x0 - 1, x0, x1, x1 + 1 == a.nx ? 0 : x1 + 1};
+            const int ys[4] = {y0 == 0 ? a.ny - 1 : y0 - 1, y0, y1, y1 + 1 == a.ny ? 0 : y1 + 1};
+            unsigned ho[4][4];
+            CornerConst<R> hq[4][4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    ho[r][c] = unsigned(ys[r] * a.nx + xs[c]) * csz;
+                    if constexpr (kPhiCell<R>) hq[r][c] = corner_const<R>(a.sc, a.lc, L, l, nv, vp + ho[r][c] / csz);
+                }
+            for (int m = mb; m < me; ++m) {
+                const unsigned so = unsigned(m - a.m0) * rowb;
+                R gI[4], gS[4], gX[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    R vI[4], vS[4], vX[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) cell_values(cell_get<R>(rprv, ho[r][c], so), hq[r][c], vI[c], vS[c], vX[c]);
+                    gI[r] = hermite_between(vI[0], vI[1], vI[2], vI[3], fx);
+                    gS[r] = hermite_between(vS[0], vS[1], vS[2], vS[3], fx);
+                    gX[r] = hermite_between(vX[0], vX[1], vX[2], vX[3], fx);
+                }
+                const R Iu = hermite_between(gI[0], gI[1], gI[2], gI[3], fy);
+                const R Su = hermite_between(gS[0], gS[1], gS[2], gS[3], fy);
+                const R Cu = hermite_between(gX[0], gX[1], gX[2], gX[3], fy);
+                CellVals<R> cell;
+                sc_point(pc, R(qf[m]), R(wf[m]), gauss, Iu, Su, Cu, rds, cell, jacc, lacc);
+                if (valid) cell_put(rcur, oc, so, make_cell(cell));
+            }
+        } else
         for (int m = mb; m < me; ++m) {
             const unsigned so = unsigned(m - a.m0) * rowb;
             const Cell<R> c00 = cell_get<R>(rprv, o00, so), c01 = cell_get<R>(rprv, o01, so);
@@ -880,6 +944,7 @@ struct EmergentArgs {
     const int* line_of;  // [nf]
     double* state;       // [2][3][nf][nxy]
     float* out;          // [nf][nxy]
+    int herm;            // 1: monotone bicubic Hermite upwind interpolation
 };
 
 template <typename R>
@@ -929,10 +994,26 @@ __global__ void emergent_step_kernel(EmergentArgs<R> a, int k) {
         const size_t g10 = fo + size_t(y1) * a.nx + x0, g11 = fo + size_t(y1) * a.nx + x1;
         const double w00 = (1.0 - fx) * (1.0 - fy), w01 = fx * (1.0 - fy);
         const double w10 = (1.0 - fx) * fy, w11 = fx * fy;
-        const double Iu = w00 * prv[g00] + w01 * prv[g01] + w10 * prv[g10] + w11 * prv[g11];
-        const double Su = w00 * prv[ps + g00] + w01 * prv[ps + g01] + w10 * prv[ps + g10] + w11 * prv[ps + g11];
-        const double Cu = w00 * prv[2 * ps + g00] + w01 * prv[2 * ps + g01] + w10 * prv[2 * ps + g10] +
-                          w11 * prv[2 * ps + g11];
+        double Iu, Su, Cu;
+        if (a.herm) {
+            const int xs[4] = {x0 == 0 ? a.nx - 1 : x0 - 1, x0, x1, x1 + 1 == a.nx ? 0 : x1 + 1};
+            const int ys[4] = {y0 == 0 ? a.ny - 1 : y0 - 1, y0, y1, y1 + 1 == a.ny ? 0 : y1 + 1};
+            double q[3][4];
+            for (int r = 0; r < 4; ++r) {
+                const size_t rowo = fo + size_t(ys[r]) * a.nx;
+                for (int f3 = 0; f3 < 3; ++f3) {
+                    const double* p3 = prv + size_t(f3) * ps + rowo;
+                    q[f3][r] = hermite_between(p3[xs[0]], p3[xs[1]], p3[xs[2]], p3[xs[3]], fx);
+                }
+            }
+            Iu = hermite_between(q[0][0], q[0][1], q[0][2], q[0][3], fy);
+            Su = hermite_between(q[1][0], q[1][1], q[1][2], q[1][3], fy);
+            Cu = hermite_between(q[2][0], q[2][1], q[2][2], q[2][3], fy);
+        } else {
+            Iu = w00 * prv[g00] + w01 * prv[g01] + w10 * prv[g10] + w11 * prv[g11];
+            Su = w00 * prv[ps + g00] + w01 * prv[ps + g01] + w10 * prv[ps + g10] + w11 * prv[ps + g11];
+            Cu = w00 * prv[2 * ps + g00] + w01 * prv[2 * ps + g01] + w10 * prv[2 * ps + g10] + w11 * prv[2 * ps + g11];
+        }
         const double dtau = 0.5 * (Cu + chi) * ds;
         double ex, pu, po, omp;
         sc_coeffs(dtau, ex, pu, po, omp);

@@ -397,6 +397,9 @@ struct Job : JobBase {
                     " does not admit " + std::to_string(nlev) + " grid levels (need nx, ny, nz-1 divisible by " +
                     std::to_string(step) + ")");
         REQUIRE(nlev == 1 || atm->nz >= 3, "multigrid needs nz >= 3");
+        if (herm())
+            REQUIRE(p->sweep_kernel == NLTE_SWEEP_AUTO || p->sweep_kernel == NLTE_SWEEP_PLANE_STEP,
+                    "Hermite upwind interpolation runs in the plane-step sweep only");
         if (p->method != NLTE_MALI) REQUIRE(nlev >= 1, "nlev >= 1");
 
         dalloc(atom_d, sizeof(AtomInfo));
@@ -430,8 +433,8 @@ struct Job : JobBase {
             }
             L.nxy = size_t(L.nx) * L.ny;
             L.nvox = L.nxy * L.nz;
-            L.fc = freq_chunks(L);
-            L.pair = pair_eligible(L, p->sweep_kernel);
+            L.fc = herm() ? 1 : freq_chunks(L);
+            L.pair = !herm() && pair_eligible(L, p->sweep_kernel);
             if (p->sweep_kernel == NLTE_SWEEP_PAIR)
                 REQUIRE(L.pair, "the two-plane sweep needs FP32, nz >= 3 and planes large enough for one "
                                 "frequency chunk per wave");
@@ -457,6 +460,9 @@ struct Job : JobBase {
             dalloc(L.nb, sizeof(double) * N * L.nvox);
             dalloc(L.tmp, sizeof(double) * N * L.nvox);
             L.maxslot = acc_slots(L.nvox, nline, sizeof(R));
+            if (herm())
+                REQUIRE(L.maxslot >= kMaxSlots, "Hermite upwind interpolation needs 8 accumulator slots per "
+                                                "quantity (at most 4 GiB of them per level)");
             march_plan(L.march, L.nxy, nline, maxfreq, sizeof(R), ctx->lds_max, p->sweep_kernel);
             if (p->sweep_kernel == NLTE_SWEEP_RESIDENT)
                 REQUIRE(L.march.F > 0, "the plane-resident sweep needs FP32 and planes of at most 4096 points");
@@ -574,8 +580,14 @@ struct Job : JobBase {
     // are split over 2 or 4 waves.  FP32 only (the FP64 kernel's registers allow one).
     int freq_chunks(const Level& L) const { return freq_chunks_for(L.nxy, nline, sizeof(R)); }
 
+    bool herm() const { return params.sc_interp == NLTE_SC_HERMITE; }
+
     void launch_step(const SweepArgs<R>& a, dim3 grid, int db, int fc, int s) {
         const unsigned threads = unsigned(db * fc * 64);
+        if (herm()) {
+            sweep_step_kernel<R, 3, true><<<grid, 3 * 64, 0, st()>>>(a, s);
+            return;
+        }
         switch (db) {
             case 12: sweep_step_kernel<R, 12><<<grid, threads, 0, st()>>>(a, s); break;
             case 6: sweep_step_kernel<R, 6><<<grid, threads, 0, st()>>>(a, s); break;
@@ -634,6 +646,7 @@ struct Job : JobBase {
     }
 
     int tile_for(int k, SweepArgs<R>& a) {
+        if (herm()) return 3;
         if (DB && DB * lev[k]->fc <= kMaxSweepWaves && kNDir / DB <= lev[k]->maxslot) return DB;
         if (level_tile.size() != size_t(nlev)) level_tile.assign(nlev, 0);
         if (!level_tile[k]) {
@@ -1166,6 +1179,7 @@ struct Job : JobBase {
             a.line_of = line_of_d.as<int>();
             a.state = estate.as<double>();
             a.out = target + size_t(d) * nf * F.nxy;
+            a.herm = params.sc_interp == NLTE_SC_HERMITE ? 1 : 0;
             for (int k = 0; k < F.nz; ++k)
                 emergent_step_kernel<R><<<blocks_for(size_t(nf) * F.nxy, 256), 256, 0, st()>>>(a, k);
             HIPCHK(hipGetLastError());
@@ -1536,7 +1550,8 @@ void nlte_atmos_destroy(nlte_ctx* ctx, nlte_atmos* atmos) {
 static bool transfer_ops_ok(const nlte_params* p) {
     auto ok = [](int op) { return op == NLTE_RESTRICT_FULL || op == NLTE_RESTRICT_HALF || op == NLTE_RESTRICT_INJECT; };
     return ok(p->restriction) && ok(p->coarse_atmos) &&
-           (p->interpolation == NLTE_INTERP_TRILINEAR || p->interpolation == NLTE_INTERP_HERMITE);
+           (p->interpolation == NLTE_INTERP_TRILINEAR || p->interpolation == NLTE_INTERP_HERMITE) &&
+           (p->sc_interp == NLTE_SC_BILINEAR || p->sc_interp == NLTE_SC_HERMITE);
 }
 
 extern "C" {
@@ -1547,7 +1562,7 @@ nlte_status nlte_job_create(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_a
         REQUIRE(atmos && atom && params && job, "null argument");
         REQUIRE(params->method >= NLTE_MALI && params->method <= NLTE_FMG, "unknown method");
         REQUIRE(params->precision == NLTE_FP64 || params->precision == NLTE_MIXED, "unknown precision");
-        REQUIRE(transfer_ops_ok(params), "unknown restriction or interpolation operator");
+        REQUIRE(transfer_ops_ok(params), "unknown restriction or interpolation scheme");
         REQUIRE(params->nu0 >= 0 && params->nu1 >= 0 && params->nu2 >= 0 && params->nu3 >= 0 && params->nu_fmg >= 0,
                 "iteration counts must be >= 0");
         REQUIRE(params->repair_frac > 0 && params->repair_frac < 1, "repair_frac must lie in (0, 1)");
@@ -1743,7 +1758,7 @@ nlte_status nlte_submit(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom*
         REQUIRE(atmos && atom && params && job, "null argument");
         REQUIRE(params->method >= NLTE_MALI && params->method <= NLTE_FMG, "unknown method");
         REQUIRE(params->precision == NLTE_FP64 || params->precision == NLTE_MIXED, "unknown precision");
-        REQUIRE(transfer_ops_ok(params), "unknown restriction or interpolation operator");
+        REQUIRE(transfer_ops_ok(params), "unknown restriction or interpolation scheme");
         REQUIRE(params->init != NLTE_INIT_USER && params->top_I == nullptr,
                 "served jobs take no host arrays in params");
         const int nlev = std::max(1, params->method == NLTE_MALI ? 1 : params->nlev);

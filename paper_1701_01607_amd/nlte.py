@@ -24,6 +24,7 @@ FP64, MIXED = 0, 1
 SWEEP_AUTO, SWEEP_PLANE_STEP, SWEEP_RESIDENT, SWEEP_PAIR = 0, 1, 2, 3
 RESTRICT_FULL, RESTRICT_HALF, RESTRICT_INJECT = 0, 1, 2
 INTERP_TRILINEAR, INTERP_HERMITE = 0, 1
+SC_BILINEAR, SC_HERMITE = 0, 1
 INIT_ZERO_RAD, INIT_LTE, INIT_USER = 0, 1, 2
 
 SYMBOLS = (
@@ -89,7 +90,7 @@ class Params(ct.Structure):
                 ("repair_frac", ct.c_double), ("fallback_mali", ct.c_int),
                 ("top_I", ct.POINTER(ct.c_double)), ("dirs_per_block", ct.c_int), ("timing", ct.c_int),
                 ("graph", ct.c_int), ("sweep_kernel", ct.c_int), ("restriction", ct.c_int),
-                ("coarse_atmos", ct.c_int), ("interpolation", ct.c_int)]
+                ("coarse_atmos", ct.c_int), ("interpolation", ct.c_int), ("sc_interp", ct.c_int)]
 
 
 class Result(ct.Structure):
@@ -194,6 +195,7 @@ class SolveParams:
     restriction: int = 0       # RESTRICT_FULL / _HALF / _INJECT
     coarse_atmos: int = 0      # RESTRICT_FULL / _INJECT (or _HALF)
     interpolation: int = 0     # INTERP_TRILINEAR / _HERMITE
+    sc_interp: int = 0         # SC_BILINEAR / SC_HERMITE
     init_pops: np.ndarray | None = None
     top_I: np.ndarray | None = None
     _keep: list = field(default_factory=list, repr=False)
@@ -202,7 +204,7 @@ class SolveParams:
         p = Params()
         for k in ("method", "precision", "nlev", "nu_fmg", "nu0", "nu1", "nu2", "nu3", "init",
                   "max_iter", "fallback_mali", "dirs_per_block", "timing", "graph", "sweep_kernel",
-                  "restriction", "coarse_atmos", "interpolation"):
+                  "restriction", "coarse_atmos", "interpolation", "sc_interp"):
             setattr(p, k, int(getattr(self, k)))
         for k in ("tol_C", "E_target", "repair_frac"):
             setattr(p, k, float(getattr(self, k)))

@@ -456,3 +456,69 @@ def test_two_plane_sweep_equals_plane_step_bitwise(nl, ctx, nx, ny, nz):
         job.close()
     for x, y in zip(*outs):
         assert np.array_equal(x, y)
+
+
+@pytest.fixture(scope="module")
+def ragged_hermite():
+    atom, atm = ragged_case()
+    lev = Level(atom, atm, sc_interp="hermite")
+    n0 = zero_radiation(lev)
+    return atom, atm, lev, n0
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
+def test_hermite_upwind_formal_solution_parity(nl, ctx, ragged_hermite, ragged, prec, tol):
+    atom, atm, lev, n0 = ragged_hermite
+    npop, nln = shapes(atom, atm)
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1,
+                                                                 sc_interp=nl.SC_HERMITE))
+    jg, og = job.formal_solution(0, nln)
+    jo, oo = formal_solution(lev, n0)
+    ej, eo = relerr(jg, jo), relerr(og, oo)
+    # in FP64 the bilinear solve differs from both by far more than the tolerance
+    jb, _ = formal_solution(ragged[2], n0)
+    print(f"prec={prec} Hermite upwind Jeff err {ej:.2e}  1-L* err {eo:.2e}; bilinear differs by {relerr(jb, jo):.2e}")
+    assert ej < tol and eo < tol
+    if prec == 0:
+        assert relerr(jb, jo) > 1000 * tol
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-3)])
+def test_hermite_upwind_mali_and_emergent_parity(nl, ctx, ragged_hermite, prec, tol):
+    atom, atm, lev, n0 = ragged_hermite
+    npop, _ = shapes(atom, atm)
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1,
+                                                                 sc_interp=nl.SC_HERMITE))
+    mus = np.array([[0.0, 0.0, 1.0], [0.3, -0.2, 0.93]])
+    Ig = job.emergent(mus, lev.nf, atm["ny"], atm["nx"])
+    Io = emergent_intensity(lev, n0, mus)
+    ee = relerr(Ig, Io)
+    job.mali(0, 3)
+    n3, _ = mali(lev, 1, n0, fine_rhs(lev), 3)
+    e = relerr(job.populations(0, npop), n3)
+    print(f"prec={prec} Hermite upwind: MALI x3 err {e:.2e}, emergent err {ee:.2e}")
+    assert e < tol
+    # the emergent solve is FP64 in both precisions but its output is FP32 (rounding 6e-8);
+    # the mixed job's FP32 level constants loosen it further
+    assert ee < (2e-7 if prec == 0 else 2e-5)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-3)])
+def test_hermite_upwind_fas_parity_and_constraints(nl, ctx, prec, tol):
+    atom, atm = mg_case()
+    n_or, st, _ = solve_fas(atom, atm, OParams(nlev=3, nu1=2, nu2=2, nu3=6, sc_interp="hermite"), cycles=2)
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
+                  nl.SolveParams(method=nl.FAS, precision=prec, nlev=3, nu1=2, nu2=2, nu3=6, E_target=0.0, tol_C=0.0,
+                                 max_iter=2, sc_interp=nl.SC_HERMITE))
+    rc, r = job.run()
+    npop, _ = shapes(atom, atm)
+    e = relerr(job.populations(2, npop), n_or)
+    print(f"prec={prec} Hermite upwind FAS 2 cycles err {e:.2e}")
+    assert r.cycles == 2 and e < tol
+    job.close()
+    for kern in (nl.SWEEP_PAIR, nl.SWEEP_RESIDENT):
+        with pytest.raises(nl.NlteError):
+            ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.FAS, precision=1, nlev=3,
+                                                                   sc_interp=nl.SC_HERMITE, sweep_kernel=kern))
+    with pytest.raises(nl.NlteError):
+        ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.FAS, nlev=3, sc_interp=2))
