@@ -277,24 +277,28 @@ inline void march_plan(P& m, size_t nxy, int nline, int maxfreq, size_t rbytes, 
     m.lds = per_f * size_t(F + 1);
 }
 
-// Frequency chunks per (direction, tile) wave group of the plane-step sweep: small planes
-// give too few waves to fill the GPU with one wave per (direction, tile, line), so their
-// frequencies are split over 2 or 4 waves.  FP32 only (the FP64 kernel's registers allow
-// one).
+// Frequency chunks per (direction, tile) wave group of the plane-step sweep.  With one
+// wave per (direction, 64 plane points, line) a launch on a small plane holds less than
+// two rounds of a full GPU (six waves per SIMD on 1024 SIMDs), and its last round runs
+// partly empty (64x64: 7680 waves, a second round a quarter full); splitting each line's
+// frequencies over 2 or 4 waves evens the rounds out.  FP32 only (the FP64 kernel's
+// registers allow one).
+constexpr double kSweepWaveTarget = 2.0 * 6.0 * 1024.0;
+inline double sweep_waves(size_t nxy, int nline) { return double((nxy + 63) / 64) * nline * kNDir; }
 inline int freq_chunks_for(size_t nxy, int nline, size_t rbytes) {
     if (rbytes != 4) return 1;
-    const double waves = double((nxy + 63) / 64) * nline * kNDir;
     int fc = 1;
-    while (fc < 4 && waves * fc < 4096.0) fc *= 2;
+    while (fc < 4 && sweep_waves(nxy, nline) * fc < kSweepWaveTarget) fc *= 2;
     return fc;
 }
 
-// Two plane steps per launch, on request, where it applies: FP32, nz >= 3, one frequency
-// chunk per wave (planes that fill the GPU) and 24 accumulator slots under 8 GiB.  It
-// moves half the plane state but measured slower than the plane-step sweep (its barrier
-// per frequency and five-wave blocks hide less latency), so it is not the default.
+// Two plane steps per launch, on request, where it applies: FP32, nz >= 3, planes that
+// fill the GPU with one frequency chunk per wave (the level then sweeps with one chunk
+// per wave throughout) and 24 accumulator slots under 8 GiB.  It moves half the plane
+// state but measured slower than the plane-step sweep (its barrier per frequency and
+// five-wave blocks hide less latency), so it is not the default.
 inline bool pair_ok(size_t nxy, int nz, int nline, size_t rbytes, int mode) {
-    if (rbytes != 4 || nz < 3 || freq_chunks_for(nxy, nline, rbytes) != 1) return false;
+    if (rbytes != 4 || nz < 3 || sweep_waves(nxy, nline) < 4096.0) return false;
     if (mode != NLTE_SWEEP_PAIR) return false;
     return double(2 * kNDir) * nline * double(nxy) * nz * double(rbytes) <= 8.0 * 1073741824.0;
 }
@@ -433,8 +437,8 @@ struct Job : JobBase {
             }
             L.nxy = size_t(L.nx) * L.ny;
             L.nvox = L.nxy * L.nz;
-            L.fc = herm() ? 1 : freq_chunks(L);
             L.pair = !herm() && pair_eligible(L, p->sweep_kernel);
+            L.fc = (herm() || L.pair) ? 1 : freq_chunks(L);
             if (p->sweep_kernel == NLTE_SWEEP_PAIR)
                 REQUIRE(L.pair, "the two-plane sweep needs FP32, nz >= 3 and planes large enough for one "
                                 "frequency chunk per wave");
@@ -575,9 +579,7 @@ struct Job : JobBase {
         return pair_ok(L.nxy, L.nz, nline, sizeof(R), mode);
     }
 
-    // Frequency chunks per (direction, tile) wave group: small planes give too few waves
-    // to fill the GPU with one wave per (direction, tile, line), so their frequencies
-    // are split over 2 or 4 waves.  FP32 only (the FP64 kernel's registers allow one).
+    // Frequency chunks per wave group of this level (freq_chunks_for).
     int freq_chunks(const Level& L) const { return freq_chunks_for(L.nxy, nline, sizeof(R)); }
 
     bool herm() const { return params.sc_interp == NLTE_SC_HERMITE; }

@@ -352,11 +352,11 @@ def test_undamped_line_far_wings_stay_finite(nl, ctx, prec, tol):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("nx,ny,shapes_", [(48, 48, (3, 6, 12)), (48, 24, (3, 6))])
+@pytest.mark.parametrize("nx,ny,shapes_", [(96, 72, (3, 6, 12)), (64, 64, (3, 6))])
 def test_block_shape_does_not_change_results(nl, ctx, prec, nx, ny, shapes_):
     """Directions are summed by one fixed tree whatever the sweep block shape, so formal
     solutions and solves are bitwise equal for 3, 6 and 12 directions per block.  The
-    48x48 plane runs one frequency chunk per wave, the 48x24 plane two (FP32)."""
+    96x72 plane runs one frequency chunk per wave, the 64x64 plane two (FP32)."""
     atom = synth.caii_like_atom(9)
     atm = synth.atmos_stratified(nx=nx, ny=ny, nz=9, dx=120 * synth.KM, seed=23)
     npop, nln = shapes(atom, atm)
@@ -378,20 +378,32 @@ def test_block_shape_does_not_change_results(nl, ctx, prec, nx, ny, shapes_):
 def test_formal_solution_parity_one_chunk_per_wave(nl, ctx, prec, tol, kern):
     if kern >= 2 and prec == 0:
         pytest.skip("the plane-resident and two-plane sweeps are FP32 only")
-    """A plane large enough for one frequency chunk per wave (the layout of the bench's
-    finest grid), against the oracle."""
-    atom = synth.caii_like_atom(9)
-    atm = synth.atmos_stratified(nx=48, ny=48, nz=9, dx=120 * synth.KM, seed=29)
-    lev = Level(atom, atm)
-    n0 = zero_radiation(lev)
+    """Planes large enough for one frequency chunk per wave (96x72; the plane-resident
+    sweep takes planes of at most 4096 points, 48x48), against the oracle."""
+    atom, atm, lev, n0, jo, oo = _one_chunk_case(48 if kern == 2 else 96, 48 if kern == 2 else 72)
     npop, nln = shapes(atom, atm)
     job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1,
                                                                  sweep_kernel=kern))
     jg, og = job.formal_solution(0, nln)
-    jo, oo = formal_solution(lev, n0)
     ej, eo = relerr(jg, jo), relerr(og, oo)
     print(f"prec={prec} kernel={kern} Jeff err {ej:.2e}  1-L* err {eo:.2e}")
     assert ej < tol and eo < tol
+
+
+_ONE_CHUNK = {}
+
+
+def _one_chunk_case(nx, ny):
+    """Atom, atmosphere, oracle level, populations and oracle formal solution, computed
+    once per plane size."""
+    if (nx, ny) not in _ONE_CHUNK:
+        atom = synth.caii_like_atom(7 if nx > 48 else 9)
+        atm = synth.atmos_stratified(nx=nx, ny=ny, nz=5 if nx > 48 else 9, dx=120 * synth.KM, seed=29)
+        lev = Level(atom, atm)
+        n0 = zero_radiation(lev)
+        jo, oo = formal_solution(lev, n0)
+        _ONE_CHUNK[(nx, ny)] = (atom, atm, lev, n0, jo, oo)
+    return _ONE_CHUNK[(nx, ny)]
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
@@ -435,11 +447,12 @@ def test_plane_resident_sweep_requests(nl, ctx):
                                                   sweep_kernel=nl.SWEEP_RESIDENT))
 
 
-@pytest.mark.parametrize("nx,ny,nz", [(48, 48, 9), (56, 48, 10)])
+@pytest.mark.parametrize("nx,ny,nz", [(96, 72, 9), (104, 72, 10)])
 def test_two_plane_sweep_equals_plane_step_bitwise(nl, ctx, nx, ny, nz):
     """The two-plane sweep computes the same cells and sums as the plane-step sweep with the
-    same code, so formal solutions and MALI iterations agree bit for bit (56 = 3.5 tiles of
-    16 and an even nz exercise ragged tiles and the closing single step)."""
+    same code, so formal solutions and MALI iterations agree bit for bit on planes where
+    the plane-step sweep also runs one frequency chunk per wave (104 = 6.5 tiles of 16 and
+    an even nz exercise ragged tiles and the closing single step)."""
     atom = synth.caii_like_atom(9)
     atm = synth.atmos_stratified(nx=nx, ny=ny, nz=nz, dx=120 * synth.KM, seed=41)
     npop, nln = shapes(atom, atm)
