@@ -311,17 +311,21 @@ def test_determinism_and_invalid_inputs(nl, ctx):
     assert ei.value.code == nl.E_INVALID
 
 
-@pytest.mark.parametrize("method", ["FAS", "MALI"])
-def test_graph_replay_equals_eager(nl, ctx, method):
+@pytest.mark.parametrize("method,ops", [("FAS", {}), ("MALI", {}),
+                                        ("FAS", {"restriction": 1, "interpolation": 1, "sc_interp": 1})],
+                         ids=["FAS", "MALI", "FAS_half_hermite"])
+def test_graph_replay_equals_eager(nl, ctx, method, ops):
     # every replay is checked: the per-cycle (per-iteration) histories and the final
-    # populations must be bitwise identical to eager execution
+    # populations must be bitwise identical to eager execution (also with the other
+    # transfer operators, whose Hermite correction adds a kernel to the captured cycle)
     atom, atm = mg_case()
     m = nl.FAS if method == "FAS" else nl.MALI
     outs = []
     for graph in (0, 1):
         job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
                       nl.SolveParams(method=m, precision=nl.MIXED, nlev=3 if m == nl.FAS else 1, nu0=3, nu1=2,
-                                     nu2=2, nu3=6, E_target=0.0, max_iter=5, graph=graph, dirs_per_block=6))
+                                     nu2=2, nu3=6, E_target=0.0, max_iter=5, graph=graph,
+                                     dirs_per_block=3 if ops else 6, **ops))
         rc, r = job.run()
         outs.append((job.history(), job.populations(job.params.nlev - 1 if m == nl.FAS else 0, (6, 17, 8, 8)),
                      r.fine_fs_equiv, list(r.formal_solutions)))

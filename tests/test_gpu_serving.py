@@ -32,8 +32,11 @@ def requests(nl):
         else:
             atom = synth.caii_like_atom(9)
             atm["ntot"] = atm["ntot"] * 0.1
+        # two requests also use the other transfer operators and the Hermite formal solution
+        ops = {3: dict(restriction=nl.RESTRICT_HALF, interpolation=nl.INTERP_HERMITE),
+               5: dict(sc_interp=nl.SC_HERMITE)}.get(j, {})
         p = nl.SolveParams(method=nl.FAS, precision=nl.MIXED, nlev=2, nu1=2, nu2=2, nu3=8, E_target=1e-4,
-                           max_iter=20, dirs_per_block=6)
+                           max_iter=20, dirs_per_block=6, **ops)
         out.append((atom, atm, p))
     return out
 
