@@ -36,6 +36,8 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import physics as ph
+
 SERIES_DTAU = 1.0e-2
 
 
@@ -203,6 +205,90 @@ def formal_solution(lev, n, want_jbar=False):
     if want_jbar:
         return Jeff, omL, Jbar
     return Jeff, omL
+
+
+def continuum_formal_solution(lev, n, want_j=False):
+    """Formal solution at the frequencies of the active continua, with the accumulations
+    of the preconditioned continuum rates.
+
+    At a continuum frequency nu every continuum t open there (nu >= its edge) adds
+    opacity chi_t = alpha_t (n_l - n_c g_t)^+ and emissivity eta_t = n_c g_t alpha_t 2 h nu^3/c^2
+    (g_t = (n_l*/n_c*) exp(-h nu/kT)); there is no background; S = sum eta / sum chi.
+    Boundaries as for the lines: I = B_nu(T) below, I = 0 above.  The net radiative rate
+    of continuum t, 4 pi int dnu/(h nu) (chi_t J - eta_t), with J = Jeff + L* S at the
+    point, is made linear in the new populations the way Rybicki & Hummer (1991, 1992)
+    precondition overlapping transitions: the local part L* S uses the new emissivity,
+    n_c E with E = sum_s g_s alpha_s 2 h nu^3/c^2 over the continua open at nu, and the
+    opacity ratio chi_t / chi of the current populations.  Per voxel and continuum this
+    gives three sums over directions and frequencies,
+
+        U_t = 4 pi sum w_d w_tk alpha_t Jeff_d / (h nu)              (times n_l: upward)
+        G_t = 4 pi sum w_d w_tk alpha_t g_t Jeff_d / (h nu)          (times n_c: downward)
+        L_t = 4 pi sum w_d w_tk (chi_t / chi) Psi_o E / (h nu)       (times n_c: removed)
+
+    with Jeff_d = I_u e + Psi_u S_u on a segment and the fixed I at a boundary, so that
+    the downward rate coefficient is G_t + F_t - L_t (F_t, the spontaneous part, is the
+    level's cont_F).  Returns an array (3, ncont, nz, ny, nx) of (U, G, L), and the mean
+    intensity J (nfc, nz, ny, nx) too if want_j.
+    """
+    nfc = lev.cont_nu.size
+    shape = (lev.nz, lev.ny, lev.nx)
+    acc = np.zeros((3, lev.ncont) + shape)
+    Jm = np.zeros((nfc,) + shape) if want_j else None
+    f = 4.0 * np.pi / (ph.H * lev.cont_nu)                         # (nfc,)
+    wa = lev.cont_w * lev.cont_alpha * f[None, :]                   # (ncont, nfc)
+    nl = [n[l] for l in lev.cont_lower]
+    nc = [n[c] for c in lev.cont_upper]
+    if len(set(lev.cont_upper)) != 1:
+        raise ValueError("active continua must share one upper level")
+    e2 = lev.cont_e[:, :, :, 0]                                     # (nfc, 1, 1)
+
+    def plane(k):
+        chis = [lev.cont_alpha[t][:, None, None] * np.maximum(nl[t][k] - nc[t][k] * lev.cont_g[t][:, k], 0.0)
+                for t in range(lev.ncont)]
+        E = sum(lev.cont_alpha[t][:, None, None] * lev.cont_g[t][:, k] for t in range(lev.ncont)) * e2
+        chi = sum(chis)
+        eta = nc[0][k] * E
+        S = safe_div(eta, chi)
+        return chis, chi, E, S
+
+    for d in range(len(lev.wmu)):
+        mu = lev.mu[d]
+        wd = lev.wmu[d]
+
+        def local(k):
+            chis, chi, E, S = plane(k)
+            return chi, S, (chis, E)
+
+        def boundary(k, mu=mu):
+            if mu[2] > 0:
+                return lev.cont_B[:, k].copy()
+            return np.zeros((nfc, lev.ny, lev.nx))
+
+        def accumulate(k, kind, data):
+            if kind == "bc":
+                I, _ = data
+                Jd, lam = I, None
+                Io = I
+            else:
+                I_u, S_u, ex, psi_u, psi_o, I_o, chi, S, (chis, E) = data
+                Jd = I_u * ex + psi_u * S_u
+                lam = (chis, chi, psi_o, E)
+                Io = I_o
+            for t in range(lev.ncont):
+                acc[0, t, k] += wd * np.tensordot(wa[t], Jd, axes=(0, 0))
+                acc[1, t, k] += wd * np.tensordot(wa[t], lev.cont_g[t][:, k] * Jd, axes=(0, 0))
+                if lam is not None:
+                    chis, chi, psi_o, E = lam
+                    acc[2, t, k] += wd * np.tensordot(f * lev.cont_w[t], safe_div(chis[t], chi) * psi_o * E,
+                                                      axes=(0, 0))
+            if want_j:
+                Jm[:, k] += wd * Io
+
+        sweep(lev, mu, local, boundary, accumulate)
+    if want_j:
+        return acc, Jm
+    return acc
 
 
 def emergent_intensity(lev, n, mus):

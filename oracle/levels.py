@@ -66,11 +66,35 @@ class Level:
 
         self.mu, self.wmu = a4_directions()
         self.nstar = ph.lte_populations(atom, T, atmos["ne"], self.ntot)
-        self.fixed = ph.collision_matrix(atom, T, atmos["ne"], self.nstar) \
-            + ph.fixed_bf_rates(atom, T, self.nstar)
+        self.active_continua = atom.get("continuum_nu") is not None
+        self.fixed = ph.collision_matrix(atom, T, atmos["ne"], self.nstar)
+        if self.active_continua:
+            self._continuum_setup(atom, T)
+        else:
+            self.fixed = self.fixed + ph.fixed_bf_rates(atom, T, self.nstar)
         self.top_I = top_I
         self.sc_interp = sc_interp   # upwind interpolation of the formal solution
         self._norm = None
+
+    # ---- active continua ---------------------------------------------------
+    def _continuum_setup(self, atom, T):
+        """Frequencies, cross-sections and weights of the active continua, the LTE ratio
+        g_t(nu) = (n_l*/n_c*) exp(-h nu/kT) per voxel, and the spontaneous part of the
+        downward rate F_t = 4 pi sum_k w_tk alpha_tk g_tk (2 h nu^3/c^2) / (h nu)."""
+        self.cont_nu = np.asarray(atom["continuum_nu"], dtype=np.float64)
+        self.cont_alpha, self.cont_w = ph.continuum_quadrature(atom, self.cont_nu)
+        self.cont_lower = [ct["lower"] for ct in atom["continua"]]
+        self.cont_upper = [ct["upper"] for ct in atom["continua"]]
+        self.ncont = len(self.cont_lower)
+        nu = self.cont_nu[:, None, None, None]
+        x = np.exp(-ph.H * nu / (ph.KB * T[None]))                  # (nfc, nz, ny, nx)
+        self.cont_g = np.stack([(self.nstar[l] / self.nstar[c])[None] * x
+                                for l, c in zip(self.cont_lower, self.cont_upper)])   # (ncont, nfc, ...)
+        self.cont_e = 2.0 * ph.H * nu ** 3 / ph.C ** 2                  # 2 h nu^3 / c^2
+        self.cont_B = ph.planck_nu(nu, T[None])                          # (nfc, nz, ny, nx)
+        f = 4.0 * np.pi / (ph.H * self.cont_nu)                          # 4 pi / (h nu)
+        self.cont_F = np.stack([np.tensordot(self.cont_w[t] * self.cont_alpha[t] * f, self.cont_g[t] * self.cont_e,
+                                             axes=(0, 0)) for t in range(self.ncont)])
 
     # ---- profile -----------------------------------------------------------
     def profile(self, k, mu):

@@ -14,6 +14,9 @@ the readings used here are:
 * Fixed bound-free transitions with a hydrogenic cross-section
   alpha0 (nu_edge/nu)^3 in a Planck radiation field at the local temperature:
   R_ic = (8 pi alpha0 nu_e^3 / c^2) sum_k E1(k h nu_e / kT), R_ci = R_ic (n_i/n_c)*.
+  Or, when the atom carries a continuum frequency grid, active continua swept by the
+  formal solution (formal.continuum_formal_solution), with the same cross-section and
+  no background at continuum frequencies.
 * Doppler width v_D = sqrt(2kT/m + xi^2); damping a = Gamma / (4 pi dnu_D) with
   Gamma = gamma_rad + gamma_vdw n_H (T/5000)^0.3.
 * Voigt function H(a,u) = Re w(u + i a), w the Faddeeva function.
@@ -133,6 +136,26 @@ def fixed_bf_rates(atom, T, nstar):
         R[i, c] += ric
         R[c, i] += ric * nstar[i] / nstar[c]
     return R
+
+
+def continuum_quadrature(atom, nu):
+    """Active continua: alpha_t(nu_k) = alpha0 (nu_edge/nu_k)^3 at or above the edge, else 0,
+    and the trapezoid weights w_tk of the integral over [nu_edge, nu_max] on the grid points
+    at or above the edge (the grid contains every edge).  Shapes (ncont, nfc)."""
+    nu = np.asarray(nu, dtype=np.float64)
+    lv = atom["levels"]
+    nc = len(atom["continua"])
+    alpha = np.zeros((nc, nu.size))
+    w = np.zeros((nc, nu.size))
+    for t, ct in enumerate(atom["continua"]):
+        nue = C * (lv[ct["upper"]]["E"] - lv[ct["lower"]]["E"])
+        on = nu >= nue * (1.0 - 1e-12)
+        idx = np.nonzero(on)[0]
+        alpha[t, idx] = ct["alpha0"] * (nue / nu[idx]) ** 3
+        d = np.diff(nu[idx])
+        w[t, idx[:-1]] += 0.5 * d
+        w[t, idx[1:]] += 0.5 * d
+    return alpha, w
 
 
 def doppler_velocity(atom, T):

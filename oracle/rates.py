@@ -14,21 +14,32 @@ at populations n, the same matrix applied to n gives W(n) (Eq. 4; Eq. 7 with the
 "extra" formal solution at n), because (n_i B_ij - n_j B_ji) S_l = n_j A_ji.
 
 Zero-radiation initialisation (Sect. 4.11): Jeff = 0 and 1 - L* = 1 (spontaneous
-emission kept, fixed bound-free rates kept).
+emission kept, fixed bound-free rates kept; active continua keep only their spontaneous
+recombination F_t).
 """
 from __future__ import annotations
 
 import numpy as np
 
 
-def rate_matrix(lev, Jeff, omL):
-    """P[i, j] (rate coefficient i -> j) per voxel, shape (N, N, nz, ny, nx)."""
+def rate_matrix(lev, Jeff, omL, cont=None):
+    """P[i, j] (rate coefficient i -> j) per voxel, shape (N, N, nz, ny, nx).
+
+    Active continua (cont = (U, G, L) from formal.continuum_formal_solution, or None for
+    no radiation) add upward U_t and downward G_t + F_t - L_t."""
     P = lev.fixed.copy()
     for l in range(lev.nline):
         Aji, Bij, Bji = lev.einstein[l]
         i, j = lev.lower[l], lev.upper[l]
         P[i, j] += Bij * Jeff[l]
         P[j, i] += Aji * omL[l] + Bji * Jeff[l]
+    if getattr(lev, "active_continua", False):
+        for t in range(lev.ncont):
+            i, c = lev.cont_lower[t], lev.cont_upper[t]
+            P[c, i] += lev.cont_F[t]
+            if cont is not None:
+                P[i, c] += cont[0, t]
+                P[c, i] += cont[1, t] - cont[2, t]
     return P
 
 
@@ -46,18 +57,18 @@ def system_matrix(P):
     return A
 
 
-def apply_W(lev, n, Jeff, omL):
+def apply_W(lev, n, Jeff, omL, cont=None):
     """W(n) per level and voxel, shape (N, nz, ny, nx): row 0 = sum n, others stat. eq."""
-    A = system_matrix(rate_matrix(lev, Jeff, omL))
+    A = system_matrix(rate_matrix(lev, Jeff, omL, cont))
     N = n.shape[0]
     nv = n.reshape(N, -1).T
     return np.einsum("vij,vj->vi", A, nv).T.reshape(n.shape)
 
 
-def solve(lev, Jeff, omL, f):
+def solve(lev, Jeff, omL, f, cont=None):
     """Solve A n = f per voxel (LAPACK gesv, partial pivoting) and rescale so that
     sum_i n_i = f_0 exactly."""
-    A = system_matrix(rate_matrix(lev, Jeff, omL))
+    A = system_matrix(rate_matrix(lev, Jeff, omL, cont))
     N = f.shape[0]
     rhs = f.reshape(N, -1).T
     n = np.linalg.solve(A, rhs[..., None])[..., 0]

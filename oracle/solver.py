@@ -35,7 +35,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .formal import formal_solution
+from .formal import continuum_formal_solution, formal_solution
 from .levels import Level, build_hierarchy
 from .rates import apply_W, fine_rhs, max_rel_change, solve, zero_radiation
 from .transfer import prolong, restrict
@@ -82,17 +82,20 @@ class Stats:
 
 
 def _fs(lev, k, n, stats):
+    """(Jeff, 1 - L*, continuum sums or None) of a formal solution at n."""
     if stats is not None:
         stats.count_fs(k)
-    return formal_solution(lev, n)
+    Jeff, omL = formal_solution(lev, n)
+    cont = continuum_formal_solution(lev, n) if getattr(lev, "active_continua", False) else None
+    return Jeff, omL, cont
 
 
 def mali(lev, k, n, f, iters, stats=None, fs0=None):
     """``iters`` MALI iterations on level k; returns (n, C of the last iteration)."""
     C = None
     for it in range(iters):
-        Jeff, omL = fs0 if (it == 0 and fs0 is not None) else _fs(lev, k, n, stats)
-        n_new = solve(lev, Jeff, omL, f)
+        Jeff, omL, cont = fs0 if (it == 0 and fs0 is not None) else _fs(lev, k, n, stats)
+        n_new = solve(lev, Jeff, omL, f, cont)
         if stats is not None:
             stats.count_solve(k)
         C = max_rel_change(n_new, n)

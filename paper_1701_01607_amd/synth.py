@@ -132,6 +132,27 @@ def caii_like_atom(nfreq=101):
     }
 
 
+def continuum_grid(atom, n_seg=6, n_top=16, top=1.6):
+    """Frequencies (Hz) for treating the atom's continua as active transitions: every
+    edge, n_seg geometric steps between consecutive edges and n_top from the highest edge
+    to `top` times it."""
+    c_light = 2.99792458e10
+    lv = atom["levels"]
+    edges = sorted({c_light * (lv[c["upper"]]["E"] - lv[c["lower"]]["E"]) for c in atom["continua"]})
+    pts = []
+    for a, b in zip(edges[:-1], edges[1:]):
+        pts.extend(np.geomspace(a, b, n_seg + 1)[:-1])
+    pts.extend(np.geomspace(edges[-1], top * edges[-1], n_top + 1))
+    return np.array(pts)
+
+
+def with_active_continua(atom, **kw):
+    """A copy of `atom` whose continua are swept as active transitions on continuum_grid()."""
+    out = dict(atom)
+    out["continuum_nu"] = continuum_grid(atom, **kw)
+    return out
+
+
 # --------------------------------------------------------------------- atmospheres
 
 
