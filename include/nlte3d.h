@@ -114,6 +114,12 @@ typedef struct {
     const nlte_line_desc* lines;
     const nlte_cont_desc* continua;
     const nlte_coll_desc* collisions;
+    int ncont_nu;              /* > 0: the continua are active transitions of the formal
+                                  solution, swept at these frequencies (RH92 preconditioning
+                                  of the overlapping continua, which must share one upper
+                                  level); 0: fixed continua with photo-rates at J = B(T) */
+    const double* cont_nu;     /* ncont_nu frequencies (Hz), increasing, containing every
+                                  continuum edge; host memory, copied */
 } nlte_atom_desc;
 
 typedef struct {

@@ -23,6 +23,7 @@ struct LineInfo {
 
 struct AtomInfo {
     int N, nline, ncont, ncoll, eps_mode;
+    int cont_active;     // 1: continua are transitions of the formal solution, 0: fixed rates
     double mass, xi, eps;
     double E[kMaxLevels], g[kMaxLevels];
     int stage[kMaxLevels];
@@ -123,7 +124,7 @@ __global__ void setup_level_kernel(SetupArgs<R> a) {
             P[lo * N + up] += cul * ws[up] / ws[lo];
         }
     }
-    for (int c = 0; c < at.ncont; ++c) {
+    for (int c = 0; c < (at.cont_active ? 0 : at.ncont); ++c) {
         const int i = at.cont_lower[c], j = at.cont_upper[c];
         const double nue = kC * (at.E[j] - at.E[i]);
         const double x = kH * nue / (kKB * T);
@@ -1025,6 +1026,182 @@ __global__ void emergent_step_kernel(EmergentArgs<R> a, int k) {
     if (k == a.nz - 1) a.out[size_t(f) * a.nxy + g] = float(I);
 }
 
+// ------------------------------------------------------------------ active continua
+// Continua as transitions of the formal solution (on request).  Per voxel: the LTE ratio
+// n_l*/n_c* of every continuum, h/kT, and the spontaneous part of the downward rate,
+// F_t = sum_k (4 pi w_tk / h nu_k) alpha_tk g_tk 2 h nu_k^3/c^2 with g = (n_l*/n_c*) e^{-h nu/kT}.
+constexpr int kMaxCont = 8;
+
+template <typename R>
+__global__ void cont_setup_kernel(const AtomInfo* atom, const double* prim, const double* nstar, const double* cnu,
+                                  const double* ce, const double* cfw, const double* calpha, int nfc, R* cr, R* hkT,
+                                  double* cF, size_t nvox) {
+    const size_t v = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    const AtomInfo& at = *atom;
+    const double T = prim[P_T * nvox + v];
+    const double hk = kH / (kKB * T);
+    hkT[v] = R(hk);
+    for (int t = 0; t < at.ncont; ++t) {
+        const double ratio = nstar[size_t(at.cont_lower[t]) * nvox + v] / nstar[size_t(at.cont_upper[t]) * nvox + v];
+        cr[size_t(t) * nvox + v] = R(ratio);
+        double F = 0.0;
+        for (int k = 0; k < nfc; ++k)
+            F += cfw[size_t(t) * nfc + k] * calpha[size_t(t) * nfc + k] * ratio * exp(-hk * cnu[k]) * ce[k];
+        cF[size_t(t) * nvox + v] = F;
+    }
+}
+
+// Plane state of the continuum sweep: intensity, source function and opacity.
+template <typename R>
+struct CCell {
+    R I, S, C;
+};
+
+template <typename R>
+struct ContArgs {
+    const AtomInfo* atom;
+    int nx, ny, nz, nfc;
+    unsigned nxy;
+    size_t nvox;
+    double dx, dy;
+    const double* z;
+    const double* n;      // [N][nvox] populations
+    const R* cr;          // [ncont][nvox] n_l*/n_c*
+    const R* hkT;         // [nvox] h/kT
+    const R* cnu;         // [nfc] frequencies (Hz)
+    const R* ce;          // [nfc] 2 h nu^3 / c^2
+    const R* cfw;         // [ncont][nfc] 4 pi w_tk / (h nu_k)
+    const R* calpha;      // [ncont][nfc] cross-sections (0 below the edge)
+    CCell<R>* state;      // [2][24][nfc][nxy]
+    R* acc;               // [3 ncont][8 slots][nvox]: U, G, L per continuum
+};
+
+// One plane step of the formal solution at the continuum frequencies, for three
+// directions per block (one wave each, 64 plane points) and every continuum frequency
+// in order.  Opacity and emissivity at a point sum over the continua open at the
+// frequency; the three sums per continuum (U: alpha Jeff, G: alpha g Jeff, L: the
+// preconditioned local part (chi_t/chi) Psi_o E, each times 4 pi w / h nu and the
+// direction weight 1/24) are added over the block's three directions as (d0 + d1) + d2
+// and stored per direction group; the rate kernel finishes the fixed tree.
+template <typename R>
+__global__ __launch_bounds__(3 * 64) void sweep_cont_kernel(ContArgs<R> a, int s) {
+    constexpr int kW = 64;
+    const int lane = int(threadIdx.x) & (kW - 1);
+    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kW);
+    const int grp = int(blockIdx.z);
+    const int d = grp * 3 + w;
+    const int h = (grp * 3) / kNHemi;
+    const AtomInfo& at = *a.atom;
+    const int nct = at.ncont;
+    const unsigned nxy = a.nxy;
+    const unsigned graw = blockIdx.x * kW + unsigned(lane);
+    const bool valid = graw < nxy;
+    const unsigned g = valid ? graw : nxy - 1;
+    const int k = (h == 0) ? s : a.nz - 1 - s;
+    const size_t nv = a.nvox;
+    const size_t v = size_t(k) * nxy + g;
+    const int nfc = a.nfc;
+    const size_t dstride = size_t(nfc) * nxy;
+    const size_t slot_stride = size_t(kNDir) * dstride;
+    CCell<R>* cur = a.state + size_t(s & 1) * slot_stride + size_t(d) * dstride;
+    const R nc = R(fmax(a.n[size_t(at.cont_upper[0]) * nv + v], 0.0));
+    R nl[kMaxCont], ratio[kMaxCont];
+#pragma unroll
+    for (int t = 0; t < kMaxCont; ++t) {
+        nl[t] = t < nct ? R(fmax(a.n[size_t(at.cont_lower[t]) * nv + v], 0.0)) : R(0);
+        ratio[t] = t < nct ? a.cr[size_t(t) * nv + v] : R(0);
+    }
+    const R hk = a.hkT[v];
+    const R wd = R(1.0 / kNDir);
+    R aU[kMaxCont], aG[kMaxCont], aL[kMaxCont];
+#pragma unroll
+    for (int t = 0; t < kMaxCont; ++t) aU[t] = aG[t] = aL[t] = R(0);
+    // upwind geometry (planes after the boundary)
+    int o00 = 0, o01 = 0, o10 = 0, o11 = 0;
+    R w00 = R(0), w01 = R(0), w10 = R(0), w11 = R(0), rds = R(0);
+    const CCell<R>* prv = nullptr;
+    if (s > 0) {
+        const double mux = c_mu[3 * d], muy = c_mu[3 * d + 1], muz = c_mu[3 * d + 2];
+        const int kp = (h == 0) ? s - 1 : a.nz - s;
+        const double ds = fabs(a.z[k] - a.z[kp]) / fabs(muz);
+        const double sx = -ds * mux / a.dx, sy = -ds * muy / a.dy;
+        const double fsx = floor(sx), fsy = floor(sy);
+        const R fx = R(sx - fsx), fy = R(sy - fsy);
+        const int x = int(g % unsigned(a.nx)), y = int(g / unsigned(a.nx));
+        int x0 = int((long long)(x + (long long)fsx) % a.nx); if (x0 < 0) x0 += a.nx;
+        int y0 = int((long long)(y + (long long)fsy) % a.ny); if (y0 < 0) y0 += a.ny;
+        const int x1 = (x0 + 1 == a.nx) ? 0 : x0 + 1;
+        const int y1 = (y0 + 1 == a.ny) ? 0 : y0 + 1;
+        o00 = y0 * a.nx + x0; o01 = y0 * a.nx + x1; o10 = y1 * a.nx + x0; o11 = y1 * a.nx + x1;
+        w00 = (R(1) - fx) * (R(1) - fy); w01 = fx * (R(1) - fy);
+        w10 = (R(1) - fx) * fy; w11 = fx * fy;
+        rds = R(ds);
+        prv = a.state + size_t((s - 1) & 1) * slot_stride + size_t(d) * dstride;
+    }
+    for (int m = 0; m < nfc; ++m) {
+        const R x = exp(-hk * a.cnu[m]);
+        const R e = a.ce[m];
+        R chis[kMaxCont], gg[kMaxCont];
+        R chi = R(0), E = R(0);
+#pragma unroll
+        for (int t = 0; t < kMaxCont; ++t) {
+            const R al = t < nct ? a.calpha[size_t(t) * nfc + m] : R(0);
+            gg[t] = ratio[t] * x;
+            chis[t] = al * fmax(nl[t] - nc * gg[t], R(0));
+            chi += chis[t];
+            E = fma(al, gg[t], E);
+        }
+        E *= e;
+        const R S = chi > R(0) ? nc * E / chi : R(0);
+        R Jd, Io, po = R(0);
+        if (s == 0) {
+            Io = (h == 0) ? e * x / (R(1) - x) : R(0);
+            Jd = Io;
+        } else {
+            const size_t fo = size_t(m) * nxy;
+            const CCell<R> c00 = prv[fo + o00], c01 = prv[fo + o01], c10 = prv[fo + o10], c11 = prv[fo + o11];
+            const R Iu = interp4(w00, w01, w10, w11, c00.I, c01.I, c10.I, c11.I);
+            const R Su = interp4(w00, w01, w10, w11, c00.S, c01.S, c10.S, c11.S);
+            const R Cu = interp4(w00, w01, w10, w11, c00.C, c01.C, c10.C, c11.C);
+            const R dtau = R(0.5) * (Cu + chi) * rds;
+            R ex, pu, omp;
+            sc_coeffs(dtau, ex, pu, po, omp);
+            Jd = fma(Iu, ex, pu * Su);
+            Io = fma(po, S, Jd);
+        }
+        if (valid) cur[size_t(m) * nxy + g] = CCell<R>{Io, S, chi};
+        const R rchi = chi > R(0) ? R(1) / chi : R(0);
+#pragma unroll
+        for (int t = 0; t < kMaxCont; ++t) {
+            if (t < nct) {
+                const R fw = a.cfw[size_t(t) * nfc + m];
+                const R wa = wd * fw * a.calpha[size_t(t) * nfc + m];
+                aU[t] = fma(wa, Jd, aU[t]);
+                aG[t] = fma(wa * gg[t], Jd, aG[t]);
+                aL[t] = fma(wd * fw, chis[t] * rchi * po * E, aL[t]);
+            }
+        }
+    }
+    // (d0 + d1) + d2 over the block's three directions, per quantity and continuum
+    __shared__ R red[3 * 3 * kMaxCont][3 * kW];
+#pragma unroll
+    for (int t = 0; t < kMaxCont; ++t) {
+        red[t][threadIdx.x] = aU[t];
+        red[kMaxCont + t][threadIdx.x] = aG[t];
+        red[2 * kMaxCont + t][threadIdx.x] = aL[t];
+    }
+    __syncthreads();
+    if (w == 0 && valid) {
+        for (int q = 0; q < 3; ++q)
+            for (int t = 0; t < nct; ++t) {
+                const R* r = red[q * kMaxCont + t];
+                const R sum = (r[lane] + r[kW + lane]) + r[2 * kW + lane];
+                a.acc[(size_t(q * nct + t) * kMaxSlots + grp) * nv + v] = sum;
+            }
+    }
+}
+
 // ------------------------------------------------------------------ rate equations
 // Rate matrix from the fixed rates and the preconditioned radiative rates of
 // Rybicki & Hummer (1991): upward B_ij Jeff, downward A_ji (1 - L*) + B_ji Jeff.
@@ -1048,16 +1225,30 @@ struct RateArgs {
     double sign;
     int mode;
     double* partial;      // [gridDim.x] max relative change (modes 0/1)
+    const R* cacc;        // active continua: [3 ncont][8 slots][nvox] (U, G, L), else null
+    const double* cF;     // active continua: [ncont][nvox] spontaneous recombination
 };
 
 template <int N>
 __device__ inline void build_matrix(const AtomInfo& at, const double* pfix, size_t nv, size_t v,
-                                    const double* Jeff, const double* omL, double (&A)[N][N]) {
+                                    const double* Jeff, const double* omL, const double* cup,
+                                    const double* cdn, double (&A)[N][N]) {
     double P[N][N];
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
         for (int j = 0; j < N; ++j) P[i][j] = pfix[size_t(i * N + j) * nv + v];
+    // active continua: upward U_t, downward G_t + F_t - L_t
+    for (int t = 0; t < (at.cont_active ? at.ncont : 0); ++t) {
+        const int lo = at.cont_lower[t], up = at.cont_upper[t];
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                if (i == lo && j == up) P[i][j] += cup[t];
+                if (i == up && j == lo) P[i][j] += cdn[t];
+            }
+    }
     for (int l = 0; l < at.nline; ++l) {
         const LineInfo& ln = at.line[l];
         const double up = ln.Bij * Jeff[l];
@@ -1153,8 +1344,23 @@ __global__ __launch_bounds__(256) void rate_kernel(RateArgs<R> a) {
                 omL[l] = double(tree_slots(a.acc + (size_t(1) * a.nslot * L + l) * nv + v, ss, a.nslot));
             }
         }
+        double cup[kMaxCont], cdn[kMaxCont];
+        for (int t = 0; t < (at.cont_active ? at.ncont : 0); ++t) {
+            const double F = a.cF[size_t(t) * nv + v];
+            if (a.mode == 1) {
+                cup[t] = 0.0;
+                cdn[t] = F;
+            } else {
+                const int nc3 = at.ncont;
+                auto sum = [&](int q) {
+                    return double(tree_slots(a.cacc + (size_t(q * nc3 + t) * kMaxSlots) * nv + v, nv, kMaxSlots));
+                };
+                cup[t] = sum(0);
+                cdn[t] = sum(1) + F - sum(2);
+            }
+        }
         double A[N][N];
-        build_matrix<N>(at, a.pfix, nv, v, Jeff, omL, A);
+        build_matrix<N>(at, a.pfix, nv, v, Jeff, omL, cup, cdn, A);
         double nold[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) nold[i] = a.n[size_t(i) * nv + v];

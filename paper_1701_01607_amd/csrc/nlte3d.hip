@@ -188,6 +188,10 @@ struct nlte_atom {
     std::vector<double> wnu;      // flat trapezoid weights in Hz
     std::vector<int> line_of;
     int nf = 0;
+    // active continua: frequencies, 2 h nu^3/c^2, and per continuum [ncont][nfc] the
+    // cross-sections (0 below the edge) and 4 pi w / (h nu) with w the trapezoid weights
+    // over the grid points at or above the edge
+    std::vector<double> cnu, ce, calpha, cfw;
 };
 
 struct nlte_atmos {
@@ -236,6 +240,7 @@ struct Level {
     double dx = 0, dy = 0;
     std::vector<double> z;
     DevBuf dz, prim, sc, sv, nstar, pfix, ntot, n, f, nb, tmp, acc, lc, partial;
+    DevBuf cr, chkT, cF, cacc;   // active continua: LTE ratios, h/kT, spontaneous rates, sums
     bool fs_valid = false;
     long long fs_count = 0;
     int nslot = 2;   // direction-group slots in acc written by the last formal solution
@@ -315,6 +320,9 @@ struct Job : JobBase {
     nlte_ctx* ctx;
     std::vector<std::unique_ptr<Level>> lev;
     DevBuf atom_d, qf, wf, line_of_d, state, topI, scalar, repairs, estate, eout, flag, nprev;
+    // active continua: frequency tables (R for the sweep, FP64 for the setup) and plane state
+    DevBuf cnu_r, ce_r, cfw_r, calpha_r, cnu_d, ce_d, cfw_d, calpha_d, cstate;
+    int nfc = 0;
     AtomInfo info{};
     int DB = 0;   // directions per sweep block (0: autotuned per level)
     int nstate = 2;   // plane-state slots (3 when a level sweeps two planes per launch)
@@ -414,6 +422,21 @@ struct Job : JobBase {
         dalloc(line_of_d, sizeof(int) * nf);
         HIPCHK(hipMemcpyAsync(qf.p, qh.data(), sizeof(R) * nf, hipMemcpyHostToDevice, st()));
         HIPCHK(hipMemcpyAsync(wf.p, wh.data(), sizeof(R) * nf, hipMemcpyHostToDevice, st()));
+        if (info.cont_active) {
+            nfc = int(atom->cnu.size());
+            auto up = [&](DevBuf& bd, DevBuf& br, const std::vector<double>& h) {
+                dalloc(bd, sizeof(double) * h.size());
+                HIPCHK(hipMemcpyAsync(bd.p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, st()));
+                std::vector<R> hr(h.begin(), h.end());
+                dalloc(br, sizeof(R) * h.size());
+                HIPCHK(hipMemcpyAsync(br.p, hr.data(), sizeof(R) * h.size(), hipMemcpyHostToDevice, st()));
+                HIPCHK(hipStreamSynchronize(st()));   // hr is a host temporary
+            };
+            up(cnu_d, cnu_r, atom->cnu);
+            up(ce_d, ce_r, atom->ce);
+            up(cfw_d, cfw_r, atom->cfw);
+            up(calpha_d, calpha_r, atom->calpha);
+        }
         HIPCHK(hipMemcpyAsync(line_of_d.p, atom->line_of.data(), sizeof(int) * nf, hipMemcpyHostToDevice, st()));
         dalloc(scalar, sizeof(double) * 4);
         dalloc(repairs, sizeof(unsigned long long));
@@ -491,6 +514,22 @@ struct Job : JobBase {
             HIPCHK(hipGetLastError());
             fine_rhs_kernel<<<blocks_for(L.nvox, 256), 256, 0, st()>>>(L.f.as<double>(), L.ntot.as<double>(), N, L.nvox);
             HIPCHK(hipGetLastError());
+            if (info.cont_active) {
+                const int nct = info.ncont;
+                dalloc(L.cr, sizeof(R) * nct * L.nvox);
+                dalloc(L.chkT, sizeof(R) * L.nvox);
+                dalloc(L.cF, sizeof(double) * nct * L.nvox);
+                dalloc(L.cacc, sizeof(R) * 3 * nct * kMaxSlots * L.nvox);
+                cont_setup_kernel<R><<<blocks_for(L.nvox, 128), 128, 0, st()>>>(
+                    atom_d.as<AtomInfo>(), L.prim.as<double>(), L.nstar.as<double>(), cnu_d.as<double>(),
+                    ce_d.as<double>(), cfw_d.as<double>(), calpha_d.as<double>(), nfc, L.cr.as<R>(), L.chkT.as<R>(),
+                    L.cF.as<double>(), L.nvox);
+                HIPCHK(hipGetLastError());
+            }
+        }
+        if (info.cont_active) {
+            const Level& Fc = *lev[nlev - 1];
+            dalloc(cstate, sizeof(CCell<R>) * 2 * kNDir * size_t(nfc) * Fc.nxy);
         }
         const Level& Fz = *lev[nlev - 1];
         // Frequency passes: each pass sweeps Q frequencies of every line.  One pass is the
@@ -679,6 +718,8 @@ struct Job : JobBase {
         ra.mode = mode;
         const unsigned nb = blocks_for(L.nvox, 256);
         ra.partial = want_C ? L.partial.as<double>() : nullptr;
+        ra.cacc = info.cont_active ? L.cacc.as<R>() : nullptr;
+        ra.cF = info.cont_active ? L.cF.as<double>() : nullptr;
         ev_begin(EV_RATES);
         switch (N) {
 #define RCASE(NN) case NN: rate_kernel<R, NN><<<nb, 256, 0, st()>>>(ra); break;
@@ -760,11 +801,33 @@ struct Job : JobBase {
             ev_end();
             L.nslot = kNDir / db;
         }
+        if (info.cont_active) cont_sweep(k);
         L.fs_valid = true;
         ++L.fs_count;
         const Level& F = *lev[nlev - 1];
         cost_units += double(L.nvox) / double(F.nvox);
-        updates += double(L.nvox) * kNDir * nf;
+        updates += double(L.nvox) * kNDir * (nf + nfc);
+    }
+
+    // Formal solution at the continuum frequencies of level k (active continua).
+    void cont_sweep(int k) {
+        Level& L = *lev[k];
+        ContArgs<R> c;
+        c.atom = atom_d.as<AtomInfo>();
+        c.nx = L.nx; c.ny = L.ny; c.nz = L.nz; c.nfc = nfc;
+        c.nxy = unsigned(L.nxy); c.nvox = L.nvox;
+        c.dx = L.dx; c.dy = L.dy;
+        c.z = L.dz.as<double>();
+        c.n = L.n.as<double>();
+        c.cr = L.cr.as<R>(); c.hkT = L.chkT.as<R>();
+        c.cnu = cnu_r.as<R>(); c.ce = ce_r.as<R>(); c.cfw = cfw_r.as<R>(); c.calpha = calpha_r.as<R>();
+        c.state = cstate.as<CCell<R>>();
+        c.acc = L.cacc.as<R>();
+        const dim3 grid(blocks_for(L.nxy, 64), 1, kNDir / 3);
+        ev_begin(EV_SWEEP);
+        for (int s = 0; s < L.nz; ++s) sweep_cont_kernel<R><<<grid, 3 * 64, 0, st()>>>(c, s);
+        HIPCHK(hipGetLastError());
+        ev_end();
     }
 
     void march_launch(int k) {
@@ -1230,6 +1293,8 @@ size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom
         bytes += 8 * size_t(nz) + 8 * size_t(nprim) * nvox + R * (6 * nline + 4) * nvox;
         bytes += 8 * (size_t(N) * 6 + size_t(N) * N + 1) * nvox + R * (2 * slots + 2) * nline * nvox;
         bytes += 8 * std::max<size_t>((nvox + 255) / 256, 1024);
+        if (atom->info.cont_active)   // LTE ratios, h/kT, spontaneous rates, U/G/L sums
+            bytes += (R * (atom->info.ncont + 1) + 8 * atom->info.ncont + R * 3 * atom->info.ncont * kMaxSlots) * nvox;
         nx /= 2; ny /= 2; nz = (nz - 1) / 2 + 1;
     }
     const char* envb = std::getenv("NLTE3D_SWEEP_STATE_MB");
@@ -1245,6 +1310,8 @@ size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom
     }
     if (!fine_resident) bytes += cell * nstate * kNDir * size_t(nline) * Q * fine_nxy;
     bytes += 8 * size_t(N) * fine_nvox;
+    if (atom->info.cont_active)       // continuum plane state and frequency tables
+        bytes += 3 * R * 2 * kNDir * atom->cnu.size() * fine_nxy + (8 + R) * 4 * atom->calpha.size();
     if (p->top_I) bytes += R * size_t(nf) * fine_nxy;
     bytes += 8 * 6 * size_t(nf) * fine_nxy;             // emergent-intensity state
     bytes += 4 * size_t(nf) * fine_nxy;                  // one direction of host-bound output
@@ -1483,6 +1550,36 @@ nlte_status nlte_atom_create(nlte_ctx* ctx, const nlte_atom_desc* d, nlte_atom**
             REQUIRE(s.lower >= 0 && s.upper < I.N && I.stage[s.upper] == I.stage[s.lower] + 1,
                     "continuum must link stage s to stage s+1");
             I.cont_lower[c] = s.lower; I.cont_upper[c] = s.upper; I.cont_alpha0[c] = s.alpha0;
+        }
+        I.cont_active = 0;
+        if (d->ncont_nu > 0) {
+            REQUIRE(d->cont_nu && I.ncont >= 1, "active continua need a frequency grid and continua");
+            const int nfc = d->ncont_nu;
+            for (int k = 0; k < nfc; ++k)
+                REQUIRE(std::isfinite(d->cont_nu[k]) && d->cont_nu[k] > 0 && (k == 0 || d->cont_nu[k] > d->cont_nu[k - 1]),
+                        "continuum frequencies must be positive and increasing");
+            a->cnu.assign(d->cont_nu, d->cont_nu + nfc);
+            a->ce.resize(nfc);
+            for (int k = 0; k < nfc; ++k) a->ce[k] = 2.0 * kH * a->cnu[k] * a->cnu[k] * a->cnu[k] / (kC * kC);
+            a->calpha.assign(size_t(I.ncont) * nfc, 0.0);
+            a->cfw.assign(size_t(I.ncont) * nfc, 0.0);
+            for (int c = 0; c < I.ncont; ++c) {
+                REQUIRE(I.cont_upper[c] == I.cont_upper[0], "active continua must share one upper level");
+                const double nue = kC * (I.E[I.cont_upper[c]] - I.E[I.cont_lower[c]]);
+                int k0 = 0;
+                while (k0 < nfc && a->cnu[k0] < nue * (1.0 - 1e-12)) ++k0;
+                REQUIRE(k0 < nfc && std::fabs(a->cnu[k0] / nue - 1.0) < 1e-9,
+                        "the continuum frequency grid must contain every edge");
+                for (int k = k0; k < nfc; ++k) {
+                    const double r = nue / a->cnu[k];
+                    a->calpha[size_t(c) * nfc + k] = I.cont_alpha0[c] * r * r * r;
+                    double w = 0.0;
+                    if (k > k0) w += 0.5 * (a->cnu[k] - a->cnu[k - 1]);
+                    if (k + 1 < nfc) w += 0.5 * (a->cnu[k + 1] - a->cnu[k]);
+                    a->cfw[size_t(c) * nfc + k] = 4.0 * kPI * w / (kH * a->cnu[k]);
+                }
+            }
+            I.cont_active = 1;
         }
         for (int c = 0; c < I.ncoll; ++c) {
             const nlte_coll_desc& s = d->collisions[c];

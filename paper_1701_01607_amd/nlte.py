@@ -71,7 +71,8 @@ class AtomDesc(ct.Structure):
     _fields_ = [("nlevel", ct.c_int), ("nline", ct.c_int), ("ncont", ct.c_int), ("ncoll", ct.c_int),
                 ("mass_amu", ct.c_double), ("xi", ct.c_double), ("epsilon", ct.c_double),
                 ("levels", ct.POINTER(LevelDesc)), ("lines", ct.POINTER(LineDesc)),
-                ("continua", ct.POINTER(ContDesc)), ("collisions", ct.POINTER(CollDesc))]
+                ("continua", ct.POINTER(ContDesc)), ("collisions", ct.POINTER(CollDesc)),
+                ("ncont_nu", ct.c_int), ("cont_nu", ct.POINTER(ct.c_double))]
 
 
 class AtmosDesc(ct.Structure):
@@ -260,8 +261,12 @@ class Context:
                                                              for c in atom["continua"]])
         colls = (CollDesc * max(1, len(atom["collisions"])))(*[
             CollDesc(c["lower"], c["upper"], c["c_ul"], c["T_ref"], c["beta"]) for c in atom["collisions"]])
+        cnu = atom.get("continuum_nu")
+        cnu = None if cnu is None else _f64(cnu)
         d = AtomDesc(len(atom["levels"]), len(atom["lines"]), len(atom["continua"]), len(atom["collisions"]),
-                     atom["mass_amu"], atom["xi"], atom["epsilon"] or 0.0, levels, lines, conts, colls)
+                     atom["mass_amu"], atom["xi"], atom["epsilon"] or 0.0, levels, lines, conts, colls,
+                     0 if cnu is None else cnu.size,
+                     None if cnu is None else cnu.ctypes.data_as(ct.POINTER(ct.c_double)))
         h = ct.c_void_p()
         self.check(self.lib.nlte_atom_create(self.h, ct.byref(d), ct.byref(h)))
         return Handle(self, h, self.lib.nlte_atom_destroy)
