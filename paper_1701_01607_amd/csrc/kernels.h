@@ -1078,17 +1078,22 @@ struct ContArgs {
 };
 
 // One plane step of the formal solution at the continuum frequencies, for three
-// directions per block (one wave each, 64 plane points) and every continuum frequency
-// in order.  Opacity and emissivity at a point sum over the continua open at the
-// frequency; the three sums per continuum (U: alpha Jeff, G: alpha g Jeff, L: the
-// preconditioned local part (chi_t/chi) Psi_o E, each times 4 pi w / h nu and the
-// direction weight 1/24) are added over the block's three directions as (d0 + d1) + d2
-// and stored per direction group; the rate kernel finishes the fixed tree.
+// directions per block over 64 plane points, the frequencies split into FC contiguous
+// chunks (block = 3 x FC waves, FC = blockDim / 192).  Opacity and emissivity at a point
+// sum over the continua open at the frequency; the three sums per continuum (U: alpha
+// Jeff, G: alpha g Jeff, L: the preconditioned local part (chi_t/chi) Psi_o E, each times
+// 4 pi w / h nu and the direction weight 1/24) are added over the chunks in order, then
+// over the block's three directions as (d0 + d1) + d2, and stored per direction group;
+// the rate kernel finishes the fixed tree.
+constexpr int kContMaxChunks = 4;
+
 template <typename R>
-__global__ __launch_bounds__(3 * 64) void sweep_cont_kernel(ContArgs<R> a, int s) {
+__global__ __launch_bounds__(3 * kContMaxChunks * 64) void sweep_cont_kernel(ContArgs<R> a, int s) {
     constexpr int kW = 64;
     const int lane = int(threadIdx.x) & (kW - 1);
-    const int w = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kW);
+    const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kW);
+    const int FC = int(blockDim.x) / (3 * kW);
+    const int w = wv % 3, cch = wv / 3;
     const int grp = int(blockIdx.z);
     const int d = grp * 3 + w;
     const int h = (grp * 3) / kNHemi;
@@ -1139,8 +1144,10 @@ __global__ __launch_bounds__(3 * 64) void sweep_cont_kernel(ContArgs<R> a, int s
         rds = R(ds);
         prv = a.state + size_t((s - 1) & 1) * slot_stride + size_t(d) * dstride;
     }
-    for (int m = 0; m < nfc; ++m) {
-        const R x = exp(-hk * a.cnu[m]);
+    const int clen = (nfc + FC - 1) / FC;
+    const int mb = min(nfc, cch * clen), me = min(nfc, mb + clen);
+    for (int m = mb; m < me; ++m) {
+        const R x = dev_exp_neg(hk * a.cnu[m]);
         const R e = a.ce[m];
         R chis[kMaxCont], gg[kMaxCont];
         R chi = R(0), E = R(0);
@@ -1153,7 +1160,8 @@ __global__ __launch_bounds__(3 * 64) void sweep_cont_kernel(ContArgs<R> a, int s
             E = fma(al, gg[t], E);
         }
         E *= e;
-        const R S = chi > R(0) ? nc * E / chi : R(0);
+        const R rchi = chi > R(0) ? dev_rcp(chi) : R(0);
+        const R S = nc * E * rchi;
         R Jd, Io, po = R(0);
         if (s == 0) {
             Io = (h == 0) ? e * x / (R(1) - x) : R(0);
@@ -1171,7 +1179,6 @@ __global__ __launch_bounds__(3 * 64) void sweep_cont_kernel(ContArgs<R> a, int s
             Io = fma(po, S, Jd);
         }
         if (valid) cur[size_t(m) * nxy + g] = CCell<R>{Io, S, chi};
-        const R rchi = chi > R(0) ? R(1) / chi : R(0);
 #pragma unroll
         for (int t = 0; t < kMaxCont; ++t) {
             if (t < nct) {
@@ -1183,23 +1190,26 @@ __global__ __launch_bounds__(3 * 64) void sweep_cont_kernel(ContArgs<R> a, int s
             }
         }
     }
-    // (d0 + d1) + d2 over the block's three directions, per quantity and continuum
-    __shared__ R red[3 * 3 * kMaxCont][3 * kW];
+    // per quantity and continuum: chunks in order, then (d0 + d1) + d2
+    __shared__ R red[3 * kContMaxChunks * kW];
 #pragma unroll
-    for (int t = 0; t < kMaxCont; ++t) {
-        red[t][threadIdx.x] = aU[t];
-        red[kMaxCont + t][threadIdx.x] = aG[t];
-        red[2 * kMaxCont + t][threadIdx.x] = aL[t];
-    }
-    __syncthreads();
-    if (w == 0 && valid) {
-        for (int q = 0; q < 3; ++q)
-            for (int t = 0; t < nct; ++t) {
-                const R* r = red[q * kMaxCont + t];
-                const R sum = (r[lane] + r[kW + lane]) + r[2 * kW + lane];
-                a.acc[(size_t(q * nct + t) * kMaxSlots + grp) * nv + v] = sum;
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int t = 0; t < kMaxCont; ++t) {
+            if (t >= nct) continue;
+            red[threadIdx.x] = q == 0 ? aU[t] : (q == 1 ? aG[t] : aL[t]);
+            __syncthreads();
+            if (wv == 0 && valid) {
+                R dsum[3];
+                for (int dd = 0; dd < 3; ++dd) {
+                    R c = red[dd * kW + lane];
+                    for (int ch = 1; ch < FC; ++ch) c += red[(ch * 3 + dd) * kW + lane];
+                    dsum[dd] = c;
+                }
+                a.acc[(size_t(q * nct + t) * kMaxSlots + grp) * nv + v] = (dsum[0] + dsum[1]) + dsum[2];
             }
-    }
+            __syncthreads();
+        }
 }
 
 // ------------------------------------------------------------------ rate equations

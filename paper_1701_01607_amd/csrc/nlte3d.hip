@@ -824,8 +824,11 @@ struct Job : JobBase {
         c.state = cstate.as<CCell<R>>();
         c.acc = L.cacc.as<R>();
         const dim3 grid(blocks_for(L.nxy, 64), 1, kNDir / 3);
+        // frequency chunks: as for the line sweep, until a launch holds two rounds of waves
+        int fc = 1;
+        while (fc < kContMaxChunks && sweep_waves(L.nxy, 1) * fc < kSweepWaveTarget) fc *= 2;
         ev_begin(EV_SWEEP);
-        for (int s = 0; s < L.nz; ++s) sweep_cont_kernel<R><<<grid, 3 * 64, 0, st()>>>(c, s);
+        for (int s = 0; s < L.nz; ++s) sweep_cont_kernel<R><<<grid, unsigned(3 * fc * 64), 0, st()>>>(c, s);
         HIPCHK(hipGetLastError());
         ev_end();
     }
