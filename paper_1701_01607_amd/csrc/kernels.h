@@ -581,16 +581,17 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !HERM ? kSweepWavesPerSimdF
                 sc_point(pc, R(qf[m]), R(wf[m]), gauss, Iu, Su, Cu, rds, cell, jacc, lacc);
                 if (valid) cell_put(rcur, oc, so, make_cell(cell));
             }
-        } else
-        for (int m = mb; m < me; ++m) {
-            const unsigned so = unsigned(m - a.m0) * rowb;
-            const Cell<R> c00 = cell_get<R>(rprv, o00, so), c01 = cell_get<R>(rprv, o01, so);
-            const Cell<R> c10 = cell_get<R>(rprv, o10, so), c11 = cell_get<R>(rprv, o11, so);
-            R Iu, Su, Cu;
-            upwind_values(qc, w00, w01, w10, w11, c00, c01, c10, c11, Iu, Su, Cu);
-            CellVals<R> cell;
-            sc_point(pc, R(qf[m]), R(wf[m]), gauss, Iu, Su, Cu, rds, cell, jacc, lacc);
-            if (valid) cell_put(rcur, oc, so, make_cell(cell));
+        } else {
+            for (int m = mb; m < me; ++m) {
+                const unsigned so = unsigned(m - a.m0) * rowb;
+                const Cell<R> c00 = cell_get<R>(rprv, o00, so), c01 = cell_get<R>(rprv, o01, so);
+                const Cell<R> c10 = cell_get<R>(rprv, o10, so), c11 = cell_get<R>(rprv, o11, so);
+                R Iu, Su, Cu;
+                upwind_values(qc, w00, w01, w10, w11, c00, c01, c10, c11, Iu, Su, Cu);
+                CellVals<R> cell;
+                sc_point(pc, R(qf[m]), R(wf[m]), gauss, Iu, Su, Cu, rds, cell, jacc, lacc);
+                if (valid) cell_put(rcur, oc, so, make_cell(cell));
+            }
         }
     }
     __shared__ R sj[kMaxSweepWaves * kW];
