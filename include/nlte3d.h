@@ -200,7 +200,10 @@ typedef struct {
 /* ---------------------------------------------------------------- lifecycle */
 /* Create a context on HIP device `device` that enqueues on `hip_stream` (a hipStream_t,
  * NULL = the device's null stream).  `hbm_budget` bounds the bytes the context may
- * allocate (0 = 90 % of free device memory). */
+ * allocate (0 = 90 % of free device memory).  If the environment variable
+ * NLTE3D_TUNE_CACHE names a file, the sweep autotuner's choices for this device's
+ * architecture are read from it (a flat JSON object; unreadable or malformed files count
+ * as empty) and every new choice is merged into it. */
 nlte_status nlte_ctx_create(int device, void* hip_stream, size_t hbm_budget, nlte_ctx** out);
 void nlte_ctx_destroy(nlte_ctx* ctx);
 /* Message of the last failing call on ctx (empty string if none); owned by ctx. */

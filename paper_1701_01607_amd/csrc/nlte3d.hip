@@ -28,6 +28,8 @@
 #include "kernels.h"
 
 #include <cstdarg>
+#include <fstream>
+#include <sstream>
 
 using namespace nlte;
 
@@ -58,6 +60,8 @@ inline unsigned blocks_for(size_t n, unsigned bs) { return unsigned((n + bs - 1)
 struct nlte_ctx {
     std::map<std::string, int> tile_cache;   // autotuned sweep tile per level shape
     std::mutex tune_mu;
+    std::string tune_path;   // NLTE3D_TUNE_CACHE: autotune results kept on disk across processes
+    std::string arch;        // device architecture, part of the on-disk keys
     int device = 0;
     hipStream_t stream = nullptr;
     size_t budget = 0;
@@ -76,6 +80,50 @@ struct nlte_ctx {
     bool stopping = false;
     size_t lds_max = 65536;                  // dynamic LDS a workgroup may use
 };
+
+// Autotune cache file: one flat JSON object {"<arch>|<level key>": <directions per block>, ...}.
+// Unreadable or malformed files count as empty; entries with other values are skipped.
+static std::map<std::string, int> read_tune_file(const std::string& path) {
+    std::map<std::string, int> m;
+    std::ifstream f(path);
+    if (!f) return m;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string t = ss.str();
+    size_t i = t.find('{');
+    if (i == std::string::npos) return m;
+    for (;;) {
+        const size_t q0 = t.find('"', i + 1);
+        if (q0 == std::string::npos) break;
+        const size_t q1 = t.find('"', q0 + 1);
+        const size_t colon = q1 == std::string::npos ? q1 : t.find(':', q1 + 1);
+        if (colon == std::string::npos) return {};
+        char* end = nullptr;
+        const long v = std::strtol(t.c_str() + colon + 1, &end, 10);
+        if (end == t.c_str() + colon + 1) return {};
+        if (v == 3 || v == 6 || v == 12) m[t.substr(q0 + 1, q1 - q0 - 1)] = int(v);
+        i = size_t(end - t.c_str());
+    }
+    return m;
+}
+
+static void write_tune_file(const std::string& path, const std::map<std::string, int>& m) {
+    const std::string tmp = path + ".tmp" + std::to_string(reinterpret_cast<uintptr_t>(&m));
+    {
+        std::ofstream f(tmp);
+        if (!f) return;
+        f << "{";
+        bool first = true;
+        for (const auto& kv : m) {
+            f << (first ? "\n  \"" : ",\n  \"") << kv.first << "\": " << kv.second;
+            first = false;
+        }
+        f << "\n}\n";
+        if (!f) return;
+    }
+    std::rename(tmp.c_str(), path.c_str());
+}
+
 
 namespace {
 
@@ -683,6 +731,11 @@ struct Job : JobBase {
         auto it = ctx->tile_cache.find(key);
         if (it != ctx->tile_cache.end()) return it->second;   // another job tuned it first
         ctx->tile_cache[key] = best;
+        if (!ctx->tune_path.empty()) {   // merge into the file (other devices' entries kept)
+            auto m = read_tune_file(ctx->tune_path);
+            m[ctx->arch + "|" + key] = best;
+            write_tune_file(ctx->tune_path, m);
+        }
         return best;
     }
 
@@ -1446,6 +1499,15 @@ nlte_status nlte_ctx_create(int device, void* hip_stream, size_t hbm_budget, nlt
         size_t fr = 0, tot = 0;
         HIPCHK(hipMemGetInfo(&fr, &tot));
         c->budget = hbm_budget ? hbm_budget : size_t(0.9 * double(fr));
+        hipDeviceProp_t prop;
+        HIPCHK(hipGetDeviceProperties(&prop, device));
+        c->arch = prop.gcnArchName;
+        if (const char* tp = std::getenv("NLTE3D_TUNE_CACHE")) {
+            c->tune_path = tp;
+            const std::string pre = c->arch + "|";
+            for (const auto& kv : read_tune_file(c->tune_path))
+                if (kv.first.compare(0, pre.size(), pre) == 0) c->tile_cache[kv.first.substr(pre.size())] = kv.second;
+        }
         // dynamic LDS for the plane-resident sweep: what the device grants a workgroup
         int lds = 0;
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
