@@ -183,6 +183,9 @@ def main():
     ap.add_argument("--mali-max-iter", type=int, default=800)
     ap.add_argument("--dirs-per-block", type=int, default=0, help="sweep block shape (0: autotune)")
     ap.add_argument("--graph", type=int, default=0, help="1: replay V-cycles from a captured HIP graph")
+    ap.add_argument("--active-continua", action="store_true",
+                    help="sweep the atom's continua as active transitions (41 continuum frequencies); the "
+                         "line-sweep roofline is then not reported")
     ap.add_argument("--kernel-probe", action="store_true",
                     help="only one MALI iteration (one formal solution + rate solve) and a 512 MiB "
                          "device copy, for hardware-counter runs")
@@ -199,6 +202,8 @@ def main():
     wl = WORKLOADS[args.workload]
     log(f"generating {args.workload} ...")
     atom, atm = synth.workload(args.workload)
+    if args.active_continua:
+        atom = synth.with_active_continua(atom)
     sample = None
     if not args.no_cpu_baseline and not args.kernel_probe:
         log("cpu baseline (oracle sample, before the GPU is initialised) ...")
@@ -297,7 +302,8 @@ def main():
         "config": {"workload": args.workload, "grid": [atm["nx"], atm["ny"], atm["nz"]], "lines": len(atom["lines"]),
                    "frequencies": nf, "directions": 24, "method": wl["method"], "levels": wl["nlev"],
                    "nu": [wl["nu_fmg"], wl["nu0"], wl["nu1"], wl["nu2"], wl["nu3"]],
-                   "E_target": wl["E_target"] or None, "tol_C": wl["tol_C"] or None},
+                   "E_target": wl["E_target"] or None, "tol_C": wl["tol_C"] or None,
+                   "continua": "active" if args.active_continua else "fixed"},
         "converged": converged,
         "updates_per_s": ups_sweep,
         "updates_per_s_wall": upd / elapsed,
@@ -316,6 +322,10 @@ def main():
                              "frac": achieved / PEAK_HBM_GBS if achieved else None,
                              "bytes_per_update": bytes_upd}},
     }
+    if args.active_continua:
+        # the sweep phase then also holds the continuum sweep, which the line-sweep
+        # models above do not describe
+        out["roofline"] = None
 
     # this box's achievable HBM bandwidth for context: a 2 GiB device-to-device copy
     src = torch.empty(2 ** 29, dtype=torch.float32, device="cuda").fill_(1.0)
