@@ -1053,11 +1053,30 @@ __global__ void cont_setup_kernel(const AtomInfo* atom, const double* prim, cons
     }
 }
 
-// Plane state of the continuum sweep: intensity, source function and opacity.
+// Plane state of the continuum sweep: intensity, source function and opacity, moved by
+// raw buffer instructions like the line sweep's cells (lane offset fixed, frequency row in
+// the scalar offset).
 template <typename R>
 struct CCell {
     R I, S, C;
 };
+typedef float f32x3c __attribute__((ext_vector_type(3)));
+__device__ inline CCell<float> ccell_get(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, float) {
+    const f32x3c x = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
+    return CCell<float>{x.x, x.y, x.z};
+}
+__device__ inline CCell<double> ccell_get(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, double) {
+    const Cell<double> c = cell_load_d(r, voff, soff);
+    return CCell<double>{c.I, c.S, c.C};
+}
+__device__ inline void ccell_put(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, const CCell<float>& c) {
+    __builtin_amdgcn_raw_buffer_store_b96(f32x3c{c.I, c.S, c.C}, r, voff, soff, 0);
+}
+__device__ inline void ccell_put(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff, const CCell<double>& c) {
+    cell_put(r, voff, soff, Cell<double>{c.I, c.S, c.C});
+}
+
+constexpr int kContRow = 2 + 2 * kMaxCont + 2;   // one frequency's table row (20 values)
 
 template <typename R>
 struct ContArgs {
@@ -1070,10 +1089,7 @@ struct ContArgs {
     const double* n;      // [N][nvox] populations
     const R* cr;          // [ncont][nvox] n_l*/n_c*
     const R* hkT;         // [nvox] h/kT
-    const R* cnu;         // [nfc] frequencies (Hz)
-    const R* ce;          // [nfc] 2 h nu^3 / c^2
-    const R* cfw;         // [ncont][nfc] 4 pi w_tk / (h nu_k)
-    const R* calpha;      // [ncont][nfc] cross-sections (0 below the edge)
+    const R* ctab;        // [nfc][kContRow]: nu, 2 h nu^3/c^2, alpha_t (8), 4 pi w_t/(h nu) (8), pad
     CCell<R>* state;      // [2][24][nfc][nxy]
     R* acc;               // [3 ncont][8 slots][nvox]: U, G, L per continuum
 };
@@ -1110,7 +1126,9 @@ __global__ __launch_bounds__(3 * kContMaxChunks * 64) void sweep_cont_kernel(Con
     const int nfc = a.nfc;
     const size_t dstride = size_t(nfc) * nxy;
     const size_t slot_stride = size_t(kNDir) * dstride;
-    CCell<R>* cur = a.state + size_t(s & 1) * slot_stride + size_t(d) * dstride;
+    constexpr unsigned csz = sizeof(CCell<R>);
+    const unsigned rowb = nxy * csz;                  // bytes per frequency row
+    const auto rcur = cell_rsrc(a.state + size_t(s & 1) * slot_stride + size_t(d) * dstride, unsigned(nfc) * rowb);
     const R nc = R(fmax(a.n[size_t(at.cont_upper[0]) * nv + v], 0.0));
     R nl[kMaxCont], ratio[kMaxCont];
 #pragma unroll
@@ -1124,9 +1142,9 @@ __global__ __launch_bounds__(3 * kContMaxChunks * 64) void sweep_cont_kernel(Con
 #pragma unroll
     for (int t = 0; t < kMaxCont; ++t) aU[t] = aG[t] = aL[t] = R(0);
     // upwind geometry (planes after the boundary)
-    int o00 = 0, o01 = 0, o10 = 0, o11 = 0;
+    unsigned o00 = 0, o01 = 0, o10 = 0, o11 = 0;
     R w00 = R(0), w01 = R(0), w10 = R(0), w11 = R(0), rds = R(0);
-    const CCell<R>* prv = nullptr;
+    auto rprv = rcur;
     if (s > 0) {
         const double mux = c_mu[3 * d], muy = c_mu[3 * d + 1], muz = c_mu[3 * d + 2];
         const int kp = (h == 0) ? s - 1 : a.nz - s;
@@ -1139,22 +1157,25 @@ __global__ __launch_bounds__(3 * kContMaxChunks * 64) void sweep_cont_kernel(Con
         int y0 = int((long long)(y + (long long)fsy) % a.ny); if (y0 < 0) y0 += a.ny;
         const int x1 = (x0 + 1 == a.nx) ? 0 : x0 + 1;
         const int y1 = (y0 + 1 == a.ny) ? 0 : y0 + 1;
-        o00 = y0 * a.nx + x0; o01 = y0 * a.nx + x1; o10 = y1 * a.nx + x0; o11 = y1 * a.nx + x1;
+        o00 = unsigned(y0 * a.nx + x0) * csz; o01 = unsigned(y0 * a.nx + x1) * csz;
+        o10 = unsigned(y1 * a.nx + x0) * csz; o11 = unsigned(y1 * a.nx + x1) * csz;
         w00 = (R(1) - fx) * (R(1) - fy); w01 = fx * (R(1) - fy);
         w10 = (R(1) - fx) * fy; w11 = fx * fy;
         rds = R(ds);
-        prv = a.state + size_t((s - 1) & 1) * slot_stride + size_t(d) * dstride;
+        rprv = cell_rsrc(a.state + size_t((s - 1) & 1) * slot_stride + size_t(d) * dstride, unsigned(nfc) * rowb);
     }
     const int clen = (nfc + FC - 1) / FC;
     const int mb = min(nfc, cch * clen), me = min(nfc, mb + clen);
     for (int m = mb; m < me; ++m) {
-        const R x = dev_exp_neg(hk * a.cnu[m]);
-        const R e = a.ce[m];
+        // the frequency's table row, wave-uniform: scalar loads
+        const const_as<R>* row = (const const_as<R>*)(a.ctab + size_t(m) * kContRow);
+        const R x = dev_exp_neg(hk * row[0]);
+        const R e = row[1];
         R chis[kMaxCont], gg[kMaxCont];
         R chi = R(0), E = R(0);
 #pragma unroll
         for (int t = 0; t < kMaxCont; ++t) {
-            const R al = t < nct ? a.calpha[size_t(t) * nfc + m] : R(0);
+            const R al = row[2 + t];   // 0 for absent continua and below the edge
             gg[t] = ratio[t] * x;
             chis[t] = al * fmax(nl[t] - nc * gg[t], R(0));
             chi += chis[t];
@@ -1168,8 +1189,9 @@ __global__ __launch_bounds__(3 * kContMaxChunks * 64) void sweep_cont_kernel(Con
             Io = (h == 0) ? e * x / (R(1) - x) : R(0);
             Jd = Io;
         } else {
-            const size_t fo = size_t(m) * nxy;
-            const CCell<R> c00 = prv[fo + o00], c01 = prv[fo + o01], c10 = prv[fo + o10], c11 = prv[fo + o11];
+            const unsigned so = unsigned(m) * rowb;
+            const CCell<R> c00 = ccell_get(rprv, o00, so, R(0)), c01 = ccell_get(rprv, o01, so, R(0));
+            const CCell<R> c10 = ccell_get(rprv, o10, so, R(0)), c11 = ccell_get(rprv, o11, so, R(0));
             const R Iu = interp4(w00, w01, w10, w11, c00.I, c01.I, c10.I, c11.I);
             const R Su = interp4(w00, w01, w10, w11, c00.S, c01.S, c10.S, c11.S);
             const R Cu = interp4(w00, w01, w10, w11, c00.C, c01.C, c10.C, c11.C);
@@ -1179,12 +1201,12 @@ __global__ __launch_bounds__(3 * kContMaxChunks * 64) void sweep_cont_kernel(Con
             Jd = fma(Iu, ex, pu * Su);
             Io = fma(po, S, Jd);
         }
-        if (valid) cur[size_t(m) * nxy + g] = CCell<R>{Io, S, chi};
+        if (valid) ccell_put(rcur, g * csz, unsigned(m) * rowb, CCell<R>{Io, S, chi});
 #pragma unroll
         for (int t = 0; t < kMaxCont; ++t) {
             if (t < nct) {
-                const R fw = a.cfw[size_t(t) * nfc + m];
-                const R wa = wd * fw * a.calpha[size_t(t) * nfc + m];
+                const R fw = row[2 + kMaxCont + t];
+                const R wa = wd * fw * row[2 + t];
                 aU[t] = fma(wa, Jd, aU[t]);
                 aG[t] = fma(wa * gg[t], Jd, aG[t]);
                 aL[t] = fma(wd * fw, chis[t] * rchi * po * E, aL[t]);

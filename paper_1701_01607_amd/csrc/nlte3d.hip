@@ -369,7 +369,7 @@ struct Job : JobBase {
     std::vector<std::unique_ptr<Level>> lev;
     DevBuf atom_d, qf, wf, line_of_d, state, topI, scalar, repairs, estate, eout, flag, nprev;
     // active continua: frequency tables (R for the sweep, FP64 for the setup) and plane state
-    DevBuf cnu_r, ce_r, cfw_r, calpha_r, cnu_d, ce_d, cfw_d, calpha_d, cstate;
+    DevBuf ctab_r, cnu_d, ce_d, cfw_d, calpha_d, cstate;
     int nfc = 0;
     AtomInfo info{};
     int DB = 0;   // directions per sweep block (0: autotuned per level)
@@ -472,18 +472,28 @@ struct Job : JobBase {
         HIPCHK(hipMemcpyAsync(wf.p, wh.data(), sizeof(R) * nf, hipMemcpyHostToDevice, st()));
         if (info.cont_active) {
             nfc = int(atom->cnu.size());
-            auto up = [&](DevBuf& bd, DevBuf& br, const std::vector<double>& h) {
+            auto up = [&](DevBuf& bd, const std::vector<double>& h) {
                 dalloc(bd, sizeof(double) * h.size());
                 HIPCHK(hipMemcpyAsync(bd.p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, st()));
-                std::vector<R> hr(h.begin(), h.end());
-                dalloc(br, sizeof(R) * h.size());
-                HIPCHK(hipMemcpyAsync(br.p, hr.data(), sizeof(R) * h.size(), hipMemcpyHostToDevice, st()));
-                HIPCHK(hipStreamSynchronize(st()));   // hr is a host temporary
             };
-            up(cnu_d, cnu_r, atom->cnu);
-            up(ce_d, ce_r, atom->ce);
-            up(cfw_d, cfw_r, atom->cfw);
-            up(calpha_d, calpha_r, atom->calpha);
+            up(cnu_d, atom->cnu);
+            up(ce_d, atom->ce);
+            up(cfw_d, atom->cfw);
+            up(calpha_d, atom->calpha);
+            // the sweep's per-frequency rows in precision R
+            std::vector<R> tab(size_t(nfc) * kContRow, R(0));
+            for (int k = 0; k < nfc; ++k) {
+                R* row = tab.data() + size_t(k) * kContRow;
+                row[0] = R(atom->cnu[k]);
+                row[1] = R(atom->ce[k]);
+                for (int t = 0; t < info.ncont; ++t) {
+                    row[2 + t] = R(atom->calpha[size_t(t) * nfc + k]);
+                    row[2 + kMaxCont + t] = R(atom->cfw[size_t(t) * nfc + k]);
+                }
+            }
+            dalloc(ctab_r, sizeof(R) * tab.size());
+            HIPCHK(hipMemcpyAsync(ctab_r.p, tab.data(), sizeof(R) * tab.size(), hipMemcpyHostToDevice, st()));
+            HIPCHK(hipStreamSynchronize(st()));   // tab is a host temporary
         }
         HIPCHK(hipMemcpyAsync(line_of_d.p, atom->line_of.data(), sizeof(int) * nf, hipMemcpyHostToDevice, st()));
         dalloc(scalar, sizeof(double) * 4);
@@ -577,6 +587,9 @@ struct Job : JobBase {
         }
         if (info.cont_active) {
             const Level& Fc = *lev[nlev - 1];
+            // a direction's column of continuum cells is addressed by 32-bit buffer offsets
+            REQUIRE(double(sizeof(CCell<R>)) * double(nfc) * double(Fc.nxy) <= 4294967295.0,
+                    "continuum frequency grid too large for this plane size");
             dalloc(cstate, sizeof(CCell<R>) * 2 * kNDir * size_t(nfc) * Fc.nxy);
         }
         const Level& Fz = *lev[nlev - 1];
@@ -873,7 +886,7 @@ struct Job : JobBase {
         c.z = L.dz.as<double>();
         c.n = L.n.as<double>();
         c.cr = L.cr.as<R>(); c.hkT = L.chkT.as<R>();
-        c.cnu = cnu_r.as<R>(); c.ce = ce_r.as<R>(); c.cfw = cfw_r.as<R>(); c.calpha = calpha_r.as<R>();
+        c.ctab = ctab_r.as<R>();
         c.state = cstate.as<CCell<R>>();
         c.acc = L.cacc.as<R>();
         const dim3 grid(blocks_for(L.nxy, 64), 1, kNDir / 3);
@@ -1367,7 +1380,8 @@ size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom
     if (!fine_resident) bytes += cell * nstate * kNDir * size_t(nline) * Q * fine_nxy;
     bytes += 8 * size_t(N) * fine_nvox;
     if (atom->info.cont_active)       // continuum plane state and frequency tables
-        bytes += 3 * R * 2 * kNDir * atom->cnu.size() * fine_nxy + (8 + R) * 4 * atom->calpha.size();
+        bytes += 3 * R * 2 * kNDir * atom->cnu.size() * fine_nxy +
+                 8 * (2 + 2 * size_t(atom->info.ncont)) * atom->cnu.size() + R * kContRow * atom->cnu.size();
     if (p->top_I) bytes += R * size_t(nf) * fine_nxy;
     bytes += 8 * 6 * size_t(nf) * fine_nxy;             // emergent-intensity state
     bytes += 4 * size_t(nf) * fine_nxy;                  // one direction of host-bound output
