@@ -43,10 +43,11 @@ VOXEL_BYTES_PER_GROUP = (11 + 2) * 4.0   # FP32; twice that in FP64
 # interpolations 21, optical depth 3, segment coefficients 7, intensity 5, quadrature
 # weight 2, accumulations 10 (57); FP32 cells add the opacity and source function of
 # the four upwind corners rebuilt from phi (4 x 6); plus the profile: the Weideman N=32
-# series (|u| < 5, evaluated in FP64) 154, the FP32 asymptotic wing with its Gaussian
-# term 64, a pure Gaussian 3.
+# series (evaluated in FP64) 154, the FP32 small-damping series (a < 0.04, |u| < 5) 35,
+# the FP32 asymptotic wing with its Gaussian term 64, a pure Gaussian 3.
 FLOPS_PER_UPDATE_BASE = {False: 57 + 24, True: 57}
-FLOPS_VOIGT_CORE, FLOPS_VOIGT_WING, FLOPS_GAUSS = 154, 64, 3
+FLOPS_VOIGT_CORE, FLOPS_VOIGT_SMALL, FLOPS_VOIGT_WING, FLOPS_GAUSS = 154, 35, 64, 3
+VOIGT_SMALL_A = 0.04
 
 WORKLOADS = {
     "caii6_64x64x129": dict(nlev=3, nu0=20, nu1=4, nu2=8, nu3=32, nu_fmg=16, method="FAS", fp64=False,
@@ -66,14 +67,16 @@ def log(*a):
 
 
 def flops_per_update(atom, atm, fp64, stride=61):
-    """Mean flops per update on the finest grid: the profile costs the Weideman series
-    where |u| < 5 (everywhere in FP64 sweeps) and the asymptotic wing elsewhere, so the
-    fraction of series evaluations is counted on a sample of voxels over all directions
-    and frequencies."""
+    """Mean flops per update on the finest grid: in FP32 sweeps the profile costs the
+    small-damping series where |u| < 5 and the damping a < 0.04, the Weideman series where
+    |u| < 5 otherwise (everywhere in FP64 sweeps) and the asymptotic wing elsewhere, so the
+    fractions are counted on a sample of voxels over all directions and frequencies.
+    Returns (flops per update, fraction of Weideman series evaluations)."""
     import numpy as np
-    kb, amu = 1.380649e-16, 1.66053906660e-24
+    kb, amu, c_light = 1.380649e-16, 1.66053906660e-24, 2.99792458e10
     sl = slice(None, None, stride)
     T = np.asarray(atm["T"], dtype=np.float64).ravel()[sl]
+    nH = np.asarray(atm["nH"], dtype=np.float64).ravel()[sl]
     vD = np.sqrt(2.0 * kb * T / (atom["mass_amu"] * amu) + atom["xi"] ** 2)
     v = np.stack([np.asarray(atm[c], dtype=np.float64).ravel()[sl] for c in ("vx", "vy", "vz")])
     m1, m2 = 1.0 / 3.0, np.sqrt(7.0) / 3.0
@@ -92,9 +95,19 @@ def flops_per_update(atom, atm, fp64, stride=61):
             flops += n * (base + FLOPS_GAUSS)
             continue
         u = (q[:, None, None] - vn[None]) / vD[None, None]
-        c = float(n) if fp64 else float(np.count_nonzero(np.abs(u) < 5.0))
+        if fp64:
+            core += n
+            flops += n * (base + FLOPS_VOIGT_CORE)
+            continue
+        lv = atom["levels"]
+        nu0 = c_light * (lv[ln["upper"]]["E"] - lv[ln["lower"]]["E"])
+        gam = ln["gamma_rad"] + ln["gamma_vdw"] * nH * (T / 5000.0) ** 0.3
+        small = (gam / (4.0 * np.pi * nu0 * vD / c_light) < VOIGT_SMALL_A)[None, None]
+        inside = np.abs(u) < 5.0
+        cs = float(np.count_nonzero(inside & small))
+        c = float(np.count_nonzero(inside)) - cs
         core += c
-        flops += n * base + c * FLOPS_VOIGT_CORE + (n - c) * FLOPS_VOIGT_WING
+        flops += n * base + cs * FLOPS_VOIGT_SMALL + c * FLOPS_VOIGT_CORE + (n - c - cs) * FLOPS_VOIGT_WING
     return flops / total, core / total
 
 

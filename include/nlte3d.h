@@ -272,6 +272,12 @@ nlte_status nlte_vcycle(nlte_ctx* ctx, nlte_job job, int level, int first);
 nlte_status nlte_restrict(nlte_ctx* ctx, nlte_job job, int level, int nq, const double* src, double* dst);
 /* Trilinear prolongation (Sect. 4.5) of q fields from grid `level-1` to `level`. */
 nlte_status nlte_prolong(nlte_ctx* ctx, nlte_job job, int level, int nq, const double* src, double* dst);
+/* The Voigt function H(a, u) = Re w(u + i a) that the sweeps use for the line profile
+ * (Sect. 3; phi = H / (sqrt(pi) dnu_D)), at n points of the device arrays a and u (FP64,
+ * a >= 0), written to the device array H.  precision NLTE_FP64: the FP64 evaluation;
+ * NLTE_MIXED: the FP32 evaluation (inputs rounded to FP32 first, the result widened).
+ * Synchronises the context's stream; n = 0 does nothing. */
+nlte_status nlte_voigt(nlte_ctx* ctx, int precision, int n, const double* a, const double* u, double* H);
 
 /* ---------------------------------------------------------------- serving
  * Continuous batching of many solves on one context.  nlte_submit queues a solve and

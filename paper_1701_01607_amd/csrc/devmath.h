@@ -6,8 +6,9 @@
 //   with p a polynomial of degree N-1 whose coefficients are cosine sums of
 //   exp(-t^2)(L^2 + t^2) at t = L tan(theta/2); L = sqrt(N / sqrt 2).  N = 32, in FP64
 //   (relative error <= 2e-8 for a >= 1e-4).  FP32 sweeps evaluate the same FP64 series for |u| < 5 and
-//   the asymptotic series of w(z) in FP32 beyond.  Lines without damping use exp(-u^2)
-//   directly.  Both series have real coefficients and are summed with Goertzel's
+//   the asymptotic series of w(z) in FP32 beyond; where the damping is small (a < 0.04)
+//   they use instead, inside |u| < 5, the Taylor series of w about the real axis (below).
+//   Lines without damping use exp(-u^2) directly.  Both series have real coefficients and are summed with Goertzel's
 //   second-order recurrence rather than complex Horner steps.
 // * Linear short-characteristics coefficients (Kunasz & Auer 1988):
 //     e = exp(-x), Psi_o = 1 - (1-e)/x, Psi_u = (1-e)/x - e,
@@ -31,6 +32,22 @@ constexpr double kSQRTPI = 1.77245385090551602730;
 constexpr double kINVSQRTPI = 0.56418958354775628695;
 
 constexpr int kVoigtNd = 32;
+
+// Small-damping FP32 Voigt function: H(a,u) = Re w(u + i a) = sum_n Re[(i a)^n w^(n)(u) / n!].
+// From w' = -2 z w + 2i/sqrt(pi), w^(n) = P_n w + Q_n i/sqrt(pi) with P_{n+1} = P_n' - 2z P_n,
+// Q_{n+1} = Q_n' + 2 P_n (P_0 = 1, Q_0 = 0), and on the real axis w(u) = exp(-u^2) +
+// (2i/sqrt(pi)) F(u) (Dawson's F).  With G = 1 - 2uF (= F') and t = u^2, the terms up to a^4
+// sum to
+//   H = exp(-t) [1 + a^2 + a^4/2 - 2(a^2 + a^4) t + (2/3) a^4 t^2]
+//       + pi^{-1/2} [(2/3) a^3 - (2a + 2a^3 - (4/3) a^3 t) G],
+// whose truncation error is below 2e-7 relative for a < 0.04 and |u| < 5.  G is evaluated
+// from a table of cubics on 80 intervals of width 1/16 in |u| (Hermite interpolation of G
+// and G' = -2F - 2uG, which the host takes from an accurate integration of F' = 1 - 2uF).
+constexpr int kDawIntervals = 80;
+constexpr float kDawInvStep = 16.0f;
+constexpr float kVoigtSmallA = 0.04f;
+// Per interval the cubic's coefficients (c0, c1, c2, c3) in the local coordinate s in [0, 1).
+__constant__ float4 c_dawg[kDawIntervals];
 
 // Weideman coefficients, highest power first; filled by the host at context creation.
 __constant__ double c_voigt_d[kVoigtNd];
@@ -137,21 +154,47 @@ __device__ inline float voigt_H_wing(float a, float u) {
     return fmaf(-ti, float(kINVSQRTPI), gauss);
 }
 
-// Profile shape: Gaussian for undamped lines, Voigt otherwise.
+// Small-damping series above, a < 0.04 and |u| < 5; `tab` holds c_dawg (in LDS or global
+// memory).  Relative error ~5e-7, mostly from rounding t = u^2 before the exponential.
+__device__ inline float voigt_H_small(float a, float u, const float4* tab) {
+    // the coefficients below are recomputed per call rather than held in registers across a
+    // caller's frequency loop (the empty asm makes `a` look loop-variant)
+    asm volatile("" : "+v"(a));
+    const float t = u * u;
+    const float x = fabsf(u) * kDawInvStep;
+    const int i = min(int(x), kDawIntervals - 1);
+    const float sx = x - float(i);
+    const float4 c = tab[i];
+    const float G = fmaf(fmaf(fmaf(c.w, sx, c.z), sx, c.y), sx, c.x);
+    const float a2 = a * a, a3 = a2 * a, a4 = a2 * a2;
+    const float ev = fmaf(fmaf(a4 * (2.0f / 3.0f), t, -2.0f * (a2 + a4)), t, 1.0f + a2 + 0.5f * a4);
+    // odd part A0 (1 + 2tG) + B0 G with A0 = 2a^3/(3 sqrt(pi)), B0 = -2(a + a^3)/sqrt(pi)
+    const float A0 = a3 * float(2.0 / 3.0 * kINVSQRTPI);
+    const float od = fmaf(G, -2.0f * float(kINVSQRTPI) * (a + a3), A0 * fmaf(t + t, G, 1.0f));
+    return fmaf(__expf(-t), ev, od);
+}
+
+// Profile shape: Gaussian for undamped lines, Voigt otherwise.  `tab` is the
+// small-damping table of the FP32 evaluation (unused in FP64).
 template <typename R>
-__device__ inline R profile_H(R a, R u, bool gauss) {
+__device__ inline R profile_H(R a, R u, bool gauss, const float4*) {
     if (gauss) return dev_exp_neg(u * u);
     return voigt_H<R>(a, u);
 }
 // FP32 sweeps: the Weideman series loses relative accuracy to cancellation in FP32
-// where H is small (|u| ~ 3-5, a << 1), so inside |u| < 5 it runs in FP64 with the FP64
-// coefficients (relative error ~2e-8 before the final rounding to FP32); the wings use
-// the FP32 asymptotic form.
+// where H is small (|u| ~ 3-5, a << 1), so inside |u| < 5 it uses the small-damping
+// series for a < 0.04 and otherwise runs in FP64 with the FP64 coefficients (relative
+// error ~2e-8 before the final rounding to FP32); the wings use the FP32 asymptotic form.
 template <>
-__device__ inline float profile_H<float>(float a, float u, bool gauss) {
+__device__ inline float profile_H<float>(float a, float u, bool gauss, const float4* tab) {
     if (gauss) return __expf(-u * u);
     if (fabsf(u) >= 5.0f) return voigt_H_wing(a, u);
-    return float(voigt_H<double>(double(a), double(u)));
+    if (a < kVoigtSmallA) return voigt_H_small(a, u, tab);
+    // The FP64 series' per-voxel set-up is redone here instead of being kept in registers
+    // across the frequency loop: the empty asm makes its input look loop-variant.
+    float al = a;
+    asm volatile("" : "+v"(al));
+    return float(voigt_H<double>(double(al), double(u)));
 }
 
 // Linear short-characteristics segment coefficients; omp = 1 - Psi_o is returned

@@ -157,13 +157,21 @@ __global__ void profile_norm_kernel(const AtomInfo* atom, const R* qf, const R* 
             for (int m = 0; m < ln.nfreq; ++m) {
                 const int f = ln.fstart + m;
                 const R u = qf[f] * ivD - vn;
-                const R H = profile_H<R>(a, u, ln.gauss != 0);
+                const R H = profile_H<R>(a, u, ln.gauss != 0, c_dawg);
                 accd += double(wf[f]) * double(H * pn);
             }
             acc += accd / kNDir;
         }
         sc[(SC_PW * L + l) * nvox + v] = R(double(pn) / acc);
     }
+}
+
+// The line profile shape H(a, u) of the sweeps (damped lines) at n points, evaluated in
+// precision R from FP64 inputs (rounded to R first).
+template <typename R>
+__global__ void voigt_eval_kernel(const double* a, const double* u, double* H, int n) {
+    const int i = int(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) H[i] = double(profile_H<R>(R(a[i]), R(u[i]), false, c_dawg));
 }
 
 // ------------------------------------------------------------------ line coefficients
@@ -410,10 +418,10 @@ __device__ inline void cell_values(const Cell<double>& c, const CornerConst<doub
 }
 
 template <typename R>
-__device__ inline void sc_point(const PointConst<R>& c, R q, R w, bool gauss, R Iu, R Su, R Cu, R rds,
-                                CellVals<R>& cell, R& jacc, R& lacc) {
+__device__ inline void sc_point(const PointConst<R>& c, R q, R w, bool gauss, const float4* tab, R Iu, R Su,
+                                R Cu, R rds, CellVals<R>& cell, R& jacc, R& lacc) {
     const R u = q * c.ivD - c.vn;
-    const R H = profile_H<R>(c.adamp, u, gauss);
+    const R H = profile_H<R>(c.adamp, u, gauss, tab);
     const R phi = H * c.pn;
     const R chi = fma(c.kpl, phi, c.chic);
     R rchi;
@@ -511,6 +519,12 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !HERM ? kSweepWavesPerSimdF
     const unsigned rowb = nxy * csz;                                  // bytes per frequency row
     const unsigned colb = unsigned(mend - a.m0) * rowb;
     const auto rcur = cell_rsrc(a.state + size_t(s % a.nstate) * slot_stride + col, colb);
+    // the small-damping Voigt table (FP32 profiles), staged in LDS
+    __shared__ float4 dawg[kDawIntervals];
+    if (sizeof(R) == 4) {
+        for (int i = int(threadIdx.x); i < kDawIntervals; i += int(blockDim.x)) dawg[i] = c_dawg[i];
+        __syncthreads();
+    }
     R jacc = R(0), lacc = R(0);
     const unsigned oc = g * csz;
     if (s == 0) {
@@ -518,7 +532,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !HERM ? kSweepWavesPerSimdF
         const R* top = a.topI ? a.topI + size_t(ln.fstart) * nxy + g : nullptr;
         for (int m = mb; m < me; ++m) {
             const R u = qf[m] * pc.ivD - pc.vn;
-            const R H = profile_H<R>(pc.adamp, u, gauss);
+            const R H = profile_H<R>(pc.adamp, u, gauss, dawg);
             const R phi = H * pc.pn;
             const R chi = fma(pc.kpl, phi, pc.chic);
             R rchi_b;
@@ -578,7 +592,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !HERM ? kSweepWavesPerSimdF
                 const R Su = hermite_between(gS[0], gS[1], gS[2], gS[3], fy);
                 const R Cu = hermite_between(gX[0], gX[1], gX[2], gX[3], fy);
                 CellVals<R> cell;
-                sc_point(pc, R(qf[m]), R(wf[m]), gauss, Iu, Su, Cu, rds, cell, jacc, lacc);
+                sc_point(pc, R(qf[m]), R(wf[m]), gauss, dawg, Iu, Su, Cu, rds, cell, jacc, lacc);
                 if (valid) cell_put(rcur, oc, so, make_cell(cell));
             }
         } else {
@@ -589,7 +603,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !HERM ? kSweepWavesPerSimdF
                 R Iu, Su, Cu;
                 upwind_values(qc, w00, w01, w10, w11, c00, c01, c10, c11, Iu, Su, Cu);
                 CellVals<R> cell;
-                sc_point(pc, R(qf[m]), R(wf[m]), gauss, Iu, Su, Cu, rds, cell, jacc, lacc);
+                sc_point(pc, R(qf[m]), R(wf[m]), gauss, dawg, Iu, Su, Cu, rds, cell, jacc, lacc);
                 if (valid) cell_put(rcur, oc, so, make_cell(cell));
             }
         }
@@ -745,7 +759,7 @@ __global__ __launch_bounds__(kPairThreads) void sweep_pair_kernel(SweepArgs<R> a
             R Iu, Su, Cu;
             upwind_values(qc, a00, a01, a10, a11, e00, e01, e10, e11, Iu, Su, Cu);
             CellVals<R> cell;
-            sc_point(c1, R(qf[m]), R(wf[m]), gauss, Iu, Su, Cu, rds1, cell, j1, l1);
+            sc_point(c1, R(qf[m]), R(wf[m]), gauss, c_dawg, Iu, Su, Cu, rds1, cell, j1, l1);
             rI[b][tid] = cell.I;
             rS[b][tid] = cell.S;
             rC[b][tid] = cell.C;
@@ -757,7 +771,7 @@ __global__ __launch_bounds__(kPairThreads) void sweep_pair_kernel(SweepArgs<R> a
             const R Su = interp4(b00, b01, b10, b11, rS[b][q00], rS[b][q01], rS[b][q10], rS[b][q11]);
             const R Cu = interp4(b00, b01, b10, b11, rC[b][q00], rC[b][q01], rC[b][q10], rC[b][q11]);
             CellVals<R> cell;
-            sc_point(c2, R(qf[m]), R(wf[m]), gauss, Iu, Su, Cu, rds2, cell, j2, l2);
+            sc_point(c2, R(qf[m]), R(wf[m]), gauss, c_dawg, Iu, Su, Cu, rds2, cell, j2, l2);
             if (valid2) cell_put(rout, oc, so, make_cell(cell));
         }
     }
@@ -877,7 +891,7 @@ __global__ __launch_bounds__(1024) void march_kernel(MarchArgs<float> a) {
                 const R vn = a.sv[SV_VX * nv + v] * R(mux) + a.sv[SV_VY * nv + v] * R(muy) +
                              a.sv[SV_VZ * nv + v] * R(muz);
                 const R u = qv * ivD - vn;
-                const R H = profile_H<R>(adamp, u, gauss);
+                const R H = profile_H<R>(adamp, u, gauss, c_dawg);
                 const R phi = H * pn;
                 const R chi = fma(kpl, phi, chic);
                 R rchi;
@@ -970,7 +984,7 @@ __global__ void emergent_step_kernel(EmergentArgs<R> a, int k) {
     const double vn = double(a.sv[SV_VX * nv + v]) * a.mux + double(a.sv[SV_VY * nv + v]) * a.muy +
                       double(a.sv[SV_VZ * nv + v]) * a.muz;
     const double u = double(a.qf[f]) * ivD - vn;
-    const double H = profile_H<double>(adamp, u, ln.gauss != 0);
+    const double H = profile_H<double>(adamp, u, ln.gauss != 0, nullptr);
     const double phi = H * pn;
     const double chi = chic + kpl * phi;
     double rchi_e;

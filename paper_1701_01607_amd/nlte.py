@@ -34,7 +34,7 @@ SYMBOLS = (
     "nlte_get_populations", "nlte_set_populations", "nlte_get_source_function",
     "nlte_emergent_intensity", "nlte_history",
     "nlte_formal_solution", "nlte_mali", "nlte_residual", "nlte_vcycle",
-    "nlte_restrict", "nlte_prolong",
+    "nlte_restrict", "nlte_prolong", "nlte_voigt",
     "nlte_serve_config", "nlte_estimate_footprint", "nlte_submit", "nlte_poll", "nlte_wait",
     "nlte_job_info",
 )
@@ -155,6 +155,7 @@ def load(path=None):
     lib.nlte_vcycle.argtypes = [P, I64, ct.c_int, ct.c_int]
     lib.nlte_restrict.argtypes = [P, I64, ct.c_int, ct.c_int, P, P]
     lib.nlte_prolong.argtypes = [P, I64, ct.c_int, ct.c_int, P, P]
+    lib.nlte_voigt.argtypes = [P, ct.c_int, ct.c_int, P, P, P]
     lib.nlte_serve_config.argtypes = [P, ct.c_int]
     lib.nlte_estimate_footprint.argtypes = [P, P, P, ct.POINTER(Params), ct.POINTER(ct.c_size_t)]
     lib.nlte_submit.argtypes = [P, P, P, ct.POINTER(Params), ct.POINTER(I64)]
@@ -248,6 +249,11 @@ class Context:
         if rc < 0:
             raise NlteError(rc, self.lib.nlte_last_error(self.h).decode())
         return rc
+
+    def voigt(self, precision, n, a_ptr, u_ptr, H_ptr):
+        """H(a, u) of the sweeps' line profile at n points (device FP64 arrays)."""
+        self.check(self.lib.nlte_voigt(self.h, precision, n, ct.c_void_p(a_ptr), ct.c_void_p(u_ptr),
+                                       ct.c_void_p(H_ptr)))
 
     # ---- inputs
     def atom(self, atom):
