@@ -263,6 +263,17 @@ nlte_status nlte_formal_solution(nlte_ctx* ctx, nlte_job job, int level, void* j
 /* `iters` MALI iterations on `level` with that level's right-hand side; *C_out gets C
  * of the last iteration (may be NULL). */
 nlte_status nlte_mali(nlte_ctx* ctx, nlte_job job, int level, int iters, double* C_out);
+/* One rate solve on `level` from given radiation (Eqs. 3, 5 and the preconditioned rates
+ * of Sect. 3): jeff = J-bar^eff and oml = 1 - Lambda-bar* per line and voxel,
+ * [nline][nz][ny][nx] in the job's precision (FP64 -> double, MIXED -> float), host or device
+ * memory per src_mem (NLTE_MEM_*), take the place of the formal solution's sums.  The
+ * level's populations are overwritten with the solution of the rate equations (row 0
+ * replaced by conservation with the level's right-hand side, rescaled so that the
+ * populations sum to it); *C_out (may be NULL) gets the maximum relative change.  Atoms
+ * with active continua are rejected (NLTE_E_INVALID): their continuum sums come from the
+ * formal solution only. */
+nlte_status nlte_rate_solve(nlte_ctx* ctx, nlte_job job, int level, const void* jeff, const void* oml, int src_mem,
+                            double* C_out);
 /* Residual r = f - W(n) with an extra formal solution (Eq. 7), [N][nz][ny][nx] FP64. */
 nlte_status nlte_residual(nlte_ctx* ctx, nlte_job job, int level, double* dst, int dst_mem);
 /* One V-cycle on levels `level`..0 (Sect. 2.2); `first` applies nu0 at the top. */

@@ -303,6 +303,7 @@ struct JobBase {
     virtual void run(nlte_result* out) = 0;
     virtual void formal_solution_out(int level, void* jeff, void* oml, int mem) = 0;
     virtual double mali_hook(int level, int iters) = 0;
+    virtual double rate_solve_hook(int level, const void* jeff, const void* oml, int mem) = 0;
     virtual void residual_out(int level, double* dst, int mem) = 0;
     virtual void vcycle_hook(int level, int first) = 0;
     virtual void get_pops(int level, double* dst, int mem) = 0;
@@ -799,15 +800,18 @@ struct Job : JobBase {
     }
 
     // --------------------------------------------------------------- kernels
-    void rate_launch(int k, int mode, const double* base, double* out, double sign, bool want_C) {
+    // `given`: acc holds two slots per quantity written by rate_solve_hook, whatever the
+    // level's sweep layout
+    void rate_launch(int k, int mode, const double* base, double* out, double sign, bool want_C,
+                     bool given = false) {
         Level& L = *lev[k];
         RateArgs<R> ra;
         ra.atom = atom_d.as<AtomInfo>();
         ra.nvox = L.nvox;
         ra.pfix = L.pfix.as<double>();
         ra.acc = L.acc.as<R>();
-        ra.nslot = L.nslot;
-        ra.march_F = L.march.F;
+        ra.nslot = given ? 2 : L.nslot;
+        ra.march_F = given ? 0 : L.march.F;
         ra.nchunk = L.march.nchunk;
         ra.n = L.n.as<double>();
         ra.f = L.f.as<double>();
@@ -1267,6 +1271,23 @@ struct Job : JobBase {
             std::memcpy(jeff, j.data(), sizeof(R) * m);
             std::memcpy(oml, o.data(), sizeof(R) * m);
         }
+    }
+
+    // One rate solve from given J-bar^eff and 1 - Lambda* (slot 0 of a two-slot layout, slot 1
+    // zero, so the slot sum is the given value exactly).
+    double rate_solve_hook(int level, const void* jeff, const void* oml, int mem) override {
+        Level& L = level_ref(level);
+        REQUIRE(!info.cont_active, "the rate-solve hook takes line radiation only (no active continua)");
+        const size_t m = size_t(nline) * L.nvox;
+        REQUIRE(L.acc.bytes >= sizeof(R) * 4 * m, "accumulator too small for the rate-solve hook");
+        R* acc = L.acc.as<R>();
+        HIPCHK(hipMemcpyAsync(acc, jeff, sizeof(R) * m, kind_from(mem), st()));
+        HIPCHK(hipMemsetAsync(acc + m, 0, sizeof(R) * m, st()));
+        HIPCHK(hipMemcpyAsync(acc + 2 * m, oml, sizeof(R) * m, kind_from(mem), st()));
+        HIPCHK(hipMemsetAsync(acc + 3 * m, 0, sizeof(R) * m, st()));
+        rate_launch(level, 0, nullptr, nullptr, 0.0, true, true);
+        L.fs_valid = false;
+        return read_scalar();
     }
 
     double mali_hook(int level, int iters) override {
@@ -1904,6 +1925,17 @@ nlte_status nlte_mali(nlte_ctx* ctx, nlte_job job, int level, int iters, double*
     return guarded(ctx, [&]() -> nlte_status {
         REQUIRE(iters >= 0, "iters must be >= 0");
         const double c = find_job(ctx, job)->mali_hook(level, iters);
+        if (C_out) *C_out = c;
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_rate_solve(nlte_ctx* ctx, nlte_job job, int level, const void* jeff, const void* oml, int src_mem,
+                            double* C_out) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(jeff && oml, "null radiation input");
+        REQUIRE(src_mem == NLTE_MEM_HOST || src_mem == NLTE_MEM_DEVICE, "bad memory kind");
+        const double c = find_job(ctx, job)->rate_solve_hook(level, jeff, oml, src_mem);
         if (C_out) *C_out = c;
         return NLTE_OK;
     });

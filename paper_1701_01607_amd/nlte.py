@@ -33,7 +33,7 @@ SYMBOLS = (
     "nlte_job_create", "nlte_job_run", "nlte_solve", "nlte_release",
     "nlte_get_populations", "nlte_set_populations", "nlte_get_source_function",
     "nlte_emergent_intensity", "nlte_history",
-    "nlte_formal_solution", "nlte_mali", "nlte_residual", "nlte_vcycle",
+    "nlte_formal_solution", "nlte_mali", "nlte_rate_solve", "nlte_residual", "nlte_vcycle",
     "nlte_restrict", "nlte_prolong", "nlte_voigt",
     "nlte_serve_config", "nlte_estimate_footprint", "nlte_submit", "nlte_poll", "nlte_wait",
     "nlte_job_info",
@@ -151,6 +151,7 @@ def load(path=None):
     lib.nlte_history.argtypes = [P, I64, P, ct.c_int]
     lib.nlte_formal_solution.argtypes = [P, I64, ct.c_int, P, P, ct.c_int]
     lib.nlte_mali.argtypes = [P, I64, ct.c_int, ct.c_int, ct.POINTER(ct.c_double)]
+    lib.nlte_rate_solve.argtypes = [P, I64, ct.c_int, P, P, ct.c_int, ct.POINTER(ct.c_double)]
     lib.nlte_residual.argtypes = [P, I64, ct.c_int, P, ct.c_int]
     lib.nlte_vcycle.argtypes = [P, I64, ct.c_int, ct.c_int]
     lib.nlte_restrict.argtypes = [P, I64, ct.c_int, ct.c_int, P, P]
@@ -406,6 +407,17 @@ class Job:
     def mali(self, level, iters):
         c = ct.c_double()
         self.ctx.check(self.lib.nlte_mali(self.ctx.h, self.id, level, iters, ct.byref(c)))
+        return c.value
+
+    def rate_solve(self, level, jeff, oml):
+        """One rate solve from given J-bar^eff and 1 - Lambda* (host arrays, rounded to the
+        job's precision); returns the maximum relative change."""
+        dt = np.float64 if self.params.precision == FP64 else np.float32
+        j = np.ascontiguousarray(jeff, dtype=dt)
+        o = np.ascontiguousarray(oml, dtype=dt)
+        c = ct.c_double()
+        self.ctx.check(self.lib.nlte_rate_solve(self.ctx.h, self.id, level, _ptr(j), _ptr(o), MEM_HOST,
+                                                ct.byref(c)))
         return c.value
 
     def residual(self, level, shape):
