@@ -422,8 +422,20 @@ struct Job : JobBase {
     std::vector<Ev> evs;
     double ms_phase[3] = {0, 0, 0};
 
+    // Active continua: their sweep needs only the populations, so outside graph capture it
+    // runs on a stream of its own, forked from the job's stream at the start of each formal
+    // solution and joined before the rate equations read its sums.
+    hipStream_t cstream = nullptr;
+    hipEvent_t cfork = nullptr, cjoin = nullptr;
+
     Job(nlte_ctx* c) : ctx(c) {}
     ~Job() override {
+        if (cstream) {
+            (void)hipStreamSynchronize(cstream);
+            (void)hipStreamDestroy(cstream);
+        }
+        if (cfork) (void)hipEventDestroy(cfork);
+        if (cjoin) (void)hipEventDestroy(cjoin);
         for (auto& e : evs) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -845,6 +857,8 @@ struct Job : JobBase {
 
     void formal_solution(int k) {
         Level& L = *lev[k];
+        const bool cont_forked = info.cont_active && !capturing;
+        if (cont_forked) cont_fork(k);
         line_coef_kernel<R><<<blocks_for(L.nvox, 256), 256, 0, st()>>>(atom_d.as<AtomInfo>(), L.n.as<double>(),
                                                                       L.lc.as<R>(), L.nvox);
         HIPCHK(hipGetLastError());
@@ -904,7 +918,15 @@ struct Job : JobBase {
             ev_end();
             L.nslot = kNDir / db;
         }
-        if (info.cont_active) cont_sweep(k);
+        if (info.cont_active) {
+            if (cont_forked) {
+                ev_begin(EV_SWEEP);   // the part of the continuum sweep not hidden by the lines
+                HIPCHK(hipStreamWaitEvent(st(), cjoin, 0));
+                ev_end();
+            } else {
+                cont_sweep(k, st());
+            }
+        }
         L.fs_valid = true;
         ++L.fs_count;
         const Level& F = *lev[nlev - 1];
@@ -912,8 +934,9 @@ struct Job : JobBase {
         updates += double(L.nvox) * kNDir * (nf + nfc);
     }
 
-    // Formal solution at the continuum frequencies of level k (active continua).
-    void cont_sweep(int k) {
+    // Formal solution at the continuum frequencies of level k (active continua), enqueued on
+    // `stream` (the job's stream, or the continuum stream between fork and join).
+    void cont_sweep(int k, hipStream_t stream) {
         Level& L = *lev[k];
         ContArgs<R> c;
         c.atom = atom_d.as<AtomInfo>();
@@ -930,10 +953,25 @@ struct Job : JobBase {
         // frequency chunks: as for the line sweep, until a launch holds two rounds of waves
         int fc = 1;
         while (fc < kContMaxChunks && sweep_waves(L.nxy, 1) * fc < kSweepWaveTarget) fc *= 2;
-        ev_begin(EV_SWEEP);
-        for (int s = 0; s < L.nz; ++s) sweep_cont_kernel<R><<<grid, unsigned(3 * fc * 64), 0, st()>>>(c, s);
+        const bool own = stream == st();
+        if (own) ev_begin(EV_SWEEP);
+        for (int s = 0; s < L.nz; ++s) sweep_cont_kernel<R><<<grid, unsigned(3 * fc * 64), 0, stream>>>(c, s);
         HIPCHK(hipGetLastError());
-        ev_end();
+        if (own) ev_end();
+    }
+
+    // Starts level k's continuum sweep on the continuum stream after everything enqueued so
+    // far on the job's stream (the populations it reads are final for this formal solution).
+    void cont_fork(int k) {
+        if (!cstream) {
+            HIPCHK(hipStreamCreateWithFlags(&cstream, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&cfork, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&cjoin, hipEventDisableTiming));
+        }
+        HIPCHK(hipEventRecord(cfork, st()));
+        HIPCHK(hipStreamWaitEvent(cstream, cfork, 0));
+        cont_sweep(k, cstream);
+        HIPCHK(hipEventRecord(cjoin, cstream));
     }
 
     void march_launch(int k) {
