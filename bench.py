@@ -204,7 +204,7 @@ def main():
                          "device copy, for hardware-counter runs")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU per process; --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
