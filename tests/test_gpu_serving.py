@@ -24,7 +24,7 @@ def nl():
 def requests(nl):
     out = []
     for j, (n, nz, two) in enumerate([(16, 17, False), (8, 9, True), (16, 33, True), (8, 17, False),
-                                      (32, 17, False), (16, 17, True)]):
+                                      (32, 17, False), (16, 17, True), (16, 17, False)]):
         atm = synth.atmos_stratified(nx=n, ny=n, nz=nz, dx=150 * synth.KM, seed=500 + j)
         if two:
             atom = synth.two_level_atom(1e-2)
@@ -32,6 +32,8 @@ def requests(nl):
         else:
             atom = synth.caii_like_atom(9)
             atm["ntot"] = atm["ntot"] * 0.1
+            if j == 6:   # active continua: their sweep runs on a second stream of the job
+                atom = synth.with_active_continua(atom)
         # two requests also use the other transfer operators and the Hermite formal solution
         ops = {3: dict(restriction=nl.RESTRICT_HALF, interpolation=nl.INTERP_HERMITE),
                5: dict(sc_interp=nl.SC_HERMITE)}.get(j, {})
