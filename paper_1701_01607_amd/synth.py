@@ -314,19 +314,29 @@ WORKLOADS = {
 }
 
 
+# Grid (nx, ny, nz) of each named workload.
+GRIDS = {
+    "two_level_16x16x32": (16, 16, 32),
+    "caii6_64x64x129": (64, 64, 129),
+    "caii6_256x256x257": (256, 256, 257),
+    "caii6_504x504x497": (504, 504, 497),
+}
+
+
 def workload(name, **kw):
     """(atom, atmosphere) for a named workload; keyword arguments override sizes/seeds."""
+    nx, ny, nz = GRIDS[name]
+    args = dict(nx=nx, ny=ny, nz=nz)
     if name == "two_level_16x16x32":
-        return two_level_atom(), atmos_isothermal(**kw)
+        args.update(kw)
+        return two_level_atom(), atmos_isothermal(**args)
+    nf = kw.pop("nfreq", 101)
     if name == "caii6_64x64x129":
-        nf = kw.pop("nfreq", 101)
-        return caii_like_atom(nf), atmos_stratified(**kw)
+        args.update(kw)
+        return caii_like_atom(nf), atmos_stratified(**args)
     if name == "caii6_256x256x257":
-        nf = kw.pop("nfreq", 101)
-        return caii_like_atom(nf), atmos_rmhd_like(**kw)
-    if name == "caii6_504x504x497":
-        nf = kw.pop("nfreq", 101)
-        args = dict(nx=504, ny=504, nz=497, dx=20.0 * KM, seed=1607004)
         args.update(kw)
         return caii_like_atom(nf), atmos_rmhd_like(**args)
-    raise KeyError(name)
+    args.update(dx=20.0 * KM, seed=1607004)
+    args.update(kw)
+    return caii_like_atom(nf), atmos_rmhd_like(**args)
