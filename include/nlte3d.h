@@ -279,15 +279,18 @@ nlte_status nlte_residual(nlte_ctx* ctx, nlte_job job, int level, double* dst, i
 /* One V-cycle on levels `level`..0 (Sect. 2.2); `first` applies nu0 at the top. */
 nlte_status nlte_vcycle(nlte_ctx* ctx, nlte_job job, int level, int first);
 /* Full-weighting restriction (Sect. 4.4) of q fields [q][nz][ny][nx] (FP64) from grid
- * `level` to grid `level-1`; src and dst are device pointers. */
+ * `level` to grid `level-1`; src and dst are device pointers (host memory is rejected with
+ * NLTE_E_INVALID). */
 nlte_status nlte_restrict(nlte_ctx* ctx, nlte_job job, int level, int nq, const double* src, double* dst);
-/* Trilinear prolongation (Sect. 4.5) of q fields from grid `level-1` to `level`. */
+/* Trilinear prolongation (Sect. 4.5) of q fields from grid `level-1` to `level` (device
+ * pointers, as for the restriction). */
 nlte_status nlte_prolong(nlte_ctx* ctx, nlte_job job, int level, int nq, const double* src, double* dst);
 /* The Voigt function H(a, u) = Re w(u + i a) that the sweeps use for the line profile
  * (Sect. 3; phi = H / (sqrt(pi) dnu_D)), at n points of the device arrays a and u (FP64,
  * a >= 0), written to the device array H.  precision NLTE_FP64: the FP64 evaluation;
  * NLTE_MIXED: the FP32 evaluation (inputs rounded to FP32 first, the result widened).
- * Synchronises the context's stream; n = 0 does nothing. */
+ * Synchronises the context's stream; n = 0 does nothing; host memory is rejected with
+ * NLTE_E_INVALID. */
 nlte_status nlte_voigt(nlte_ctx* ctx, int precision, int n, const double* a, const double* u, double* H);
 
 /* ---------------------------------------------------------------- serving

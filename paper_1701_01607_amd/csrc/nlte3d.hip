@@ -54,6 +54,17 @@ struct Error : std::runtime_error {
 
 inline unsigned blocks_for(size_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }
 
+// True for memory the device can address directly (device or managed allocations), so that
+// entry points whose kernels take caller pointers reject host memory instead of faulting.
+inline bool device_memory(const void* p) {
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();   // host memory unknown to the runtime: clear the error
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
 }  // namespace
 
 // ===================================================================== context
@@ -1997,6 +2008,7 @@ nlte_status nlte_vcycle(nlte_ctx* ctx, nlte_job job, int level, int first) {
 nlte_status nlte_restrict(nlte_ctx* ctx, nlte_job job, int level, int nq, const double* src, double* dst) {
     return guarded(ctx, [&]() -> nlte_status {
         REQUIRE(nq >= 1 && src && dst, "bad restriction arguments");
+        REQUIRE(device_memory(src) && device_memory(dst), "restriction arrays must be device memory");
         find_job(ctx, job)->restrict_hook(level, nq, src, dst);
         return NLTE_OK;
     });
@@ -2005,6 +2017,7 @@ nlte_status nlte_restrict(nlte_ctx* ctx, nlte_job job, int level, int nq, const 
 nlte_status nlte_prolong(nlte_ctx* ctx, nlte_job job, int level, int nq, const double* src, double* dst) {
     return guarded(ctx, [&]() -> nlte_status {
         REQUIRE(nq >= 1 && src && dst, "bad prolongation arguments");
+        REQUIRE(device_memory(src) && device_memory(dst), "prolongation arrays must be device memory");
         find_job(ctx, job)->prolong_hook(level, nq, src, dst);
         return NLTE_OK;
     });
@@ -2015,6 +2028,7 @@ nlte_status nlte_voigt(nlte_ctx* ctx, int precision, int n, const double* a, con
         REQUIRE(precision == NLTE_FP64 || precision == NLTE_MIXED, "precision must be NLTE_FP64 or NLTE_MIXED");
         REQUIRE(n >= 0 && (n == 0 || (a && u && H)), "bad Voigt arguments");
         if (n == 0) return NLTE_OK;
+        REQUIRE(device_memory(a) && device_memory(u) && device_memory(H), "Voigt arrays must be device memory");
         if (precision == NLTE_FP64)
             voigt_eval_kernel<double><<<blocks_for(size_t(n), 256), 256, 0, ctx->stream>>>(a, u, H, n);
         else
