@@ -140,6 +140,12 @@ __global__ void setup_level_kernel(SetupArgs<R> a) {
 template <typename R>
 __global__ void profile_norm_kernel(const AtomInfo* atom, const R* qf, const R* wf, R* sc,
                                    const R* sv, size_t nvox) {
+    // the small-damping Voigt table (FP32 profiles), staged in LDS as in the sweep
+    __shared__ float4 dawg[kDawIntervals];
+    if (sizeof(R) == 4) {
+        for (int i = int(threadIdx.x); i < kDawIntervals; i += int(blockDim.x)) dawg[i] = c_dawg[i];
+        __syncthreads();
+    }
     const size_t v = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (v >= nvox) return;
     const AtomInfo& at = *atom;
@@ -157,7 +163,7 @@ __global__ void profile_norm_kernel(const AtomInfo* atom, const R* qf, const R* 
             for (int m = 0; m < ln.nfreq; ++m) {
                 const int f = ln.fstart + m;
                 const R u = qf[f] * ivD - vn;
-                const R H = profile_H<R>(a, u, ln.gauss != 0, c_dawg);
+                const R H = profile_H<R>(a, u, ln.gauss != 0, dawg);
                 accd += double(wf[f]) * double(H * pn);
             }
             acc += accd / kNDir;
