@@ -23,6 +23,9 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32 (published)
 PEAK_HBM_GBS = 8000.0           # MI355X HBM3E (published)
 PEAK_FP64_TFLOPS = 78.6         # MI355X vector FP64 (published)
+# FP32 FMAs without the packed (two per lane) form, which this code does not use:
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz.
+PEAK_FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 # Algorithmic HBM bytes per voxel-direction-frequency update of the sweep.  The plane
 # state (one cell per direction, frequency and plane point: I and phi, 8 B, in FP32;
@@ -323,14 +326,17 @@ def main():
         "cycles": r.cycles, "fine_fs_equiv": r.fine_fs_equiv, "E_est": r.E_est,
         "phase_ms": {"setup": r.ms_setup, "sweep": r.ms_sweep, "rates": r.ms_rates, "transfer": r.ms_transfer,
                      "total": r.ms_total},
-        # The sweep issues VALU instructions on ~82 % of the cycles and moves HBM at ~70 % of
-        # the device-copy rate (counter runs): vector ALU issue binds it.  traffic is the
-        # measured HBM rate (GB/s); the hbm block gives the algorithmic one.
+        # The sweep issues VALU instructions on ~76-81 % of the cycles and moves HBM at ~69 %
+        # of the device-copy rate (counter runs): vector ALU issue is its largest resource.
+        # traffic is the measured HBM rate (GB/s); the hbm block gives the algorithmic one;
+        # unpacked_fp32 relates the flops to the ceiling without packed FP32 instructions.
         "roofline": {"bound": "alu", "achieved": achieved_alu, "peak": peak_alu, "unit": "TFLOP/s",
                      "frac": achieved_alu / peak_alu if achieved_alu else None, "traffic": traffic,
                      "kernel": f"sweep_step_kernel<{'double' if wl['fp64'] else 'float'},{r.dirs_per_block}>",
                      "avg_launch_us": avg_launch_us, "launches": launches,
                      "flops_per_update": fl, "voigt_core_fraction": core_frac,
+                     "unpacked_fp32": None if wl["fp64"] or not achieved_alu else
+                     {"peak": PEAK_FP32_UNPACKED_TFLOPS, "frac": achieved_alu / PEAK_FP32_UNPACKED_TFLOPS},
                      "hbm": {"achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                              "frac": achieved / PEAK_HBM_GBS if achieved else None,
                              "bytes_per_update": bytes_upd}},
