@@ -22,11 +22,17 @@ SIZE_P = [0.4, 0.3, 0.2, 0.1]
 
 
 def make_request(j, rng, sizes, probs):
-    """(atom, atmosphere, params) of request j: size drawn from `sizes`, two-level or
+    """(atom, atmosphere, params, tag) of request j: size drawn from `sizes`, two-level or
     six-level with equal odds, atmosphere seed 10000 + j."""
-    nx, ny, nz = sizes[rng.choice(len(sizes), p=probs)]
+    size = sizes[rng.choice(len(sizes), p=probs)]
     two = rng.random() < 0.5
-    atm = synth.atmos_stratified(nx=nx, ny=ny, nz=nz, dx=48 * synth.KM, seed=10000 + j)
+    return build_request(10000 + j, size, two)
+
+
+def build_request(seed, size, two):
+    """(atom, atmosphere, params, tag) of one solve of the given size and atom kind."""
+    nx, ny, nz = size
+    atm = synth.atmos_stratified(nx=nx, ny=ny, nz=nz, dx=48 * synth.KM, seed=seed)
     if two:
         atom = synth.two_level_atom(1e-3)
         atm["chi_c"] = None
@@ -89,6 +95,12 @@ def run_stream(ctx, requests, rate_hz, seed=1607005, max_running=4, log=None):
     return recs
 
 
+def expected_run_time(times, probs):
+    """Mean single-stream run time of a request of the mix: times[i] = (two-level, six-level)
+    run times of size i, probs[i] the size's odds, the two atoms equally likely."""
+    return float(sum(p * 0.5 * (t2 + t6) for p, (t2, t6) in zip(probs, times)))
+
+
 def busy_fraction(recs, t0, t1):
     """Fraction of [t0, t1] during which at least one solve was running on the device."""
     iv = sorted((r["t_submit"] + r["queue_s"], r["t_done"]) for r in recs)
@@ -134,10 +146,16 @@ def main():
     reqs = [make_request(j, rng, sizes, probs) for j in range(args.requests)]
     rate = args.rate
     if rate <= 0:
-        # capacity: run a few requests back to back (one at a time) and take 80 % of it
-        cal = run_stream(ctx, reqs[:4], rate_hz=1e6, max_running=1)
-        per = np.mean([r["run_s"] for r in cal])
-        rate = 0.8 / per
+        # capacity: one solve of each size and atom alone (seeds outside the stream's), the
+        # mean run time of a request of the mix from the size odds, and 80 % of its inverse
+        times = []
+        for i, size in enumerate(sizes):
+            cal = run_stream(ctx, [build_request(90000 + 2 * i + k, size, k == 0) for k in (0, 1)],
+                             rate_hz=1e6, max_running=1)
+            by = {r["kind"]: r["run_s"] for r in cal}
+            times.append((by["two-level"], by["six-level"]))
+            print(json.dumps({"calibration": list(size), "run_s": by}), flush=True)
+        rate = 0.8 / expected_run_time(times, probs)
     recs = run_stream(ctx, reqs, rate_hz=rate, max_running=args.max_running,
                       log=lambda r: print(json.dumps(r), flush=True))
     out = summarize(recs)

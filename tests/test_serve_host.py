@@ -33,3 +33,20 @@ def test_summary_percentiles_and_rate():
     assert out["p50_s"] == pytest.approx(np.percentile(lat, 50))
     assert out["converged"] == 10
     assert out["atmospheres_per_hr"] == pytest.approx(3600.0 * 10 / (max(r["t_done"] for r in recs)))
+
+
+def test_expected_run_time_weights_sizes_and_atoms():
+    serve = _serve()
+    times = [(1.0, 3.0), (2.0, 10.0)]
+    # 0.75 * (1 + 3) / 2 + 0.25 * (2 + 10) / 2
+    assert serve.expected_run_time(times, [0.75, 0.25]) == pytest.approx(0.75 * 2.0 + 0.25 * 6.0)
+
+
+def test_requests_follow_the_mix_and_are_reproducible():
+    serve = _serve()
+    rng1, rng2 = np.random.default_rng(7), np.random.default_rng(7)
+    sizes, probs = serve.SIZES[:2], np.array([0.5, 0.5])
+    a = [serve.make_request(j, rng1, [(8, 8, 9), (16, 16, 17)], probs)[3] for j in range(6)]
+    b = [serve.make_request(j, rng2, [(8, 8, 9), (16, 16, 17)], probs)[3] for j in range(6)]
+    assert a == b and {t[0] for t in a} <= {"two-level", "six-level"}
+    assert len(sizes) == 2
