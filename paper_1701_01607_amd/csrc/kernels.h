@@ -1131,13 +1131,21 @@ __global__ __launch_bounds__(3 * kContMaxChunks * 64) void sweep_cont_kernel(Con
     const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kW);
     const int FC = int(blockDim.x) / (3 * kW);
     const int w = wv % 3, cch = wv / 3;
-    const int grp = int(blockIdx.z);
+    // XCD-aware order, as in the line sweep: with the block count a multiple of 8, XCD x
+    // takes the x-th contiguous eighth of the (tile, direction group) list, so the tiles
+    // whose upwind rows overlap share an L2.
+    const unsigned T = gridDim.x;
+    const unsigned nb = T * gridDim.z;
+    const unsigned lin = blockIdx.x + T * blockIdx.z;
+    const unsigned work = (nb % 8u == 0u) ? (lin % 8u) * (nb / 8u) + lin / 8u : lin;
+    const unsigned bx = work % T;
+    const int grp = int(work / T);
     const int d = grp * 3 + w;
     const int h = (grp * 3) / kNHemi;
     const AtomInfo& at = *a.atom;
     const int nct = at.ncont;
     const unsigned nxy = a.nxy;
-    const unsigned graw = blockIdx.x * kW + unsigned(lane);
+    const unsigned graw = bx * kW + unsigned(lane);
     const bool valid = graw < nxy;
     const unsigned g = valid ? graw : nxy - 1;
     const int k = (h == 0) ? s : a.nz - 1 - s;
