@@ -167,12 +167,34 @@ def z_grid(nz, zmin, zmax, ratio=2.67, zfine=0.3):
     return z
 
 
+def _workers():
+    """Threads for the plane-parallel parts of the generators (NumPy and SciPy release the
+    GIL inside their array loops)."""
+    import os
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _by_chunks(fn, n, chunk=None):
+    """Call fn(i0, i1) over [0, n) in contiguous chunks on a thread pool.  Every chunk
+    writes its own slice, so the result does not depend on the chunking."""
+    from concurrent.futures import ThreadPoolExecutor
+    w = _workers()
+    step = chunk or max(1, -(-n // (4 * w)))
+    if w == 1 or n <= step:
+        fn(0, n)
+        return
+    with ThreadPoolExecutor(w) as ex:
+        list(ex.map(lambda i: fn(i, min(n, i + step)), range(0, n, step)))
+
+
 def gaussian_random_field(rng, nx, ny, nz, corr_xy, corr_z):
     """Unit-variance Gaussian random field, periodic in x and y.
 
     White noise is filtered with a Gaussian spectrum of correlation length
     ``corr_xy`` cells horizontally (FFT, hence periodic) and smoothed with a Gaussian of
-    ``corr_z`` cells vertically (truncated at 3 sigma, mirrored ends).
+    ``corr_z`` cells vertically (truncated at 3 sigma, mirrored ends).  Planes (for the
+    FFT) and columns (for the vertical smoothing) are processed on a thread pool; each
+    is transformed on its own, so the values are those of the whole-array calls.
     """
     from scipy.ndimage import gaussian_filter1d
 
@@ -180,12 +202,33 @@ def gaussian_random_field(rng, nx, ny, nz, corr_xy, corr_z):
     kx = np.fft.rfftfreq(nx)[None, :]
     ky = np.fft.fftfreq(ny)[:, None]
     filt = np.exp(-2.0 * (np.pi * corr_xy) ** 2 * (kx ** 2 + ky ** 2))
-    out = np.fft.irfft2(np.fft.rfft2(noise, axes=(-2, -1)) * filt[None], s=(ny, nx), axes=(-2, -1))
+    out = np.empty_like(noise)
+
+    def planes(k0, k1):
+        out[k0:k1] = np.fft.irfft2(np.fft.rfft2(noise[k0:k1], axes=(-2, -1)) * filt[None], s=(ny, nx),
+                                   axes=(-2, -1))
+
+    _by_chunks(planes, nz)
     del noise
     if corr_z > 0 and nz > 1:
-        out = gaussian_filter1d(out, corr_z, axis=0, mode="mirror", truncate=3.0)
+        src = out
+        out = np.empty_like(src)
+
+        def columns(j0, j1):
+            # the column block with z last (contiguous), smoothed along z, written back
+            blk = np.ascontiguousarray(np.moveaxis(src[:, j0:j1, :], 0, -1))
+            out[:, j0:j1, :] = np.moveaxis(gaussian_filter1d(blk, corr_z, axis=-1, mode="mirror", truncate=3.0),
+                                           -1, 0)
+
+        _by_chunks(columns, ny)
+        del src
     sd = out.std()
-    return out / sd if sd > 0 else out
+    if sd > 0:
+        def scale(k0, k1):
+            out[k0:k1] /= sd
+
+        _by_chunks(scale, nz)
+    return out
 
 
 def atmos_isothermal(nx=16, ny=16, nz=32, dx=100.0 * KM, dz=100.0 * KM, T=5000.0,
@@ -227,11 +270,18 @@ def _mean_structure(z):
     return T, nH, frac
 
 
+_BACKGROUND_SCALE = np.array([1.0, 1.0, 2.2, 2.2, 2.2, 2.0, 2.0, 2.0])
+
+
+def _background_base(nH, ne, T):
+    return 1.0e-24 * nH * (ne / 1.0e13) * (T / 5000.0) ** 2
+
+
 def _background(nH, ne, T, nline):
     """Background continuum opacity per line (cm^-1), a round-number scaling with
     n_H * n_e that puts continuum optical depth unity near z = 0."""
-    scale = np.array([1.0, 1.0, 2.2, 2.2, 2.2, 2.0, 2.0, 2.0])[:nline]
-    base = 1.0e-24 * nH * (ne / 1.0e13) * (T / 5000.0) ** 2
+    scale = _BACKGROUND_SCALE[:nline]
+    base = _background_base(nH, ne, T)
     return np.stack([s * base for s in scale], axis=0)
 
 
@@ -263,7 +313,9 @@ def atmos_rmhd_like(nx=256, ny=256, nz=257, dx=48.0 * KM, zmin=-0.5 * MM, zmax=6
                     seed=1607003, nline=5, nshock=6, vmax=10.0 * KM):
     """Stratified atmosphere with granulation-scale photospheric fields (1-1.5 Mm,
     amplitude decaying with height) and seeded step-like shock fronts in the
-    chromosphere (T x 1.5-2.5 and density x 2-4 across a 1-2 cell front)."""
+    chromosphere (T x 1.5-2.5 and density x 2-4 across a 1-2 cell front).  The fields
+    are assembled slab by slab in z on a thread pool (element-wise, so the values do
+    not depend on the slabs)."""
     rng = np.random.default_rng(seed)
     z = z_grid(nz, zmin, zmax)
     T0, nH0, frac = _mean_structure(z)
@@ -273,13 +325,9 @@ def atmos_rmhd_like(nx=256, ny=256, nz=257, dx=48.0 * KM, zmin=-0.5 * MM, zmax=6
     vel = [gaussian_random_field(rng, nx, ny, nz, 1.0 * MM / dx, 0.3 * MM / dzm) for _ in range(3)]
     decay = np.exp(-np.clip(z, 0.0, None) / (0.4 * MM))[:, None, None]
     rise = (1.0 / (1.0 + np.exp(-(z - 1.0 * MM) / (0.2 * MM))))[:, None, None]
-    T = T0[:, None, None] * (1.0 + 0.10 * gran * decay + 0.08 * chrom * rise)
-    nH = nH0[:, None, None] * np.exp(0.3 * gran * decay + 0.2 * chrom * rise - 0.1)
-    # shock fronts: planes or spherical caps above 1 Mm
-    xs = (np.arange(nx) * dx)[None, None, :]
-    ys = (np.arange(ny) * dx)[None, :, None]
-    zs = z[:, None, None]
+    # shock fronts: planes or spherical caps above 1 Mm (parameters drawn in order first)
     Lx = nx * dx
+    shocks = []
     for _ in range(nshock):
         cx, cy = rng.uniform(0, Lx), rng.uniform(0, Lx)
         zc = rng.uniform(1.2 * MM, min(zmax, 4.0 * MM))
@@ -287,20 +335,43 @@ def atmos_rmhd_like(nx=256, ny=256, nz=257, dx=48.0 * KM, zmin=-0.5 * MM, zmax=6
         width = rng.uniform(1.0, 2.0) * dx
         tfac = rng.uniform(1.5, 2.5)
         rfac = rng.uniform(2.0, 4.0)
-        ddx = (xs - cx + 0.5 * Lx) % Lx - 0.5 * Lx
-        ddy = (ys - cy + 0.5 * Lx) % Lx - 0.5 * Lx
-        r = np.sqrt(ddx ** 2 + ddy ** 2 + (zs - (zc - rad)) ** 2)
-        inside = 1.0 / (1.0 + np.exp((r - rad) / (0.5 * width)))
-        cap = inside * (zs > zc - 0.5 * rad)
-        T = T * (1.0 + (tfac - 1.0) * cap)
-        nH = nH * (1.0 + (rfac - 1.0) * cap)
-    ne = nH * frac[:, None, None] * (T / T0[:, None, None]) ** 2
-    v = [np.clip(0.4 * vmax * f, -vmax, vmax) for f in vel]
+        shocks.append((cx, cy, zc, rad, width, tfac, rfac))
+    xs = (np.arange(nx) * dx)[None, None, :]
+    ys = (np.arange(ny) * dx)[None, :, None]
+    shape = (nz, ny, nx)
+    T, nH, ne = np.empty(shape), np.empty(shape), np.empty(shape)
+    v = [np.empty(shape) for _ in range(3)]
+    chi_c = np.empty((nline,) + shape)
+    scale = _BACKGROUND_SCALE[:nline]
+
+    def slab(k0, k1):
+        sl = slice(k0, k1)
+        t0 = T0[sl, None, None]
+        Ts = t0 * (1.0 + 0.10 * gran[sl] * decay[sl] + 0.08 * chrom[sl] * rise[sl])
+        nHs = nH0[sl, None, None] * np.exp(0.3 * gran[sl] * decay[sl] + 0.2 * chrom[sl] * rise[sl] - 0.1)
+        zs = z[sl, None, None]
+        for cx, cy, zc, rad, width, tfac, rfac in shocks:
+            ddx = (xs - cx + 0.5 * Lx) % Lx - 0.5 * Lx
+            ddy = (ys - cy + 0.5 * Lx) % Lx - 0.5 * Lx
+            r = np.sqrt(ddx ** 2 + ddy ** 2 + (zs - (zc - rad)) ** 2)
+            inside = 1.0 / (1.0 + np.exp((r - rad) / (0.5 * width)))
+            cap = inside * (zs > zc - 0.5 * rad)
+            Ts = Ts * (1.0 + (tfac - 1.0) * cap)
+            nHs = nHs * (1.0 + (rfac - 1.0) * cap)
+        T[sl], nH[sl] = Ts, nHs
+        ne[sl] = nHs * frac[sl, None, None] * (Ts / t0) ** 2
+        for c in range(3):
+            v[c][sl] = np.clip(0.4 * vmax * vel[c][sl], -vmax, vmax)
+        base = _background_base(nHs, ne[sl], Ts)
+        for l in range(nline):
+            chi_c[l, sl] = scale[l] * base
+
+    _by_chunks(slab, nz)
     return {
         "nx": nx, "ny": ny, "nz": nz, "dx": float(dx), "dy": float(dx), "z": z,
         "T": T, "ne": ne, "nH": nH, "ntot": 2.0e-6 * nH,
         "vx": v[0], "vy": v[1], "vz": v[2],
-        "chi_c": _background(nH, ne, T, nline),
+        "chi_c": chi_c,
     }
 
 
