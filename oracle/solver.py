@@ -103,6 +103,21 @@ def mali(lev, k, n, f, iters, stats=None, fs0=None):
     return n, C
 
 
+def apply_correction(n_old, Ie, repair_frac):
+    """The relative coarse-grid correction with the negative-population repair.
+
+    Eq. 12: n_new = n_old (1 + I e), with I e the relative correction interpolated to
+    this grid.  Sect. 4.10: where that value is not positive, the new population is
+    ``repair_frac`` (10 %) of the uncorrected one instead (the equality case is repaired
+    too, so that later relative corrections stay defined).  Returns (n_new, number of
+    repaired entries).
+    """
+    n_new = n_old * (1.0 + Ie)
+    bad = n_new <= 0.0
+    n_new[bad] = repair_frac * n_old[bad]
+    return n_new, int(np.count_nonzero(bad))
+
+
 def vcycle(levels, k, n, f, p, first=False, stats=None, fs0=None):
     """One FAS V-cycle on levels k, k-1, ..., 1 with right-hand side f on level k."""
     lev = levels[k - 1]
@@ -125,13 +140,9 @@ def vcycle(levels, k, n, f, p, first=False, stats=None, fs0=None):
     else:
         nc = vcycle(levels, k - 1, nc, fc, p, False, stats, fs_c)
     e = (nc - n_before) / n_before
-    n_old = n
-    n = n_old * (1.0 + prolong(e, lev.z, p.interpolation))
-    bad = n <= 0.0
-    if np.any(bad):
-        n[bad] = p.repair_frac * n_old[bad]
-        if stats is not None:
-            stats.repairs += int(bad.sum())
+    n, rep = apply_correction(n, prolong(e, lev.z, p.interpolation), p.repair_frac)
+    if stats is not None:
+        stats.repairs += rep
     n, _ = mali(lev, k, n, f, p.nu2, stats)
     return n
 
