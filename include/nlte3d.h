@@ -138,12 +138,24 @@ typedef struct {
     int nlev;                  /* number of grids (1 for MALI) */
     int nu_fmg, nu0, nu1, nu2, nu3;   /* iteration counts (Sect. 2.2, 2.3, 4.12) */
     int init;                  /* NLTE_INIT_* */
-    const double* init_pops;   /* NLTE_INIT_USER: [N][nz][ny][nx] host memory */
+    const double* init_pops;   /* NLTE_INIT_USER: [N][nz][ny][nx] host memory, the finest grid's
+                                  populations (MALI and FAS; FMG starts from its coarsest
+                                  grid and rejects them).  A FAS run resumed from the
+                                  populations of an earlier one repeats that run's further
+                                  cycles bit for bit when nu0 = 0 (nu0 > 0 applies to the
+                                  first cycle of every run). */
     double tol_C;              /* stop when C <= tol_C (<= 0 disables) */
     double E_target;           /* stop when rho/(1-rho) C <= E_target, rho < 1 (<= 0 disables) */
     int max_iter;              /* cap on MALI iterations (MALI) or V-cycles (FAS/FMG) */
     double repair_frac;        /* negative-population repair fraction (0.1, Sect. 4.10) */
-    int fallback_mali;         /* on divergence continue with MALI instead of failing */
+    int fallback_mali;         /* FAS/FMG: when the divergence guard fires (a non-finite cycle
+                                  correction, or the growth test of diverge_cycles), restore
+                                  the finest populations from the start of the failing cycle
+                                  and continue with plain MALI iterations on the finest grid
+                                  under the same stop rule (its C and rho from the MALI
+                                  iterations alone), within max_iter further iterations;
+                                  result.fallback = 1.  0: the run fails with
+                                  NLTE_E_DIVERGED. */
     const double* top_I;       /* prescribed incoming intensity at the top [nf][ny][nx] or NULL */
     int dirs_per_block;        /* sweep directions per workgroup: 0 = autotune, else 3/6/12 (results do not depend on it) */
     int timing;                /* 1: time each phase with HIP events on the context stream */
@@ -178,15 +190,22 @@ typedef struct {
                                   with three directions per block and needs levels whose
                                   8-slot accumulators fit in 4 GiB; it applies to the
                                   emergent intensity too. */
+    int diverge_cycles;        /* divergence guard of FAS/FMG (Sect. 4.10: cycles can diverge when
+                                  coarse grids produce many negative populations): the run
+                                  diverges when the cycle correction C grows, C_i >
+                                  diverge_growth C_{i-1} with C_i > 1e-3, in this many
+                                  consecutive cycles; 0 = 3, < 0 = off (a non-finite C
+                                  always counts) */
+    double diverge_growth;     /* growth factor of that test; 0 = 1 */
 } nlte_params;
 
 typedef struct {
     int status;
     int iterations;            /* finest-level MALI iterations (MALI) */
     int cycles;                /* V-cycles at the finest level */
-    double C;                  /* last max relative change (Eq. 18) */
+    double C;                  /* last max relative change (Eq. 16) */
     double rho;                /* last C_i / C_{i-1} */
-    double E_est;              /* rho / (1 - rho) C (Eq. 20) */
+    double E_est;              /* rho / (1 - rho) C (Eq. 18) */
     long long repairs;         /* negative-population repairs */
     long long formal_solutions[8];   /* per level, index 0 = coarsest */
     double fine_fs_equiv;      /* work in finest-grid formal solutions (Sect. 4.9 cost units) */
@@ -195,6 +214,9 @@ typedef struct {
     long long sweep_launches;  /* plane-step sweep kernel launches (formal solutions x planes) */
     int dirs_per_block;        /* sweep block shape used on the finest level (3, 6 or 12; 0 if none ran) */
     int sweep_kernel;          /* NLTE_SWEEP_PLANE_STEP, _PAIR or _RESIDENT on the finest level */
+    int fallback;              /* 1: FAS/FMG diverged and the run continued as plain MALI
+                                  (params.fallback_mali); iterations counts those MALI
+                                  iterations and cycles the cycles before it */
 } nlte_result;
 
 /* ---------------------------------------------------------------- lifecycle */
@@ -250,7 +272,14 @@ nlte_status nlte_get_source_function(nlte_ctx* ctx, nlte_job job, double* dst, i
  * frequencies of all lines in atom order. */
 nlte_status nlte_emergent_intensity(nlte_ctx* ctx, nlte_job job, int ndir, const double* mu,
                                     float* dst, int dst_mem);
-/* Convergence history: up to `cap` values of C per MALI iteration (MALI) or per cycle. */
+/* The job's work so far, including stage-hook calls: formal solutions per level, finest-grid
+ * formal-solution equivalents, updates, sweep launches and block shape, repairs, the last C,
+ * and (with params.timing) the phase times measured with HIP events on the job's stream;
+ * status, iterations, cycles, rho and E_est are those of the last nlte_job_run (0 before). */
+nlte_status nlte_job_stats(nlte_ctx* ctx, nlte_job job, nlte_result* out);
+/* Convergence history: up to `cap` values of C per MALI iteration (MALI) or per cycle
+ * (FAS/FMG; after a fallback to MALI the MALI iterations follow the cycles).  Returns the
+ * number of values held, or -1 for an unknown job. */
 int nlte_history(nlte_ctx* ctx, nlte_job job, double* C, int cap);
 
 /* ---------------------------------------------------------------- stage hooks
@@ -276,8 +305,11 @@ nlte_status nlte_rate_solve(nlte_ctx* ctx, nlte_job job, int level, const void* 
                             double* C_out);
 /* Residual r = f - W(n) with an extra formal solution (Eq. 7), [N][nz][ny][nx] FP64. */
 nlte_status nlte_residual(nlte_ctx* ctx, nlte_job job, int level, double* dst, int dst_mem);
-/* One V-cycle on levels `level`..0 (Sect. 2.2); `first` applies nu0 at the top. */
-nlte_status nlte_vcycle(nlte_ctx* ctx, nlte_job job, int level, int first);
+/* One V-cycle on levels `level`..0 (Sect. 2.2); `first` applies nu0 at the top.
+ * *repairs (may be NULL) gets the job's count of negative-population repairs so far
+ * (Sect. 4.10: entries where the corrected population n_old (1 + I e) was <= 0 and
+ * repair_frac * n_old was taken instead). */
+nlte_status nlte_vcycle(nlte_ctx* ctx, nlte_job job, int level, int first, long long* repairs);
 /* Full-weighting restriction (Sect. 4.4) of q fields [q][nz][ny][nx] (FP64) from grid
  * `level` to grid `level-1`; src and dst are device pointers (host memory is rejected with
  * NLTE_E_INVALID). */

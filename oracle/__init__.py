@@ -21,7 +21,7 @@ multigrid method", in FP64 NumPy/SciPy:
                 4.5).
 * ``solver``    MALI iteration, FAS V-cycle and full multigrid with the relative
                 correction and negative-population repair (Sect. 2.2, 2.3, 4.6,
-                4.10, 4.11, 4.12; Eqs. 6-14, 17-21).
+                4.10, 4.11, 4.12; Eqs. 6-14, 16-18, 21).
 
 The oracle shares no code with the HIP path; only the seeded input generators in
 ``paper_1701_01607_amd.synth`` feed both, and the oracle does not import them.

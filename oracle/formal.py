@@ -152,11 +152,12 @@ def sweep(geom, mu, local, boundary, accumulate=None, keep_top=False):
     return I_p if keep_top else None
 
 
-def formal_solution(lev, n, want_jbar=False):
+def formal_solution(lev, n, want_jbar=False, dirs=None):
     """Formal solution at populations n on level ``lev``.
 
     Returns (Jeff, one_minus_Lstar) with shape (nline, nz, ny, nx), plus the plain
-    Jbar = sum w phi~ I if want_jbar.
+    Jbar = sum w phi~ I if want_jbar.  ``dirs`` restricts the direction sums to a subset
+    of the A4 directions (their partial sums; the default is all of them).
     """
     kk, ee = lev.line_coefficients(n)
     norm = lev.norm()
@@ -168,7 +169,7 @@ def formal_solution(lev, n, want_jbar=False):
     Jbar = np.zeros(shape) if want_jbar else None
     fs = lev.fstart
 
-    for d in range(len(lev.wmu)):
+    for d in (range(len(lev.wmu)) if dirs is None else dirs):
         mu = lev.mu[d]
 
         def local(k, mu=mu):

@@ -107,16 +107,21 @@ class Level:
         dnuD = self.nu0[lo][:, None, None] * vD / ph.C
         return ph.voigt_H(a, u) / (np.sqrt(np.pi) * dnuD)
 
+    def norm_sum(self, dirs=None):
+        """sum_d sum_m w_d w_m phi per (line, voxel) over the directions ``dirs`` (all by
+        default)."""
+        acc = np.zeros((self.nline, self.nz, self.ny, self.nx))
+        for d in (range(len(self.wmu)) if dirs is None else dirs):
+            for k in range(self.nz):
+                phi = self.profile(k, self.mu[d])
+                wp = self.wmu[d] * self.wnu[:, None, None] * phi
+                acc[:, k] += np.add.reduceat(wp, self.fstart, axis=0)
+        return acc
+
     def norm(self):
         """Profile normalisation N_l per (line, voxel): 1 / sum_d sum_m w_d w_m phi."""
         if self._norm is None:
-            acc = np.zeros((self.nline, self.nz, self.ny, self.nx))
-            for d in range(len(self.wmu)):
-                for k in range(self.nz):
-                    phi = self.profile(k, self.mu[d])
-                    wp = self.wmu[d] * self.wnu[:, None, None] * phi
-                    acc[:, k] += np.add.reduceat(wp, self.fstart, axis=0)
-            self._norm = 1.0 / acc
+            self._norm = 1.0 / self.norm_sum()
         return self._norm
 
     # ---- population-dependent line quantities --------------------------------

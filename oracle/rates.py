@@ -90,7 +90,7 @@ def zero_radiation(lev, f=None):
 
 
 def max_rel_change(n_new, n_old):
-    """C = max |(n_new - n_old) / n_new| over levels and voxels (Eq. 18)."""
+    """C = max |(n_new - n_old) / n_new| over levels and voxels (Eq. 16)."""
     return float(np.max(np.abs((n_new - n_old) / n_new)))
 
 

@@ -21,9 +21,9 @@ Follows Sect. 2.2 and 2.3 of the paper in its order and notation:
   atmosphere, nu_FMG iterations there with f = [n_tot, 0, ...], then for every finer
   level the full approximation is interpolated (Eq. 14) and one V-cycle is applied on
   every intermediate level; at the finest level regular V-cycles follow.
-* Convergence (Sect. 3.3): C_i = max |(n_i - n_{i-1}) / n_i| (Eq. 18) over all levels
+* Convergence (Sect. 3.3): C_i = max |(n_i - n_{i-1}) / n_i| (Eq. 16) over all levels
   and voxels; for cycles it is taken between successive finest-level cycle ends.  The
-  error estimate is E = rho / (1 - rho) C with rho = C_{i}/C_{i-1} (Eq. 20), which holds
+  error estimate is E = rho / (1 - rho) C with rho = C_{i}/C_{i-1} (Eq. 18), which holds
   once the corrections are in their asymptotic linear regime; the first correction,
   made from the initial populations, is not, so rho is taken from the second
   correction on (three or more corrections before E is used).

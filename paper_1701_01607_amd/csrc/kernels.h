@@ -964,16 +964,18 @@ struct EmergentArgs {
     const R* lc;
     const R* qf;
     const int* line_of;  // [nf]
-    double* state;       // [2][3][nf][nxy]
+    double* state;       // [2][3][fn][nxy]: this chunk's plane state
     float* out;          // [nf][nxy]
     int herm;            // 1: monotone bicubic Hermite upwind interpolation
+    int f0, fn;          // the launch covers frequencies f0 .. f0+fn-1 (each independent of the others)
 };
 
 template <typename R>
 __global__ void emergent_step_kernel(EmergentArgs<R> a, int k) {
     const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= size_t(a.nf) * a.nxy) return;
-    const int f = int(idx / a.nxy);
+    if (idx >= size_t(a.fn) * a.nxy) return;
+    const int fl = int(idx / a.nxy);   // frequency within the chunk (state index)
+    const int f = a.f0 + fl;
     const size_t g = idx % a.nxy;
     const AtomInfo& at = *a.atom;
     const int l = a.line_of[f];
@@ -995,7 +997,7 @@ __global__ void emergent_step_kernel(EmergentArgs<R> a, int k) {
     const double chi = chic + kpl * phi;
     double rchi_e;
     const double S = source_fn(chi, chic, etac, kpl, el, phi, rchi_e);
-    const size_t ps = size_t(a.nf) * a.nxy;
+    const size_t ps = size_t(a.fn) * a.nxy;
     double* cur = a.state + size_t(k & 1) * 3 * ps;
     double I;
     if (k == 0) {
@@ -1011,7 +1013,7 @@ __global__ void emergent_step_kernel(EmergentArgs<R> a, int k) {
         int y0 = int((long long)(y + (long long)fsy) % a.ny); if (y0 < 0) y0 += a.ny;
         const int x1 = (x0 + 1 == a.nx) ? 0 : x0 + 1;
         const int y1 = (y0 + 1 == a.ny) ? 0 : y0 + 1;
-        const size_t fo = size_t(f) * a.nxy;
+        const size_t fo = size_t(fl) * a.nxy;
         const size_t g00 = fo + size_t(y0) * a.nx + x0, g01 = fo + size_t(y0) * a.nx + x1;
         const size_t g10 = fo + size_t(y1) * a.nx + x0, g11 = fo + size_t(y1) * a.nx + x1;
         const double w00 = (1.0 - fx) * (1.0 - fy), w01 = fx * (1.0 - fy);
@@ -1041,9 +1043,9 @@ __global__ void emergent_step_kernel(EmergentArgs<R> a, int k) {
         sc_coeffs(dtau, ex, pu, po, omp);
         I = Iu * ex + pu * Su + po * S;
     }
-    cur[size_t(f) * a.nxy + g] = I;
-    cur[ps + size_t(f) * a.nxy + g] = S;
-    cur[2 * ps + size_t(f) * a.nxy + g] = chi;
+    cur[size_t(fl) * a.nxy + g] = I;
+    cur[ps + size_t(fl) * a.nxy + g] = S;
+    cur[2 * ps + size_t(fl) * a.nxy + g] = chi;
     if (k == a.nz - 1) a.out[size_t(f) * a.nxy + g] = float(I);
 }
 

@@ -317,6 +317,8 @@ struct JobBase {
     virtual double rate_solve_hook(int level, const void* jeff, const void* oml, int mem) = 0;
     virtual void residual_out(int level, double* dst, int mem) = 0;
     virtual void vcycle_hook(int level, int first) = 0;
+    virtual long long repair_count() = 0;
+    virtual void stats(nlte_result* out) = 0;
     virtual void get_pops(int level, double* dst, int mem) = 0;
     virtual void set_pops(int level, const double* src, int mem) = 0;
     virtual void source_function(double* dst, int mem) = 0;
@@ -1164,16 +1166,29 @@ struct Job : JobBase {
         sweep_launches += graph_launches;
     }
 
-    // Stop rule (Eq. 20): E = rho/(1-rho) C, rho = C_i/C_{i-1}, valid in the asymptotic
+    // Stop rule (Eq. 18): E = rho/(1-rho) C, rho = C_i/C_{i-1}, valid in the asymptotic
     // linear regime; the first correction (from the initial populations) is excluded, so
-    // rho needs the second and a later correction.
-    bool stop(double& rho, double& E) {
-        const double C = history.back();
-        rho = history.size() >= 3 ? C / history[history.size() - 2] : INFINITY;
+    // rho needs the second and a later correction of the sequence h.
+    bool stop(const std::vector<double>& h, double& rho, double& E) {
+        const double C = h.back();
+        rho = h.size() >= 3 ? C / h[h.size() - 2] : INFINITY;
         E = (rho < 1.0) ? rho / (1.0 - rho) * C : INFINITY;
         if (params.tol_C > 0 && C <= params.tol_C) return true;
         if (params.E_target > 0 && rho < 1.0 && E <= params.E_target) return true;
         return false;
+    }
+
+    // Divergence guard of the cycles (Sect. 4.10): a non-finite correction, or C growing
+    // (C_i > diverge_growth C_{i-1} with C_i above 1e-3, where a converging run no longer
+    // is) in diverge_cycles consecutive cycles.  `run` counts the growing cycles so far.
+    const char* diverging(int& run) const {
+        const double C = history.back();
+        if (!std::isfinite(C)) return "non-finite cycle correction";
+        const int K = params.diverge_cycles == 0 ? 3 : params.diverge_cycles;
+        if (K < 0 || history.size() < 2) return nullptr;
+        const double g = params.diverge_growth > 0 ? params.diverge_growth : 1.0;
+        run = (C > g * history[history.size() - 2] && C > 1e-3) ? run + 1 : 0;
+        return run >= K ? "growing cycle correction" : nullptr;
     }
 
     void check_finite(int k) {
@@ -1193,7 +1208,7 @@ struct Job : JobBase {
         Level& F = *lev[top];
         int status = NLTE_W_NOT_CONVERGED;
         double rho = INFINITY, E = INFINITY;
-        int iters = 0, cycles = 0;
+        int iters = 0, cycles = 0, grow_run = 0, fell_back = 0;
         const int maxit = params.max_iter > 0 ? params.max_iter : 1000;
         if (params.method == NLTE_MALI || nlev == 1 && params.method != NLTE_FAS && params.method != NLTE_FMG) {
             for (int it = 0; it < maxit; ++it) {
@@ -1202,7 +1217,7 @@ struct Job : JobBase {
                 history.push_back(read_scalar());
                 ++iters;
                 if (!std::isfinite(history.back())) throw Error(NLTE_E_DIVERGED, "non-finite MALI correction");
-                if (stop(rho, E)) { status = NLTE_OK; break; }
+                if (stop(history, rho, E)) { status = NLTE_OK; break; }
             }
         } else {
             bool first = true;
@@ -1230,13 +1245,30 @@ struct Job : JobBase {
                 }
                 first = false;
                 ++cycles;
-                if (!std::isfinite(history.back())) {
-                    if (params.fallback_mali) {
-                        throw Error(NLTE_E_DIVERGED, "FAS diverged (fallback to MALI needs a restart)");
+                const char* why = diverging(grow_run);
+                if (why) {
+                    if (!params.fallback_mali) throw Error(NLTE_E_DIVERGED, why);
+                    if (log_enabled()) log_line("cycle %d: %s; continuing with MALI", cycles, why);
+                    // populations from the start of the failing cycle, then plain MALI on
+                    // the finest grid under the same stop rule, over its own corrections
+                    dcopy(nprev.as<double>(), F.n.as<double>(), size_t(N) * F.nvox);
+                    F.fs_valid = false;
+                    fell_back = 1;
+                    status = NLTE_W_NOT_CONVERGED;
+                    rho = E = INFINITY;
+                    std::vector<double> hm;
+                    for (int it = 0; it < maxit; ++it) {
+                        mali(top, 1);
+                        hm.push_back(read_scalar());
+                        history.push_back(hm.back());
+                        ++iters;
+                        if (!std::isfinite(hm.back()))
+                            throw Error(NLTE_E_DIVERGED, "non-finite MALI correction after the fallback");
+                        if (stop(hm, rho, E)) { status = NLTE_OK; break; }
                     }
-                    throw Error(NLTE_E_DIVERGED, "non-finite cycle correction");
+                    break;
                 }
-                const bool done = stop(rho, E);
+                const bool done = stop(history, rho, E);
                 if (log_enabled()) log_line("cycle %d: C = %.3e  rho = %.3e  E = %.3e", cycles, history.back(), rho, E);
                 if (done) { status = NLTE_OK; break; }
             }
@@ -1267,6 +1299,7 @@ struct Job : JobBase {
         r.dirs_per_block = fine_db;
         r.sweep_kernel = lev[nlev - 1]->march.F ? NLTE_SWEEP_RESIDENT
                          : lev[nlev - 1]->pair ? NLTE_SWEEP_PAIR : NLTE_SWEEP_PLANE_STEP;
+        r.fallback = fell_back;
         res = r;
         if (out) *out = r;
     }
@@ -1360,6 +1393,31 @@ struct Job : JobBase {
         HIPCHK(hipStreamSynchronize(st()));
     }
 
+    // Counters and phase times accumulated so far, also over stage hooks.
+    void stats(nlte_result* out) override {
+        ev_resolve();
+        nlte_result r = res;
+        r.C = history.empty() ? 0.0 : history.back();
+        r.repairs = repair_count();
+        for (int k = 0; k < nlev && k < 8; ++k) r.formal_solutions[k] = lev[k]->fs_count;
+        r.fine_fs_equiv = cost_units;
+        r.updates = updates;
+        r.ms_setup = ms_setup;
+        r.ms_sweep = ms_phase[EV_SWEEP];
+        r.ms_rates = ms_phase[EV_RATES];
+        r.ms_transfer = ms_phase[EV_TRANSFER];
+        r.sweep_launches = sweep_launches;
+        r.dirs_per_block = fine_db;
+        *out = r;
+    }
+
+    long long repair_count() override {
+        unsigned long long rep = 0;
+        HIPCHK(hipMemcpyAsync(&rep, repairs.p, sizeof(rep), hipMemcpyDeviceToHost, st()));
+        HIPCHK(hipStreamSynchronize(st()));
+        return (long long)rep;
+    }
+
     void get_pops(int level, double* dst, int mem) override {
         Level& L = level_ref(level);
         HIPCHK(hipMemcpyAsync(dst, L.n.p, sizeof(double) * N * L.nvox, kind_to(mem), st()));
@@ -1391,9 +1449,7 @@ struct Job : JobBase {
 
     void emergent(int ndir, const double* mu, float* dst, int mem) override {
         Level& F = *lev[nlev - 1];
-        line_coef_kernel<R><<<blocks_for(F.nvox, 256), 256, 0, st()>>>(atom_d.as<AtomInfo>(), F.n.as<double>(),
-                                                                      F.lc.as<R>(), F.nvox);
-        HIPCHK(hipGetLastError());
+        check_mu(ndir, mu);
         if (!estate.p) dalloc(estate, sizeof(double) * 2 * 3 * size_t(nf) * F.nxy);
         DevBuf o;
         float* target = dst;
@@ -1401,10 +1457,31 @@ struct Job : JobBase {
             dalloc(o, sizeof(float) * size_t(ndir) * nf * F.nxy);
             target = o.as<float>();
         }
+        emergent_launch(ndir, mu, target, estate.as<double>(), nf);
+        if (mem != NLTE_MEM_DEVICE)
+            HIPCHK(hipMemcpyAsync(dst, target, sizeof(float) * size_t(ndir) * nf * F.nxy, hipMemcpyDeviceToHost, st()));
+        HIPCHK(hipStreamSynchronize(st()));
+    }
+
+    void check_mu(int ndir, const double* mu) const {
         for (int d = 0; d < ndir; ++d) {
-            double m[3] = {mu[3 * d], mu[3 * d + 1], mu[3 * d + 2]};
+            const double m[3] = {mu[3 * d], mu[3 * d + 1], mu[3 * d + 2]};
             const double nrm = std::sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
             REQUIRE(nrm > 0 && m[2] / nrm > 1e-6, "emergent directions must point upward");
+        }
+    }
+
+    // Upward formal solution for each direction at the finest populations, frequencies in
+    // chunks of fn (their plane state [2][3][fn][nxy] in `state`); I of the top plane to
+    // out[d][f][nxy].  Every frequency is independent, so the chunking does not change it.
+    void emergent_launch(int ndir, const double* mu, float* out, double* state, int fn) {
+        Level& F = *lev[nlev - 1];
+        line_coef_kernel<R><<<blocks_for(F.nvox, 256), 256, 0, st()>>>(atom_d.as<AtomInfo>(), F.n.as<double>(),
+                                                                      F.lc.as<R>(), F.nvox);
+        HIPCHK(hipGetLastError());
+        for (int d = 0; d < ndir; ++d) {
+            const double m[3] = {mu[3 * d], mu[3 * d + 1], mu[3 * d + 2]};
+            const double nrm = std::sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
             EmergentArgs<R> a;
             a.atom = atom_d.as<AtomInfo>();
             a.nx = F.nx; a.ny = F.ny; a.nz = F.nz; a.nf = nf;
@@ -1414,16 +1491,17 @@ struct Job : JobBase {
             a.z = F.dz.as<double>();
             a.sc = F.sc.as<R>(); a.sv = F.sv.as<R>(); a.lc = F.lc.as<R>(); a.qf = qf.as<R>();
             a.line_of = line_of_d.as<int>();
-            a.state = estate.as<double>();
-            a.out = target + size_t(d) * nf * F.nxy;
+            a.state = state;
+            a.out = out + size_t(d) * nf * F.nxy;
             a.herm = params.sc_interp == NLTE_SC_HERMITE ? 1 : 0;
-            for (int k = 0; k < F.nz; ++k)
-                emergent_step_kernel<R><<<blocks_for(size_t(nf) * F.nxy, 256), 256, 0, st()>>>(a, k);
+            for (int f0 = 0; f0 < nf; f0 += fn) {
+                a.f0 = f0;
+                a.fn = std::min(fn, nf - f0);
+                for (int k = 0; k < F.nz; ++k)
+                    emergent_step_kernel<R><<<blocks_for(size_t(a.fn) * F.nxy, 256), 256, 0, st()>>>(a, k);
+            }
             HIPCHK(hipGetLastError());
         }
-        if (mem != NLTE_MEM_DEVICE)
-            HIPCHK(hipMemcpyAsync(dst, target, sizeof(float) * size_t(ndir) * nf * F.nxy, hipMemcpyDeviceToHost, st()));
-        HIPCHK(hipStreamSynchronize(st()));
     }
 
     void restrict_hook(int level, int nq, const double* src, double* dst) override {
@@ -1500,6 +1578,9 @@ double now_s() {
 // (submission already checked that it fits an empty context),
 // then builds and runs it on its own stream; several workers run jobs concurrently, so
 // their kernels overlap on the device and a queued job starts as soon as memory frees.
+// A job leaves the queue and becomes RUNNING in one step under qmu, and its final state
+// is published last, under qmu, after its times, status and accounting are written:
+// nlte_release, which waits under qmu for a final state, then owns the job alone.
 void serve_worker(nlte_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     for (;;) {
@@ -1517,15 +1598,16 @@ void serve_worker(nlte_ctx* ctx) {
                         ctx->reserved += head->footprint;
                         ctx->running++;
                         j = head;
+                        j->t_admit = now_s();
+                        j->state = NLTE_JOB_RUNNING;
                         break;
                     }
                 }
                 ctx->qcv.wait(lk);
             }
         }
-        j->t_admit = now_s();
-        j->state = 1;
         bool reservation_held = true;
+        int final_state = NLTE_JOB_DONE;
         try {
             HIPCHK(hipStreamCreateWithFlags(&j->own_stream, hipStreamNonBlocking));
             j->build_served();
@@ -1537,21 +1619,21 @@ void serve_worker(nlte_ctx* ctx) {
             nlte_result r{};
             j->run(&r);
             j->final_status = r.status;
-            j->state = 2;
         } catch (const Error& e) {
             j->final_status = e.code;
             j->error = e.what();
-            j->state = 3;
+            final_state = NLTE_JOB_FAILED;
         } catch (const std::exception& e) {
             j->final_status = NLTE_E_INVALID;
             j->error = e.what();
-            j->state = 3;
+            final_state = NLTE_JOB_FAILED;
         }
         j->t_done = now_s();
         {
             std::lock_guard<std::mutex> lk(ctx->qmu);
             ctx->running--;
             if (reservation_held) ctx->reserved -= j->footprint;
+            j->state = final_state;   // published last: the worker does not touch j again
         }
         ctx->qcv.notify_all();
     }
@@ -1835,18 +1917,29 @@ static bool transfer_ops_ok(const nlte_params* p) {
            (p->sc_interp == NLTE_SC_BILINEAR || p->sc_interp == NLTE_SC_HERMITE);
 }
 
+// Checks of the solve parameters shared by nlte_job_create and nlte_submit.
+static void check_params(const nlte_params* p) {
+    REQUIRE(p->method >= NLTE_MALI && p->method <= NLTE_FMG, "unknown method");
+    REQUIRE(p->precision == NLTE_FP64 || p->precision == NLTE_MIXED, "unknown precision");
+    REQUIRE(transfer_ops_ok(p), "unknown restriction or interpolation scheme");
+    REQUIRE(p->nu0 >= 0 && p->nu1 >= 0 && p->nu2 >= 0 && p->nu3 >= 0 && p->nu_fmg >= 0,
+            "iteration counts must be >= 0");
+    REQUIRE(p->repair_frac > 0 && p->repair_frac < 1, "repair_frac must lie in (0, 1)");
+    REQUIRE(p->max_iter >= 0, "max_iter must be >= 0");
+    REQUIRE(p->init >= NLTE_INIT_ZERO_RAD && p->init <= NLTE_INIT_USER, "unknown initialisation");
+    REQUIRE(std::isfinite(p->diverge_growth) && p->diverge_growth >= 0, "diverge_growth must be >= 0");
+    REQUIRE(p->sweep_kernel >= NLTE_SWEEP_AUTO && p->sweep_kernel <= NLTE_SWEEP_PAIR, "unknown sweep kernel");
+    REQUIRE(p->dirs_per_block == 0 || p->dirs_per_block == 3 || p->dirs_per_block == 6 || p->dirs_per_block == 12,
+            "dirs_per_block must be 0, 3, 6 or 12");
+}
+
 extern "C" {
 
 nlte_status nlte_job_create(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom* atom,
                             const nlte_params* params, nlte_job* job) {
     return guarded(ctx, [&]() -> nlte_status {
         REQUIRE(atmos && atom && params && job, "null argument");
-        REQUIRE(params->method >= NLTE_MALI && params->method <= NLTE_FMG, "unknown method");
-        REQUIRE(params->precision == NLTE_FP64 || params->precision == NLTE_MIXED, "unknown precision");
-        REQUIRE(transfer_ops_ok(params), "unknown restriction or interpolation scheme");
-        REQUIRE(params->nu0 >= 0 && params->nu1 >= 0 && params->nu2 >= 0 && params->nu3 >= 0 && params->nu_fmg >= 0,
-                "iteration counts must be >= 0");
-        REQUIRE(params->repair_frac > 0 && params->repair_frac < 1, "repair_frac must lie in (0, 1)");
+        check_params(params);
         std::unique_ptr<JobBase> j;
         if (params->precision == NLTE_FP64) {
             auto* p = new Job<double>(ctx);
@@ -1897,17 +1990,11 @@ nlte_status nlte_release(nlte_ctx* ctx, nlte_job job) {
     return guarded(ctx, [&]() -> nlte_status {
         JobBase* j = find_job(ctx, job, false);
         if (j->served) {
-            {
-                std::lock_guard<std::mutex> lk(ctx->qmu);
-                auto it = std::find(ctx->queue.begin(), ctx->queue.end(), j);
-                if (it != ctx->queue.end()) ctx->queue.erase(it);
-                else
-                    while (j->state == 1) {   // running: let it finish
-                        ctx->qmu.unlock();
-                        std::this_thread::sleep_for(std::chrono::milliseconds(1));
-                        ctx->qmu.lock();
-                    }
-            }
+            std::unique_lock<std::mutex> lk(ctx->qmu);
+            auto it = std::find(ctx->queue.begin(), ctx->queue.end(), j);
+            if (it != ctx->queue.end()) ctx->queue.erase(it);
+            else   // admitted: wait for its worker to publish the final state
+                ctx->qcv.wait(lk, [&]() { return j->state >= NLTE_JOB_DONE; });
         } else {
             HIPCHK(hipStreamSynchronize(ctx->stream));
         }
@@ -1947,6 +2034,14 @@ nlte_status nlte_emergent_intensity(nlte_ctx* ctx, nlte_job job, int ndir, const
     return guarded(ctx, [&]() -> nlte_status {
         REQUIRE(ndir >= 1 && mu && dst, "bad emergent-intensity arguments");
         find_job(ctx, job)->emergent(ndir, mu, dst, dst_mem);
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_job_stats(nlte_ctx* ctx, nlte_job job, nlte_result* out) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(out, "null result");
+        find_job(ctx, job)->stats(out);
         return NLTE_OK;
     });
 }
@@ -1998,9 +2093,11 @@ nlte_status nlte_residual(nlte_ctx* ctx, nlte_job job, int level, double* dst, i
     });
 }
 
-nlte_status nlte_vcycle(nlte_ctx* ctx, nlte_job job, int level, int first) {
+nlte_status nlte_vcycle(nlte_ctx* ctx, nlte_job job, int level, int first, long long* repairs) {
     return guarded(ctx, [&]() -> nlte_status {
-        find_job(ctx, job)->vcycle_hook(level, first);
+        JobBase* j = find_job(ctx, job);
+        j->vcycle_hook(level, first);
+        if (repairs) *repairs = j->repair_count();
         return NLTE_OK;
     });
 }
@@ -2066,9 +2163,7 @@ nlte_status nlte_submit(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom*
                         nlte_job* job) {
     return guarded(ctx, [&]() -> nlte_status {
         REQUIRE(atmos && atom && params && job, "null argument");
-        REQUIRE(params->method >= NLTE_MALI && params->method <= NLTE_FMG, "unknown method");
-        REQUIRE(params->precision == NLTE_FP64 || params->precision == NLTE_MIXED, "unknown precision");
-        REQUIRE(transfer_ops_ok(params), "unknown restriction or interpolation scheme");
+        check_params(params);
         REQUIRE(params->init != NLTE_INIT_USER && params->top_I == nullptr,
                 "served jobs take no host arrays in params");
         const int nlev = std::max(1, params->method == NLTE_MALI ? 1 : params->nlev);
@@ -2128,7 +2223,7 @@ nlte_status nlte_wait(nlte_ctx* ctx, nlte_job job, int timeout_ms) {
         if (timeout_ms >= 0 && (now_s() - t0) * 1e3 >= timeout_ms) return NLTE_W_QUEUED;
         ctx->qcv.wait_for(lk, std::chrono::milliseconds(2));
     }
-    return j->state == 2 ? j->final_status : j->final_status;
+    return j->final_status;
 }
 
 nlte_status nlte_job_info(nlte_ctx* ctx, nlte_job job, nlte_job_info_t* info) {

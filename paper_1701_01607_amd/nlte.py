@@ -31,7 +31,7 @@ SYMBOLS = (
     "nlte_ctx_create", "nlte_ctx_destroy", "nlte_last_error", "nlte_version",
     "nlte_atom_create", "nlte_atom_destroy", "nlte_atmos_create", "nlte_atmos_destroy",
     "nlte_job_create", "nlte_job_run", "nlte_solve", "nlte_release",
-    "nlte_get_populations", "nlte_set_populations", "nlte_get_source_function",
+    "nlte_get_populations", "nlte_set_populations", "nlte_get_source_function", "nlte_job_stats",
     "nlte_emergent_intensity", "nlte_history",
     "nlte_formal_solution", "nlte_mali", "nlte_rate_solve", "nlte_residual", "nlte_vcycle",
     "nlte_restrict", "nlte_prolong", "nlte_voigt",
@@ -91,7 +91,8 @@ class Params(ct.Structure):
                 ("repair_frac", ct.c_double), ("fallback_mali", ct.c_int),
                 ("top_I", ct.POINTER(ct.c_double)), ("dirs_per_block", ct.c_int), ("timing", ct.c_int),
                 ("graph", ct.c_int), ("sweep_kernel", ct.c_int), ("restriction", ct.c_int),
-                ("coarse_atmos", ct.c_int), ("interpolation", ct.c_int), ("sc_interp", ct.c_int)]
+                ("coarse_atmos", ct.c_int), ("interpolation", ct.c_int), ("sc_interp", ct.c_int),
+                ("diverge_cycles", ct.c_int), ("diverge_growth", ct.c_double)]
 
 
 class Result(ct.Structure):
@@ -101,7 +102,7 @@ class Result(ct.Structure):
                 ("fine_fs_equiv", ct.c_double), ("updates", ct.c_double),
                 ("ms_total", ct.c_double), ("ms_setup", ct.c_double), ("ms_sweep", ct.c_double),
                 ("ms_rates", ct.c_double), ("ms_transfer", ct.c_double), ("sweep_launches", ct.c_longlong),
-                ("dirs_per_block", ct.c_int), ("sweep_kernel", ct.c_int)]
+                ("dirs_per_block", ct.c_int), ("sweep_kernel", ct.c_int), ("fallback", ct.c_int)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "formal_solutions"}
@@ -149,11 +150,12 @@ def load(path=None):
     lib.nlte_get_source_function.argtypes = [P, I64, P, ct.c_int]
     lib.nlte_emergent_intensity.argtypes = [P, I64, ct.c_int, P, P, ct.c_int]
     lib.nlte_history.argtypes = [P, I64, P, ct.c_int]
+    lib.nlte_job_stats.argtypes = [P, I64, ct.POINTER(Result)]
     lib.nlte_formal_solution.argtypes = [P, I64, ct.c_int, P, P, ct.c_int]
     lib.nlte_mali.argtypes = [P, I64, ct.c_int, ct.c_int, ct.POINTER(ct.c_double)]
     lib.nlte_rate_solve.argtypes = [P, I64, ct.c_int, P, P, ct.c_int, ct.POINTER(ct.c_double)]
     lib.nlte_residual.argtypes = [P, I64, ct.c_int, P, ct.c_int]
-    lib.nlte_vcycle.argtypes = [P, I64, ct.c_int, ct.c_int]
+    lib.nlte_vcycle.argtypes = [P, I64, ct.c_int, ct.c_int, ct.POINTER(ct.c_longlong)]
     lib.nlte_restrict.argtypes = [P, I64, ct.c_int, ct.c_int, P, P]
     lib.nlte_prolong.argtypes = [P, I64, ct.c_int, ct.c_int, P, P]
     lib.nlte_voigt.argtypes = [P, ct.c_int, ct.c_int, P, P, P]
@@ -199,6 +201,8 @@ class SolveParams:
     coarse_atmos: int = 0      # RESTRICT_FULL / _INJECT (or _HALF)
     interpolation: int = 0     # INTERP_TRILINEAR / _HERMITE
     sc_interp: int = 0         # SC_BILINEAR / SC_HERMITE
+    diverge_cycles: int = 0    # consecutive growing cycles that count as divergence (0: 3, < 0: off)
+    diverge_growth: float = 0.0   # growth factor of that test (0: 1)
     init_pops: np.ndarray | None = None
     top_I: np.ndarray | None = None
     _keep: list = field(default_factory=list, repr=False)
@@ -207,9 +211,9 @@ class SolveParams:
         p = Params()
         for k in ("method", "precision", "nlev", "nu_fmg", "nu0", "nu1", "nu2", "nu3", "init",
                   "max_iter", "fallback_mali", "dirs_per_block", "timing", "graph", "sweep_kernel",
-                  "restriction", "coarse_atmos", "interpolation", "sc_interp"):
+                  "restriction", "coarse_atmos", "interpolation", "sc_interp", "diverge_cycles"):
             setattr(p, k, int(getattr(self, k)))
-        for k in ("tol_C", "E_target", "repair_frac"):
+        for k in ("tol_C", "E_target", "repair_frac", "diverge_growth"):
             setattr(p, k, float(getattr(self, k)))
         self._keep = []
         if self.init_pops is not None:
@@ -369,6 +373,12 @@ class Job:
         rc = self.ctx.check(self.lib.nlte_job_run(self.ctx.h, self.id, ct.byref(r)))
         return rc, r
 
+    def stats(self):
+        """Counters and phase times accumulated so far (also over stage hooks)."""
+        r = Result()
+        self.ctx.check(self.lib.nlte_job_stats(self.ctx.h, self.id, ct.byref(r)))
+        return r
+
     def populations(self, level, shape):
         out = np.empty(shape, dtype=np.float64)
         self.ctx.check(self.lib.nlte_get_populations(self.ctx.h, self.id, level, _ptr(out), MEM_HOST))
@@ -426,7 +436,10 @@ class Job:
         return out
 
     def vcycle(self, level, first=False):
-        self.ctx.check(self.lib.nlte_vcycle(self.ctx.h, self.id, level, int(first)))
+        """One V-cycle on levels level..0; returns the job's repair count so far."""
+        rep = ct.c_longlong()
+        self.ctx.check(self.lib.nlte_vcycle(self.ctx.h, self.id, level, int(first), ct.byref(rep)))
+        return rep.value
 
     def restrict(self, level, src_ptr, dst_ptr, nq):
         self.ctx.check(self.lib.nlte_restrict(self.ctx.h, self.id, level, nq, ct.c_void_p(src_ptr),

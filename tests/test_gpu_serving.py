@@ -65,6 +65,10 @@ def test_each_result_is_the_same_alone_and_in_the_mix(nl):
         overlap = 0
         infos = {i: jobs[i].info() for i in order}
         for i in order:
+            inf = infos[i]
+            assert inf.state == nl.JOB_DONE
+            assert 0 < inf.t_submit <= inf.t_admit <= inf.t_done, (i, inf.t_submit, inf.t_admit, inf.t_done)
+        for i in order:
             for k in order:
                 if i < k and infos[i].t_admit < infos[k].t_done and infos[k].t_admit < infos[i].t_done:
                     overlap += 1
@@ -100,6 +104,7 @@ def test_over_budget_requests_wait_instead_of_failing(nl):
     for j in jobs:
         assert j.wait() >= 0
         infos.append(j.info())
+        assert 0 < infos[-1].t_submit <= infos[-1].t_admit <= infos[-1].t_done
         j.close()           # frees memory for the next queued job
     for a, b in zip(infos[:-1], infos[1:]):
         assert b.t_admit >= a.t_done - 1e-3, "a job was admitted beyond the budget"
@@ -116,4 +121,20 @@ def test_submit_rejects_what_can_never_fit(nl):
     with pytest.raises(nl.NlteError) as ei:
         ctx.submit(M, A, p)
     assert ei.value.code in (nl.E_INVALID, nl.E_OOM)
+    ctx.close()
+
+
+def test_submit_checks_parameters_as_job_create_does(nl):
+    import torch
+    atom, atm, p = requests(nl)[0]
+    ctx = nl.Context(0, torch.cuda.current_stream().cuda_stream)
+    M, A = ctx.atmos(atm), ctx.atom(atom)
+    bad = [dict(repair_frac=0.0), dict(repair_frac=1.0), dict(nu2=-1), dict(max_iter=-3), dict(init=7),
+           dict(diverge_growth=-1.0), dict(dirs_per_block=5)]
+    for kw in bad:
+        q = nl.SolveParams(**{**p.__dict__, **kw, "_keep": []})
+        for call in (lambda: ctx.submit(M, A, q), lambda: ctx.job(M, A, q)):
+            with pytest.raises(nl.NlteError) as ei:
+                call()
+            assert ei.value.code == nl.E_INVALID, kw
     ctx.close()
