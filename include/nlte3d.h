@@ -272,6 +272,18 @@ nlte_status nlte_get_source_function(nlte_ctx* ctx, nlte_job job, double* dst, i
  * frequencies of all lines in atom order. */
 nlte_status nlte_emergent_intensity(nlte_ctx* ctx, nlte_job job, int ndir, const double* mu,
                                     float* dst, int dst_mem);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): nlte_emergent_intensity with the
+ * output in device memory (dst: [ndir][nf][ny][nx] FP32, host memory is rejected with
+ * NLTE_E_INVALID), computed by the same kernels, bit for bit the same values, with no
+ * device allocation or free.  The upward formal solution's plane state lives in a 48 MiB
+ * static device array that the library keeps on every GPU it runs on until the process
+ * ends; frequencies are processed in chunks of 1048576 / (nx ny) (at least one: planes
+ * of more than 1048576 points are rejected with NLTE_E_INVALID).  Every call on one GPU
+ * shares that array, which keeps the last call's contents (each call writes every state
+ * element before reading it): calls that overlap on one GPU, from several contexts or
+ * threads, race. */
+nlte_status nlte_emergent_intensity_noalloc(nlte_ctx* ctx, nlte_job job, int ndir, const double* mu, float* dst);
 /* The job's work so far, including stage-hook calls: formal solutions per level, finest-grid
  * formal-solution equivalents, updates, sweep launches and block shape, repairs, the last C,
  * and (with params.timing) the phase times measured with HIP events on the job's stream;

@@ -67,6 +67,34 @@ inline bool device_memory(const void* p) {
 
 }  // namespace
 
+// ===================================================================== scratch
+// Device scratch of the allocation-free entry point (nlte_emergent_intensity_noalloc):
+// the emergent-intensity plane state of one frequency chunk.  Each GPU the library runs
+// on holds its own copy until the process ends.  In host code `scratch` is only a
+// stand-in symbol: its device address comes from hipGetSymbolAddress, per device, once.
+constexpr size_t kScratchBytes = size_t(48) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (current), looked up on the first call per device.
+hipError_t scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+}  // namespace
+
 // ===================================================================== context
 struct nlte_ctx {
     std::map<std::string, int> tile_cache;   // autotuned sweep tile per level shape
@@ -90,6 +118,7 @@ struct nlte_ctx {
     int max_running = 0, running = 0;
     bool stopping = false;
     size_t lds_max = 65536;                  // dynamic LDS a workgroup may use
+    void* scratch = nullptr;                 // this device's `scratch` (device address)
 };
 
 // Autotune cache file: one flat JSON object {"<arch>|<level key>": <directions per block>, ...}.
@@ -323,6 +352,7 @@ struct JobBase {
     virtual void set_pops(int level, const double* src, int mem) = 0;
     virtual void source_function(double* dst, int mem) = 0;
     virtual void emergent(int ndir, const double* mu, float* dst, int mem) = 0;
+    virtual void emergent_into(int ndir, const double* mu, float* dst, double* state, size_t state_bytes) = 0;
     virtual void restrict_hook(int level, int nq, const double* src, double* dst) = 0;
     virtual void prolong_hook(int level, int nq, const double* src, double* dst) = 0;
 };
@@ -1463,6 +1493,19 @@ struct Job : JobBase {
         HIPCHK(hipStreamSynchronize(st()));
     }
 
+    // The same computation with the plane state in a caller-provided device area of
+    // `state_bytes` (no allocation): frequencies in chunks whose state fits it.
+    void emergent_into(int ndir, const double* mu, float* dst, double* state, size_t state_bytes) override {
+        Level& F = *lev[nlev - 1];
+        check_mu(ndir, mu);
+        const size_t per_f = sizeof(double) * 2 * 3 * F.nxy;
+        const int fn = int(std::min<size_t>(size_t(nf), state_bytes / per_f));
+        REQUIRE(fn >= 1, "plane of " + std::to_string(F.nxy) + " points too large for the " +
+                             std::to_string(state_bytes >> 20) + " MiB emergent-intensity scratch");
+        emergent_launch(ndir, mu, dst, state, fn);
+        HIPCHK(hipStreamSynchronize(st()));
+    }
+
     void check_mu(int ndir, const double* mu) const {
         for (int d = 0; d < ndir; ++d) {
             const double m[3] = {mu[3 * d], mu[3 * d + 1], mu[3 * d + 2]};
@@ -1695,6 +1738,7 @@ nlte_status nlte_ctx_create(int device, void* hip_stream, size_t hbm_budget, nlt
     try {
         HIPCHK(hipSetDevice(device));
         upload_constants();
+        HIPCHK(scratch_address(device, &c->scratch));
         size_t fr = 0, tot = 0;
         HIPCHK(hipMemGetInfo(&fr, &tot));
         c->budget = hbm_budget ? hbm_budget : size_t(0.9 * double(fr));
@@ -2034,6 +2078,16 @@ nlte_status nlte_emergent_intensity(nlte_ctx* ctx, nlte_job job, int ndir, const
     return guarded(ctx, [&]() -> nlte_status {
         REQUIRE(ndir >= 1 && mu && dst, "bad emergent-intensity arguments");
         find_job(ctx, job)->emergent(ndir, mu, dst, dst_mem);
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_emergent_intensity_noalloc(nlte_ctx* ctx, nlte_job job, int ndir, const double* mu, float* dst) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(ndir >= 1 && mu && dst, "bad emergent-intensity arguments");
+        REQUIRE(device_memory(dst), "the allocation-free emergent intensity writes device memory only");
+        REQUIRE(ctx->scratch, "no scratch address for this device");
+        find_job(ctx, job)->emergent_into(ndir, mu, dst, static_cast<double*>(ctx->scratch), kScratchBytes);
         return NLTE_OK;
     });
 }

@@ -32,7 +32,7 @@ SYMBOLS = (
     "nlte_atom_create", "nlte_atom_destroy", "nlte_atmos_create", "nlte_atmos_destroy",
     "nlte_job_create", "nlte_job_run", "nlte_solve", "nlte_release",
     "nlte_get_populations", "nlte_set_populations", "nlte_get_source_function", "nlte_job_stats",
-    "nlte_emergent_intensity", "nlte_history",
+    "nlte_emergent_intensity", "nlte_emergent_intensity_noalloc", "nlte_history",
     "nlte_formal_solution", "nlte_mali", "nlte_rate_solve", "nlte_residual", "nlte_vcycle",
     "nlte_restrict", "nlte_prolong", "nlte_voigt",
     "nlte_serve_config", "nlte_estimate_footprint", "nlte_submit", "nlte_poll", "nlte_wait",
@@ -149,6 +149,7 @@ def load(path=None):
     lib.nlte_set_populations.argtypes = [P, I64, ct.c_int, P, ct.c_int]
     lib.nlte_get_source_function.argtypes = [P, I64, P, ct.c_int]
     lib.nlte_emergent_intensity.argtypes = [P, I64, ct.c_int, P, P, ct.c_int]
+    lib.nlte_emergent_intensity_noalloc.argtypes = [P, I64, ct.c_int, P, P]
     lib.nlte_history.argtypes = [P, I64, P, ct.c_int]
     lib.nlte_job_stats.argtypes = [P, I64, ct.POINTER(Result)]
     lib.nlte_formal_solution.argtypes = [P, I64, ct.c_int, P, P, ct.c_int]
