@@ -257,6 +257,20 @@ nlte_status nlte_solve(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom* 
                        const nlte_params* params, nlte_result* result, nlte_job* job);
 /* Free the job's device state. */
 nlte_status nlte_release(nlte_ctx* ctx, nlte_job job);
+/* Run several created jobs to their stop rules together.  Small grids underfill the GPU
+ * (Sect. 4.9: coarse grids cost more than their share), so every plane step of the jobs'
+ * formal solutions is one launch per class of frequency chunks over a device work list of
+ * (job, plane tile, line, direction group) items; the rest runs per job, on the context's
+ * stream.  The jobs go through the same method schedule in lockstep and each leaves the
+ * batch when its own stop rule, iteration cap or divergence guard ends its run.  Each job's
+ * populations and history are bit for bit those of nlte_job_run on it alone.  The jobs must
+ * share precision, method, number of grids and iteration counts (nu_fmg, nu0..nu3), sweep
+ * with the plane-step kernel and bilinear upwind interpolation in one frequency pass, and
+ * have no active continua and no graph replay (else NLTE_E_INVALID before any work); sizes,
+ * atoms and stop rules may differ.  results[j] (njobs entries) gets job j's result, with
+ * ms_sweep the batch's sweep time.  Returns the most severe warning of the jobs, or the
+ * error of the first job that failed (the other results stay valid). */
+nlte_status nlte_batch_run(nlte_ctx* ctx, int njobs, const nlte_job* jobs, nlte_result* results);
 
 /* ---------------------------------------------------------------- outputs */
 /* Populations of grid `level` (0 = coarsest, nlev-1 = finest) as [N][nz][ny][nx] FP64. */
@@ -358,12 +372,21 @@ typedef struct {
     int status;                /* final status of a finished job */
     double t_submit, t_admit, t_done;   /* seconds on a monotonic clock */
     size_t footprint;          /* device bytes reserved at admission */
+    int batch;                 /* serving batch the job ran in (nlte_serve_batching), 0 if alone */
     nlte_result result;        /* valid when state == NLTE_JOB_DONE */
     char error[256];           /* message of a failed job */
 } nlte_job_info_t;
 
 /* Start up to `max_running` worker threads (1..16): the number of concurrent solves. */
 nlte_status nlte_serve_config(nlte_ctx* ctx, int max_running);
+/* Continuous batching of served jobs (1..64; 1, the default, runs each job alone): a
+ * worker runs the job it admits together with queued jobs that can share its batch (as in
+ * nlte_batch_run: one precision, method, number of grids and iteration counts, plane-step
+ * bilinear sweeps, no active continua, no graphs), up to batch_max at a time, in queue
+ * order as their footprints fit the budget; between cycles (MALI: iterations) it admits
+ * more such jobs into the running batch, and each job is published as soon as its own run
+ * ends.  Results are bit for bit those of the same jobs alone. */
+nlte_status nlte_serve_batching(nlte_ctx* ctx, int batch_max);
 /* Device bytes a job with these inputs will allocate (its admission footprint). */
 nlte_status nlte_estimate_footprint(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom* atom,
                                     const nlte_params* params, size_t* bytes);

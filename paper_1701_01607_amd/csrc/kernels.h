@@ -466,6 +466,7 @@ struct SweepArgs {
     int add;             // 1: add this pass's sums to acc; 0: overwrite
     int nstate;          // plane-state slots (2, or 3 with the two-plane kernel), used by step % nstate
     int dslots;          // 1: one acc slot per direction (24) instead of one per block
+    int fc;              // frequency chunks per (direction, tile) of this level (work-list launches)
 };
 
 constexpr int kMaxSweepWaves = 12;
@@ -476,28 +477,25 @@ constexpr int kSweepWavesPerSimdF32 = 6;
 // HERM: upwind values by monotone bicubic Hermite interpolation on the 4x4 surrounding
 // points (x along the four rows, then y) instead of bilinear; one frequency chunk per
 // wave, three directions per block.
-template <typename R, int DB, bool HERM = false>
-__global__ __launch_bounds__((sizeof(R) == 4 && !HERM ? kMaxSweepWaves : DB) * 64)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !HERM ? kSweepWavesPerSimdF32 : 1))) void sweep_step_kernel(
-    SweepArgs<R> a, int s) {
+// XCD-aware order: the dispatcher deals consecutive blocks round-robin to the 8 XCDs;
+// when the block count divides by 8, XCD x takes the x-th contiguous eighth of the work
+// list, so the tiles that read each other's upwind rows (same line and directions) share
+// an L2.
+__device__ inline unsigned xcd_work(unsigned lin, unsigned nb) {
+    return (nb % 8u == 0u) ? (lin % 8u) * (nb / 8u) + lin / 8u : lin;
+}
+
+// The plane step of one block: tile bx (64 plane points) of line l for direction group
+// grp, with FC frequency chunks per direction; the block holds DB x FCW waves, and waves
+// of chunk c >= FC (when one launch serves levels with different FC) have no frequencies.
+template <typename R, int DB, bool HERM>
+__device__ __forceinline__ void sweep_step_body(const SweepArgs<R>& a, int s, unsigned bx, int l, int grp, int FC) {
     static_assert(DB == 3 || DB == 6 || DB == 12, "direction groups follow the fixed tree");
     static_assert(!HERM || DB == 3, "the Hermite variant runs three directions per block");
     constexpr int kW = 64;
     const int lane = int(threadIdx.x) & (kW - 1);
     const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kW);
-    const int FC = int(blockDim.x) / (kW * DB);
     const int w = wv % DB, c = wv / DB;
-    // XCD-aware order: the dispatcher deals consecutive blocks round-robin to the 8 XCDs;
-    // when the block count divides by 8, XCD x takes the x-th contiguous eighth of the
-    // (tile, line, group) work list, so the tiles that read each other's upwind rows
-    // (same line and directions) share an L2.
-    const unsigned T = gridDim.x;
-    const unsigned nb = T * gridDim.y * gridDim.z;
-    const unsigned lin = blockIdx.x + T * (blockIdx.y + gridDim.y * blockIdx.z);
-    const unsigned work = (nb % 8u == 0u) ? (lin % 8u) * (nb / 8u) + lin / 8u : lin;
-    const unsigned bx = work % T;
-    const int l = int((work / T) % gridDim.y);
-    const int grp = int(work / (T * gridDim.y));
     const int d = grp * DB + w;
     const int h = (grp * DB) / kNHemi;
     const AtomInfo& at = *a.atom;
@@ -663,6 +661,39 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !HERM ? kSweepWavesPerSimdF
         *aj = jt;
         *al = lt;
     }
+}
+
+
+template <typename R, int DB, bool HERM = false>
+__global__ __launch_bounds__((sizeof(R) == 4 && !HERM ? kMaxSweepWaves : DB) * 64)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 && !HERM ? kSweepWavesPerSimdF32 : 1))) void sweep_step_kernel(
+    SweepArgs<R> a, int s) {
+    const unsigned T = gridDim.x;
+    const unsigned work = xcd_work(blockIdx.x + T * (blockIdx.y + gridDim.y * blockIdx.z), T * gridDim.y * gridDim.z);
+    const unsigned bx = work % T;
+    const int l = int((work / T) % gridDim.y);
+    const int grp = int(work / (T * gridDim.y));
+    sweep_step_body<R, DB, HERM>(a, s, bx, l, grp, int(blockDim.x) / (64 * DB));
+}
+
+// One plane step for several grids in one launch (a work list): grid j (its level's sweep
+// arguments jobs[j]) owns blocks first[j] .. first[j+1]-1, (tile, line, direction group)
+// in the order of the one-grid launch.  Grids are sorted by plane count, most first, and
+// the launch covers the first nact of them (those with a plane at step s).  Every block
+// computes exactly what the one-grid launch computes for that tile, with that grid's own
+// frequency chunks, so the results do not depend on the other grids of the list.
+template <typename R, int DB>
+__global__ __launch_bounds__((sizeof(R) == 4 ? kMaxSweepWaves : DB) * 64)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? kSweepWavesPerSimdF32 : 1))) void sweep_list_kernel(
+    const SweepArgs<R>* __restrict__ jobs, const unsigned* __restrict__ first, int nact, int s) {
+    const unsigned work = xcd_work(blockIdx.x, gridDim.x);
+    int j = 0;
+    while (j + 1 < nact && first[j + 1] <= work) ++j;
+    const SweepArgs<R> a = jobs[j];
+    const unsigned local = work - first[j];
+    const unsigned T = (a.nxy + 63u) / 64u;
+    const unsigned L = unsigned(a.atom->nline);
+    sweep_step_body<R, DB, false>(a, s, local % T, int((local / T) % L), int(local / (T * L)), a.fc);
 }
 
 // Two plane steps per launch (steps s and s+1, s >= 1), FP32.  Workgroup: one direction,

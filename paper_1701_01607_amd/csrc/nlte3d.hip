@@ -116,6 +116,8 @@ struct nlte_ctx {
     std::deque<struct JobBase*> queue;       // lock order: mu before qmu; workers take qmu only
     std::vector<std::thread> workers;
     int max_running = 0, running = 0;
+    int batch_max = 1;                       // served jobs one worker may run as one batch
+    int next_batch = 1;                      // ids of serving batches
     bool stopping = false;
     size_t lds_max = 65536;                  // dynamic LDS a workgroup may use
     void* scratch = nullptr;                 // this device's `scratch` (device address)
@@ -332,9 +334,11 @@ struct JobBase {
     std::string error;
     double t_submit = 0, t_admit = 0, t_done = 0;
     size_t footprint = 0;
+    int batch_id = 0;                   // serving batch the job ran in (0: alone)
     const nlte_atmos* src_atmos = nullptr;
     const nlte_atom* src_atom = nullptr;
     hipStream_t own_stream = nullptr;
+    hipStream_t batch_stream = nullptr;   // set while the job runs in a batch: all its work goes there
     virtual void build_served() = 0;
     nlte_params params{};
     int N = 0, nline = 0, nf = 0, nlev = 1, prec = NLTE_FP64;
@@ -522,7 +526,7 @@ struct Job : JobBase {
         evs.clear();
     }
 
-    hipStream_t st() const { return own_stream ? own_stream : ctx->stream; }
+    hipStream_t st() const { return batch_stream ? batch_stream : own_stream ? own_stream : ctx->stream; }
 
     // all device buffers of a job come through here
     void dalloc(DevBuf& b, size_t bytes) { b.alloc(ctx, bytes, served); }
@@ -898,14 +902,18 @@ struct Job : JobBase {
         lev[k]->fs_valid = false;
     }
 
-    void formal_solution(int k) {
+    // Line coefficients k+, e of level k from its populations (Sect. 3).
+    void line_coef(int k) {
         Level& L = *lev[k];
-        const bool cont_forked = info.cont_active && !capturing;
-        if (cont_forked) cont_fork(k);
         line_coef_kernel<R><<<blocks_for(L.nvox, 256), 256, 0, st()>>>(atom_d.as<AtomInfo>(), L.n.as<double>(),
                                                                       L.lc.as<R>(), L.nvox);
         HIPCHK(hipGetLastError());
-        SweepArgs<R> a;
+    }
+
+    // Arguments of level k's plane-step sweep (frequency pass fields left to the caller).
+    SweepArgs<R> sweep_args(int k) {
+        Level& L = *lev[k];
+        SweepArgs<R> a{};
         a.atom = atom_d.as<AtomInfo>();
         a.nx = L.nx; a.ny = L.ny; a.nz = L.nz; a.nf = nf;
         a.nxy = unsigned(L.nxy); a.nvox = L.nvox;
@@ -918,6 +926,52 @@ struct Job : JobBase {
         a.acc = L.acc.as<R>();
         a.nstate = nstate;
         a.dslots = L.pair ? 1 : 0;
+        a.fc = L.fc;
+        return a;
+    }
+
+    // Bookkeeping after a formal solution of level k.
+    void fs_account(int k) {
+        Level& L = *lev[k];
+        L.fs_valid = true;
+        ++L.fs_count;
+        const Level& F = *lev[nlev - 1];
+        cost_units += double(L.nvox) / double(F.nvox);
+        updates += double(L.nvox) * kNDir * (nf + nfc);
+    }
+
+    // True where level k can share work-list sweep launches with other jobs: the plane-step
+    // sweep with bilinear upwind interpolation, one frequency pass, no active continua.
+    bool list_sweep_ok(int k) const {
+        const Level& L = *lev[k];
+        return !herm() && !L.march.F && !L.pair && Qpass >= maxfreq && !info.cont_active && !capturing;
+    }
+
+    // The job's part of a work-list formal solution of level k: its line coefficients and
+    // sweep arguments (all frequencies in one pass, overwrite the sums).
+    SweepArgs<R> list_prepare(int k) {
+        line_coef(k);
+        SweepArgs<R> a = sweep_args(k);
+        a.m0 = 0;
+        a.Q = Qpass;
+        a.add = 0;
+        return a;
+    }
+
+    // After the shared launches: db directions per block wrote kNDir/db slots per quantity.
+    void list_finish(int k, int db, long long launches) {
+        lev[k]->nslot = kNDir / db;
+        if (k == nlev - 1) fine_db = db;
+        sweep_launches += launches;
+        fs_account(k);
+    }
+
+    void formal_solution(int k) {
+        Level& L = *lev[k];
+        const bool cont_forked = info.cont_active && !capturing;
+        if (cont_forked) cont_fork(k);
+        line_coef(k);
+        SweepArgs<R> a = sweep_args(k);
         if (L.march.F) {
             march_launch(k);
         } else if (L.pair) {
@@ -970,11 +1024,7 @@ struct Job : JobBase {
                 cont_sweep(k, st());
             }
         }
-        L.fs_valid = true;
-        ++L.fs_count;
-        const Level& F = *lev[nlev - 1];
-        cost_units += double(L.nvox) / double(F.nvox);
-        updates += double(L.nvox) * kNDir * (nf + nfc);
+        fs_account(k);
     }
 
     // Formal solution at the continuum frequencies of level k (active continua), enqueued on
@@ -1104,16 +1154,39 @@ struct Job : JobBase {
         }
         mali(k, nu_pre);
         if (!L.fs_valid) formal_solution(k);                // the extra formal solution (Eq. 7)
-        apply_W(k, L.f.as<double>(), L.tmp.as<double>(), -1.0);   // r = f - W(n)
+        vc_restrict(k);
+        formal_solution(k - 1);                             // W*(R n), shared with the first coarse iteration
+        vc_coarse_rhs(k);
+        if (k - 1 == 0) mali(0, params.nu3);
+        else vcycle(k - 1, false);
+        vc_correct(k);
+        mali(k, params.nu2);
+    }
+
+    // V-cycle phases between the formal solutions and smoothing passes (Sect. 2.2).
+    // Residual r = f - W(n) at the accumulators of level k (Eq. 7); restriction of n and r.
+    void vc_restrict(int k) {
+        Level& L = *lev[k];
+        apply_W(k, L.f.as<double>(), L.tmp.as<double>(), -1.0);
         L.fs_valid = false;
         Level& C = *lev[k - 1];
         restrict_fields(k, N, L.n.as<double>(), C.n.as<double>());
         restrict_fields(k, N, L.tmp.as<double>(), C.tmp.as<double>());
-        formal_solution(k - 1);                             // W*(R n), shared with the first coarse iteration
-        apply_W(k - 1, C.tmp.as<double>(), C.f.as<double>(), 1.0);  // f = R r + W(R n)  (Eq. 10)
+    }
+
+    // Coarse right-hand side f = R r + W(R n) from the coarse accumulators (Eq. 10), and
+    // n_before = R n kept for the relative correction.
+    void vc_coarse_rhs(int k) {
+        Level& C = *lev[k - 1];
+        apply_W(k - 1, C.tmp.as<double>(), C.f.as<double>(), 1.0);
         dcopy(C.n.as<double>(), C.nb.as<double>(), size_t(N) * C.nvox);
-        if (k - 1 == 0) mali(0, params.nu3);
-        else vcycle(k - 1, false);
+    }
+
+    // Relative correction interpolated to level k with the negative-population repair
+    // (Eqs. 11-12, Sect. 4.10).
+    void vc_correct(int k) {
+        Level& L = *lev[k];
+        Level& C = *lev[k - 1];
         if (params.interpolation == NLTE_INTERP_HERMITE) {
             // e on the coarse grid first (C.tmp is free once the coarse right-hand side is formed)
             const size_t nc = size_t(N) * C.nvox;
@@ -1126,7 +1199,6 @@ struct Job : JobBase {
             params.repair_frac, repairs.as<unsigned long long>(), C.tmp.as<double>(), params.interpolation);
         HIPCHK(hipGetLastError());
         L.fs_valid = false;
-        mali(k, params.nu2);
     }
 
     void cycle_change_enqueue(int k) {
@@ -1232,36 +1304,98 @@ struct Job : JobBase {
         if (h) throw Error(NLTE_E_DIVERGED, "non-finite populations");
     }
 
+    // Progress of one run (nlte_job_run, or a batch in which the job takes part).
+    struct RunState {
+        std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+        int status = NLTE_W_NOT_CONVERGED;
+        int iters = 0, cycles = 0, grow_run = 0, fell_back = 0;
+        double rho = INFINITY, E = INFINITY;
+        bool first = true;   // the next cycle is the run's first (nu0)
+    };
+
+    int max_iterations() const { return params.max_iter > 0 ? params.max_iter : 1000; }
+
+    bool is_mali() const {
+        return params.method == NLTE_MALI || (nlev == 1 && params.method != NLTE_FAS && params.method != NLTE_FMG);
+    }
+
+    // Full multigrid from the coarsest grid (Sect. 2.3): nu_FMG iterations there, then per
+    // finer grid the interpolated full approximation (Eq. 14) and one V-cycle below the top.
+    void fmg_prologue() {
+        mali(0, params.nu_fmg);
+        for (int k = 1; k <= nlev - 1; ++k) fmg_lift(k);
+    }
+    void fmg_lift(int k) {
+        prolong_fields(k, N, lev[k - 1]->n.as<double>(), lev[k]->n.as<double>());
+        lev[k]->fs_valid = false;
+        if (k < nlev - 1) vcycle(k, false);
+    }
+
+    // After a MALI iteration whose C is in history: true when the run is over.
+    bool iteration_end(RunState& rs) {
+        ++rs.iters;
+        if (!std::isfinite(history.back())) throw Error(NLTE_E_DIVERGED, "non-finite MALI correction");
+        if (stop(history, rs.rho, rs.E)) { rs.status = NLTE_OK; return true; }
+        return rs.iters >= max_iterations();
+    }
+
+    // After a cycle whose C is in history: the divergence guard (with the fallback to MALI,
+    // run here to its end) and the stop rule.  True when the run is over.
+    bool cycle_end(RunState& rs) {
+        rs.first = false;
+        ++rs.cycles;
+        const char* why = diverging(rs.grow_run);
+        if (why) {
+            if (!params.fallback_mali) throw Error(NLTE_E_DIVERGED, why);
+            if (log_enabled()) log_line("cycle %d: %s; continuing with MALI", rs.cycles, why);
+            fallback_to_mali(rs);
+            return true;
+        }
+        const bool done = stop(history, rs.rho, rs.E);
+        if (log_enabled()) log_line("cycle %d: C = %.3e  rho = %.3e  E = %.3e", rs.cycles, history.back(), rs.rho, rs.E);
+        if (done) { rs.status = NLTE_OK; return true; }
+        return rs.cycles >= max_iterations();
+    }
+
+    // Populations from the start of the failing cycle, then plain MALI on the finest grid
+    // under the same stop rule, over its own corrections.
+    void fallback_to_mali(RunState& rs) {
+        Level& F = *lev[nlev - 1];
+        dcopy(nprev.as<double>(), F.n.as<double>(), size_t(N) * F.nvox);
+        F.fs_valid = false;
+        rs.fell_back = 1;
+        rs.status = NLTE_W_NOT_CONVERGED;
+        rs.rho = rs.E = INFINITY;
+        std::vector<double> hm;
+        for (int it = 0; it < max_iterations(); ++it) {
+            mali(nlev - 1, 1);
+            hm.push_back(read_scalar());
+            history.push_back(hm.back());
+            ++rs.iters;
+            if (!std::isfinite(hm.back())) throw Error(NLTE_E_DIVERGED, "non-finite MALI correction after the fallback");
+            if (stop(hm, rs.rho, rs.E)) { rs.status = NLTE_OK; break; }
+        }
+    }
+
     void run(nlte_result* out) override {
-        auto t0 = std::chrono::steady_clock::now();
+        RunState rs;
         const int top = nlev - 1;
         Level& F = *lev[top];
-        int status = NLTE_W_NOT_CONVERGED;
-        double rho = INFINITY, E = INFINITY;
-        int iters = 0, cycles = 0, grow_run = 0, fell_back = 0;
-        const int maxit = params.max_iter > 0 ? params.max_iter : 1000;
-        if (params.method == NLTE_MALI || nlev == 1 && params.method != NLTE_FAS && params.method != NLTE_FMG) {
+        const int maxit = max_iterations();
+        if (is_mali()) {
             for (int it = 0; it < maxit; ++it) {
                 if (params.graph && it > 0) replay([&]() { mali(top, 1); });
                 else mali(top, 1);
                 history.push_back(read_scalar());
-                ++iters;
-                if (!std::isfinite(history.back())) throw Error(NLTE_E_DIVERGED, "non-finite MALI correction");
-                if (stop(history, rho, E)) { status = NLTE_OK; break; }
+                if (iteration_end(rs)) break;
             }
         } else {
-            bool first = true;
             if (params.method == NLTE_FMG) {
-                mali(0, params.nu_fmg);
-                for (int k = 1; k <= top; ++k) {
-                    prolong_fields(k, N, lev[k - 1]->n.as<double>(), lev[k]->n.as<double>());
-                    lev[k]->fs_valid = false;
-                    if (k < top) vcycle(k, false);
-                }
-                first = false;
+                fmg_prologue();
+                rs.first = false;
             }
             for (int c = 0; c < maxit; ++c) {
-                if (params.graph && !first) {
+                if (params.graph && !rs.first) {
                     replay([&]() {
                         dcopy(F.n.as<double>(), nprev.as<double>(), size_t(N) * F.nvox);
                         vcycle(top, false);
@@ -1270,57 +1404,35 @@ struct Job : JobBase {
                     history.push_back(read_scalar());
                 } else {
                     dcopy(F.n.as<double>(), nprev.as<double>(), size_t(N) * F.nvox);
-                    vcycle(top, first);
+                    vcycle(top, rs.first);
                     history.push_back(cycle_change(top));
                 }
-                first = false;
-                ++cycles;
-                const char* why = diverging(grow_run);
-                if (why) {
-                    if (!params.fallback_mali) throw Error(NLTE_E_DIVERGED, why);
-                    if (log_enabled()) log_line("cycle %d: %s; continuing with MALI", cycles, why);
-                    // populations from the start of the failing cycle, then plain MALI on
-                    // the finest grid under the same stop rule, over its own corrections
-                    dcopy(nprev.as<double>(), F.n.as<double>(), size_t(N) * F.nvox);
-                    F.fs_valid = false;
-                    fell_back = 1;
-                    status = NLTE_W_NOT_CONVERGED;
-                    rho = E = INFINITY;
-                    std::vector<double> hm;
-                    for (int it = 0; it < maxit; ++it) {
-                        mali(top, 1);
-                        hm.push_back(read_scalar());
-                        history.push_back(hm.back());
-                        ++iters;
-                        if (!std::isfinite(hm.back()))
-                            throw Error(NLTE_E_DIVERGED, "non-finite MALI correction after the fallback");
-                        if (stop(hm, rho, E)) { status = NLTE_OK; break; }
-                    }
-                    break;
-                }
-                const bool done = stop(history, rho, E);
-                if (log_enabled()) log_line("cycle %d: C = %.3e  rho = %.3e  E = %.3e", cycles, history.back(), rho, E);
-                if (done) { status = NLTE_OK; break; }
+                if (cycle_end(rs)) break;
             }
         }
-        check_finite(top);
+        finish(rs, out);
+    }
+
+    // The result of a run: final checks and counters.
+    void finish(const RunState& rs, nlte_result* out) {
+        check_finite(nlev - 1);
         ev_resolve();
         unsigned long long rep = 0;
         HIPCHK(hipMemcpyAsync(&rep, repairs.p, sizeof(rep), hipMemcpyDeviceToHost, st()));
         HIPCHK(hipStreamSynchronize(st()));
         auto t1 = std::chrono::steady_clock::now();
         nlte_result r{};
-        r.status = status;
-        r.iterations = iters;
-        r.cycles = cycles;
+        r.status = rs.status;
+        r.iterations = rs.iters;
+        r.cycles = rs.cycles;
         r.C = history.empty() ? 0.0 : history.back();
-        r.rho = rho;
-        r.E_est = E;
+        r.rho = rs.rho;
+        r.E_est = rs.E;
         r.repairs = (long long)rep;
         for (int k = 0; k < nlev && k < 8; ++k) r.formal_solutions[k] = lev[k]->fs_count;
         r.fine_fs_equiv = cost_units;
         r.updates = updates;
-        r.ms_total = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        r.ms_total = std::chrono::duration<double, std::milli>(t1 - rs.t0).count();
         r.ms_setup = ms_setup;
         r.ms_sweep = ms_phase[EV_SWEEP];
         r.ms_rates = ms_phase[EV_RATES];
@@ -1329,7 +1441,7 @@ struct Job : JobBase {
         r.dirs_per_block = fine_db;
         r.sweep_kernel = lev[nlev - 1]->march.F ? NLTE_SWEEP_RESIDENT
                          : lev[nlev - 1]->pair ? NLTE_SWEEP_PAIR : NLTE_SWEEP_PLANE_STEP;
-        r.fallback = fell_back;
+        r.fallback = rs.fell_back;
         res = r;
         if (out) *out = r;
     }
@@ -1561,6 +1673,351 @@ struct Job : JobBase {
 };
 
 
+
+// ===================================================================== batches
+// Several jobs solved together (small grids underfill the device: Sect. 4.9 notes that
+// coarse grids cost more than their share).  Their formal solutions share work-list
+// launches - per plane step, one launch per class of frequency chunks over the tiles of
+// every job still sweeping (sweep_list_kernel) - and everything else runs per job, all
+// on one stream.  The jobs go through the same method schedule in lockstep and each
+// leaves the batch when its own stop rule (or cap, or guard) ends its run.  Every job
+// computes exactly what it computes alone: each keeps its frequency chunks, and the
+// direction sums do not depend on the block shape.
+template <typename R>
+struct Batch {
+    nlte_ctx* ctx = nullptr;
+    hipStream_t stream = nullptr;
+    std::vector<Job<R>*> jobs;
+    std::vector<typename Job<R>::RunState> rs;
+    std::vector<int> done;              // 1 once a job's run has ended
+    std::vector<std::string> error;     // message of a job that failed
+    std::vector<nlte_status> code;
+    // device work lists, cached per (level, job set): per frequency-chunk class the
+    // SweepArgs of its jobs, then their first blocks
+    struct Table {
+        DevBuf buf;
+        struct Cls { int fc = 0, n = 0; size_t args = 0, first = 0; std::vector<int> idx, nz; std::vector<unsigned> first_h; };
+        std::vector<Cls> cls;
+        int maxnz = 0;
+    };
+    std::map<std::pair<int, std::vector<int>>, std::unique_ptr<Table>> tables;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+    double ms_sweep = 0;
+    long long launches = 0;
+
+    ~Batch() {
+        for (auto& e : evs) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+    }
+
+    Table& table(int k, const std::vector<int>& set) {
+        auto key = std::make_pair(k, set);
+        auto it = tables.find(key);
+        if (it != tables.end()) return *it->second;
+        auto t = std::make_unique<Table>();
+        std::vector<SweepArgs<R>> args;
+        for (int fc : {1, 2, 4}) {
+            typename Table::Cls c;
+            c.fc = fc;
+            std::vector<std::pair<int, int>> order;   // (nz, job) for the jobs of this class
+            for (int j : set)
+                if (jobs[j]->lev[k]->fc == fc) order.push_back({jobs[j]->lev[k]->nz, j});
+            if (order.empty()) continue;
+            std::stable_sort(order.begin(), order.end(), [](auto& a, auto& b) { return a.first > b.first; });
+            const int db = kMaxSweepWaves / fc;
+            c.first_h.push_back(0);
+            for (auto& o : order) {
+                const Level& L = *jobs[o.second]->lev[k];
+                c.idx.push_back(o.second);
+                c.nz.push_back(L.nz);
+                c.first_h.push_back(c.first_h.back() + unsigned((L.nxy + 63) / 64) * unsigned(jobs[o.second]->nline) *
+                                                           unsigned(kNDir / db));
+                t->maxnz = std::max(t->maxnz, L.nz);
+            }
+            c.n = int(order.size());
+            t->cls.push_back(c);
+        }
+        // one device buffer: every class's SweepArgs array, then its first-block array
+        size_t bytes = 0;
+        for (auto& c : t->cls) {
+            c.args = bytes;
+            bytes += sizeof(SweepArgs<R>) * c.n;
+            bytes = (bytes + 255) & ~size_t(255);
+            c.first = bytes;
+            bytes += sizeof(unsigned) * (c.n + 1);
+            bytes = (bytes + 255) & ~size_t(255);
+        }
+        std::vector<unsigned char> host(bytes, 0);
+        for (auto& c : t->cls) {
+            for (int i = 0; i < c.n; ++i) {
+                SweepArgs<R> a = jobs[c.idx[i]]->sweep_args(k);
+                a.m0 = 0;
+                a.Q = jobs[c.idx[i]]->Qpass;
+                a.add = 0;
+                std::memcpy(host.data() + c.args + sizeof(SweepArgs<R>) * i, &a, sizeof(a));
+            }
+            std::memcpy(host.data() + c.first, c.first_h.data(), sizeof(unsigned) * (c.n + 1));
+        }
+        t->buf.alloc(ctx, bytes);
+        HIPCHK(hipMemcpyAsync(t->buf.p, host.data(), bytes, hipMemcpyHostToDevice, stream));
+        HIPCHK(hipStreamSynchronize(stream));   // host is a temporary
+        Table& ref = *t;
+        tables[key] = std::move(t);
+        return ref;
+    }
+
+    template <int DB>
+    void launch(const Table& t, const typename Table::Cls& c, int nact, int s) {
+        const auto* a = reinterpret_cast<const SweepArgs<R>*>(static_cast<const unsigned char*>(t.buf.p) + c.args);
+        const auto* f = reinterpret_cast<const unsigned*>(static_cast<const unsigned char*>(t.buf.p) + c.first);
+        sweep_list_kernel<R, DB><<<c.first_h[nact], unsigned(DB * c.fc * 64), 0, stream>>>(a, f, nact, s);
+    }
+
+    // One formal solution of level k for the jobs in `set`.
+    void formal_solution(int k, const std::vector<int>& set) {
+        if (set.empty()) return;
+        Table& t = table(k, set);
+        for (int j : set) jobs[j]->line_coef(k);
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        evs.push_back({e0, e1});
+        HIPCHK(hipEventRecord(e0, stream));
+        for (int s = 0; s < t.maxnz; ++s)
+            for (auto& c : t.cls) {
+                int nact = 0;
+                while (nact < c.n && c.nz[nact] > s) ++nact;
+                if (!nact) continue;
+                switch (c.fc) {
+                    case 1: launch<12>(t, c, nact, s); break;
+                    case 2: launch<6>(t, c, nact, s); break;
+                    default: launch<3>(t, c, nact, s); break;
+                }
+                ++launches;
+            }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipEventRecord(e1, stream));
+        for (auto& c : t.cls)
+            for (int i = 0; i < c.n; ++i) jobs[c.idx[i]]->list_finish(k, kMaxSweepWaves / c.fc, c.nz[i]);
+    }
+
+    // iters[j] MALI iterations on level k for the jobs in `set`.
+    void mali(int k, const std::vector<int>& set, const std::vector<int>& iters) {
+        int most = 0;
+        for (int j : set) most = std::max(most, iters[j]);
+        for (int it = 0; it < most; ++it) {
+            std::vector<int> part, need;
+            for (int j : set)
+                if (iters[j] > it) {
+                    part.push_back(j);
+                    if (!(it == 0 && jobs[j]->lev[k]->fs_valid)) need.push_back(j);
+                }
+            formal_solution(k, need);
+            for (int j : part) {
+                jobs[j]->rate_launch(k, 0, nullptr, nullptr, 0.0, true);
+                jobs[j]->lev[k]->fs_valid = false;
+            }
+        }
+    }
+
+    std::vector<int> all(int n) const { return std::vector<int>(jobs.size(), n); }
+
+    // One FAS V-cycle on levels k..0 for the jobs in `set` (the same steps as Job::vcycle).
+    void vcycle(int k, const std::vector<int>& set, const std::vector<char>& first) {
+        const nlte_params& p = jobs[set[0]]->params;
+        std::vector<int> pre(jobs.size(), 0);
+        for (int j : set) pre[j] = (first[j] && p.nu0 > 0) ? p.nu0 : p.nu1;
+        if (k == 0) {
+            mali(0, set, pre);
+            mali(0, set, all(p.nu2));
+            return;
+        }
+        mali(k, set, pre);
+        std::vector<int> need;
+        for (int j : set)
+            if (!jobs[j]->lev[k]->fs_valid) need.push_back(j);
+        formal_solution(k, need);
+        for (int j : set) jobs[j]->vc_restrict(k);
+        formal_solution(k - 1, set);
+        for (int j : set) jobs[j]->vc_coarse_rhs(k);
+        if (k - 1 == 0) mali(0, set, all(p.nu3));
+        else vcycle(k - 1, set, std::vector<char>(jobs.size(), 0));
+        for (int j : set) jobs[j]->vc_correct(k);
+        mali(k, set, all(p.nu2));
+    }
+
+    // Ends job j's run: result into out[j], or the error that stopped it.
+    template <typename F>
+    void guarded_step(int j, F&& fn) {
+        try {
+            fn();
+        } catch (const Error& e) {
+            done[j] = 1;
+            code[j] = e.code;
+            error[j] = e.what();
+        } catch (const std::exception& e) {
+            done[j] = 1;
+            code[j] = NLTE_E_INVALID;
+            error[j] = e.what();
+        }
+    }
+
+    // Adds jobs (built, with their initial populations) to the batch; returns their indices.
+    std::vector<int> add(const std::vector<Job<R>*>& js) {
+        std::vector<int> idx;
+        for (Job<R>* j : js) {
+            idx.push_back(int(jobs.size()));
+            jobs.push_back(j);
+            rs.emplace_back();
+            done.push_back(0);
+            error.emplace_back();
+            code.push_back(NLTE_OK);
+            out.emplace_back();
+        }
+        return idx;
+    }
+
+    std::vector<int> active() const {
+        std::vector<int> a;
+        for (size_t j = 0; j < jobs.size(); ++j)
+            if (!done[j]) a.push_back(int(j));
+        return a;
+    }
+
+    std::vector<nlte_result> out;   // per job, valid once done
+
+    // The start of newly added jobs' runs: full multigrid from their coarsest grids (FMG;
+    // Sect. 2.3), else nothing (FAS starts with a first cycle, MALI with an iteration).
+    void start(const std::vector<int>& set) {
+        if (set.empty()) return;
+        Job<R>& j0 = *jobs[set[0]];
+        if (j0.is_mali() || j0.params.method != NLTE_FMG) return;
+        const int top = j0.nlev - 1;
+        mali(0, set, all(j0.params.nu_fmg));
+        for (int k = 1; k <= top; ++k) {
+            for (int j : set) {
+                jobs[j]->prolong_fields(k, jobs[j]->N, jobs[j]->lev[k - 1]->n.template as<double>(),
+                                        jobs[j]->lev[k]->n.template as<double>());
+                jobs[j]->lev[k]->fs_valid = false;
+            }
+            if (k < top) vcycle(k, set, std::vector<char>(jobs.size(), 0));
+        }
+        for (int j : set) rs[j].first = false;
+    }
+
+    // One cycle (FAS/FMG) or MALI iteration of the jobs in `set`; returns the jobs whose
+    // runs ended with it (their results in out[], or their errors).
+    std::vector<int> step(const std::vector<int>& set) {
+        std::vector<int> ended;
+        if (set.empty()) return ended;
+        Job<R>& j0 = *jobs[set[0]];
+        const int top = j0.nlev - 1;
+        const bool m = j0.is_mali();
+        if (m) {
+            mali(top, set, all(1));
+        } else {
+            std::vector<char> first(jobs.size(), 0);
+            for (int j : set) {
+                Level& F = *jobs[j]->lev[top];
+                jobs[j]->dcopy(F.n.template as<double>(), jobs[j]->nprev.template as<double>(),
+                               size_t(jobs[j]->N) * F.nvox);
+                first[j] = rs[j].first ? 1 : 0;
+            }
+            vcycle(top, set, first);
+            for (int j : set) jobs[j]->cycle_change_enqueue(top);
+        }
+        for (int j : set) {
+            bool over = false;
+            guarded_step(j, [&]() {
+                jobs[j]->history.push_back(jobs[j]->read_scalar());
+                over = m ? jobs[j]->iteration_end(rs[j]) : jobs[j]->cycle_end(rs[j]);
+            });
+            if (done[j]) {            // failed
+                ended.push_back(j);
+                continue;
+            }
+            if (over) {
+                guarded_step(j, [&]() { jobs[j]->finish(rs[j], &out[j]); });
+                done[j] = 1;
+                ended.push_back(j);
+            }
+        }
+        // sweep time of the batch so far (events resolved as they complete)
+        HIPCHK(hipStreamSynchronize(stream));
+        for (auto& e : evs) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e.first, e.second));
+            ms_sweep += ms;
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        evs.clear();
+        for (int j : ended) {
+            if (code[j] < 0) {
+                out[j] = nlte_result{};
+                out[j].status = code[j];
+            }
+            out[j].ms_sweep = ms_sweep;   // the batch's sweep time so far, shared by its jobs
+            if (code[j] >= 0) jobs[j]->res = out[j];
+        }
+        return ended;
+    }
+
+    void run(nlte_result* res) {
+        start(active());
+        for (std::vector<int> a = active(); !a.empty(); a = active()) step(a);
+        for (size_t j = 0; j < jobs.size(); ++j) res[j] = out[j];
+    }
+};
+
+// True when job j can run in a batch with job a (built jobs).
+template <typename R>
+bool batchable(const Job<R>& a, const Job<R>& j) {
+    const nlte_params& p = j.params;
+    const nlte_params& q = a.params;
+    if (p.method != q.method || j.nlev != a.nlev || p.nu_fmg != q.nu_fmg || p.nu0 != q.nu0 || p.nu1 != q.nu1 ||
+        p.nu2 != q.nu2 || p.nu3 != q.nu3 || p.graph)
+        return false;
+    for (int k = 0; k < j.nlev; ++k)
+        if (!j.list_sweep_ok(k)) return false;
+    return true;
+}
+
+// Checks that jobs can share a batch, and runs it.
+template <typename R>
+nlte_status run_batch(nlte_ctx* ctx, const std::vector<JobBase*>& in, hipStream_t stream, nlte_result* out,
+                      std::string* first_error) {
+    Batch<R> b;
+    b.ctx = ctx;
+    b.stream = stream;
+    std::vector<Job<R>*> js;
+    for (JobBase* jb : in) {
+        auto* j = dynamic_cast<Job<R>*>(jb);
+        REQUIRE(j, "a batch takes jobs of one precision");
+        js.push_back(j);
+    }
+    for (Job<R>* j : js) REQUIRE(batchable(*js[0], *j), "a batch takes jobs of one method, number of grids and "
+                                                         "iteration counts, with plane-step bilinear sweeps in "
+                                                         "one frequency pass, no active continua and no graphs");
+    b.add(js);
+    for (Job<R>* j : b.jobs) j->batch_stream = stream;
+    try {
+        b.run(out);
+    } catch (...) {
+        for (Job<R>* j : b.jobs) j->batch_stream = nullptr;
+        throw;
+    }
+    for (Job<R>* j : b.jobs) j->batch_stream = nullptr;
+    nlte_status worst = NLTE_OK;
+    for (size_t j = 0; j < b.jobs.size(); ++j)
+        if (b.code[j] < 0) {
+            if (worst >= 0) {
+                worst = b.code[j];
+                if (first_error) *first_error = "job " + std::to_string(j) + ": " + b.error[j];
+            }
+        }
+    return worst;
+}
+
 // Device bytes a job will allocate (same formulas as Job::build; the emergent-intensity
 // state is included so that an admitted job never exceeds its reservation).
 size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom* atom, const nlte_params* p) {
@@ -1624,6 +2081,186 @@ double now_s() {
 // A job leaves the queue and becomes RUNNING in one step under qmu, and its final state
 // is published last, under qmu, after its times, status and accounting are written:
 // nlte_release, which waits under qmu for a final state, then owns the job alone.
+// With batching (nlte_serve_batching), the worker runs the head together with queued jobs
+// that can share its batch, and admits more of them between cycles as they arrive.
+
+// Takes job j out of the queue as RUNNING with its footprint reserved (qmu held).
+static void admit_locked(nlte_ctx* ctx, JobBase* j) {
+    ctx->reserved += j->footprint;
+    ctx->running++;
+    j->t_admit = now_s();
+    j->state = NLTE_JOB_RUNNING;
+}
+
+// Publishes a finished job (the worker does not touch it afterwards).
+static void publish(nlte_ctx* ctx, JobBase* j, int final_state, bool reservation_held) {
+    j->t_done = now_s();
+    {
+        std::lock_guard<std::mutex> lk(ctx->qmu);
+        ctx->running--;
+        if (reservation_held) ctx->reserved -= j->footprint;
+        j->state = final_state;
+    }
+    ctx->qcv.notify_all();
+}
+
+// Served jobs whose parameters let them share a batch (checked again once built).
+static bool batch_key_equal(const JobBase* a, const JobBase* b) {
+    const nlte_params& p = a->params;
+    const nlte_params& q = b->params;
+    auto nl = [](const nlte_params& x) { return x.method == NLTE_MALI ? 1 : std::max(1, x.nlev); };
+    return a->prec == b->prec && p.method == q.method && nl(p) == nl(q) && p.nu_fmg == q.nu_fmg &&
+           p.nu0 == q.nu0 && p.nu1 == q.nu1 && p.nu2 == q.nu2 && p.nu3 == q.nu3;
+}
+static bool batch_candidate(const JobBase* j) {
+    const nlte_params& p = j->params;
+    return !p.graph && p.sc_interp == NLTE_SC_BILINEAR &&
+           (p.sweep_kernel == NLTE_SWEEP_AUTO || p.sweep_kernel == NLTE_SWEEP_PLANE_STEP) &&
+           !j->src_atom->info.cont_active;
+}
+
+// Admits queued jobs that can join a batch keyed by `ref` and fit the budget, in queue
+// order, up to `room` of them (qmu taken here).
+static std::vector<JobBase*> admit_joiners(nlte_ctx* ctx, const JobBase* ref, int room) {
+    std::vector<JobBase*> out;
+    if (room <= 0) return out;
+    std::lock_guard<std::mutex> lk(ctx->qmu);
+    for (auto it = ctx->queue.begin(); it != ctx->queue.end() && int(out.size()) < room;) {
+        JobBase* q = *it;
+        if (batch_candidate(q) && batch_key_equal(ref, q) && ctx->used + ctx->reserved + q->footprint <= ctx->budget) {
+            it = ctx->queue.erase(it);
+            admit_locked(ctx, q);
+            out.push_back(q);
+        } else {
+            ++it;
+        }
+    }
+    return out;
+}
+
+static void run_alone(nlte_ctx* ctx, JobBase* j, bool reservation_held);
+
+// A serving batch: the head and every compatible job admitted with it or later.
+template <typename R>
+void serve_batch(nlte_ctx* ctx, JobBase* head) {
+    hipStream_t bs = nullptr;
+    if (hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        run_alone(ctx, head, true);
+        return;
+    }
+    int bid;
+    {
+        std::lock_guard<std::mutex> lk(ctx->qmu);
+        bid = ctx->next_batch++;
+    }
+    Batch<R> b;
+    b.ctx = ctx;
+    b.stream = bs;
+    std::vector<JobBase*> pending = {head};
+    for (JobBase* q : admit_joiners(ctx, head, ctx->batch_max - 1)) pending.push_back(q);
+    Job<R>* ref = nullptr;
+    for (;;) {
+        std::vector<Job<R>*> fresh;
+        for (JobBase* p : pending) {
+            auto* j = static_cast<Job<R>*>(p);
+            bool held = true;
+            try {
+                j->batch_stream = bs;
+                j->build_served();
+                {
+                    std::lock_guard<std::mutex> lk(ctx->qmu);
+                    ctx->reserved -= j->footprint;
+                    held = false;
+                }
+                if (ref && !batchable(*ref, *j)) {   // found unsuited once built: alone, here
+                    j->batch_stream = nullptr;
+                    run_alone(ctx, j, false);
+                    continue;
+                }
+                if (!ref) {
+                    if (!batchable(*j, *j)) {
+                        j->batch_stream = nullptr;
+                        run_alone(ctx, j, false);
+                        continue;
+                    }
+                    ref = j;
+                }
+                j->batch_id = bid;
+                fresh.push_back(j);
+            } catch (const Error& e) {
+                j->batch_stream = nullptr;
+                j->final_status = e.code;
+                j->error = e.what();
+                publish(ctx, j, NLTE_JOB_FAILED, held);
+            } catch (const std::exception& e) {
+                j->batch_stream = nullptr;
+                j->final_status = NLTE_E_INVALID;
+                j->error = e.what();
+                publish(ctx, j, NLTE_JOB_FAILED, held);
+            }
+        }
+        pending.clear();
+        std::vector<int> ended;
+        try {
+            b.start(b.add(fresh));
+            ended = b.step(b.active());
+        } catch (const std::exception& e) {   // the batch as a whole failed: fail its jobs
+            const nlte_status c = dynamic_cast<const Error*>(&e) ? static_cast<const Error&>(e).code : NLTE_E_DEVICE;
+            for (int j : b.active()) {
+                b.done[j] = 1;
+                b.code[j] = c;
+                b.error[j] = e.what();
+                ended.push_back(j);
+            }
+        }
+        for (int j : ended) {
+            Job<R>* job = b.jobs[j];
+            job->batch_stream = nullptr;
+            if (b.code[j] < 0) {
+                job->final_status = b.code[j];
+                job->error = b.error[j];
+                publish(ctx, job, NLTE_JOB_FAILED, false);
+            } else {
+                job->final_status = b.out[j].status;
+                publish(ctx, job, NLTE_JOB_DONE, false);
+            }
+        }
+        const int live = int(b.active().size());
+        if (ref && !ctx->stopping) pending = admit_joiners(ctx, ref, ctx->batch_max - live);
+        if (live == 0 && pending.empty()) break;
+    }
+    (void)hipStreamSynchronize(bs);
+    (void)hipStreamDestroy(bs);
+}
+
+static void run_alone(nlte_ctx* ctx, JobBase* j, bool reservation_held) {
+    int final_state = NLTE_JOB_DONE;
+    try {
+        if (!j->own_stream) HIPCHK(hipStreamCreateWithFlags(&j->own_stream, hipStreamNonBlocking));
+        if (reservation_held) {
+            j->build_served();
+            {   // the job's buffers now count in `used`; drop the reservation
+                std::lock_guard<std::mutex> lk(ctx->qmu);
+                ctx->reserved -= j->footprint;
+                reservation_held = false;
+            }
+        }
+        nlte_result r{};
+        j->run(&r);
+        j->final_status = r.status;
+    } catch (const Error& e) {
+        j->final_status = e.code;
+        j->error = e.what();
+        final_state = NLTE_JOB_FAILED;
+    } catch (const std::exception& e) {
+        j->final_status = NLTE_E_INVALID;
+        j->error = e.what();
+        final_state = NLTE_JOB_FAILED;
+    }
+    publish(ctx, j, final_state, reservation_held);
+}
+
 void serve_worker(nlte_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     for (;;) {
@@ -1638,47 +2275,20 @@ void serve_worker(nlte_ctx* ctx) {
                     const bool fits = ctx->used + ctx->reserved + head->footprint <= ctx->budget;
                     if (fits) {
                         ctx->queue.pop_front();
-                        ctx->reserved += head->footprint;
-                        ctx->running++;
+                        admit_locked(ctx, head);
                         j = head;
-                        j->t_admit = now_s();
-                        j->state = NLTE_JOB_RUNNING;
                         break;
                     }
                 }
                 ctx->qcv.wait(lk);
             }
         }
-        bool reservation_held = true;
-        int final_state = NLTE_JOB_DONE;
-        try {
-            HIPCHK(hipStreamCreateWithFlags(&j->own_stream, hipStreamNonBlocking));
-            j->build_served();
-            {   // the job's buffers now count in `used`; drop the reservation
-                std::lock_guard<std::mutex> lk(ctx->qmu);
-                ctx->reserved -= j->footprint;
-                reservation_held = false;
-            }
-            nlte_result r{};
-            j->run(&r);
-            j->final_status = r.status;
-        } catch (const Error& e) {
-            j->final_status = e.code;
-            j->error = e.what();
-            final_state = NLTE_JOB_FAILED;
-        } catch (const std::exception& e) {
-            j->final_status = NLTE_E_INVALID;
-            j->error = e.what();
-            final_state = NLTE_JOB_FAILED;
+        if (ctx->batch_max > 1 && batch_candidate(j)) {
+            if (j->prec == NLTE_FP64) serve_batch<double>(ctx, j);
+            else serve_batch<float>(ctx, j);
+        } else {
+            run_alone(ctx, j, true);
         }
-        j->t_done = now_s();
-        {
-            std::lock_guard<std::mutex> lk(ctx->qmu);
-            ctx->running--;
-            if (reservation_held) ctx->reserved -= j->footprint;
-            j->state = final_state;   // published last: the worker does not touch j again
-        }
-        ctx->qcv.notify_all();
     }
 }
 
@@ -2092,6 +2702,26 @@ nlte_status nlte_emergent_intensity_noalloc(nlte_ctx* ctx, nlte_job job, int ndi
     });
 }
 
+nlte_status nlte_batch_run(nlte_ctx* ctx, int njobs, const nlte_job* jobs, nlte_result* results) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(njobs >= 1 && jobs && results, "bad batch arguments");
+        std::vector<JobBase*> js;
+        for (int i = 0; i < njobs; ++i) {
+            JobBase* j = find_job(ctx, jobs[i]);
+            REQUIRE(!j->served, "served jobs are batched by the serving loop");
+            REQUIRE(std::find(js.begin(), js.end(), j) == js.end(), "a job appears twice in the batch");
+            js.push_back(j);
+        }
+        std::string msg;
+        const nlte_status s = js[0]->prec == NLTE_FP64 ? run_batch<double>(ctx, js, ctx->stream, results, &msg)
+                                                       : run_batch<float>(ctx, js, ctx->stream, results, &msg);
+        if (s < 0) throw Error(s, msg);
+        nlte_status warn = NLTE_OK;
+        for (int i = 0; i < njobs; ++i) warn = std::max(warn, results[i].status);
+        return warn;
+    });
+}
+
 nlte_status nlte_job_stats(nlte_ctx* ctx, nlte_job job, nlte_result* out) {
     return guarded(ctx, [&]() -> nlte_status {
         REQUIRE(out, "null result");
@@ -2194,6 +2824,15 @@ nlte_status nlte_voigt(nlte_ctx* ctx, int precision, int n, const double* a, con
 
 extern "C" {
 
+nlte_status nlte_serve_batching(nlte_ctx* ctx, int batch_max) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(batch_max >= 1 && batch_max <= 64, "batch_max must be 1..64");
+        std::lock_guard<std::mutex> lk(ctx->qmu);
+        ctx->batch_max = batch_max;
+        return NLTE_OK;
+    });
+}
+
 nlte_status nlte_serve_config(nlte_ctx* ctx, int max_running) {
     return guarded(ctx, [&]() -> nlte_status {
         REQUIRE(max_running >= 1 && max_running <= 16, "max_running must be 1..16");
@@ -2291,6 +2930,7 @@ nlte_status nlte_job_info(nlte_ctx* ctx, nlte_job job, nlte_job_info_t* info) {
         info->t_admit = j->t_admit;
         info->t_done = j->t_done;
         info->footprint = j->footprint;
+        info->batch = j->batch_id;
         if (j->state >= 2) info->result = j->res;
         std::snprintf(info->error, sizeof(info->error), "%s", j->error.c_str());
         return NLTE_OK;

@@ -30,12 +30,12 @@ INIT_ZERO_RAD, INIT_LTE, INIT_USER = 0, 1, 2
 SYMBOLS = (
     "nlte_ctx_create", "nlte_ctx_destroy", "nlte_last_error", "nlte_version",
     "nlte_atom_create", "nlte_atom_destroy", "nlte_atmos_create", "nlte_atmos_destroy",
-    "nlte_job_create", "nlte_job_run", "nlte_solve", "nlte_release",
+    "nlte_job_create", "nlte_job_run", "nlte_solve", "nlte_release", "nlte_batch_run",
     "nlte_get_populations", "nlte_set_populations", "nlte_get_source_function", "nlte_job_stats",
     "nlte_emergent_intensity", "nlte_emergent_intensity_noalloc", "nlte_history",
     "nlte_formal_solution", "nlte_mali", "nlte_rate_solve", "nlte_residual", "nlte_vcycle",
     "nlte_restrict", "nlte_prolong", "nlte_voigt",
-    "nlte_serve_config", "nlte_estimate_footprint", "nlte_submit", "nlte_poll", "nlte_wait",
+    "nlte_serve_config", "nlte_serve_batching", "nlte_estimate_footprint", "nlte_submit", "nlte_poll", "nlte_wait",
     "nlte_job_info",
 )
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
@@ -112,7 +112,8 @@ class Result(ct.Structure):
 
 class JobInfo(ct.Structure):
     _fields_ = [("state", ct.c_int), ("status", ct.c_int), ("t_submit", ct.c_double), ("t_admit", ct.c_double),
-                ("t_done", ct.c_double), ("footprint", ct.c_size_t), ("result", Result), ("error", ct.c_char * 256)]
+                ("t_done", ct.c_double), ("footprint", ct.c_size_t), ("batch", ct.c_int), ("result", Result),
+                ("error", ct.c_char * 256)]
 
 
 _lib = None
@@ -145,6 +146,7 @@ def load(path=None):
     lib.nlte_job_run.argtypes = [P, I64, ct.POINTER(Result)]
     lib.nlte_solve.argtypes = [P, P, P, ct.POINTER(Params), ct.POINTER(Result), ct.POINTER(I64)]
     lib.nlte_release.argtypes = [P, I64]
+    lib.nlte_batch_run.argtypes = [P, ct.c_int, ct.POINTER(I64), ct.POINTER(Result)]
     lib.nlte_get_populations.argtypes = [P, I64, ct.c_int, P, ct.c_int]
     lib.nlte_set_populations.argtypes = [P, I64, ct.c_int, P, ct.c_int]
     lib.nlte_get_source_function.argtypes = [P, I64, P, ct.c_int]
@@ -161,6 +163,7 @@ def load(path=None):
     lib.nlte_prolong.argtypes = [P, I64, ct.c_int, ct.c_int, P, P]
     lib.nlte_voigt.argtypes = [P, ct.c_int, ct.c_int, P, P, P]
     lib.nlte_serve_config.argtypes = [P, ct.c_int]
+    lib.nlte_serve_batching.argtypes = [P, ct.c_int]
     lib.nlte_estimate_footprint.argtypes = [P, P, P, ct.POINTER(Params), ct.POINTER(ct.c_size_t)]
     lib.nlte_submit.argtypes = [P, P, P, ct.POINTER(Params), ct.POINTER(I64)]
     lib.nlte_poll.argtypes = [P, I64, ct.POINTER(ct.c_int)]
@@ -301,9 +304,20 @@ class Context:
         self.check(self.lib.nlte_job_create(self.h, atmos_h.h, atom_h.h, ct.byref(p), ct.byref(j)))
         return Job(self, j.value, params)
 
+    def batch_run(self, jobs):
+        """Run created jobs to their stop rules together (shared work-list sweeps); returns
+        (status, [Result per job])."""
+        ids = (ct.c_int64 * len(jobs))(*[j.id for j in jobs])
+        res = (Result * len(jobs))()
+        rc = self.check(self.lib.nlte_batch_run(self.h, len(jobs), ids, res))
+        return rc, list(res)
+
     # ---- serving
     def serve_config(self, max_running):
         self.check(self.lib.nlte_serve_config(self.h, int(max_running)))
+
+    def serve_batching(self, batch_max):
+        self.check(self.lib.nlte_serve_batching(self.h, int(batch_max)))
 
     def footprint(self, atmos_h, atom_h, params: SolveParams):
         b = ct.c_size_t()

@@ -21,12 +21,17 @@ SIZES = [(32, 32, 33), (64, 64, 129), (128, 128, 129), (256, 256, 257)]
 SIZE_P = [0.4, 0.3, 0.2, 0.1]
 
 
-def make_request(j, rng, sizes, probs):
-    """(atom, atmosphere, params, tag) of request j: size drawn from `sizes`, two-level or
+def draw_request(j, rng, sizes, probs):
+    """(seed, size, two-level?) of request j: size drawn from `sizes`, two-level or
     six-level with equal odds, atmosphere seed 10000 + j."""
     size = sizes[rng.choice(len(sizes), p=probs)]
     two = rng.random() < 0.5
-    return build_request(10000 + j, size, two)
+    return 10000 + j, size, two
+
+
+def make_request(j, rng, sizes, probs):
+    """(atom, atmosphere, params, tag) of request j (see draw_request)."""
+    return build_request(*draw_request(j, rng, sizes, probs))
 
 
 def build_request(seed, size, two):
@@ -46,11 +51,15 @@ def build_request(seed, size, two):
     return atom, atm, p, ("two-level" if two else "six-level", (nx, ny, nz))
 
 
-def run_stream(ctx, requests, rate_hz, seed=1607005, max_running=4, log=None):
+def run_stream(ctx, requests, rate_hz, seed=1607005, max_running=4, log=None, batch_max=1):
     """Submit requests at Poisson arrival times while a collector thread releases each
-    solve as soon as it is done (freeing its memory for queued ones); returns records."""
+    solve as soon as it is done (freeing its memory for queued ones); returns records.
+    A request is an (atom, atmosphere, params, tag) tuple or a callable that builds one
+    (called while waiting for its arrival time, so the host's input generation overlaps
+    the stream)."""
     import threading
     ctx.serve_config(max_running)
+    ctx.serve_batching(batch_max)
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate_hz, size=len(requests))
     arrivals = np.cumsum(gaps) - gaps[0]
@@ -71,7 +80,8 @@ def run_stream(ctx, requests, rate_hz, seed=1607005, max_running=4, log=None):
                     rec = {"kind": tag[0], "grid": tag[1], "status": inf.status,
                            "latency_s": inf.t_done - inf.t_submit, "queue_s": inf.t_admit - inf.t_submit,
                            "run_s": inf.t_done - inf.t_admit, "footprint_mb": inf.footprint / 2 ** 20,
-                           "cycles": inf.result.cycles, "t_submit": inf.t_submit, "t_done": inf.t_done}
+                           "cycles": inf.result.cycles, "t_submit": inf.t_submit, "t_done": inf.t_done,
+                           "batch": inf.batch, "fallback": inf.result.fallback}
                     job.close()
                     with lock:
                         pending.remove(item)
@@ -83,7 +93,8 @@ def run_stream(ctx, requests, rate_hz, seed=1607005, max_running=4, log=None):
     th = threading.Thread(target=collect)
     th.start()
     t0 = time.monotonic()
-    for (atom, atm, p, tag), ta in zip(requests, arrivals):
+    for req, ta in zip(requests, arrivals):
+        atom, atm, p, tag = req() if callable(req) else req
         while time.monotonic() - t0 < ta:
             time.sleep(min(0.005, ta - (time.monotonic() - t0)))
         A, M = ctx.atom(atom), ctx.atmos(atm)
@@ -135,6 +146,8 @@ def main():
     ap.add_argument("--rate", type=float, default=0.0, help="arrivals per second (0: 80%% of measured capacity)")
     ap.add_argument("--max-running", type=int, default=4)
     ap.add_argument("--max-size", type=int, default=3, help="use the first N sizes of the mix")
+    ap.add_argument("--batch", type=int, default=1,
+                    help="continuous batching: compatible requests share batches of up to this many")
     args = ap.parse_args()
     import torch
     torch.cuda.init()
@@ -143,7 +156,8 @@ def main():
     probs = np.array(SIZE_P[: args.max_size])
     probs = probs / probs.sum()
     rng = np.random.default_rng(1607005)
-    reqs = [make_request(j, rng, sizes, probs) for j in range(args.requests)]
+    draws = [draw_request(j, rng, sizes, probs) for j in range(args.requests)]
+    reqs = [lambda d=d: build_request(*d) for d in draws]
     rate = args.rate
     if rate <= 0:
         # capacity: one solve of each size and atom alone (seeds outside the stream's), the
@@ -157,9 +171,9 @@ def main():
             print(json.dumps({"calibration": list(size), "run_s": by}), flush=True)
         rate = 0.8 / expected_run_time(times, probs)
     recs = run_stream(ctx, reqs, rate_hz=rate, max_running=args.max_running,
-                      log=lambda r: print(json.dumps(r), flush=True))
+                      log=lambda r: print(json.dumps(r), flush=True), batch_max=args.batch)
     out = summarize(recs)
-    out.update({"rate_hz": rate, "max_running": args.max_running, "sizes": sizes})
+    out.update({"rate_hz": rate, "max_running": args.max_running, "batch_max": args.batch, "sizes": sizes})
     print(json.dumps(out))
 
 

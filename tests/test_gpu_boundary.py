@@ -201,3 +201,28 @@ def test_diverging_cycles_fall_back_to_mali(nl, ctx, prec):
     ok = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(E_target=1e-3, max_iter=50, fallback_mali=1, **cyc))
     rc2, r2 = ok.run()
     assert rc2 == nl.OK and r2.fallback == 0
+
+
+def test_naturally_diverging_cycles_match_the_oracle_and_fall_back(nl, ctx):
+    # An 8x8x9 atmosphere whose 4x4x5 coarse grid makes the FAS cycles diverge (Sect. 4.10):
+    # the oracle's corrections C grow in cycles 8, 9 and 10 (above 1e-3), where the default
+    # guard stops the run; with the fallback the run ends as plain MALI.
+    from oracle.solver import solve_fas
+    atom = synth.caii_like_atom(9)
+    atm = synth.atmos_stratified(nx=8, ny=8, nz=9, dx=150 * synth.KM, seed=801)
+    atm["ntot"] = atm["ntot"] * 0.1
+    _, st, _ = solve_fas(atom, atm, OParams(nlev=2, nu1=2, nu2=2, nu3=8, E_target=None, tol_C=None), cycles=10)
+    C = np.array(st.C)
+    grew = [c > p and c > 1e-3 for p, c in zip(C[:-1], C[1:])]
+    assert grew[-3:] == [True, True, True] and not all(grew[-4:])   # fires at cycle 10, not before
+    cyc = dict(method=nl.FAS, precision=nl.FP64, nlev=2, nu1=2, nu2=2, nu3=8, E_target=1e-3, max_iter=300)
+    with pytest.raises(nl.NlteError) as ei:
+        ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(**cyc)).run()
+    assert ei.value.code == nl.E_DIVERGED
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(fallback_mali=1, **cyc))
+    rc, r = job.run()
+    h = job.history()
+    e = float(np.max(np.abs(h[:10] / C - 1)))
+    print(f"diverging cycles: gpu C {h[:10]}; oracle err {e:.2e}; then {r.iterations} MALI iterations")
+    assert r.cycles == 10 and r.fallback == 1 and rc == nl.OK
+    assert e < 1e-6

@@ -138,3 +138,59 @@ def test_submit_checks_parameters_as_job_create_does(nl):
                 call()
             assert ei.value.code == nl.E_INVALID, kw
     ctx.close()
+
+
+def test_continuous_batching_gives_each_result_alone_and_shares_batches(nl):
+    import torch
+    ctx = nl.Context(0, torch.cuda.current_stream().cuda_stream)
+    # six-level FAS requests of several sizes (batchable together), one two-level request
+    # with other iteration counts (its own batch) and one Hermite request (alone).  The
+    # second request's cycles diverge (its 4x4x5 coarse grid; Sect. 4.10), so every request
+    # asks for the fallback to MALI, which that one then takes inside its batch.
+    reqs = []
+    for j, (n, nz) in enumerate([(16, 17), (8, 9), (16, 33), (32, 17), (8, 17), (16, 17), (8, 9), (32, 9)]):
+        atm = synth.atmos_stratified(nx=n, ny=n, nz=nz, dx=150 * synth.KM, seed=800 + j)
+        atm["ntot"] = atm["ntot"] * 0.1
+        reqs.append((synth.caii_like_atom(9), atm,
+                     nl.SolveParams(method=nl.FAS, precision=nl.MIXED, nlev=2, nu1=2, nu2=2, nu3=8,
+                                    E_target=(1e-4, 1e-3)[j % 2], max_iter=200, fallback_mali=1)))
+    atm = synth.atmos_stratified(nx=16, ny=16, nz=17, dx=150 * synth.KM, seed=850)
+    atm["chi_c"] = None
+    reqs.append((synth.two_level_atom(1e-2), atm,
+                 nl.SolveParams(method=nl.FAS, precision=nl.MIXED, nlev=2, nu1=3, nu2=3, nu3=8, E_target=1e-4,
+                                max_iter=20)))
+    atm = synth.atmos_stratified(nx=16, ny=16, nz=17, dx=150 * synth.KM, seed=851)
+    atm["ntot"] = atm["ntot"] * 0.1
+    reqs.append((synth.caii_like_atom(9), atm,
+                 nl.SolveParams(method=nl.FAS, precision=nl.MIXED, nlev=2, nu1=2, nu2=2, nu3=8, E_target=1e-4,
+                                max_iter=20, sc_interp=nl.SC_HERMITE)))
+    alone = []
+    for atom, atm, p in reqs:
+        job = ctx.job(ctx.atmos(atm), ctx.atom(atom), p)
+        rc, r = job.run()
+        alone.append((job.history(), job.populations(1, (len(atom["levels"]), atm["nz"], atm["ny"], atm["nx"])),
+                      r.fallback))
+        job.close()
+    assert alone[1][2] == 1 and sum(a[2] for a in alone) == 1
+    ctx.serve_config(2)
+    ctx.serve_batching(6)
+    handles = [(ctx.atmos(atm), ctx.atom(atom)) for atom, atm, _ in reqs]
+    jobs = [ctx.submit(M, A, p) for (M, A), (_, _, p) in zip(handles, reqs)]
+    for j in jobs:
+        assert j.wait() >= 0
+    infos = [j.info() for j in jobs]
+    for i, (j, inf, (atom, atm, p)) in enumerate(zip(jobs, infos, reqs)):
+        assert inf.state == nl.JOB_DONE and 0 < inf.t_submit <= inf.t_admit <= inf.t_done, i
+        got = j.populations(1, (len(atom["levels"]), atm["nz"], atm["ny"], atm["nx"]))
+        assert np.array_equal(j.history(), alone[i][0]), f"request {i}: history differs"
+        assert np.array_equal(got, alone[i][1]), f"request {i}: populations differ"
+        assert inf.result.fallback == alone[i][2]
+    batches = [inf.batch for inf in infos]
+    print(f"batch ids {batches}")
+    six = batches[:8]
+    assert max(six.count(b) for b in set(six) if b) >= 2          # six-level requests shared a batch
+    assert batches[9] == 0                                          # Hermite: alone
+    assert batches[8] not in six                                    # other iteration counts: another batch
+    for j in jobs:
+        j.close()
+    ctx.close()
