@@ -47,8 +47,9 @@ STATE_BYTES_PER_UPDATE = {False: 16.0, True: 48.0}   # keyed by "FP64 sweep"
 # HBM bytes per update of the finest-grid sweep launches from FETCH_SIZE + WRITE_SIZE
 # counter runs of `bench.py --kernel-probe` (each scaled by the counter's reading for a
 # plain device copy of known size), keyed by (workload, directions per block).  Only for
-# the kernel as it was when the counters were taken.
-MEASURED_BYTES_PER_UPDATE = {}
+# the kernel as it was when the counters were taken: FETCH 13.07 B + WRITE 8.01 B on the
+# 504x504x497 grid (each upwind cell reaches HBM about 1.6 times for its four readers).
+MEASURED_BYTES_PER_UPDATE = {("caii6_504x504x497", 12): 21.08}
 VOXEL_BYTES_PER_GROUP = (11 + 2) * 4.0   # FP32; twice that in FP64
 
 # Algorithmic flops per update (FMA = 2; a reciprocal, exponential or cosine = 1) of the
@@ -230,6 +231,8 @@ def roofline(atom, atm, fp64, upd, ms_sweep, launches, dirs_per_block, workload)
     traffic = per_launch * measured / (avg_launch_us * 1e-6) / 1e9 if measured else None
     return {"bound": "alu", "achieved": achieved_alu, "peak": peak_alu, "unit": "TFLOP/s",
             "frac": achieved_alu / peak_alu, "traffic": traffic,
+            "traffic_unit": "GB/s (measured HBM bytes per launch / average launch time)",
+            "traffic_bytes_per_update": measured,
             "kernel": f"sweep_step_kernel<{'double' if fp64 else 'float'},{dirs_per_block}>",
             "avg_launch_us": avg_launch_us, "launches": launches, "updates_per_launch": per_launch,
             "flops_per_update": fl, "voigt_core_fraction": core_frac,

@@ -49,9 +49,7 @@ typedef int nlte_status;
 #define NLTE_FMG  2                 /* full multigrid followed by FAS V-cycles */
 
 #define NLTE_SWEEP_AUTO        0    /* sweep kernel chosen per grid level */
-#define NLTE_SWEEP_PLANE_STEP  1
-#define NLTE_SWEEP_RESIDENT    2
-#define NLTE_SWEEP_PAIR        3    /* two plane steps per launch (FP32) */
+#define NLTE_SWEEP_PLANE_STEP  1    /* plane state in HBM, one launch per plane step */
 
 #define NLTE_FP64  0                /* formal solution in FP64 */
 #define NLTE_MIXED 1                /* formal solution and accumulation in FP32; rate
@@ -163,17 +161,9 @@ typedef struct {
                                   HIP graph on a job-private stream and replay it; the first
                                   cycle (nu0) runs eagerly.  Phase timing is not available
                                   for replayed work. */
-    int sweep_kernel;          /* NLTE_SWEEP_AUTO, NLTE_SWEEP_PLANE_STEP (plane state in HBM,
-                                  one launch per plane), NLTE_SWEEP_PAIR (FP32: two plane
-                                  steps per launch, the intermediate plane kept in LDS per
-                                  16x16 tile; same results as PLANE_STEP bit for bit; needs
-                                  planes that fill the GPU with one frequency chunk per wave;
-                                  measured slower than PLANE_STEP)
-                                  or NLTE_SWEEP_RESIDENT (FP32 only: each workgroup marches a
-                                  few frequencies of one direction through all planes with
-                                  the plane in LDS; planes of up to 4096 points; measured
-                                  slower except on the smallest grids).  AUTO takes
-                                  PLANE_STEP. */
+    int sweep_kernel;          /* NLTE_SWEEP_AUTO or NLTE_SWEEP_PLANE_STEP (the same kernel:
+                                  plane state in HBM, one launch per plane step); other
+                                  values are rejected with NLTE_E_INVALID */
     int restriction;           /* NLTE_RESTRICT_*: restriction of populations and residuals
                                   in FAS/FMG (Sect. 4.4); the paper's choice, and the
                                   zero default, is full weighting */
@@ -213,7 +203,7 @@ typedef struct {
     double ms_total, ms_setup, ms_sweep, ms_rates, ms_transfer;   /* phase times need params.timing */
     long long sweep_launches;  /* plane-step sweep kernel launches (formal solutions x planes) */
     int dirs_per_block;        /* sweep block shape used on the finest level (3, 6 or 12; 0 if none ran) */
-    int sweep_kernel;          /* NLTE_SWEEP_PLANE_STEP, _PAIR or _RESIDENT on the finest level */
+    int sweep_kernel;          /* NLTE_SWEEP_PLANE_STEP */
     int fallback;              /* 1: FAS/FMG diverged and the run continued as plain MALI
                                   (params.fallback_mali); iterations counts those MALI
                                   iterations and cycles the cycles before it */
@@ -385,7 +375,11 @@ nlte_status nlte_serve_config(nlte_ctx* ctx, int max_running);
  * bilinear sweeps, no active continua, no graphs), up to batch_max at a time, in queue
  * order as their footprints fit the budget; between cycles (MALI: iterations) it admits
  * more such jobs into the running batch, and each job is published as soon as its own run
- * ends.  Results are bit for bit those of the same jobs alone. */
+ * ends.  Only grids too small to fill the device alone are batched: a batch's summed
+ * finest plane-step work (nx * ny * 24 directions * frequencies) stays within that of a
+ * 64 x 64 plane of 505 frequencies, and its jobs' finest formal solutions are within a
+ * factor 4 of its first job's (the batch advances them in lockstep).  Other jobs run alone
+ * on their own streams.  Results are bit for bit those of the same jobs alone. */
 nlte_status nlte_serve_batching(nlte_ctx* ctx, int batch_max);
 /* Device bytes a job with these inputs will allocate (its admission footprint). */
 nlte_status nlte_estimate_footprint(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom* atom,

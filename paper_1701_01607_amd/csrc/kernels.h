@@ -279,11 +279,6 @@ constexpr int kMaxSlots = 8;
 
 template <typename R>
 __device__ __host__ inline R tree_slots(const R* x, size_t stride, int nslot) {
-    if (nslot == kNDir) {   // one slot per direction: groups of three first
-        R g[8];
-        for (int q = 0; q < 8; ++q) g[q] = (x[(3 * q) * stride] + x[(3 * q + 1) * stride]) + x[(3 * q + 2) * stride];
-        return ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]));
-    }
     if (nslot == 2) return x[0] + x[stride];
     if (nslot == 4) return (x[0] + x[stride]) + (x[2 * stride] + x[3 * stride]);
     return ((x[0] + x[stride]) + (x[2 * stride] + x[3 * stride])) +
@@ -464,8 +459,7 @@ struct SweepArgs {
     R* acc;              // [2 qty][24/DB slots][nline][nvox]
     int m0, Q;           // this pass covers frequencies m0 .. m0+Q-1 of every line
     int add;             // 1: add this pass's sums to acc; 0: overwrite
-    int nstate;          // plane-state slots (2, or 3 with the two-plane kernel), used by step % nstate
-    int dslots;          // 1: one acc slot per direction (24) instead of one per block
+    int nstate;          // plane-state slots (2), used by step % nstate
     int fc;              // frequency chunks per (direction, tile) of this level (work-list launches)
 };
 
@@ -629,15 +623,6 @@ __device__ __forceinline__ void sweep_step_body(const SweepArgs<R>& a, int s, un
                 dl[q] += sl[(cc * DB + q) * kW + lane];
             }
         }
-        if (a.dslots) {
-            // one slot per direction; the readers apply the whole tree
-#pragma unroll
-            for (int q = 0; q < DB; ++q) {
-                a.acc[((size_t(0) * kNDir + grp * DB + q) * L + l) * nv + v] = dj[q];
-                a.acc[((size_t(1) * kNDir + grp * DB + q) * L + l) * nv + v] = dl[q];
-            }
-            return;
-        }
         // groups of three directions, then pairs of groups (the fixed tree)
         R gj[DB / 3], gl[DB / 3];
 #pragma unroll
@@ -694,290 +679,6 @@ __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? kSweepWavesPerSimdF32 : 1)))
     const unsigned T = (a.nxy + 63u) / 64u;
     const unsigned L = unsigned(a.atom->nline);
     sweep_step_body<R, DB, false>(a, s, local % T, int((local / T) % L), int(local / (T * L)), a.fc);
-}
-
-// Two plane steps per launch (steps s and s+1, s >= 1), FP32.  Workgroup: one direction,
-// one line, one 16x16 tile of the output plane (step s+1).  Its upwind corners lie in a
-// 17x17 region of the intermediate plane (step s), shifted by the integer part of the
-// step-(s+1) offset; the workgroup computes that region from the stored plane of step
-// s-1 into LDS (five waves, 289 cells), then the tile from LDS (four waves), and stores
-// only the tile.  The plane of step s never goes to HBM: per two planes the state moves
-// once each way instead of twice.  The regions overlap by one row and column; each
-// intermediate voxel is accumulated once, by the workgroup whose tile shifted by the
-// same offset (its "core") contains it - the shifted tiles partition the plane.  Sums go
-// to one slot per direction, cells and sums are computed by the same code as the
-// plane-step kernel (bit-identical results).  State slots rotate by step % 3.
-constexpr int kPairT = 16;
-constexpr int kPairR = kPairT + 1;
-constexpr int kPairThreads = 320;   // 5 waves: 289 region cells, then 256 tile points
-
-__device__ inline int wrap_idx(long long i, int n) {
-    long long r = i % n;
-    return int(r < 0 ? r + n : r);
-}
-
-template <typename R>
-__global__ __launch_bounds__(kPairThreads) void sweep_pair_kernel(SweepArgs<R> a, int s) {
-    const int tid = int(threadIdx.x);
-    const int ntx = (a.nx + kPairT - 1) / kPairT, nty = (a.ny + kPairT - 1) / kPairT;
-    const unsigned T = gridDim.x, nb = T * gridDim.y * gridDim.z;
-    const unsigned lin = blockIdx.x + T * (blockIdx.y + gridDim.y * blockIdx.z);
-    const unsigned work = (nb % 8u == 0u) ? (lin % 8u) * (nb / 8u) + lin / 8u : lin;
-    const int tile = int(work % T);
-    const int l = int((work / T) % gridDim.y);
-    const int d = int(work / (T * gridDim.y));
-    const int tx = tile % ntx, ty = tile / ntx;
-    (void)nty;
-    const int X0 = tx * kPairT, Y0 = ty * kPairT;
-    const AtomInfo& at = *a.atom;
-    const LineInfo& ln = at.line[l];
-    const int L = at.nline;
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const unsigned nxy = a.nxy;
-    const size_t nv = a.nvox;
-    const bool up = d < kNHemi;
-    const int k0 = up ? s - 1 : nz - s, k1 = up ? s : nz - 1 - s, k2 = up ? s + 1 : nz - 2 - s;
-    const double mux = c_mu[3 * d], muy = c_mu[3 * d + 1], muz = c_mu[3 * d + 2];
-    // offsets of the two steps
-    const double ds1 = fabs(a.z[k1] - a.z[k0]) / fabs(muz), ds2 = fabs(a.z[k2] - a.z[k1]) / fabs(muz);
-    const double sx1 = -ds1 * mux / a.dx, sy1 = -ds1 * muy / a.dy;
-    const double sx2 = -ds2 * mux / a.dx, sy2 = -ds2 * muy / a.dy;
-    const double fsx1 = floor(sx1), fsy1 = floor(sy1), fsx2 = floor(sx2), fsy2 = floor(sy2);
-    const R fx1 = R(sx1 - fsx1), fy1 = R(sy1 - fsy1), fx2 = R(sx2 - fsx2), fy2 = R(sy2 - fsy2);
-    const R a00 = (R(1) - fx1) * (R(1) - fy1), a01 = fx1 * (R(1) - fy1);
-    const R a10 = (R(1) - fx1) * fy1, a11 = fx1 * fy1;
-    const R b00 = (R(1) - fx2) * (R(1) - fy2), b01 = fx2 * (R(1) - fy2);
-    const R b10 = (R(1) - fx2) * fy2, b11 = fx2 * fy2;
-    const R rds1 = R(ds1), rds2 = R(ds2);
-    const long long ix1 = (long long)fsx1, iy1 = (long long)fsy1;
-    const long long ix2 = (long long)fsx2, iy2 = (long long)fsy2;
-    // this thread's intermediate cell (phase 1) and tile point (phase 2)
-    const bool p1 = tid < kPairR * kPairR;
-    const int ri = p1 ? tid % kPairR : 0, rj = p1 ? tid / kPairR : 0;
-    const int x1 = wrap_idx(X0 + ix2 + ri, nx), y1 = wrap_idx(Y0 + iy2 + rj, ny);
-    const bool core1 = p1 && ri < kPairT && rj < kPairT && X0 + ri < nx && Y0 + rj < ny;
-    const bool p2 = tid < kPairT * kPairT;
-    const int oi = tid % kPairT, oj = tid / kPairT;
-    const bool valid2 = p2 && X0 + oi < nx && Y0 + oj < ny;
-    const int x2 = valid2 ? X0 + oi : 0, y2 = valid2 ? Y0 + oj : 0;
-    const size_t v1 = size_t(k1) * nxy + size_t(y1) * nx + x1;
-    const size_t v2 = size_t(k2) * nxy + size_t(y2) * nx + x2;
-    const PointConst<R> c1 = point_const<R>(a.sc, a.sv, a.lc, L, l, nv, v1, mux, muy, muz);
-    const PointConst<R> c2 = point_const<R>(a.sc, a.sv, a.lc, L, l, nv, v2, mux, muy, muz);
-    // upwind corners of the intermediate cell on the stored plane (byte offsets in a row)
-    const unsigned csz = sizeof(Cell<R>);
-    const int xa = wrap_idx(x1 + ix1, nx), ya = wrap_idx(y1 + iy1, ny);
-    const int xb = xa + 1 == nx ? 0 : xa + 1, yb = ya + 1 == ny ? 0 : ya + 1;
-    const unsigned o00 = unsigned(ya * nx + xa) * csz, o01 = unsigned(ya * nx + xb) * csz;
-    const unsigned o10 = unsigned(yb * nx + xa) * csz, o11 = unsigned(yb * nx + xb) * csz;
-    const unsigned oc = unsigned(y2 * nx + x2) * csz;
-    const size_t vp = size_t(k0) * nxy;
-    const Corners<R> qc = corners_at<R>(a.sc, a.lc, L, l, nv, vp + size_t(ya) * nx + xa, vp + size_t(ya) * nx + xb,
-                                        vp + size_t(yb) * nx + xa, vp + size_t(yb) * nx + xb);
-    const int nf = ln.nfreq;                        // single pass: a.m0 = 0, a.Q >= nf
-    const size_t dstride = size_t(L) * a.Q * nxy;
-    const size_t slot_stride = size_t(kNDir) * dstride;
-    const size_t col = size_t(d) * dstride + size_t(l) * a.Q * nxy;
-    const unsigned rowb = nxy * csz;
-    const unsigned colb = unsigned(nf) * rowb;
-    const auto rprv = cell_rsrc(a.state + size_t((s - 1) % a.nstate) * slot_stride + col, colb);
-    const auto rout = cell_rsrc(a.state + size_t((s + 1) % a.nstate) * slot_stride + col, colb);
-    const bool gauss = ln.gauss != 0;
-    const const_as<R>* qf = (const const_as<R>*)(a.qf + ln.fstart);
-    const const_as<R>* wf = (const const_as<R>*)(a.wf + ln.fstart);
-    __shared__ R rI[2][kPairR * kPairR], rS[2][kPairR * kPairR], rC[2][kPairR * kPairR];
-    R j1 = R(0), l1 = R(0), j2 = R(0), l2 = R(0);
-    for (int m = 0; m < nf; ++m) {
-        const int b = m & 1;
-        const unsigned so = unsigned(m) * rowb;
-        if (p1) {
-            const Cell<R> e00 = cell_get<R>(rprv, o00, so), e01 = cell_get<R>(rprv, o01, so);
-            const Cell<R> e10 = cell_get<R>(rprv, o10, so), e11 = cell_get<R>(rprv, o11, so);
-            R Iu, Su, Cu;
-            upwind_values(qc, a00, a01, a10, a11, e00, e01, e10, e11, Iu, Su, Cu);
-            CellVals<R> cell;
-            sc_point(c1, R(qf[m]), R(wf[m]), gauss, c_dawg, Iu, Su, Cu, rds1, cell, j1, l1);
-            rI[b][tid] = cell.I;
-            rS[b][tid] = cell.S;
-            rC[b][tid] = cell.C;
-        }
-        __syncthreads();   // the region of frequency m is complete (buffer b is next written at m+2)
-        if (p2) {
-            const int q00 = oj * kPairR + oi, q01 = q00 + 1, q10 = q00 + kPairR, q11 = q10 + 1;
-            const R Iu = interp4(b00, b01, b10, b11, rI[b][q00], rI[b][q01], rI[b][q10], rI[b][q11]);
-            const R Su = interp4(b00, b01, b10, b11, rS[b][q00], rS[b][q01], rS[b][q10], rS[b][q11]);
-            const R Cu = interp4(b00, b01, b10, b11, rC[b][q00], rC[b][q01], rC[b][q10], rC[b][q11]);
-            CellVals<R> cell;
-            sc_point(c2, R(qf[m]), R(wf[m]), gauss, c_dawg, Iu, Su, Cu, rds2, cell, j2, l2);
-            if (valid2) cell_put(rout, oc, so, make_cell(cell));
-        }
-    }
-    if (core1) {
-        a.acc[((size_t(0) * kNDir + d) * L + l) * nv + v1] = j1;
-        a.acc[((size_t(1) * kNDir + d) * L + l) * nv + v1] = l1;
-    }
-    if (valid2) {
-        a.acc[((size_t(0) * kNDir + d) * L + l) * nv + v2] = j2;
-        a.acc[((size_t(1) * kNDir + d) * L + l) * nv + v2] = l2;
-    }
-}
-
-// Plane-resident sweep for planes that fit in LDS.  One workgroup takes one direction,
-// one line and a chunk of F consecutive frequencies and marches through every plane of
-// the sweep in one launch, keeping its F planes of cells (I, S and chi as separate arrays)
-// in F + 1 LDS buffers: the new plane of frequency f is written into the spare buffer,
-// which then becomes frequency f's plane while the old one becomes the spare.  At the
-// start of plane step s frequency f lives in buffer (f - s) mod (F + 1) and its new plane
-// goes to buffer (f - s - 1) mod (F + 1); one barrier per (plane, frequency) orders the
-// reads of a buffer before it is overwritten.  No cell leaves the chip.  Thread t owns
-// plane points t, t + T, ...  Per plane the block writes the partial sums of its F
-// frequencies for each point to its own slot (direction, chunk); the rate equations add
-// the slots in a fixed order (deterministic).  Same arithmetic per update as the
-// plane-step kernel.
-template <typename R>
-struct MarchArgs {
-    const AtomInfo* atom;
-    int nx, ny, nz;
-    unsigned nxy;
-    size_t nvox;
-    double dx, dy;
-    const double* z;
-    const R* sc;
-    const R* sv;
-    const R* lc;
-    const R* qf;
-    const R* wf;
-    const R* topI;       // [nf][nxy] or null
-    R* acc;              // [2 qty][24 * nchunk slots][nline][nvox]
-    int F, nchunk;       // frequencies per chunk, chunks per line (largest line)
-};
-
-template <int PPT>
-__global__ __launch_bounds__(1024) void march_kernel(MarchArgs<float> a) {
-    using R = float;
-    extern __shared__ float march_lds[];
-    const int c = blockIdx.x, l = blockIdx.y, d = blockIdx.z;
-    const AtomInfo& at = *a.atom;
-    const LineInfo& ln = at.line[l];
-    const int L = at.nline;
-    const int mb = c * a.F;
-    const int nfh = min(ln.nfreq - mb, a.F);   // frequencies of this chunk (uniform)
-    if (nfh <= 0) return;                        // the whole block leaves: no barrier reached
-    const unsigned nxy = a.nxy;
-    const size_t nv = a.nvox;
-    const unsigned T = blockDim.x;
-    const int NB = a.F + 1;                      // LDS buffers
-    const size_t bstride = size_t(3) * nxy;      // one buffer: I, S, chi planes
-    const double mux = c_mu[3 * d], muy = c_mu[3 * d + 1], muz = c_mu[3 * d + 2];
-    const bool up = d < kNHemi;
-    const bool gauss = ln.gauss != 0;
-    const const_as<R>* qf = (const const_as<R>*)(a.qf + ln.fstart + mb);
-    const const_as<R>* wf = (const const_as<R>*)(a.wf + ln.fstart + mb);
-    const size_t nslot = size_t(kNDir) * a.nchunk;
-    R* pj = a.acc + ((size_t(0) * nslot + size_t(d) * a.nchunk + c) * L + l) * nv;
-    R* pl = a.acc + ((size_t(1) * nslot + size_t(d) * a.nchunk + c) * L + l) * nv;
-    for (int s = 0; s < a.nz; ++s) {
-        const int k = up ? s : a.nz - 1 - s;
-        R fx = R(0), fy = R(0), rds = R(0);
-        double fsx = 0.0, fsy = 0.0;
-        if (s > 0) {
-            const int kp = up ? s - 1 : a.nz - s;
-            const double ds = fabs(a.z[k] - a.z[kp]) / fabs(muz);
-            const double sx = -ds * mux / a.dx, sy = -ds * muy / a.dy;
-            fsx = floor(sx);
-            fsy = floor(sy);
-            fx = R(sx - fsx);
-            fy = R(sy - fsy);
-            rds = R(ds);
-        }
-        const R w00 = (R(1) - fx) * (R(1) - fy), w01 = fx * (R(1) - fy);
-        const R w10 = (R(1) - fx) * fy, w11 = fx * fy;
-        R jp[PPT], lp[PPT];
-#pragma unroll
-        for (int i = 0; i < PPT; ++i) {
-            jp[i] = R(0);
-            lp[i] = R(0);
-        }
-        for (int f = 0; f < nfh; ++f) {
-            const int src = ((f - s) % NB + NB) % NB, dst = ((f - s - 1) % NB + NB) % NB;
-            const R* oI = march_lds + size_t(src) * bstride;
-            const R* oS = oI + nxy;
-            const R* oC = oI + 2 * size_t(nxy);
-            R* nI = march_lds + size_t(dst) * bstride;
-            R* nS = nI + nxy;
-            R* nC = nI + 2 * size_t(nxy);
-            const R qv = qf[f], wv = wf[f];
-#pragma unroll
-            for (int i = 0; i < PPT; ++i) {
-                const unsigned p = threadIdx.x + unsigned(i) * T;
-                const bool valid = p < nxy;
-                unsigned g = valid ? p : nxy - 1;
-                // an empty asm makes g opaque to the optimiser, so the point's constants are
-                // loaded here for every frequency (L1 hits) instead of being hoisted out of
-                // the frequency loop and held in registers for all points
-                asm volatile("" : "+v"(g));
-                const size_t v = size_t(k) * nxy + g;
-                const R chic = a.sc[(SC_CHIC * L + l) * nv + v];
-                const R etac = a.sc[(SC_ETAC * L + l) * nv + v];
-                const R adamp = a.sc[(SC_ADAMP * L + l) * nv + v];
-                const R pn = a.sc[(SC_PN * L + l) * nv + v];
-                const R pw = a.sc[(SC_PW * L + l) * nv + v] * R(1.0 / kNDir);
-                const R kpl = a.lc[size_t(l) * nv + v];
-                const R el = a.lc[size_t(L + l) * nv + v];
-                const R ivD = a.sv[SV_INVVD * nv + v];
-                const R vn = a.sv[SV_VX * nv + v] * R(mux) + a.sv[SV_VY * nv + v] * R(muy) +
-                             a.sv[SV_VZ * nv + v] * R(muz);
-                const R u = qv * ivD - vn;
-                const R H = profile_H<R>(adamp, u, gauss, c_dawg);
-                const R phi = H * pn;
-                const R chi = fma(kpl, phi, chic);
-                R rchi;
-                const R S = source_fn(chi, chic, etac, kpl, el, phi, rchi);
-                const R wphi = wv * H * pw;
-                R Inew;
-                if (s == 0) {
-                    Inew = up ? a.sc[(SC_B * L + l) * nv + v]
-                              : (a.topI ? a.topI[size_t(ln.fstart + mb + f) * nxy + g] : R(0));
-                    jp[i] += wphi * Inew;
-                    lp[i] += wphi;
-                } else {
-                    const int x = int(g % unsigned(a.nx)), y = int(g / unsigned(a.nx));
-                    int x0 = int((long long)(x + (long long)fsx) % a.nx); if (x0 < 0) x0 += a.nx;
-                    int y0 = int((long long)(y + (long long)fsy) % a.ny); if (y0 < 0) y0 += a.ny;
-                    const int x1 = (x0 + 1 == a.nx) ? 0 : x0 + 1;
-                    const int y1 = (y0 + 1 == a.ny) ? 0 : y0 + 1;
-                    const unsigned g00 = unsigned(y0 * a.nx + x0), g01 = unsigned(y0 * a.nx + x1);
-                    const unsigned g10 = unsigned(y1 * a.nx + x0), g11 = unsigned(y1 * a.nx + x1);
-                    const R Iu = fma(w00, oI[g00], fma(w01, oI[g01], fma(w10, oI[g10], w11 * oI[g11])));
-                    const R Su = fma(w00, oS[g00], fma(w01, oS[g01], fma(w10, oS[g10], w11 * oS[g11])));
-                    const R Cu = fma(w00, oC[g00], fma(w01, oC[g01], fma(w10, oC[g10], w11 * oC[g11])));
-                    const R dtau = R(0.5) * (Cu + chi) * rds;
-                    R ex, pu, po, omp;
-                    sc_coeffs(dtau, ex, pu, po, omp);
-                    const R Ith = fma(Iu, ex, pu * Su);
-                    Inew = fma(po, S, Ith);
-                    const R por = po * rchi;
-                    jp[i] = fma(wphi, fma(por, etac, Ith), jp[i]);
-                    lp[i] = fma(wphi, fma(por, chic, omp), lp[i]);
-                }
-                if (valid) {
-                    nI[p] = Inew;
-                    nS[p] = S;
-                    nC[p] = chi;
-                }
-            }
-            __syncthreads();   // frequency f's new plane is complete and its old one unread
-        }
-#pragma unroll
-        for (int i = 0; i < PPT; ++i) {
-            const unsigned p = threadIdx.x + unsigned(i) * T;
-            if (p < nxy) {
-                const size_t v = size_t(k) * nxy + p;
-                pj[v] = jp[i];
-                pl[v] = lp[i];
-            }
-        }
-    }
 }
 
 // Emergent intensity: one plane step of an upward sweep for a single direction (thread
@@ -1309,9 +1010,7 @@ struct RateArgs {
     size_t nvox;
     const double* pfix;   // [N*N][nvox]
     const R* acc;         // [2][nslot][nline][nvox]
-    int nslot;            // 2, 4 or 8 direction-group slots per quantity (plane-step sweep)
-    int march_F;          // > 0: plane-resident sweep, slots (direction, chunk of march_F)
-    int nchunk;           //      chunks per direction
+    int nslot;            // 2, 4 or 8 direction-group slots per quantity
     double* n;            // [N][nvox]  (mode 0/1: updated in place)
     const double* f;      // [N][nvox]
     const double* base;   // mode 2
@@ -1419,19 +1118,6 @@ __global__ __launch_bounds__(256) void rate_kernel(RateArgs<R> a) {
             if (a.mode == 1) {
                 Jeff[l] = 0.0;
                 omL[l] = 1.0;
-            } else if (a.march_F > 0) {
-                // directions in order, each over its chunks in order, in FP64
-                const int nch = (at.line[l].nfreq + a.march_F - 1) / a.march_F;
-                const size_t ns = size_t(kNDir) * a.nchunk;
-                double sj = 0.0, so = 0.0;
-                for (int d = 0; d < kNDir; ++d)
-                    for (int c = 0; c < nch; ++c) {
-                        const size_t slot = size_t(d) * a.nchunk + c;
-                        sj += double(a.acc[(slot * L + l) * nv + v]);
-                        so += double(a.acc[((ns + slot) * L + l) * nv + v]);
-                    }
-                Jeff[l] = sj;
-                omL[l] = so;
             } else {
                 const size_t ss = size_t(L) * nv;
                 Jeff[l] = double(tree_slots(a.acc + (size_t(0) * a.nslot * L + l) * nv + v, ss, a.nslot));

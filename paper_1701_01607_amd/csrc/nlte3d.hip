@@ -119,7 +119,6 @@ struct nlte_ctx {
     int batch_max = 1;                       // served jobs one worker may run as one batch
     int next_batch = 1;                      // ids of serving batches
     bool stopping = false;
-    size_t lds_max = 65536;                  // dynamic LDS a workgroup may use
     void* scratch = nullptr;                 // this device's `scratch` (device address)
 };
 
@@ -375,41 +374,7 @@ struct Level {
     int nslot = 2;   // direction-group slots in acc written by the last formal solution
     int fc = 1;      // frequency chunks per (direction, tile): fixed by the level shape
     int maxslot = 8; // direction-group slots allocated in acc (8 allows every block shape)
-    bool pair = false;   // two plane steps per launch (FP32, one frequency chunk, 24 acc slots)
-    struct MarchPlan {
-        int ppt = 0, threads = 0, F = 0, nchunk = 0;   // F = 0: plane-step sweep
-        size_t lds = 0;
-    } march;
 };
-
-// Plane-resident sweep plan for a plane of nxy points (FP32 only, on request): points
-// per thread, threads per workgroup, frequencies per chunk F (as many as the LDS holds, up
-// to 3 / 6 / 16 by points per thread, but no more than keep >= 1024 workgroups busy) and
-// chunks per line.  F = 0 where the plane does not fit, in FP64, or unless requested: on
-// the workloads measured it is slower than the plane-step sweep except on the smallest
-// grids (its partial sums per (direction, chunk) and its four waves per SIMD cost more
-// than the plane state's HBM round trip saves).
-template <typename P>
-inline void march_plan(P& m, size_t nxy, int nline, int maxfreq, size_t rbytes, size_t lds_max, int mode) {
-    m.ppt = m.threads = m.F = m.nchunk = 0;
-    m.lds = 0;
-    if (rbytes != 4 || mode != NLTE_SWEEP_RESIDENT || maxfreq < 1) return;
-    int ppt, fmax;
-    if (nxy <= 1024) { ppt = 1; fmax = 16; }
-    else if (nxy <= 2048) { ppt = 2; fmax = 6; }
-    else if (nxy <= 4096) { ppt = 4; fmax = 3; }
-    else return;
-    const size_t per_f = 3 * sizeof(float) * nxy;   // one LDS buffer; F frequencies need F + 1
-    int F = std::min(fmax, int(lds_max / per_f) - 1);
-    const int fpar = std::max(1, int(double(kNDir) * nline * maxfreq / 1024.0));
-    F = std::min(std::min(F, maxfreq), fpar);
-    if (F < 1) return;
-    m.ppt = ppt;
-    m.F = F;
-    m.threads = ppt == 1 ? int((nxy + 63) / 64 * 64) : 1024;
-    m.nchunk = (maxfreq + F - 1) / F;
-    m.lds = per_f * size_t(F + 1);
-}
 
 // Frequency chunks per (direction, tile) wave group of the plane-step sweep.  With one
 // wave per (direction, 64 plane points, line) a launch on a small plane holds less than
@@ -424,17 +389,6 @@ inline int freq_chunks_for(size_t nxy, int nline, size_t rbytes) {
     int fc = 1;
     while (fc < 4 && sweep_waves(nxy, nline) * fc < kSweepWaveTarget) fc *= 2;
     return fc;
-}
-
-// Two plane steps per launch, on request, where it applies: FP32, nz >= 3, planes that
-// fill the GPU with one frequency chunk per wave (the level then sweeps with one chunk
-// per wave throughout) and 24 accumulator slots under 8 GiB.  It moves half the plane
-// state but measured slower than the plane-step sweep (its barrier per frequency and
-// five-wave blocks hide less latency), so it is not the default.
-inline bool pair_ok(size_t nxy, int nz, int nline, size_t rbytes, int mode) {
-    if (rbytes != 4 || nz < 3 || sweep_waves(nxy, nline) < 4096.0) return false;
-    if (mode != NLTE_SWEEP_PAIR) return false;
-    return double(2 * kNDir) * nline * double(nxy) * nz * double(rbytes) <= 8.0 * 1073741824.0;
 }
 
 // Accumulator slots for a level: every block shape (down to 3 directions, 8 slots) on
@@ -454,7 +408,7 @@ struct Job : JobBase {
     int nfc = 0;
     AtomInfo info{};
     int DB = 0;   // directions per sweep block (0: autotuned per level)
-    int nstate = 2;   // plane-state slots (3 when a level sweeps two planes per launch)
+    int nstate = 2;   // plane-state slots: the plane being swept and its upwind plane
     int fine_db = 0;   // block shape of the last finest-level formal solution
     std::vector<double> hz_top;
     double updates_per_fs_fine = 0;
@@ -611,11 +565,7 @@ struct Job : JobBase {
             }
             L.nxy = size_t(L.nx) * L.ny;
             L.nvox = L.nxy * L.nz;
-            L.pair = !herm() && pair_eligible(L, p->sweep_kernel);
-            L.fc = (herm() || L.pair) ? 1 : freq_chunks(L);
-            if (p->sweep_kernel == NLTE_SWEEP_PAIR)
-                REQUIRE(L.pair, "the two-plane sweep needs FP32, nz >= 3 and planes large enough for one "
-                                "frequency chunk per wave");
+            L.fc = herm() ? 1 : freq_chunks(L);
             dalloc(L.dz, sizeof(double) * L.nz);
             HIPCHK(hipMemcpyAsync(L.dz.p, L.z.data(), sizeof(double) * L.nz, hipMemcpyHostToDevice, st()));
             dalloc(L.prim, sizeof(double) * nprim * L.nvox);
@@ -641,11 +591,7 @@ struct Job : JobBase {
             if (herm())
                 REQUIRE(L.maxslot >= kMaxSlots, "Hermite upwind interpolation needs 8 accumulator slots per "
                                                 "quantity (at most 4 GiB of them per level)");
-            march_plan(L.march, L.nxy, nline, maxfreq, sizeof(R), ctx->lds_max, p->sweep_kernel);
-            if (p->sweep_kernel == NLTE_SWEEP_RESIDENT)
-                REQUIRE(L.march.F > 0, "the plane-resident sweep needs FP32 and planes of at most 4096 points");
-            const size_t slots = L.march.F ? size_t(kNDir) * L.march.nchunk : (L.pair ? size_t(kNDir) : size_t(L.maxslot));
-            dalloc(L.acc, sizeof(R) * 2 * slots * nline * L.nvox);
+            dalloc(L.acc, sizeof(R) * 2 * size_t(L.maxslot) * nline * L.nvox);
             dalloc(L.lc, sizeof(R) * 2 * nline * L.nvox);
             dalloc(L.partial, sizeof(double) * std::max<size_t>(blocks_for(L.nvox, 256), 1024));
             SetupArgs<R> sa;
@@ -694,23 +640,11 @@ struct Job : JobBase {
         const double cap_bytes = envb ? std::atof(envb) * 1048576.0 : 0.25 * double(ctx->budget);
         // a pass's (direction, line) column is addressed by 32-bit buffer offsets
         const double colmax = 4294967295.0 / (double(sizeof(Cell<R>)) * double(Fz.nxy));
-        bool any_pair = false;
-        for (auto& Lp : lev) any_pair = any_pair || Lp->pair;
-        nstate = any_pair ? 3 : 2;
-        for (;;) {
-            const double per_q = double(sizeof(Cell<R>)) * nstate * kNDir * nline * Fz.nxy;
-            Qpass = std::max(1, std::min(maxfreq, int(cap_bytes / per_q)));
-            Qpass = std::max(1, std::min(Qpass, int(colmax)));
-            if (nstate == 2 || Qpass >= maxfreq) break;
-            // the two-plane sweep needs every frequency in one pass: fall back
-            REQUIRE(p->sweep_kernel != NLTE_SWEEP_PAIR, "the two-plane sweep needs the plane state of all "
-                                                        "frequencies in one pass");
-            for (auto& Lp : lev) Lp->pair = false;
-            nstate = 2;
-        }
-        // the plane state is needed only where a level sweeps plane by plane (planes shrink
-        // towards the coarse levels, so the finest level decides)
-        if (!Fz.march.F) dalloc(state, sizeof(Cell<R>) * nstate * kNDir * size_t(nline) * Qpass * Fz.nxy);
+        const double per_q = double(sizeof(Cell<R>)) * nstate * kNDir * nline * Fz.nxy;
+        Qpass = std::max(1, std::min(maxfreq, int(cap_bytes / per_q)));
+        Qpass = std::max(1, std::min(Qpass, int(colmax)));
+        // planes shrink towards the coarse levels, so the finest level sizes the plane state
+        dalloc(state, sizeof(Cell<R>) * nstate * kNDir * size_t(nline) * Qpass * Fz.nxy);
         dalloc(nprev, sizeof(double) * N * Fz.nvox);
         if (p->top_I) {
             dalloc(topI, sizeof(R) * size_t(nf) * Fz.nxy);
@@ -737,14 +671,8 @@ struct Job : JobBase {
         if (log_enabled())
             for (int k = 0; k < nlev; ++k) {
                 const Level& L = *lev[k];
-                if (L.march.F)
-                    log_line("level %d (%dx%dx%d): plane-resident sweep, %d frequencies x %d chunks, %d threads, %zu B LDS",
-                             k, L.nx, L.ny, L.nz, L.march.F, L.march.nchunk, L.march.threads, L.march.lds);
-                else if (L.pair)
-                    log_line("level %d (%dx%dx%d): two-plane sweep (16x16 tiles)", k, L.nx, L.ny, L.nz);
-                else
-                    log_line("level %d (%dx%dx%d): plane-step sweep, %d frequency chunks per wave group", k, L.nx,
-                             L.ny, L.nz, L.fc);
+                log_line("level %d (%dx%dx%d): plane-step sweep, %d frequency chunks per wave group", k, L.nx,
+                         L.ny, L.nz, L.fc);
             }
         choose_tile();
         ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
@@ -765,11 +693,6 @@ struct Job : JobBase {
 
     static dim3 sweep_grid(const Level& L, int nline, int db) {
         return dim3(blocks_for(L.nxy, 64), nline, kNDir / db);
-    }
-
-    // Two plane steps per launch when requested and the level qualifies (see pair_ok).
-    bool pair_eligible(const Level& L, int mode) const {
-        return pair_ok(L.nxy, L.nz, nline, sizeof(R), mode);
     }
 
     // Frequency chunks per wave group of this level (freq_chunks_for).
@@ -870,8 +793,6 @@ struct Job : JobBase {
         ra.pfix = L.pfix.as<double>();
         ra.acc = L.acc.as<R>();
         ra.nslot = given ? 2 : L.nslot;
-        ra.march_F = given ? 0 : L.march.F;
-        ra.nchunk = L.march.nchunk;
         ra.n = L.n.as<double>();
         ra.f = L.f.as<double>();
         ra.base = base;
@@ -925,7 +846,6 @@ struct Job : JobBase {
         a.state = state.as<Cell<R>>();
         a.acc = L.acc.as<R>();
         a.nstate = nstate;
-        a.dslots = L.pair ? 1 : 0;
         a.fc = L.fc;
         return a;
     }
@@ -944,7 +864,7 @@ struct Job : JobBase {
     // sweep with bilinear upwind interpolation, one frequency pass, no active continua.
     bool list_sweep_ok(int k) const {
         const Level& L = *lev[k];
-        return !herm() && !L.march.F && !L.pair && Qpass >= maxfreq && !info.cont_active && !capturing;
+        return !herm() && Qpass >= maxfreq && !info.cont_active && !capturing;
     }
 
     // The job's part of a work-list formal solution of level k: its line coefficients and
@@ -972,49 +892,20 @@ struct Job : JobBase {
         if (cont_forked) cont_fork(k);
         line_coef(k);
         SweepArgs<R> a = sweep_args(k);
-        if (L.march.F) {
-            march_launch(k);
-        } else if (L.pair) {
-            // boundary step and, for an even number of planes, the last step plane by
-            // plane; every other pair of steps in one launch
-            a.m0 = 0;
+        const int db = tile_for(k, a);
+        if (k == nlev - 1) fine_db = db;
+        const dim3 grid = sweep_grid(L, nline, db);
+        ev_begin(EV_SWEEP);
+        for (int m0 = 0; m0 < maxfreq; m0 += Qpass) {
+            a.m0 = m0;
             a.Q = Qpass;
-            a.add = 0;
-            const int db = tile_for(k, a);
-            if (k == nlev - 1) fine_db = db;
-            const dim3 grid = sweep_grid(L, nline, db);
-            const dim3 pgrid(unsigned(((L.nx + kPairT - 1) / kPairT) * ((L.ny + kPairT - 1) / kPairT)),
-                             unsigned(nline), unsigned(kNDir));
-            ev_begin(EV_SWEEP);
-            launch_step(a, grid, db, L.fc, 0);
-            int s = 1;
-            if constexpr (sizeof(R) == 4) {
-                for (; s + 1 < L.nz; s += 2) {
-                    sweep_pair_kernel<float><<<pgrid, kPairThreads, 0, st()>>>(a, s);
-                    ++sweep_launches;
-                }
-            }
-            for (; s < L.nz; ++s) launch_step(a, grid, db, L.fc, s);
-            sweep_launches += 1 + (L.nz % 2 == 0 ? 1 : 0);
-            HIPCHK(hipGetLastError());
-            ev_end();
-            L.nslot = kNDir;
-        } else {
-            const int db = tile_for(k, a);
-            if (k == nlev - 1) fine_db = db;
-            const dim3 grid = sweep_grid(L, nline, db);
-            ev_begin(EV_SWEEP);
-            for (int m0 = 0; m0 < maxfreq; m0 += Qpass) {
-                a.m0 = m0;
-                a.Q = Qpass;
-                a.add = m0 > 0 ? 1 : 0;
-                for (int s = 0; s < L.nz; ++s) launch_step(a, grid, db, L.fc, s);
-                sweep_launches += L.nz;
-            }
-            HIPCHK(hipGetLastError());
-            ev_end();
-            L.nslot = kNDir / db;
+            a.add = m0 > 0 ? 1 : 0;
+            for (int s = 0; s < L.nz; ++s) launch_step(a, grid, db, L.fc, s);
+            sweep_launches += L.nz;
         }
+        HIPCHK(hipGetLastError());
+        ev_end();
+        L.nslot = kNDir / db;
         if (info.cont_active) {
             if (cont_forked) {
                 ev_begin(EV_SWEEP);   // the part of the continuum sweep not hidden by the lines
@@ -1065,39 +956,6 @@ struct Job : JobBase {
         HIPCHK(hipStreamWaitEvent(cstream, cfork, 0));
         cont_sweep(k, cstream);
         HIPCHK(hipEventRecord(cjoin, cstream));
-    }
-
-    void march_launch(int k) {
-        Level& L = *lev[k];
-        if constexpr (sizeof(R) == 4) {
-            MarchArgs<float> m;
-            m.atom = atom_d.as<AtomInfo>();
-            m.nx = L.nx; m.ny = L.ny; m.nz = L.nz;
-            m.nxy = unsigned(L.nxy); m.nvox = L.nvox;
-            m.dx = L.dx; m.dy = L.dy;
-            m.z = L.dz.as<double>();
-            m.sc = L.sc.as<float>(); m.sv = L.sv.as<float>(); m.lc = L.lc.as<float>();
-            m.qf = qf.as<float>(); m.wf = wf.as<float>();
-            m.topI = (k == nlev - 1 && topI.p) ? topI.as<float>() : nullptr;
-            m.acc = L.acc.as<float>();
-            m.F = L.march.F;
-            m.nchunk = L.march.nchunk;
-            const dim3 grid(unsigned(L.march.nchunk), unsigned(nline), unsigned(kNDir));
-            const unsigned thr = unsigned(L.march.threads);
-            const size_t lds = L.march.lds;
-            ev_begin(EV_SWEEP);
-            switch (L.march.ppt) {
-                case 4: march_kernel<4><<<grid, thr, lds, st()>>>(m); break;
-                case 2: march_kernel<2><<<grid, thr, lds, st()>>>(m); break;
-                default: march_kernel<1><<<grid, thr, lds, st()>>>(m); break;
-            }
-            HIPCHK(hipGetLastError());
-            ev_end();
-            ++sweep_launches;
-        } else {
-            (void)L;
-            throw Error(NLTE_E_INVALID, "plane-resident sweep is FP32 only");
-        }
     }
 
     double read_scalar() {
@@ -1439,8 +1297,7 @@ struct Job : JobBase {
         r.ms_transfer = ms_phase[EV_TRANSFER];
         r.sweep_launches = sweep_launches;
         r.dirs_per_block = fine_db;
-        r.sweep_kernel = lev[nlev - 1]->march.F ? NLTE_SWEEP_RESIDENT
-                         : lev[nlev - 1]->pair ? NLTE_SWEEP_PAIR : NLTE_SWEEP_PLANE_STEP;
+        r.sweep_kernel = NLTE_SWEEP_PLANE_STEP;
         r.fallback = rs.fell_back;
         res = r;
         if (out) *out = r;
@@ -1461,31 +1318,14 @@ struct Job : JobBase {
         // direction-group slots summed on the host side of the copy, by the same tree
         // as the rate equations
         const size_t m = size_t(nline) * L.nvox;
-        const size_t ns = L.march.F ? size_t(kNDir) * L.march.nchunk : size_t(L.nslot);
+        const size_t ns = size_t(L.nslot);
         std::vector<R> a(size_t(2) * ns * m);
         HIPCHK(hipMemcpyAsync(a.data(), L.acc.p, sizeof(R) * a.size(), hipMemcpyDeviceToHost, st()));
         HIPCHK(hipStreamSynchronize(st()));
         std::vector<R> j(m), o(m);
-        if (L.march.F) {
-            for (int l = 0; l < nline; ++l) {
-                const int nch = (info.line[l].nfreq + L.march.F - 1) / L.march.F;
-                for (size_t v = 0; v < L.nvox; ++v) {
-                    double sj = 0.0, so = 0.0;
-                    for (int d = 0; d < kNDir; ++d)
-                        for (int c = 0; c < nch; ++c) {
-                            const size_t slot = size_t(d) * L.march.nchunk + c;
-                            sj += double(a[(slot * nline + l) * L.nvox + v]);
-                            so += double(a[((ns + slot) * nline + l) * L.nvox + v]);
-                        }
-                    j[size_t(l) * L.nvox + v] = R(sj);
-                    o[size_t(l) * L.nvox + v] = R(so);
-                }
-            }
-        } else {
-            for (size_t i = 0; i < m; ++i) {
-                j[i] = tree_slots(a.data() + i, m, L.nslot);
-                o[i] = tree_slots(a.data() + size_t(L.nslot) * m + i, m, L.nslot);
-            }
+        for (size_t i = 0; i < m; ++i) {
+            j[i] = tree_slots(a.data() + i, m, L.nslot);
+            o[i] = tree_slots(a.data() + size_t(L.nslot) * m + i, m, L.nslot);
         }
         if (mem == NLTE_MEM_DEVICE) {
             HIPCHK(hipMemcpyAsync(jeff, j.data(), sizeof(R) * m, hipMemcpyHostToDevice, st()));
@@ -2031,15 +1871,9 @@ size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom
     size_t fine_nxy = size_t(nx) * ny, fine_nvox = fine_nxy * nz;
     int maxfreq = 0;
     for (int l = 0; l < nline; ++l) maxfreq = std::max(maxfreq, atom->info.line[l].nfreq);
-    bool fine_resident = false, any_pair = false;
     for (int k = nlev - 1; k >= 0; --k) {
         const size_t nvox = size_t(nx) * ny * nz;
-        Level::MarchPlan mp;
-        march_plan(mp, size_t(nx) * ny, nline, maxfreq, R, ctx->lds_max, p->sweep_kernel);
-        if (k == nlev - 1) fine_resident = mp.F > 0;
-        const bool pr = !mp.F && pair_ok(size_t(nx) * ny, nz, nline, R, p->sweep_kernel);
-        any_pair = any_pair || pr;
-        const size_t slots = mp.F ? size_t(kNDir) * mp.nchunk : (pr ? size_t(kNDir) : size_t(acc_slots(nvox, nline, R)));
+        const size_t slots = size_t(acc_slots(nvox, nline, R));
         bytes += 8 * size_t(nz) + 8 * size_t(nprim) * nvox + R * (6 * nline + 4) * nvox;
         bytes += 8 * (size_t(N) * 6 + size_t(N) * N + 1) * nvox + R * (2 * slots + 2) * nline * nvox;
         bytes += 8 * std::max<size_t>((nvox + 255) / 256, 1024);
@@ -2049,16 +1883,11 @@ size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom
     }
     const char* envb = std::getenv("NLTE3D_SWEEP_STATE_MB");
     const double cap = envb ? std::atof(envb) * 1048576.0 : 0.25 * double(ctx->budget);
-    int nstate = any_pair ? 3 : 2;
-    int Q = 1;
-    for (;;) {
-        const double per_q = double(cell) * nstate * kNDir * nline * fine_nxy;
-        Q = std::max(1, std::min(maxfreq, int(cap / per_q)));
-        Q = std::max(1, std::min(Q, int(4294967295.0 / (double(cell) * double(fine_nxy)))));
-        if (nstate == 2 || Q >= maxfreq) break;
-        nstate = 2;
-    }
-    if (!fine_resident) bytes += cell * nstate * kNDir * size_t(nline) * Q * fine_nxy;
+    const int nstate = 2;
+    const double per_q = double(cell) * nstate * kNDir * nline * fine_nxy;
+    int Q = std::max(1, std::min(maxfreq, int(cap / per_q)));
+    Q = std::max(1, std::min(Q, int(4294967295.0 / (double(cell) * double(fine_nxy)))));
+    bytes += cell * nstate * kNDir * size_t(nline) * Q * fine_nxy;
     bytes += 8 * size_t(N) * fine_nvox;
     if (atom->info.cont_active)       // continuum plane state and frequency tables
         bytes += 3 * R * 2 * kNDir * atom->cnu.size() * fine_nxy +
@@ -2112,22 +1941,42 @@ static bool batch_key_equal(const JobBase* a, const JobBase* b) {
     return a->prec == b->prec && p.method == q.method && nl(p) == nl(q) && p.nu_fmg == q.nu_fmg &&
            p.nu0 == q.nu0 && p.nu1 == q.nu1 && p.nu2 == q.nu2 && p.nu3 == q.nu3;
 }
+// Serving batches exist to fill the device with grids too small to fill it alone.  One
+// plane step of 64x64 points x 24 directions x 505 frequencies (49.6 M updates) already
+// runs at the full sweep rate, so served jobs share a batch only while their summed
+// finest-grid plane-step work stays within that.  A batch advances its jobs in lockstep,
+// one formal solution at a time, so a small grid tied to a large one would wait for every
+// plane of the large one: only jobs whose finest-grid formal solutions are within a factor
+// of 4 of the batch's first job share it.
+constexpr double kBatchFill = 64.0 * 64.0 * 24.0 * 505.0;
+constexpr double kBatchSpread = 4.0;
+static double plane_work(const JobBase* j) {
+    return double(j->src_atmos->nx) * double(j->src_atmos->ny) * 24.0 * double(j->src_atom->nf);
+}
+static double fs_work(const JobBase* j) { return plane_work(j) * double(j->src_atmos->nz); }
+static bool batch_similar(const JobBase* a, const JobBase* b) {
+    const double r = fs_work(a) / fs_work(b);
+    return r <= kBatchSpread && r >= 1.0 / kBatchSpread;
+}
+
 static bool batch_candidate(const JobBase* j) {
     const nlte_params& p = j->params;
     return !p.graph && p.sc_interp == NLTE_SC_BILINEAR &&
            (p.sweep_kernel == NLTE_SWEEP_AUTO || p.sweep_kernel == NLTE_SWEEP_PLANE_STEP) &&
-           !j->src_atom->info.cont_active;
+           !j->src_atom->info.cont_active && plane_work(j) < kBatchFill;
 }
 
 // Admits queued jobs that can join a batch keyed by `ref` and fit the budget, in queue
-// order, up to `room` of them (qmu taken here).
-static std::vector<JobBase*> admit_joiners(nlte_ctx* ctx, const JobBase* ref, int room) {
+// order, up to `room` of them and `fill` plane-step work in all (qmu taken here).
+static std::vector<JobBase*> admit_joiners(nlte_ctx* ctx, const JobBase* ref, int room, double fill) {
     std::vector<JobBase*> out;
     if (room <= 0) return out;
     std::lock_guard<std::mutex> lk(ctx->qmu);
     for (auto it = ctx->queue.begin(); it != ctx->queue.end() && int(out.size()) < room;) {
         JobBase* q = *it;
-        if (batch_candidate(q) && batch_key_equal(ref, q) && ctx->used + ctx->reserved + q->footprint <= ctx->budget) {
+        if (batch_candidate(q) && batch_key_equal(ref, q) && batch_similar(ref, q) && plane_work(q) <= fill &&
+            ctx->used + ctx->reserved + q->footprint <= ctx->budget) {
+            fill -= plane_work(q);
             it = ctx->queue.erase(it);
             admit_locked(ctx, q);
             out.push_back(q);
@@ -2158,7 +2007,8 @@ void serve_batch(nlte_ctx* ctx, JobBase* head) {
     b.ctx = ctx;
     b.stream = bs;
     std::vector<JobBase*> pending = {head};
-    for (JobBase* q : admit_joiners(ctx, head, ctx->batch_max - 1)) pending.push_back(q);
+    for (JobBase* q : admit_joiners(ctx, head, ctx->batch_max - 1, kBatchFill - plane_work(head)))
+        pending.push_back(q);
     Job<R>* ref = nullptr;
     for (;;) {
         std::vector<Job<R>*> fresh;
@@ -2226,8 +2076,11 @@ void serve_batch(nlte_ctx* ctx, JobBase* head) {
                 publish(ctx, job, NLTE_JOB_DONE, false);
             }
         }
-        const int live = int(b.active().size());
-        if (ref && !ctx->stopping) pending = admit_joiners(ctx, ref, ctx->batch_max - live);
+        const std::vector<int> act = b.active();
+        const int live = int(act.size());
+        double fill = kBatchFill;
+        for (int i : act) fill -= plane_work(b.jobs[i]);
+        if (ref && !ctx->stopping) pending = admit_joiners(ctx, ref, ctx->batch_max - live, fill);
         if (live == 0 && pending.empty()) break;
     }
     (void)hipStreamSynchronize(bs);
@@ -2360,24 +2213,6 @@ nlte_status nlte_ctx_create(int device, void* hip_stream, size_t hbm_budget, nlt
             const std::string pre = c->arch + "|";
             for (const auto& kv : read_tune_file(c->tune_path))
                 if (kv.first.compare(0, pre.size(), pre) == 0) c->tile_cache[kv.first.substr(pre.size())] = kv.second;
-        }
-        // dynamic LDS for the plane-resident sweep: what the device grants a workgroup
-        int lds = 0;
-        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
-            c->lds_max = size_t(lds);
-        if (c->lds_max > 65536) {
-            const int v = int(c->lds_max);
-            const bool ok =
-                hipFuncSetAttribute(reinterpret_cast<const void*>(&march_kernel<4>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess &&
-                hipFuncSetAttribute(reinterpret_cast<const void*>(&march_kernel<2>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess &&
-                hipFuncSetAttribute(reinterpret_cast<const void*>(&march_kernel<1>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess;
-            if (!ok) {
-                (void)hipGetLastError();
-                c->lds_max = 65536;
-            }
         }
     } catch (const Error& e) {
         delete c;
@@ -2582,7 +2417,7 @@ static void check_params(const nlte_params* p) {
     REQUIRE(p->max_iter >= 0, "max_iter must be >= 0");
     REQUIRE(p->init >= NLTE_INIT_ZERO_RAD && p->init <= NLTE_INIT_USER, "unknown initialisation");
     REQUIRE(std::isfinite(p->diverge_growth) && p->diverge_growth >= 0, "diverge_growth must be >= 0");
-    REQUIRE(p->sweep_kernel >= NLTE_SWEEP_AUTO && p->sweep_kernel <= NLTE_SWEEP_PAIR, "unknown sweep kernel");
+    REQUIRE(p->sweep_kernel == NLTE_SWEEP_AUTO || p->sweep_kernel == NLTE_SWEEP_PLANE_STEP, "unknown sweep kernel");
     REQUIRE(p->dirs_per_block == 0 || p->dirs_per_block == 3 || p->dirs_per_block == 6 || p->dirs_per_block == 12,
             "dirs_per_block must be 0, 3, 6 or 12");
 }

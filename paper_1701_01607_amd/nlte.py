@@ -21,7 +21,7 @@ W_NOT_CONVERGED, W_QUEUED = 1, 2
 MEM_HOST, MEM_DEVICE = 0, 1
 MALI, FAS, FMG = 0, 1, 2
 FP64, MIXED = 0, 1
-SWEEP_AUTO, SWEEP_PLANE_STEP, SWEEP_RESIDENT, SWEEP_PAIR = 0, 1, 2, 3
+SWEEP_AUTO, SWEEP_PLANE_STEP = 0, 1
 RESTRICT_FULL, RESTRICT_HALF, RESTRICT_INJECT = 0, 1, 2
 INTERP_TRILINEAR, INTERP_HERMITE = 0, 1
 SC_BILINEAR, SC_HERMITE = 0, 1

@@ -6,6 +6,8 @@ Reports p50/p99 time-to-convergence (arrival to result ready), atmospheres/hr ov
 stream and the admission statistics.  Usage:
 
     python -m paper_1701_01607_amd.serve --requests 24 --max-running 4
+    python -m paper_1701_01607_amd.serve --requests 100 --first 100 --rate 0.2 --max-size 4 > part2.log
+    python -m paper_1701_01607_amd.serve --combine part1.log part2.log
 """
 from __future__ import annotations
 
@@ -34,6 +36,25 @@ def make_request(j, rng, sizes, probs):
     return build_request(*draw_request(j, rng, sizes, probs))
 
 
+def draw_stream(n, sizes, probs, seed=1607005):
+    """The first n requests of the seeded stream: [(seed, size, two-level?), ...] and their
+    inter-arrival gaps at unit rate (exponential, mean 1).  One generator gives request j's
+    size, atom and gap in turn, so any contiguous part of the stream is the same whatever
+    its length."""
+    rng = np.random.default_rng(seed)
+    draws, gaps = [], []
+    for j in range(n):
+        draws.append(draw_request(j, rng, sizes, probs))
+        gaps.append(rng.exponential(1.0))
+    return draws, np.array(gaps)
+
+
+def arrival_times(gaps, rate_hz):
+    """Arrival times of a part of the stream at the given rate, the first at 0."""
+    t = np.cumsum(np.asarray(gaps, dtype=float) / rate_hz)
+    return t - t[0] if len(t) else t
+
+
 def build_request(seed, size, two):
     """(atom, atmosphere, params, tag) of one solve of the given size and atom kind."""
     nx, ny, nz = size
@@ -51,21 +72,24 @@ def build_request(seed, size, two):
     return atom, atm, p, ("two-level" if two else "six-level", (nx, ny, nz))
 
 
-def run_stream(ctx, requests, rate_hz, seed=1607005, max_running=4, log=None, batch_max=1):
-    """Submit requests at Poisson arrival times while a collector thread releases each
-    solve as soon as it is done (freeing its memory for queued ones); returns records.
-    A request is an (atom, atmosphere, params, tag) tuple or a callable that builds one
-    (called while waiting for its arrival time, so the host's input generation overlaps
-    the stream)."""
+def run_stream(ctx, requests, arrivals, max_running=4, log=None, batch_max=1, prefetch=4):
+    """Submit requests at the given arrival times (seconds from the start) while a
+    collector thread releases each solve as soon as it is done (freeing its memory for
+    queued ones); returns records.  A request is an (atom, atmosphere, params, tag) tuple
+    or a callable that builds one; callables run on a producer thread up to `prefetch`
+    requests ahead, so the host's input generation overlaps the stream."""
+    import queue
     import threading
     ctx.serve_config(max_running)
     ctx.serve_batching(batch_max)
-    rng = np.random.default_rng(seed)
-    gaps = rng.exponential(1.0 / rate_hz, size=len(requests))
-    arrivals = np.cumsum(gaps) - gaps[0]
     pending, recs = [], []
     lock = threading.Lock()
     done_submitting = threading.Event()
+    built = queue.Queue(maxsize=max(1, prefetch))
+
+    def produce():
+        for req in requests:
+            built.put(req() if callable(req) else req)
 
     def collect():
         while True:
@@ -90,19 +114,23 @@ def run_stream(ctx, requests, rate_hz, seed=1607005, max_running=4, log=None, ba
                         log(rec)
             time.sleep(0.002)
 
+    producer = threading.Thread(target=produce, daemon=True)
+    producer.start()
     th = threading.Thread(target=collect)
     th.start()
     t0 = time.monotonic()
-    for req, ta in zip(requests, arrivals):
-        atom, atm, p, tag = req() if callable(req) else req
-        while time.monotonic() - t0 < ta:
-            time.sleep(min(0.005, ta - (time.monotonic() - t0)))
-        A, M = ctx.atom(atom), ctx.atmos(atm)
-        job = ctx.submit(M, A, p)
-        with lock:
-            pending.append((job, tag))
-    done_submitting.set()
-    th.join()
+    try:
+        for ta in arrivals:
+            atom, atm, p, tag = built.get()
+            while time.monotonic() - t0 < ta:
+                time.sleep(min(0.005, ta - (time.monotonic() - t0)))
+            A, M = ctx.atom(atom), ctx.atmos(atm)
+            job = ctx.submit(M, A, p)
+            with lock:
+                pending.append((job, tag))
+    finally:
+        done_submitting.set()
+        th.join()
     return recs
 
 
@@ -140,40 +168,87 @@ def summarize(recs):
             "device_busy_fraction": busy_fraction(recs, t0, t1)}
 
 
+def combine(parts):
+    """Summary of a stream served in consecutive parts (each a list of records from its
+    own run and clock): latencies pooled, makespans and busy time added."""
+    parts = [p for p in parts if p]
+    sums = [summarize(p) for p in parts]
+    lat = np.array([r["latency_s"] for p in parts for r in p])
+    span = sum(s["makespan_s"] for s in sums)
+    n = sum(s["requests"] for s in sums)
+    return {"requests": n, "converged": sum(s["converged"] for s in sums),
+            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "atmospheres_per_hr": 3600.0 * n / span, "makespan_s": span,
+            "mean_queue_s": float(np.mean([r["queue_s"] for p in parts for r in p])),
+            "device_busy_fraction": sum(s["device_busy_fraction"] * s["makespan_s"] for s in sums) / span,
+            "parts": len(parts)}
+
+
+def calibrate(ctx, sizes, probs):
+    """Single-stream capacity of the mix: one solve of each size and atom alone (seeds
+    outside the stream's); returns the mean run time of a request of the mix."""
+    times = []
+    for i, size in enumerate(sizes):
+        cal = run_stream(ctx, [build_request(90000 + 2 * i + k, size, k == 0) for k in (0, 1)],
+                         arrivals=[0.0, 0.0], max_running=1)
+        by = {r["kind"]: r["run_s"] for r in cal}
+        times.append((by["two-level"], by["six-level"]))
+        print(json.dumps({"calibration": list(size), "run_s": by}), flush=True)
+    return expected_run_time(times, probs)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--first", type=int, default=0,
+                    help="serve requests first .. first+requests-1 of the seeded stream")
     ap.add_argument("--rate", type=float, default=0.0, help="arrivals per second (0: 80%% of measured capacity)")
     ap.add_argument("--max-running", type=int, default=4)
     ap.add_argument("--max-size", type=int, default=3, help="use the first N sizes of the mix")
     ap.add_argument("--batch", type=int, default=1,
                     help="continuous batching: compatible requests share batches of up to this many")
+    ap.add_argument("--calibrate", type=int, default=0,
+                    help="N > 0: only measure capacity: one solve of each size and atom alone (single-stream "
+                         "capacity of the mix) and a burst of N requests of the mix submitted at once")
+    ap.add_argument("--combine", nargs="+", default=None, metavar="LOG",
+                    help="no GPU: summarise the records printed by runs of consecutive parts of a stream")
     args = ap.parse_args()
+    if args.combine:
+        parts = []
+        for path in args.combine:
+            with open(path) as f:
+                parts.append([r for r in (json.loads(x) for x in f if x.startswith("{")) if "latency_s" in r])
+        print(json.dumps(combine(parts)))
+        return
     import torch
     torch.cuda.init()
     ctx = nlte.Context(0, torch.cuda.current_stream().cuda_stream)
     sizes = SIZES[: args.max_size]
     probs = np.array(SIZE_P[: args.max_size])
     probs = probs / probs.sum()
-    rng = np.random.default_rng(1607005)
-    draws = [draw_request(j, rng, sizes, probs) for j in range(args.requests)]
+    draws, gaps = draw_stream(args.first + args.requests, sizes, probs)
+    draws, gaps = draws[args.first:], gaps[args.first:]
     reqs = [lambda d=d: build_request(*d) for d in draws]
     rate = args.rate
+    if args.calibrate > 0:
+        single = calibrate(ctx, sizes, probs)
+        bd, _ = draw_stream(args.calibrate, sizes, probs, seed=50000)
+        burst = [lambda d=(50000 + j, size, two): build_request(*d) for j, (_, size, two) in enumerate(bd)]
+        recs = run_stream(ctx, burst, arrivals=np.zeros(len(burst)), max_running=args.max_running,
+                          batch_max=args.batch)
+        out = summarize(recs)
+        print(json.dumps({"single_stream_s_per_request": single, "single_stream_rate_80pct_hz": 0.8 / single,
+                          "burst": out, "burst_rate_80pct_hz": 0.8 * len(recs) / out["makespan_s"],
+                          "max_running": args.max_running, "batch_max": args.batch}))
+        return
     if rate <= 0:
-        # capacity: one solve of each size and atom alone (seeds outside the stream's), the
-        # mean run time of a request of the mix from the size odds, and 80 % of its inverse
-        times = []
-        for i, size in enumerate(sizes):
-            cal = run_stream(ctx, [build_request(90000 + 2 * i + k, size, k == 0) for k in (0, 1)],
-                             rate_hz=1e6, max_running=1)
-            by = {r["kind"]: r["run_s"] for r in cal}
-            times.append((by["two-level"], by["six-level"]))
-            print(json.dumps({"calibration": list(size), "run_s": by}), flush=True)
-        rate = 0.8 / expected_run_time(times, probs)
-    recs = run_stream(ctx, reqs, rate_hz=rate, max_running=args.max_running,
+        rate = 0.8 / calibrate(ctx, sizes, probs)
+    print(json.dumps({"stream": {"first": args.first, "requests": args.requests, "rate_hz": rate}}), flush=True)
+    recs = run_stream(ctx, reqs, arrival_times(gaps, rate), max_running=args.max_running,
                       log=lambda r: print(json.dumps(r), flush=True), batch_max=args.batch)
     out = summarize(recs)
-    out.update({"rate_hz": rate, "max_running": args.max_running, "batch_max": args.batch, "sizes": sizes})
+    out.update({"rate_hz": rate, "first": args.first, "max_running": args.max_running, "batch_max": args.batch,
+                "sizes": sizes})
     print(json.dumps(out))
 
 

@@ -62,32 +62,42 @@ def ragged():
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
 @pytest.mark.parametrize("dpb", [0, 3, 12])
-@pytest.mark.parametrize("kern", [1, 2], ids=["plane_step", "resident"])
-def test_formal_solution_parity(nl, ctx, ragged, prec, tol, dpb, kern):
-    if kern == 2 and prec == 0:
-        pytest.skip("the plane-resident sweep is FP32 only")
+def test_formal_solution_parity(nl, ctx, ragged, prec, tol, dpb):
     atom, atm, lev, n0 = ragged
     npop, nln = shapes(atom, atm)
     job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1,
-                                                                 dirs_per_block=dpb, sweep_kernel=kern))
+                                                                 dirs_per_block=dpb))
     g0 = job.populations(0, npop)
     assert relerr(g0, n0) < 1e-11
     jg, og = job.formal_solution(0, nln)
     jo, oo = formal_solution(lev, n0)
     ej, eo = relerr(jg, jo), relerr(og, oo)
-    print(f"prec={prec} dirs_per_block={dpb} kernel={kern} Jeff err {ej:.2e}  1-L* err {eo:.2e}")
+    print(f"prec={prec} dirs_per_block={dpb} Jeff err {ej:.2e}  1-L* err {eo:.2e}")
+    assert ej < tol and eo < tol
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
+def test_formal_solution_parity_wide_ragged_rows(nl, ctx, prec, tol):
+    # a wide plane whose 64-point tiles straddle rows (100 points per row), the last tile
+    # partly empty
+    atom = synth.caii_like_atom(7)
+    atm = synth.atmos_stratified(nx=100, ny=7, nz=6, dx=90 * synth.KM, seed=23)
+    lev = Level(atom, atm)
+    n0 = zero_radiation(lev)
+    npop, nln = shapes(atom, atm)
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1))
+    jg, og = job.formal_solution(0, nln)
+    jo, oo = formal_solution(lev, n0)
+    ej, eo = relerr(jg, jo), relerr(og, oo)
+    print(f"prec={prec} 100x7x6 Jeff err {ej:.2e}  1-L* err {eo:.2e}")
     assert ej < tol and eo < tol
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-3)])
-@pytest.mark.parametrize("kern", [1, 2], ids=["plane_step", "resident"])
-def test_mali_iterations_parity(nl, ctx, ragged, prec, tol, kern):
-    if kern == 2 and prec == 0:
-        pytest.skip("the plane-resident sweep is FP32 only")
+def test_mali_iterations_parity(nl, ctx, ragged, prec, tol):
     atom, atm, lev, n0 = ragged
     npop, _ = shapes(atom, atm)
-    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1,
-                                                                 sweep_kernel=kern))
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1))
     Cg = job.mali(0, 3)
     n3, Co = mali(lev, 1, n0, fine_rhs(lev), 3)
     e = relerr(job.populations(0, npop), n3)
@@ -141,10 +151,7 @@ def mg_case(nfreq=7):
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-3)])
-@pytest.mark.parametrize("kern", [1, 2], ids=["plane_step", "resident"])
-def test_vcycle_parity(nl, ctx, prec, tol, kern):
-    if kern == 2 and prec == 0:
-        pytest.skip("the plane-resident sweep is FP32 only")
+def test_vcycle_parity(nl, ctx, prec, tol):
     atom, atm = mg_case()
     p = OParams(nlev=3, nu0=3, nu1=2, nu2=2, nu3=6)
     levels = build_hierarchy(atom, atm, 3)
@@ -152,7 +159,7 @@ def test_vcycle_parity(nl, ctx, prec, tol, kern):
     n = zero_radiation(fine)
     n = vcycle(levels, 3, n, fine_rhs(fine), p, first=True)
     job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
-                  nl.SolveParams(method=nl.FAS, precision=prec, nlev=3, nu0=3, nu1=2, nu2=2, nu3=6, sweep_kernel=kern))
+                  nl.SolveParams(method=nl.FAS, precision=prec, nlev=3, nu0=3, nu1=2, nu2=2, nu3=6))
     job.vcycle(2, first=True)
     npop, _ = shapes(atom, atm)
     e = relerr(job.populations(2, npop), n)
@@ -162,16 +169,13 @@ def test_vcycle_parity(nl, ctx, prec, tol, kern):
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-3)])
 @pytest.mark.parametrize("fmg", [False, True])
-@pytest.mark.parametrize("kern", [1, 2], ids=["plane_step", "resident"])
-def test_fas_fmg_fixed_cycles_parity(nl, ctx, prec, tol, fmg, kern):
-    if kern == 2 and prec == 0:
-        pytest.skip("the plane-resident sweep is FP32 only")
+def test_fas_fmg_fixed_cycles_parity(nl, ctx, prec, tol, fmg):
     atom, atm = mg_case()
     p = OParams(nlev=3, nu1=2, nu2=2, nu3=6, nu_fmg=4)
     n_or, st, _ = solve_fas(atom, atm, p, fmg=fmg, cycles=2)
     job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
                   nl.SolveParams(method=nl.FMG if fmg else nl.FAS, precision=prec, nlev=3, nu1=2, nu2=2, nu3=6,
-                                 nu_fmg=4, E_target=0.0, tol_C=0.0, max_iter=2, sweep_kernel=kern))
+                                 nu_fmg=4, E_target=0.0, tol_C=0.0, max_iter=2))
     rc, r = job.run()
     npop, _ = shapes(atom, atm)
     e = relerr(job.populations(2, npop), n_or)
@@ -384,19 +388,14 @@ def test_block_shape_does_not_change_results(nl, ctx, prec, nx, ny, shapes_):
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
-@pytest.mark.parametrize("kern", [1, 2, 3], ids=["plane_step", "resident", "two_plane"])
-def test_formal_solution_parity_one_chunk_per_wave(nl, ctx, prec, tol, kern):
-    if kern >= 2 and prec == 0:
-        pytest.skip("the plane-resident and two-plane sweeps are FP32 only")
-    """Planes large enough for one frequency chunk per wave (96x72; the plane-resident
-    sweep takes planes of at most 4096 points, 48x48), against the oracle."""
-    atom, atm, lev, n0, jo, oo = _one_chunk_case(48 if kern == 2 else 96, 48 if kern == 2 else 72)
+def test_formal_solution_parity_one_chunk_per_wave(nl, ctx, prec, tol):
+    """Planes large enough for one frequency chunk per wave (96x72), against the oracle."""
+    atom, atm, lev, n0, jo, oo = _one_chunk_case(96, 72)
     npop, nln = shapes(atom, atm)
-    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1,
-                                                                 sweep_kernel=kern))
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1))
     jg, og = job.formal_solution(0, nln)
     ej, eo = relerr(jg, jo), relerr(og, oo)
-    print(f"prec={prec} kernel={kern} Jeff err {ej:.2e}  1-L* err {eo:.2e}")
+    print(f"prec={prec} Jeff err {ej:.2e}  1-L* err {eo:.2e}")
     assert ej < tol and eo < tol
 
 
@@ -407,8 +406,8 @@ def _one_chunk_case(nx, ny):
     """Atom, atmosphere, oracle level, populations and oracle formal solution, computed
     once per plane size."""
     if (nx, ny) not in _ONE_CHUNK:
-        atom = synth.caii_like_atom(7 if nx > 48 else 9)
-        atm = synth.atmos_stratified(nx=nx, ny=ny, nz=5 if nx > 48 else 9, dx=120 * synth.KM, seed=29)
+        atom = synth.caii_like_atom(7)
+        atm = synth.atmos_stratified(nx=nx, ny=ny, nz=5, dx=120 * synth.KM, seed=29)
         lev = Level(atom, atm)
         n0 = zero_radiation(lev)
         jo, oo = formal_solution(lev, n0)
@@ -417,10 +416,7 @@ def _one_chunk_case(nx, ny):
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
-@pytest.mark.parametrize("kern", [1, 2], ids=["plane_step", "resident"])
-def test_strongly_damped_line_parity(nl, ctx, prec, tol, kern):
-    if kern == 2 and prec == 0:
-        pytest.skip("the plane-resident sweep is FP32 only")
+def test_strongly_damped_line_parity(nl, ctx, prec, tol):
     """Damping well above the Doppler width (a ~ 40), so that the profile wings beyond
     |u| = 5 lie far off the real axis of the Faddeeva function."""
     atom = synth.two_level_atom(1e-2, q_max=16 * synth.KM, nfreq=33)
@@ -429,8 +425,7 @@ def test_strongly_damped_line_parity(nl, ctx, prec, tol, kern):
     lev = Level(atom, atm)
     n0 = zero_radiation(lev)
     npop, nln = shapes(atom, atm)
-    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1,
-                                                                 sweep_kernel=kern))
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1))
     jg, og = job.formal_solution(0, nln)
     jo, oo = formal_solution(lev, n0)
     assert np.isfinite(jg).all() and np.isfinite(og).all()
@@ -439,46 +434,20 @@ def test_strongly_damped_line_parity(nl, ctx, prec, tol, kern):
     assert ej < tol and eo < tol
 
 
-def test_plane_resident_sweep_requests(nl, ctx):
-    """The plane-resident sweep runs where asked and applies; it refuses FP64 and planes
-    too large for LDS instead of silently switching kernels."""
+def test_unknown_sweep_kernels_are_refused(nl, ctx):
+    """Only the plane-step sweep exists (AUTO names it too); other values are refused
+    when the job is created."""
     atom, atm = ragged_case(nfreq=9, seed=37)
     A, M = ctx.atmos(atm), ctx.atom(atom)
-    job = ctx.job(A, M, nl.SolveParams(method=nl.MALI, precision=nl.MIXED, nlev=1, max_iter=2, E_target=0.0,
-                                       sweep_kernel=nl.SWEEP_RESIDENT))
+    job = ctx.job(A, M, nl.SolveParams(method=nl.MALI, precision=nl.MIXED, nlev=1, max_iter=1, E_target=0.0,
+                                       sweep_kernel=nl.SWEEP_AUTO))
     rc, r = job.run()
-    assert r.sweep_kernel == nl.SWEEP_RESIDENT
+    assert r.sweep_kernel == nl.SWEEP_PLANE_STEP
     job.close()
-    with pytest.raises(nl.NlteError):
-        ctx.job(A, M, nl.SolveParams(method=nl.MALI, precision=nl.FP64, nlev=1, sweep_kernel=nl.SWEEP_RESIDENT))
-    big = synth.atmos_stratified(nx=96, ny=96, nz=3, dx=120 * synth.KM, seed=37)
-    with pytest.raises(nl.NlteError):
-        ctx.job(ctx.atmos(big), M, nl.SolveParams(method=nl.MALI, precision=nl.MIXED, nlev=1,
-                                                  sweep_kernel=nl.SWEEP_RESIDENT))
-
-
-@pytest.mark.parametrize("nx,ny,nz", [(96, 72, 9), (104, 72, 10)])
-def test_two_plane_sweep_equals_plane_step_bitwise(nl, ctx, nx, ny, nz):
-    """The two-plane sweep computes the same cells and sums as the plane-step sweep with the
-    same code, so formal solutions and MALI iterations agree bit for bit on planes where
-    the plane-step sweep also runs one frequency chunk per wave (104 = 6.5 tiles of 16 and
-    an even nz exercise ragged tiles and the closing single step)."""
-    atom = synth.caii_like_atom(9)
-    atm = synth.atmos_stratified(nx=nx, ny=ny, nz=nz, dx=120 * synth.KM, seed=41)
-    npop, nln = shapes(atom, atm)
-    A, M = ctx.atmos(atm), ctx.atom(atom)
-    outs = []
-    for kern in (nl.SWEEP_PLANE_STEP, nl.SWEEP_PAIR):
-        job = ctx.job(A, M, nl.SolveParams(method=nl.MALI, precision=nl.MIXED, nlev=1, max_iter=3, E_target=0.0,
-                                           sweep_kernel=kern))
-        jg, og = job.formal_solution(0, nln)
-        job.mali(0, 3)
-        rc, r = job.run()
-        assert r.sweep_kernel == kern
-        outs.append((jg, og, job.populations(0, npop)))
-        job.close()
-    for x, y in zip(*outs):
-        assert np.array_equal(x, y)
+    for kern in (-1, 2, 3):
+        with pytest.raises(nl.NlteError) as ei:
+            ctx.job(A, M, nl.SolveParams(method=nl.MALI, precision=nl.MIXED, nlev=1, sweep_kernel=kern))
+        assert ei.value.code == nl.E_INVALID
 
 
 @pytest.fixture(scope="module")
@@ -539,9 +508,5 @@ def test_hermite_upwind_fas_parity_and_constraints(nl, ctx, prec, tol):
     print(f"prec={prec} Hermite upwind FAS 2 cycles err {e:.2e}")
     assert r.cycles == 2 and e < tol
     job.close()
-    for kern in (nl.SWEEP_PAIR, nl.SWEEP_RESIDENT):
-        with pytest.raises(nl.NlteError):
-            ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.FAS, precision=1, nlev=3,
-                                                                   sc_interp=nl.SC_HERMITE, sweep_kernel=kern))
     with pytest.raises(nl.NlteError):
         ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.FAS, nlev=3, sc_interp=2))

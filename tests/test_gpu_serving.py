@@ -194,3 +194,47 @@ def test_continuous_batching_gives_each_result_alone_and_shares_batches(nl):
     for j in jobs:
         j.close()
     ctx.close()
+
+
+def test_serving_batches_only_small_grids_of_similar_size(nl):
+    import torch
+    ctx = nl.Context(0, torch.cuda.current_stream().cuda_stream)
+
+    def six(n, nz, nf, seed, **kw):
+        atm = synth.atmos_stratified(nx=n, ny=n, nz=nz, dx=150 * synth.KM, seed=seed)
+        atm["ntot"] = atm["ntot"] * 0.1
+        return (synth.caii_like_atom(nf), atm,
+                nl.SolveParams(method=nl.FAS, precision=nl.MIXED, nlev=2, nu1=2, nu2=2, nu3=8, E_target=1e-3,
+                               max_iter=20, **kw))
+
+    # the first request is never batched (Hermite upwind interpolation) and keeps the one
+    # worker busy while the others queue up behind it
+    reqs = [six(32, 33, 9, 860, sc_interp=nl.SC_HERMITE),
+            six(8, 9, 9, 861),          # head of a batch
+            six(32, 33, 9, 862),        # 58x the head's formal-solution work: a batch of its own
+            six(8, 17, 9, 863),         # 1.9x the head's: joins it
+            six(64, 9, 101, 864)]       # one 64x64 plane step of 505 frequencies fills the device: alone
+    alone = []
+    for atom, atm, p in reqs:
+        job = ctx.job(ctx.atmos(atm), ctx.atom(atom), p)
+        job.run()
+        alone.append(job.populations(1, (len(atom["levels"]), atm["nz"], atm["ny"], atm["nx"])))
+        job.close()
+    ctx.serve_config(1)
+    ctx.serve_batching(8)
+    handles = [(ctx.atmos(atm), ctx.atom(atom)) for atom, atm, _ in reqs]
+    jobs = [ctx.submit(M, A, p) for (M, A), (_, _, p) in zip(handles, reqs)]
+    for j in jobs:
+        assert j.wait() >= 0
+    infos = [j.info() for j in jobs]
+    for i, (j, (atom, atm, _)) in enumerate(zip(jobs, reqs)):
+        got = j.populations(1, (len(atom["levels"]), atm["nz"], atm["ny"], atm["nx"]))
+        assert np.array_equal(got, alone[i]), f"request {i}: populations differ"
+    b = [inf.batch for inf in infos]
+    print(f"batch ids {b}")
+    assert b[0] == 0 and b[4] == 0
+    assert b[1] != 0 and b[3] == b[1]
+    assert b[2] not in (0, b[1])
+    for j in jobs:
+        j.close()
+    ctx.close()

@@ -50,3 +50,27 @@ def test_requests_follow_the_mix_and_are_reproducible():
     b = [serve.make_request(j, rng2, [(8, 8, 9), (16, 16, 17)], probs)[3] for j in range(6)]
     assert a == b and {t[0] for t in a} <= {"two-level", "six-level"}
     assert len(sizes) == 2
+
+
+def test_stream_parts_do_not_depend_on_the_stream_length():
+    serve = _serve()
+    probs = np.array(serve.SIZE_P)
+    d10, g10 = serve.draw_stream(10, serve.SIZES, probs)
+    d30, g30 = serve.draw_stream(30, serve.SIZES, probs)
+    assert d10 == d30[:10] and np.array_equal(g10, g30[:10])
+    assert [d[0] for d in d30] == [10000 + j for j in range(30)]
+    t = serve.arrival_times(g30[10:20], 0.5)
+    assert t[0] == 0.0 and np.allclose(np.diff(t), g30[11:20] / 0.5)
+
+
+def test_combined_parts_pool_latencies_and_add_makespans():
+    serve = _serve()
+    a = [rec(0.0, 0.0, 2.0), rec(1.0, 0.5, 4.0)]          # makespan 4, busy [0,4] = 4
+    b = [rec(100.0, 0.0, 101.0), rec(105.0, 0.0, 106.0)]   # makespan 6, busy 2
+    out = serve.combine([a, b])
+    lat = np.array([2.0, 3.0, 1.0, 1.0])
+    assert out["requests"] == 4 and out["parts"] == 2
+    assert out["makespan_s"] == pytest.approx(10.0)
+    assert out["atmospheres_per_hr"] == pytest.approx(3600.0 * 4 / 10.0)
+    assert out["p99_s"] == pytest.approx(np.percentile(lat, 99))
+    assert out["device_busy_fraction"] == pytest.approx((4.0 + 2.0) / 10.0)
