@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "voigt_coef.h"
+
 namespace nlte {
 
 constexpr double kH = 6.62607015e-27;      // erg s
@@ -30,8 +32,6 @@ constexpr double kAMU = 1.66053906660e-24; // g
 constexpr double kPI = 3.14159265358979323846;
 constexpr double kSQRTPI = 1.77245385090551602730;
 constexpr double kINVSQRTPI = 0.56418958354775628695;
-
-constexpr int kVoigtNd = 32;
 
 // Small-damping FP32 Voigt function: H(a,u) = Re w(u + i a) = sum_n Re[(i a)^n w^(n)(u) / n!].
 // From w' = -2 z w + 2i/sqrt(pi), w^(n) = P_n w + Q_n i/sqrt(pi) with P_{n+1} = P_n' - 2z P_n,
@@ -49,15 +49,19 @@ constexpr float kVoigtSmallA = 0.04f;
 // Per interval the cubic's coefficients (c0, c1, c2, c3) in the local coordinate s in [0, 1).
 __constant__ float4 c_dawg[kDawIntervals];
 
-// Weideman coefficients, highest power first; filled by the host at context creation.
-__constant__ double c_voigt_d[kVoigtNd];
-__constant__ double c_voigt_Ld;
-
+// Weideman coefficients, highest power first (voigt_coef.h, compiled-in literals).
 template <typename R> struct VoigtTraits;
+// Each coefficient passes through an empty volatile asm where it is used, so the compiler
+// writes it into a scalar register pair right there (two s_mov) instead of hoisting all
+// 64 dwords out of the frequency loop, where they would crowd out the loop's other scalars.
 template <> struct VoigtTraits<double> {
     static constexpr int N = kVoigtNd;
-    __device__ static double coef(int i) { return c_voigt_d[i]; }
-    __device__ static double L() { return c_voigt_Ld; }
+    __device__ static double coef(int i) {
+        double c = kVoigtCoefD[i];
+        asm volatile("" : "+s"(c));
+        return c;
+    }
+    __device__ static constexpr double L() { return kVoigtLd; }
 };
 
 __device__ inline float dev_rcp(float x) { return __builtin_amdgcn_rcpf(x); }   // v_rcp_f32, 1 ulp

@@ -221,25 +221,6 @@ struct DevBuf {
 };
 
 // ----------------------------------------------------------------- constant tables
-// Weideman (1994) coefficients for N terms: a_n = (1/2M) sum_{k=-M+1}^{M-1} F(k) cos(pi n k/M),
-// F(k) = exp(-t^2)(L^2 + t^2), t = L tan(k pi / 2M), M = 2N, L = sqrt(N / sqrt 2);
-// stored highest power first (index j holds a_{N-j}).
-void weideman_coefficients(int N, std::vector<double>& coef, double& L) {
-    const int M = 2 * N;
-    L = std::sqrt(N / std::sqrt(2.0));
-    std::vector<double> F(2 * M - 1);
-    for (int k = -M + 1; k <= M - 1; ++k) {
-        const double t = L * std::tan(k * M_PI / (2.0 * M));
-        F[k + M - 1] = std::exp(-t * t) * (L * L + t * t);
-    }
-    coef.assign(N, 0.0);
-    for (int n = 1; n <= N; ++n) {
-        double s = 0.0;
-        for (int k = -M + 1; k <= M - 1; ++k) s += F[k + M - 1] * std::cos(M_PI * n * k / M);
-        coef[N - n] = s / (2.0 * M);
-    }
-}
-
 // Table of the small-damping FP32 Voigt evaluation: G = 1 - 2uF(u) (F Dawson's function)
 // on intervals of width 1/16 in u, as the cubic Hermite interpolant of G and
 // G' = -2F - 2uG between the nodes, in monomial form in the local coordinate s in [0, 1).
@@ -288,11 +269,6 @@ void a4_set(double* mu) {
 }
 
 void upload_constants() {
-    std::vector<double> cd;
-    double Ld;
-    weideman_coefficients(kVoigtNd, cd, Ld);
-    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_voigt_d), cd.data(), sizeof(double) * kVoigtNd));
-    HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_voigt_Ld), &Ld, sizeof(double)));
     std::vector<float4> dg;
     dawson_table(dg);
     HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(c_dawg), dg.data(), sizeof(float4) * kDawIntervals));
@@ -391,11 +367,13 @@ inline int freq_chunks_for(size_t nxy, int nline, size_t rbytes) {
     return fc;
 }
 
-// Accumulator slots for a level: every block shape (down to 3 directions, 8 slots) on
-// levels whose 8-slot accumulators stay under 4 GiB; larger levels keep 2 slots and
-// sweep with 12-direction blocks.
+// Accumulator slots for a level: 8, which allow every block shape down to three
+// directions per block, wherever the 8-slot accumulators take at most 48 GiB (in FP32 with
+// five lines up to ~160 M voxels), else 2 (12-direction blocks).  Small blocks pay on
+// large planes too: on 504x504 planes three-direction blocks re-read fewer upwind cells
+// from HBM than twelve-direction ones (the autotuner picks them there).
 inline int acc_slots(size_t nvox, int nline, size_t rbytes) {
-    return double(2 * kMaxSlots) * nline * double(nvox) * double(rbytes) <= 4294967296.0 ? kMaxSlots : 2;
+    return double(2 * kMaxSlots) * nline * double(nvox) * double(rbytes) <= 48.0 * 1073741824.0 ? kMaxSlots : 2;
 }
 
 template <typename R>
@@ -590,7 +568,7 @@ struct Job : JobBase {
             L.maxslot = acc_slots(L.nvox, nline, sizeof(R));
             if (herm())
                 REQUIRE(L.maxslot >= kMaxSlots, "Hermite upwind interpolation needs 8 accumulator slots per "
-                                                "quantity (at most 4 GiB of them per level)");
+                                                "quantity (at most 48 GiB of them per level)");
             dalloc(L.acc, sizeof(R) * 2 * size_t(L.maxslot) * nline * L.nvox);
             dalloc(L.lc, sizeof(R) * 2 * nline * L.nvox);
             dalloc(L.partial, sizeof(double) * std::max<size_t>(blocks_for(L.nvox, 256), 1024));
