@@ -671,11 +671,24 @@ template <typename R, int DB>
 __global__ __launch_bounds__((sizeof(R) == 4 ? kMaxSweepWaves : DB) * 64)
 __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? kSweepWavesPerSimdF32 : 1))) void sweep_list_kernel(
     const SweepArgs<R>* __restrict__ jobs, const unsigned* __restrict__ first, int nact, int s) {
+    // The list is read through the constant address space with a wave-uniform index: the
+    // compiler then copies the job's arguments with scalar loads into scalar registers, as
+    // it does a kernel's own arguments (read as ordinary global data they would occupy
+    // vector registers and spill).  The host compilation pass, which never runs this code,
+    // has no such address space and reads plain memory.
+#if defined(__HIP_DEVICE_COMPILE__)
+    const auto* jl = (const __attribute__((address_space(4))) SweepArgs<R>*)(jobs);
+    const auto* fl = (const __attribute__((address_space(4))) unsigned*)(first);
+#else
+    const SweepArgs<R>* jl = jobs;
+    const unsigned* fl = first;
+#endif
     const unsigned work = xcd_work(blockIdx.x, gridDim.x);
     int j = 0;
-    while (j + 1 < nact && first[j + 1] <= work) ++j;
-    const SweepArgs<R> a = jobs[j];
-    const unsigned local = work - first[j];
+    while (j + 1 < nact && fl[j + 1] <= work) ++j;
+    j = __builtin_amdgcn_readfirstlane(j);
+    const SweepArgs<R> a = jl[j];
+    const unsigned local = work - fl[j];
     const unsigned T = (a.nxy + 63u) / 64u;
     const unsigned L = unsigned(a.atom->nline);
     sweep_step_body<R, DB, false>(a, s, local % T, int((local / T) % L), int(local / (T * L)), a.fc);

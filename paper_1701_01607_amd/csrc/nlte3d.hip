@@ -367,6 +367,11 @@ inline int freq_chunks_for(size_t nxy, int nline, size_t rbytes) {
     return fc;
 }
 
+// Directions per block of the work-list sweep for a level with fc frequency chunks: FP32
+// blocks hold 12 waves (12/fc directions), FP64 blocks three directions (their registers
+// allow one wave per SIMD).
+inline int list_block_dirs(size_t rbytes, int fc) { return rbytes == 8 ? 3 : kMaxSweepWaves / fc; }
+
 // Accumulator slots for a level: 8, which allow every block shape down to three
 // directions per block, wherever the 8-slot accumulators take at most 48 GiB (in FP32 with
 // five lines up to ~160 M voxels), else 2 (12-direction blocks).  Small blocks pay on
@@ -839,10 +844,12 @@ struct Job : JobBase {
     }
 
     // True where level k can share work-list sweep launches with other jobs: the plane-step
-    // sweep with bilinear upwind interpolation, one frequency pass, no active continua.
+    // sweep with bilinear upwind interpolation, one frequency pass, no active continua, and
+    // accumulator slots for the work list's block shape.
     bool list_sweep_ok(int k) const {
         const Level& L = *lev[k];
-        return !herm() && Qpass >= maxfreq && !info.cont_active && !capturing;
+        return !herm() && Qpass >= maxfreq && !info.cont_active && !capturing &&
+               kNDir / list_block_dirs(sizeof(R), L.fc) <= L.maxslot;
     }
 
     // The job's part of a work-list formal solution of level k: its line coefficients and
@@ -1527,6 +1534,8 @@ struct Batch {
         for (auto& e : evs) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
     }
 
+    static int class_db(int fc) { return list_block_dirs(sizeof(R), fc); }
+
     Table& table(int k, const std::vector<int>& set) {
         auto key = std::make_pair(k, set);
         auto it = tables.find(key);
@@ -1541,7 +1550,7 @@ struct Batch {
                 if (jobs[j]->lev[k]->fc == fc) order.push_back({jobs[j]->lev[k]->nz, j});
             if (order.empty()) continue;
             std::stable_sort(order.begin(), order.end(), [](auto& a, auto& b) { return a.first > b.first; });
-            const int db = kMaxSweepWaves / fc;
+            const int db = class_db(fc);
             c.first_h.push_back(0);
             for (auto& o : order) {
                 const Level& L = *jobs[o.second]->lev[k];
@@ -1605,9 +1614,9 @@ struct Batch {
                 int nact = 0;
                 while (nact < c.n && c.nz[nact] > s) ++nact;
                 if (!nact) continue;
-                switch (c.fc) {
-                    case 1: launch<12>(t, c, nact, s); break;
-                    case 2: launch<6>(t, c, nact, s); break;
+                switch (class_db(c.fc)) {
+                    case 12: launch<12>(t, c, nact, s); break;
+                    case 6: launch<6>(t, c, nact, s); break;
                     default: launch<3>(t, c, nact, s); break;
                 }
                 ++launches;
@@ -1615,7 +1624,7 @@ struct Batch {
         HIPCHK(hipGetLastError());
         HIPCHK(hipEventRecord(e1, stream));
         for (auto& c : t.cls)
-            for (int i = 0; i < c.n; ++i) jobs[c.idx[i]]->list_finish(k, kMaxSweepWaves / c.fc, c.nz[i]);
+            for (int i = 0; i < c.n; ++i) jobs[c.idx[i]]->list_finish(k, class_db(c.fc), c.nz[i]);
     }
 
     // iters[j] MALI iterations on level k for the jobs in `set`.

@@ -89,7 +89,11 @@ def run_stream(ctx, requests, arrivals, max_running=4, log=None, batch_max=1, pr
 
     def produce():
         for req in requests:
-            built.put(req() if callable(req) else req)
+            try:
+                built.put(req() if callable(req) else req)
+            except BaseException as e:     # handed to the submitting thread, which raises it
+                built.put(e)
+                return
 
     def collect():
         while True:
@@ -121,7 +125,10 @@ def run_stream(ctx, requests, arrivals, max_running=4, log=None, batch_max=1, pr
     t0 = time.monotonic()
     try:
         for ta in arrivals:
-            atom, atm, p, tag = built.get()
+            item = built.get()
+            if isinstance(item, BaseException):
+                raise item
+            atom, atm, p, tag = item
             while time.monotonic() - t0 < ta:
                 time.sleep(min(0.005, ta - (time.monotonic() - t0)))
             A, M = ctx.atom(atom), ctx.atmos(atm)

@@ -74,3 +74,20 @@ def test_combined_parts_pool_latencies_and_add_makespans():
     assert out["atmospheres_per_hr"] == pytest.approx(3600.0 * 4 / 10.0)
     assert out["p99_s"] == pytest.approx(np.percentile(lat, 99))
     assert out["device_busy_fraction"] == pytest.approx((4.0 + 2.0) / 10.0)
+
+
+def test_a_failing_request_builder_stops_the_stream_with_its_error():
+    serve = _serve()
+
+    class NoDevice:
+        def serve_config(self, n):
+            pass
+
+        def serve_batching(self, n):
+            pass
+
+    def broken():
+        raise ValueError("atmosphere generator failed")
+
+    with pytest.raises(ValueError, match="generator failed"):
+        serve.run_stream(NoDevice(), [broken], [0.0])
