@@ -53,7 +53,7 @@ def shape(atom, atm):
     return (len(atom["levels"]), atm["nz"], atm["ny"], atm["nx"])
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-3)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-5)])
 def test_iteration_cap_warns_and_keeps_a_readable_result(nl, ctx, prec, tol):
     atom, atm = ragged_case()
     lev = Level(atom, atm)
@@ -109,7 +109,7 @@ def test_a_run_resumed_from_its_populations_repeats_it_bitwise(nl, ctx, prec, me
     assert np.array_equal(resumed.history(), longrun.history()[first:])
 
 
-@pytest.mark.parametrize("prec,tol_fs,tol_n", [(0, 1e-9, 1e-8), (1, 2e-4, 1e-3)])
+@pytest.mark.parametrize("prec,tol_fs,tol_n", [(0, 1e-9, 1e-8), (1, 1e-5, 1e-5)])
 def test_prescribed_upper_boundary_parity(nl, ctx, prec, tol_fs, tol_n):
     atom, atm = ragged_case()
     lev0 = Level(atom, atm)
@@ -129,7 +129,9 @@ def test_prescribed_upper_boundary_parity(nl, ctx, prec, tol_fs, tol_n):
     assert relerr(jo, jfree) > 1e-3          # the boundary matters in this case
     job.mali(0, 2)
     n2, _ = mali(lev, 1, n0, fine_rhs(lev), 2)
-    assert relerr(job.populations(0, shape(atom, atm)), n2) < tol_n
+    en = relerr(job.populations(0, shape(atom, atm)), n2)
+    print(f"prec={prec} prescribed top: populations after 2 MALI err {en:.2e}")
+    assert en < tol_n
 
 
 def rough_case():
@@ -147,7 +149,7 @@ def rough_case():
     return atom, atm, levels, n
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 2e-3)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 2e-5)])
 def test_vcycle_negative_population_repair_parity(nl, ctx, prec, tol):
     atom, atm, levels, n = rough_case()
     st = Stats()

@@ -5,10 +5,11 @@
   dependent velocity: every column of the GPU result must equal the oracle's 1x1x129
   column, element by element (formal solution, then three MALI iterations).
 * The bench workload itself (64x64x129, random 3D fields): the FP32-sweep FAS solve
-  against the FP64 FAS solve, the labelled proxy reference, to the stated 1e-3; particle
+  against the FP64 FAS solve, the labelled proxy reference, to 1e-5 (measured 1.0e-6); particle
   conservation and positivity.
 * Twins of the 256x256x257 and 504x504x497 workloads (same generator, horizontal size /8,
-  25 frequencies per line, 4-level FMG): FP32 sweep against FP64 to 1e-3.
+  25 frequencies per line, 4-level FMG): FP32 sweep against FP64 to 1e-5 (measured 4.6e-7
+  and 9.4e-7).
 """
 import numpy as np
 import pytest
@@ -52,7 +53,7 @@ def homogeneous(nx, ny):
     return atm
 
 
-@pytest.mark.parametrize("prec,tol_fs,tol_n", [(0, 1e-9, 1e-9), (1, 2e-4, 1e-3)], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("prec,tol_fs,tol_n", [(0, 1e-9, 1e-9), (1, 1e-5, 1e-5)], ids=["fp64", "fp32"])
 def test_full_size_homogeneous_equals_1d_oracle(nl, ctx, prec, tol_fs, tol_n):
     atom = synth.caii_like_atom(101)
     atm3, atm1 = homogeneous(64, 64), homogeneous(1, 1)
@@ -93,7 +94,7 @@ def test_bench_workload_fp32_against_fp64(nl, ctx):
           f"C {r32.C:.2e} / {r64.C:.2e}")
     assert np.isfinite(n32).all() and (n32 > 0).all()
     assert cons < 1e-12
-    assert e < 1e-3
+    assert e < 1e-5
 
 
 @pytest.mark.parametrize("name,nx,ny", [("caii6_256x256x257", 32, 32), ("caii6_504x504x497", 64, 64)])
@@ -107,4 +108,4 @@ def test_fmg_twins_fp32_against_fp64(nl, ctx, name, nx, ny):
           f"C {r32.C:.2e} / {r64.C:.2e}")
     assert np.isfinite(n32).all() and (n32 > 0).all()
     assert cons < 1e-12
-    assert e < 1e-3
+    assert e < 1e-5

@@ -6,7 +6,8 @@
 * A 16x16x33 twin of the radiation-MHD-like generator (granulation fields and shock
   fronts, Sect. 3.1's Model 1 stand-in): full multigrid on four grids and two V-cycles.
 
-Tolerances: FP64 path 1e-7, FP32 sweep 1e-3 (relative, every population).
+Tolerances: FP64 path 1e-7, FP32 sweep 1e-5 (relative, every population; measured 1.3e-10
+and 6e-7 at most).
 """
 import numpy as np
 import pytest
@@ -75,7 +76,7 @@ def gpu_job(nl, ctx, atom, atm, prec):
     return ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.FAS, precision=prec, nlev=2, **NU))
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-3)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-5)])
 def test_bench_grid_three_mali_iterations_parity(nl, ctx, bench_grid, oracle_mali3, prec, tol):
     atom, atm, _ = bench_grid
     job = gpu_job(nl, ctx, atom, atm, prec)
@@ -85,7 +86,7 @@ def test_bench_grid_three_mali_iterations_parity(nl, ctx, bench_grid, oracle_mal
     assert e < tol
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-3)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-5)])
 def test_bench_grid_vcycle_parity(nl, ctx, bench_grid, oracle_vcycle, prec, tol):
     atom, atm, _ = bench_grid
     job = gpu_job(nl, ctx, atom, atm, prec)
@@ -114,7 +115,7 @@ def test_rmhd_twin_has_shock_fronts(rmhd_twin):
     assert jump > np.log(1.3)        # a front raises T by more than 30 % between planes
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-3)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-5)])
 def test_rmhd_twin_four_level_fmg_parity(nl, ctx, rmhd_twin, prec, tol):
     atom, atm, n_or, st = rmhd_twin
     job = ctx.job(ctx.atmos(atm), ctx.atom(atom),

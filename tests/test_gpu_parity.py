@@ -1,9 +1,9 @@
 """Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
 
 Same seeded inputs on both sides; comparisons after a fixed number of iterations or
-cycles.  Tolerances: FP64 path 1e-9 per stage (populations 1e-6 after solves), mixed
-path (FP32 sweep) 1e-3 on populations as stated for the method, with the measured error
-printed.  Grids are chosen ragged (plane sizes that are not multiples of the sweep tile)
+cycles.  Tolerances: FP64 path 1e-9 per stage (1e-8 to 1e-7 on populations after
+cycles), mixed path (FP32 sweep) 1e-5, about 10x the largest FP32 error measured on
+these cases (2e-7 to 1e-6), and printed.  Grids are chosen ragged (plane sizes that are not multiples of the sweep tile)
 and span several tiles.
 """
 import numpy as np
@@ -60,7 +60,7 @@ def ragged():
     return atom, atm, lev, n0
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-5)])
 @pytest.mark.parametrize("dpb", [0, 3, 12])
 def test_formal_solution_parity(nl, ctx, ragged, prec, tol, dpb):
     atom, atm, lev, n0 = ragged
@@ -76,7 +76,7 @@ def test_formal_solution_parity(nl, ctx, ragged, prec, tol, dpb):
     assert ej < tol and eo < tol
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-5)])
 def test_formal_solution_parity_wide_ragged_rows(nl, ctx, prec, tol):
     # a wide plane whose 64-point tiles straddle rows (100 points per row), the last tile
     # partly empty
@@ -93,7 +93,7 @@ def test_formal_solution_parity_wide_ragged_rows(nl, ctx, prec, tol):
     assert ej < tol and eo < tol
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-3)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-5)])
 def test_mali_iterations_parity(nl, ctx, ragged, prec, tol):
     atom, atm, lev, n0 = ragged
     npop, _ = shapes(atom, atm)
@@ -129,7 +129,7 @@ def test_residual_and_source_function_parity(nl, ctx, ragged):
     assert relerr(Sg, So) < 1e-12
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-5)])
+@pytest.mark.parametrize("prec,tol", [(0, 2e-7), (1, 2e-6)])
 def test_emergent_intensity_parity(nl, ctx, ragged, prec, tol):
     atom, atm, lev, n0 = ragged
     job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1))
@@ -137,10 +137,12 @@ def test_emergent_intensity_parity(nl, ctx, ragged, prec, tol):
     Ig = job.emergent(mus, lev.nf, atm["ny"], atm["nx"])
     Io = emergent_intensity(lev, n0, mus)
     # the output solve is FP64 in both precisions; the mixed job stores its level
-    # constants (damping, Doppler width, velocities) in FP32, hence the looser bound
+    # constants (damping, Doppler width, velocities) in FP32, hence the looser FP32 bound.
+    # In FP64 the two sides' Voigt functions differ most (the kernels' N = 32 Weideman
+    # series is good to ~1e-8 relative where the profile is small near |u| = 5).
     e = relerr(Ig, Io)
     print(f"prec={prec} emergent err {e:.2e}")
-    assert e < max(tol, 2e-6)
+    assert e < tol
 
 
 def mg_case(nfreq=7):
@@ -150,7 +152,7 @@ def mg_case(nfreq=7):
     return atom, atm
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-3)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-5)])
 def test_vcycle_parity(nl, ctx, prec, tol):
     atom, atm = mg_case()
     p = OParams(nlev=3, nu0=3, nu1=2, nu2=2, nu3=6)
@@ -167,7 +169,7 @@ def test_vcycle_parity(nl, ctx, prec, tol):
     assert e < tol
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-3)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-5)])
 @pytest.mark.parametrize("fmg", [False, True])
 def test_fas_fmg_fixed_cycles_parity(nl, ctx, prec, tol, fmg):
     atom, atm = mg_case()
@@ -275,7 +277,7 @@ def test_hermite_prolongation_parity(nl, ctx):
     job.close()
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-3)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-5)])
 @pytest.mark.parametrize("restr,coarse,interp,fmg", [(1, 0, 0, False), (2, 0, 0, False), (0, 2, 0, False),
                                                      (0, 0, 1, False), (0, 0, 1, True)],
                          ids=["half", "inject", "inject_atmos", "hermite", "hermite_fmg"])
@@ -345,7 +347,7 @@ def test_graph_replay_equals_eager(nl, ctx, method, ops):
     assert outs[0][2] == pytest.approx(outs[1][2]) and outs[0][3] == outs[1][3]
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-3)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-5)])
 def test_undamped_line_far_wings_stay_finite(nl, ctx, prec, tol):
     # Doppler line with velocities up to 10 km/s and v_D ~ 1 km/s: exp(-u^2) and the
     # opacity underflow (or become denormal) in FP32 far out in the wings; those points
@@ -387,7 +389,7 @@ def test_block_shape_does_not_change_results(nl, ctx, prec, nx, ny, shapes_):
             assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-5)])
 def test_formal_solution_parity_one_chunk_per_wave(nl, ctx, prec, tol):
     """Planes large enough for one frequency chunk per wave (96x72), against the oracle."""
     atom, atm, lev, n0, jo, oo = _one_chunk_case(96, 72)
@@ -415,7 +417,7 @@ def _one_chunk_case(nx, ny):
     return _ONE_CHUNK[(nx, ny)]
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-5)])
 def test_strongly_damped_line_parity(nl, ctx, prec, tol):
     """Damping well above the Doppler width (a ~ 40), so that the profile wings beyond
     |u| = 5 lie far off the real axis of the Faddeeva function."""
@@ -458,7 +460,7 @@ def ragged_hermite():
     return atom, atm, lev, n0
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 2e-4)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-5)])
 def test_hermite_upwind_formal_solution_parity(nl, ctx, ragged_hermite, ragged, prec, tol):
     atom, atm, lev, n0 = ragged_hermite
     npop, nln = shapes(atom, atm)
@@ -475,7 +477,7 @@ def test_hermite_upwind_formal_solution_parity(nl, ctx, ragged_hermite, ragged, 
         assert relerr(jb, jo) > 1000 * tol
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-3)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-5)])
 def test_hermite_upwind_mali_and_emergent_parity(nl, ctx, ragged_hermite, prec, tol):
     atom, atm, lev, n0 = ragged_hermite
     npop, _ = shapes(atom, atm)
@@ -495,7 +497,7 @@ def test_hermite_upwind_mali_and_emergent_parity(nl, ctx, ragged_hermite, prec, 
     assert ee < (2e-7 if prec == 0 else 2e-5)
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-3)])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-5)])
 def test_hermite_upwind_fas_parity_and_constraints(nl, ctx, prec, tol):
     atom, atm = mg_case()
     n_or, st, _ = solve_fas(atom, atm, OParams(nlev=3, nu1=2, nu2=2, nu3=6, sc_interp="hermite"), cycles=2)
