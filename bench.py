@@ -268,12 +268,12 @@ def solve_params(nlte, wl, **kw):
     return nlte.SolveParams(**p)
 
 
-def m2_extras(nlte, ctx, torch, np, solves=2, mali_max_iter=800):
-    """The 64x64x129 workload solved end to end: FAS-FP32 atmospheres/hr, the plain
-    MALI-FP64 solve beside it, and the FP32 error per result (populations, line source
+def solve_extras(nlte, ctx, torch, np, name="caii6_64x64x129", solves=2, mali_max_iter=800, fp32_error=True):
+    """A workload solved end to end with the FP32 sweep (atmospheres/hr over `solves`
+    timed solves after a warm-up one), the plain MALI-FP64 solve of the same atmosphere
+    beside it, and (fp32_error) the FP32 error per result (populations, line source
     functions, emergent intensity) against the FP64 path run with the same cycles."""
     from paper_1701_01607_amd import synth
-    name = "caii6_64x64x129"
     wl = WORKLOADS[name]
     atom, atm = synth.workload(name)
     A, M = ctx.atom(atom), ctx.atmos(atm)
@@ -298,14 +298,16 @@ def m2_extras(nlte, ctx, torch, np, solves=2, mali_max_iter=800):
         rc, r, n32, S32, I32 = solve(nlte.MIXED)
     torch.cuda.synchronize()
     t_solve = (time.perf_counter() - t0) / solves
-    log(f"{name} FAS-FP32: rc={rc} cycles={r.cycles} E_est={r.E_est:.3e} {t_solve:.2f} s per solve")
-    _, r64, n64, S64, I64 = solve(nlte.FP64, E_target=0.0, max_iter=r.cycles)
-    ok = np.isfinite(S64) & np.isfinite(S32)
-    err = {"n": float(np.max(np.abs(n32 / n64 - 1))),
-           "S_l": float(np.max(np.abs(S32[ok] / S64[ok] - 1))),
-           "I_top": float(np.max(np.abs(I32.astype(np.float64) / I64.astype(np.float64) - 1))),
-           "reference": f"FAS with the FP64 sweep, the same {r.cycles} cycles",
-           "n_tiny_excluded": False}
+    log(f"{name} {wl['method']}-FP32: rc={rc} cycles={r.cycles} E_est={r.E_est:.3e} {t_solve:.2f} s per solve")
+    err = None
+    if fp32_error:
+        _, r64, n64, S64, I64 = solve(nlte.FP64, E_target=0.0, max_iter=r.cycles)
+        ok = np.isfinite(S64) & np.isfinite(S32)
+        err = {"n": float(np.max(np.abs(n32 / n64 - 1))),
+               "S_l": float(np.max(np.abs(S32[ok] / S64[ok] - 1))),
+               "I_top": float(np.max(np.abs(I32.astype(np.float64) / I64.astype(np.float64) - 1))),
+               "reference": f"{wl['method']} with the FP64 sweep, the same {r.cycles} cycles",
+               "n_tiny_excluded": False}
     mp = nlte.SolveParams(method=nlte.MALI, precision=nlte.FP64, nlev=1, E_target=1e-3, max_iter=mali_max_iter,
                           timing=1)
     torch.cuda.synchronize()
@@ -321,7 +323,7 @@ def m2_extras(nlte, ctx, torch, np, solves=2, mali_max_iter=800):
             "converged": rc == 0, "cycles": r.cycles, "E_est": r.E_est, "fine_fs_equiv": r.fine_fs_equiv,
             "fp32_error_vs_fp64": err,
             "mali_fp64": {"seconds": tm, "iterations": rm.iterations, "converged": rcm == 0, "E_est": rm.E_est,
-                          "atmospheres_per_hr": 3600.0 / tm, "speedup_fas_fp32": tm / t_solve,
+                          "atmospheres_per_hr": 3600.0 / tm, "speedup_fp32_multigrid": tm / t_solve,
                           "max_rel_diff_vs_fas": float(np.max(np.abs(n32 / nm - 1)))}}
 
 
@@ -406,7 +408,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="caii6_504x504x497", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mali", action="store_true", help="skip the 64x64x129 solves reported beside the steps")
+    ap.add_argument("--no-mali", action="store_true", help="skip the whole solves reported beside the steps")
+    ap.add_argument("--no-fp32-error", action="store_true",
+                    help="other workloads: skip the FP64 solve with the same cycles that measures the FP32 error")
     ap.add_argument("--mali-max-iter", type=int, default=800)
     ap.add_argument("--dirs-per-block", type=int, default=0, help="sweep block shape (0: autotune)")
     ap.add_argument("--graph", type=int, default=0, help="1: replay V-cycles from a captured HIP graph")
@@ -587,11 +591,12 @@ def main():
     del M
     if not args.no_mali and not wl["fp64"]:
         if fine_step:
-            out["solve_64x64x129"] = m2_extras(nlte, ctx, torch, np, mali_max_iter=args.mali_max_iter)
+            out["solve_64x64x129"] = solve_extras(nlte, ctx, torch, np, mali_max_iter=args.mali_max_iter)
         else:
-            m2 = m2_extras(nlte, ctx, torch, np, solves=1, mali_max_iter=args.mali_max_iter)
-            out["mali_fp64"] = m2["mali_fp64"]
-            out["fp32_error_vs_fp64"] = m2["fp32_error_vs_fp64"]
+            ex = solve_extras(nlte, ctx, torch, np, name=args.workload, solves=1, mali_max_iter=args.mali_max_iter,
+                              fp32_error=not args.no_fp32_error)
+            out["mali_fp64"] = ex["mali_fp64"]
+            out["fp32_error_vs_fp64"] = ex["fp32_error_vs_fp64"]
     if sample is not None:
         feq = M4_FINE_FS_EQUIV if fine_step else out.get("fine_fs_equiv", 60.0)
         out["cpu_baseline"] = cpu_baseline(sample, fine_updates, feq)
