@@ -462,7 +462,12 @@ def main():
     stream = torch.cuda.current_stream()
     ctx = nlte.Context(0, stream.cuda_stream)
     A = ctx.atom(atom)
+    torch.cuda.synchronize()
+    t_up = time.perf_counter()
     M = ctx.atmos(atm)              # resident on the device before the timed region
+    torch.cuda.synchronize()
+    upload_s = time.perf_counter() - t_up
+    log(f"atmosphere uploaded from host memory in {upload_s:.2f} s")
     params = solve_params(nlte, wl, timing=0 if args.graph else 1, dirs_per_block=args.dirs_per_block,
                           graph=args.graph)
     nf = sum(len(l["q"]) for l in atom["lines"])
@@ -587,6 +592,7 @@ def main():
         roofline(atom, atm, wl["fp64"], upd, sweep_ms, launches, dpb, args.workload),
     }
     out.update(extra)
+    out["atmosphere_upload_s"] = upload_s   # host to device, once per atmosphere, outside every figure
     out["hbm_copy_gbs"] = hbm_copy_gbs(torch)
     del M
     if not args.no_mali and not wl["fp64"]:
