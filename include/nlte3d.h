@@ -155,7 +155,10 @@ typedef struct {
                                   result.fallback = 1.  0: the run fails with
                                   NLTE_E_DIVERGED. */
     const double* top_I;       /* prescribed incoming intensity at the top [nf][ny][nx] or NULL */
-    int dirs_per_block;        /* sweep directions per workgroup: 0 = autotune, else 3/6/12 (results do not depend on it) */
+    int dirs_per_block;        /* sweep directions per workgroup: 0 = autotune, else 3/6/12 where a
+                                  level's frequency chunks (3/6/12 directions x 4/2/1 chunks
+                                  per 12-wave block) and accumulator slots allow it, else
+                                  autotuned there (results do not depend on it) */
     int timing;                /* 1: time each phase with HIP events on the context stream */
     int graph;                 /* 1: capture one V-cycle (FAS/FMG) or one MALI iteration as a
                                   HIP graph on a job-private stream and replay it; the first
@@ -178,7 +181,7 @@ typedef struct {
                                   solution (Sect. 3 names linear and Hermite-spline);
                                   bilinear by default.  Hermite runs the plane-step sweep
                                   with three directions per block and needs levels whose
-                                  8-slot accumulators fit in 4 GiB; it applies to the
+                                  8-slot accumulators fit in 48 GiB; it applies to the
                                   emergent intensity too. */
     int diverge_cycles;        /* divergence guard of FAS/FMG (Sect. 4.10: cycles can diverge when
                                   coarse grids produce many negative populations): the run
