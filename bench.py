@@ -344,14 +344,14 @@ def batch_bench(args):
             atom, atm = synth.workload(args.workload)
             atm["ntot"] = atm["ntot"] * (0.5 + j / max(1, n - 1))
             inputs.append((atom, atm))
-        params = solve_params(nlte, wl)
+        params = solve_params(nlte, wl, graph=int(args.graph), timing=0 if args.graph else 1)
         kind = "two_level_16x16x32 x %d (MALI FP64, tol_C 1e-4)" % n
     else:
         for j in range(n):
             atm = synth.atmos_stratified(nx=16, ny=16, nz=33, dx=150 * synth.KM, seed=1607100 + j)
             inputs.append((synth.caii_like_atom(101), atm))
         params = nlte.SolveParams(method=nlte.FAS, precision=nlte.MIXED, nlev=3, nu0=20, nu1=4, nu2=8, nu3=32,
-                                  E_target=1e-3, max_iter=60, timing=1)
+                                  E_target=1e-3, max_iter=60, timing=0 if args.graph else 1, graph=int(args.graph))
         kind = "caii6_16x16x33 x %d (FAS FP32, 3 grids, E <= 1e-3)" % n
     torch.cuda.init()
     ctx = nlte.Context(0, torch.cuda.current_stream().cuda_stream)
@@ -387,14 +387,16 @@ def batch_bench(args):
     same = all(np.array_equal(ha, hb) for (_, ha), (_, hb) in zip(ra, rb))
     la = sum(r.sweep_launches for r, _ in ra)
     sa = sum(r.ms_sweep for r, _ in ra)
-    out = {"metric": "batched small solves", "kind": kind, "n": n,
+    # replayed graphs are not timed: launch times only for eager runs
+    per_launch = (lambda ms, n_: 1e3 * ms / n_ if n_ and not args.graph else None)
+    out = {"metric": "batched small solves", "kind": kind, "n": n, "graph": bool(args.graph),
            "alone": {"seconds": t1 - t0, "atmospheres_per_hr": 3600.0 * n / (t1 - t0),
-                     "sweep_launches": la, "sweep_ms": sa, "us_per_launch": 1e3 * sa / la if la else None},
+                     "sweep_launches": la, "sweep_ms": sa, "us_per_launch": per_launch(sa, la)},
            "batched": {"seconds": t2 - t1, "atmospheres_per_hr": 3600.0 * n / (t2 - t1),
                        "sweep_ms": rb[0][0].ms_sweep,
                        # one launch per plane step and chunk class: the longest job's count
                        "sweep_launches": max(r.sweep_launches for r, _ in rb),
-                       "us_per_launch": 1e3 * rb[0][0].ms_sweep / max(r.sweep_launches for r, _ in rb)},
+                       "us_per_launch": per_launch(rb[0][0].ms_sweep, max(r.sweep_launches for r, _ in rb))},
            "speedup": (t1 - t0) / (t2 - t1), "histories_equal": same,
            "iterations_or_cycles": [max(r.iterations, r.cycles) for r, _ in ra]}
     print(json.dumps(out))

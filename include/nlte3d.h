@@ -258,10 +258,13 @@ nlte_status nlte_release(nlte_ctx* ctx, nlte_job job);
  * batch when its own stop rule, iteration cap or divergence guard ends its run.  Each job's
  * populations and history are bit for bit those of nlte_job_run on it alone.  The jobs must
  * share precision, method, number of grids and iteration counts (nu_fmg, nu0..nu3), sweep
- * with the plane-step kernel and bilinear upwind interpolation in one frequency pass, and
- * have no active continua and no graph replay (else NLTE_E_INVALID before any work); sizes,
- * atoms and stop rules may differ.  results[j] (njobs entries) gets job j's result, with
- * ms_sweep the batch's sweep time.  Returns the most severe warning of the jobs, or the
+ * with the plane-step kernel and bilinear upwind interpolation in one frequency pass, have
+ * no active continua, and all or none ask for graph replay (params.graph; else
+ * NLTE_E_INVALID before any work); sizes, atoms and stop rules may differ.  With graph
+ * replay the batch runs on a private stream that follows the context's: each repeated step
+ * of a job set (a MALI iteration, a cycle after the first) runs eagerly once, is captured
+ * as a HIP graph the next time and replayed after that.  results[j] (njobs entries) gets
+ * job j's result, with ms_sweep the batch's sweep time (eager steps only).  Returns the most severe warning of the jobs, or the
  * error of the first job that failed (the other results stay valid). */
 nlte_status nlte_batch_run(nlte_ctx* ctx, int njobs, const nlte_job* jobs, nlte_result* results);
 
@@ -375,7 +378,7 @@ nlte_status nlte_serve_config(nlte_ctx* ctx, int max_running);
 /* Continuous batching of served jobs (1..64; 1, the default, runs each job alone): a
  * worker runs the job it admits together with queued jobs that can share its batch (as in
  * nlte_batch_run: one precision, method, number of grids and iteration counts, plane-step
- * bilinear sweeps, no active continua, no graphs), up to batch_max at a time, in queue
+ * bilinear sweeps, no active continua, the same graph setting), up to batch_max at a time, in queue
  * order as their footprints fit the budget; between cycles (MALI: iterations) it admits
  * more such jobs into the running batch, and each job is published as soon as its own run
  * ends.  Only grids too small to fill the device alone are batched: a batch's summed

@@ -1530,8 +1530,122 @@ struct Batch {
     double ms_sweep = 0;
     long long launches = 0;
 
+    // HIP-graph replay of repeated steps, when every job asked for it (params.graph): a step
+    // (one MALI iteration, or one cycle after the first) of a given job set runs eagerly once,
+    // creating its work lists; the next time it is captured, and from then on replayed.  The
+    // host bookkeeping of the captured step (formal-solution counts, updates, launches) is
+    // recorded at capture and added per replay; replayed work is not timed.
+    bool graphs = false;
+    bool capturing = false;
+    struct Book {
+        std::vector<long long> fs;   // per level
+        double cost = 0, upd = 0;
+        long long launches = 0;
+    };
+    struct Replay {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        std::vector<Book> delta;      // per job of the set
+        long long launches = 0;       // the batch's own launch count
+        bool eager_only = false;      // capture failed once: this step stays eager
+    };
+    std::map<std::pair<std::vector<int>, int>, Replay> replays;
+    std::map<std::pair<std::vector<int>, int>, int> eager_runs;
+
     ~Batch() {
         for (auto& e : evs) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+        for (auto& r : replays) drop(r.second);
+    }
+
+    static void drop(Replay& r) {
+        if (r.exec) (void)hipGraphExecDestroy(r.exec);
+        if (r.graph) (void)hipGraphDestroy(r.graph);
+        r.exec = nullptr;
+        r.graph = nullptr;
+    }
+
+    Book book(int j) const {
+        const Job<R>& J = *jobs[j];
+        Book b;
+        for (auto& L : J.lev) b.fs.push_back(L->fs_count);
+        b.cost = J.cost_units;
+        b.upd = J.updates;
+        b.launches = J.sweep_launches;
+        return b;
+    }
+
+    void set_book(int j, const Book& b) {
+        Job<R>& J = *jobs[j];
+        for (size_t k = 0; k < J.lev.size(); ++k) J.lev[k]->fs_count = b.fs[k];
+        J.cost_units = b.cost;
+        J.updates = b.upd;
+        J.sweep_launches = b.launches;
+    }
+
+    // Runs `work` for the jobs in `set`: eagerly, or as a captured graph (see `graphs`).
+    template <typename F>
+    void run_step(const std::vector<int>& set, int kind, bool repeatable, F&& work) {
+        const auto key = std::make_pair(set, kind);
+        Replay& r = replays[key];
+        if (!graphs || !repeatable || r.eager_only || eager_runs[key] < 1) {
+            work();
+            if (repeatable) ++eager_runs[key];
+            return;
+        }
+        if (!r.exec) {
+            std::vector<Book> before;
+            for (int j : set) before.push_back(book(j));
+            const long long l0 = launches;
+            for (int j : set) jobs[j]->capturing = true;
+            capturing = true;
+            bool ok = true;
+            HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            try {
+                work();
+            } catch (...) {
+                ok = false;
+            }
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(stream, &g);
+            capturing = false;
+            for (int j : set) jobs[j]->capturing = false;
+            if (ok && ec == hipSuccess && g && hipGraphInstantiate(&r.exec, g, nullptr, nullptr, 0) == hipSuccess) {
+                r.graph = g;
+                r.delta.clear();
+                for (size_t i = 0; i < set.size(); ++i) {
+                    const Book after = book(set[i]);
+                    Book d;
+                    for (size_t k = 0; k < after.fs.size(); ++k) d.fs.push_back(after.fs[k] - before[i].fs[k]);
+                    d.cost = after.cost - before[i].cost;
+                    d.upd = after.upd - before[i].upd;
+                    d.launches = after.launches - before[i].launches;
+                    r.delta.push_back(d);
+                    set_book(set[i], before[i]);
+                }
+                r.launches = launches - l0;
+                launches = l0;
+            } else {
+                // nothing ran on the device: undo the host bookkeeping and run eagerly
+                (void)hipGetLastError();
+                if (g) (void)hipGraphDestroy(g);
+                r.exec = nullptr;
+                r.eager_only = true;
+                for (size_t i = 0; i < set.size(); ++i) set_book(set[i], before[i]);
+                launches = l0;
+                work();
+                return;
+            }
+        }
+        HIPCHK(hipGraphLaunch(r.exec, stream));
+        for (size_t i = 0; i < set.size(); ++i) {
+            Book b = book(set[i]);
+            for (size_t k = 0; k < b.fs.size(); ++k) b.fs[k] += r.delta[i].fs[k];
+            b.cost += r.delta[i].cost;
+            b.upd += r.delta[i].upd;
+            b.launches += r.delta[i].launches;
+            set_book(set[i], b);
+        }
+        launches += r.launches;
     }
 
     static int class_db(int fc) { return list_block_dirs(sizeof(R), fc); }
@@ -1540,6 +1654,7 @@ struct Batch {
         auto key = std::make_pair(k, set);
         auto it = tables.find(key);
         if (it != tables.end()) return *it->second;
+        if (capturing) throw Error(NLTE_E_INVALID, "work list missing during graph capture");
         auto t = std::make_unique<Table>();
         std::vector<SweepArgs<R>> args;
         for (int fc : {1, 2, 4}) {
@@ -1604,11 +1719,13 @@ struct Batch {
         if (set.empty()) return;
         Table& t = table(k, set);
         for (int j : set) jobs[j]->line_coef(k);
-        hipEvent_t e0, e1;
-        HIPCHK(hipEventCreate(&e0));
-        HIPCHK(hipEventCreate(&e1));
-        evs.push_back({e0, e1});
-        HIPCHK(hipEventRecord(e0, stream));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (!capturing) {
+            HIPCHK(hipEventCreate(&e0));
+            HIPCHK(hipEventCreate(&e1));
+            evs.push_back({e0, e1});
+            HIPCHK(hipEventRecord(e0, stream));
+        }
         for (int s = 0; s < t.maxnz; ++s)
             for (auto& c : t.cls) {
                 int nact = 0;
@@ -1622,7 +1739,7 @@ struct Batch {
                 ++launches;
             }
         HIPCHK(hipGetLastError());
-        HIPCHK(hipEventRecord(e1, stream));
+        if (!capturing) HIPCHK(hipEventRecord(e1, stream));
         for (auto& c : t.cls)
             for (int i = 0; i < c.n; ++i) jobs[c.idx[i]]->list_finish(k, class_db(c.fc), c.nz[i]);
     }
@@ -1740,17 +1857,23 @@ struct Batch {
         const int top = j0.nlev - 1;
         const bool m = j0.is_mali();
         if (m) {
-            mali(top, set, all(1));
+            run_step(set, 0, true, [&]() { mali(top, set, all(1)); });
         } else {
             std::vector<char> first(jobs.size(), 0);
+            bool any_first = false;
             for (int j : set) {
-                Level& F = *jobs[j]->lev[top];
-                jobs[j]->dcopy(F.n.template as<double>(), jobs[j]->nprev.template as<double>(),
-                               size_t(jobs[j]->N) * F.nvox);
                 first[j] = rs[j].first ? 1 : 0;
+                any_first = any_first || first[j];
             }
-            vcycle(top, set, first);
-            for (int j : set) jobs[j]->cycle_change_enqueue(top);
+            run_step(set, 1, !any_first, [&]() {
+                for (int j : set) {
+                    Level& F = *jobs[j]->lev[top];
+                    jobs[j]->dcopy(F.n.template as<double>(), jobs[j]->nprev.template as<double>(),
+                                   size_t(jobs[j]->N) * F.nvox);
+                }
+                vcycle(top, set, first);
+                for (int j : set) jobs[j]->cycle_change_enqueue(top);
+            });
         }
         for (int j : set) {
             bool over = false;
@@ -1768,6 +1891,19 @@ struct Batch {
                 ended.push_back(j);
             }
         }
+        // graphs of job sets with an ended job never run again
+        if (!ended.empty())
+            for (auto it = replays.begin(); it != replays.end();) {
+                bool stale = false;
+                for (int j : it->first.first)
+                    stale = stale || std::find(ended.begin(), ended.end(), j) != ended.end();
+                if (stale) {
+                    drop(it->second);
+                    it = replays.erase(it);
+                } else {
+                    ++it;
+                }
+            }
         // sweep time of the batch so far (events resolved as they complete)
         HIPCHK(hipStreamSynchronize(stream));
         for (auto& e : evs) {
@@ -1802,7 +1938,7 @@ bool batchable(const Job<R>& a, const Job<R>& j) {
     const nlte_params& p = j.params;
     const nlte_params& q = a.params;
     if (p.method != q.method || j.nlev != a.nlev || p.nu_fmg != q.nu_fmg || p.nu0 != q.nu0 || p.nu1 != q.nu1 ||
-        p.nu2 != q.nu2 || p.nu3 != q.nu3 || p.graph)
+        p.nu2 != q.nu2 || p.nu3 != q.nu3 || (p.graph != 0) != (q.graph != 0))
         return false;
     for (int k = 0; k < j.nlev; ++k)
         if (!j.list_sweep_ok(k)) return false;
@@ -1813,9 +1949,6 @@ bool batchable(const Job<R>& a, const Job<R>& j) {
 template <typename R>
 nlte_status run_batch(nlte_ctx* ctx, const std::vector<JobBase*>& in, hipStream_t stream, nlte_result* out,
                       std::string* first_error) {
-    Batch<R> b;
-    b.ctx = ctx;
-    b.stream = stream;
     std::vector<Job<R>*> js;
     for (JobBase* jb : in) {
         auto* j = dynamic_cast<Job<R>*>(jb);
@@ -1824,9 +1957,41 @@ nlte_status run_batch(nlte_ctx* ctx, const std::vector<JobBase*>& in, hipStream_
     }
     for (Job<R>* j : js) REQUIRE(batchable(*js[0], *j), "a batch takes jobs of one method, number of grids and "
                                                          "iteration counts, with plane-step bilinear sweeps in "
-                                                         "one frequency pass, no active continua and no graphs");
+                                                         "one frequency pass, no active continua, and graph "
+                                                         "replay asked for by all of them or by none");
+    // Graph capture needs a stream of its own (the context's may be the null stream): the
+    // batch then runs on a private stream that follows the context's and that the
+    // context's stream waits for at the end.
+    struct Private {
+        hipStream_t parent = nullptr, s = nullptr;
+        hipEvent_t ev = nullptr;
+        ~Private() {
+            if (!s) {
+                if (ev) (void)hipEventDestroy(ev);
+                return;
+            }
+            if (hipEventRecord(ev, s) == hipSuccess) (void)hipStreamWaitEvent(parent, ev, 0);
+            (void)hipStreamSynchronize(s);
+            (void)hipStreamDestroy(s);
+            (void)hipEventDestroy(ev);
+        }
+    } priv;
+    const bool graphs = !in.empty() && in[0]->params.graph != 0;
+    hipStream_t bs = stream;
+    if (graphs) {
+        priv.parent = stream;
+        HIPCHK(hipEventCreateWithFlags(&priv.ev, hipEventDisableTiming));
+        HIPCHK(hipStreamCreateWithFlags(&priv.s, hipStreamNonBlocking));
+        HIPCHK(hipEventRecord(priv.ev, stream));
+        HIPCHK(hipStreamWaitEvent(priv.s, priv.ev, 0));
+        bs = priv.s;
+    }
+    Batch<R> b;
+    b.ctx = ctx;
+    b.stream = bs;
+    b.graphs = graphs;
     b.add(js);
-    for (Job<R>* j : b.jobs) j->batch_stream = stream;
+    for (Job<R>* j : b.jobs) j->batch_stream = bs;
     try {
         b.run(out);
     } catch (...) {
@@ -1926,7 +2091,8 @@ static bool batch_key_equal(const JobBase* a, const JobBase* b) {
     const nlte_params& q = b->params;
     auto nl = [](const nlte_params& x) { return x.method == NLTE_MALI ? 1 : std::max(1, x.nlev); };
     return a->prec == b->prec && p.method == q.method && nl(p) == nl(q) && p.nu_fmg == q.nu_fmg &&
-           p.nu0 == q.nu0 && p.nu1 == q.nu1 && p.nu2 == q.nu2 && p.nu3 == q.nu3;
+           p.nu0 == q.nu0 && p.nu1 == q.nu1 && p.nu2 == q.nu2 && p.nu3 == q.nu3 &&
+           (p.graph != 0) == (q.graph != 0);
 }
 // Serving batches exist to fill the device with grids too small to fill it alone.  One
 // plane step of 64x64 points x 24 directions x 505 frequencies (49.6 M updates) already
@@ -1948,7 +2114,7 @@ static bool batch_similar(const JobBase* a, const JobBase* b) {
 
 static bool batch_candidate(const JobBase* j) {
     const nlte_params& p = j->params;
-    return !p.graph && p.sc_interp == NLTE_SC_BILINEAR &&
+    return p.sc_interp == NLTE_SC_BILINEAR &&
            (p.sweep_kernel == NLTE_SWEEP_AUTO || p.sweep_kernel == NLTE_SWEEP_PLANE_STEP) &&
            !j->src_atom->info.cont_active && plane_work(j) < kBatchFill;
 }
@@ -1993,6 +2159,7 @@ void serve_batch(nlte_ctx* ctx, JobBase* head) {
     Batch<R> b;
     b.ctx = ctx;
     b.stream = bs;
+    b.graphs = head->params.graph != 0;
     std::vector<JobBase*> pending = {head};
     for (JobBase* q : admit_joiners(ctx, head, ctx->batch_max - 1, kBatchFill - plane_work(head)))
         pending.push_back(q);

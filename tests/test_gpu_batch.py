@@ -117,10 +117,47 @@ def test_a_job_falling_back_to_mali_inside_a_batch(nl, ctx):
         assert a[:3] == b[:3] and np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4]), i
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("method", ["FAS", "MALI"])
+def test_graph_replayed_batches_equal_alone_solves(nl, ctx, prec, method):
+    """Jobs asking for HIP-graph replay batch together: each repeated step of the job set
+    is captured once and replayed; populations, histories and the counters the host keeps
+    for replayed work (formal solutions, updates, launches) equal the alone runs'."""
+    inputs = mixed_inputs()[:4] if method == "FAS" else [
+        (synth.two_level_atom(), synth.atmos_isothermal(nx=16, ny=16, nz=32 - 8 * (j % 2))) for j in range(3)]
+
+    def params_for(i):
+        if method == "FAS":
+            return nl.SolveParams(method=nl.FAS, precision=prec, nlev=2, nu0=3, nu1=2, nu2=2, nu3=8,
+                                  E_target=(1e-3, 1e-5, 1e-4)[i % 3], max_iter=20, graph=1)
+        return nl.SolveParams(method=nl.MALI, precision=prec, nlev=1, tol_C=(1e-4, 1e-3)[i % 2], E_target=0.0,
+                              max_iter=400, graph=1)
+
+    level = 1 if method == "FAS" else 0
+    alone = []
+    for i, (atom, atm) in enumerate(inputs):
+        job = ctx.job(ctx.atmos(atm), ctx.atom(atom), params_for(i))
+        rc, r = job.run()
+        alone.append((rc, r.iterations, r.cycles, job.history(), pops(job, atom, atm, level), r.updates,
+                      r.fine_fs_equiv))
+        job.close()
+    jobs = [ctx.job(ctx.atmos(atm), ctx.atom(atom), params_for(i)) for i, (atom, atm) in enumerate(inputs)]
+    rc, res = ctx.batch_run(jobs)
+    for i, (j, r, (atom, atm)) in enumerate(zip(jobs, res, inputs)):
+        a = alone[i]
+        assert (r.status, r.iterations, r.cycles) == a[:3], i
+        assert np.array_equal(j.history(), a[3]), f"job {i}: history differs"
+        assert np.array_equal(pops(j, atom, atm, level), a[4]), f"job {i}: populations differ"
+        assert r.updates == a[5] and abs(r.fine_fs_equiv - a[6]) < 1e-9, f"job {i}: bookkeeping differs"
+    print(f"prec={prec} {method}: steps alone {[a[1] if method == 'MALI' else a[2] for a in alone]}")
+    for j in jobs:
+        j.close()
+
+
 def test_incompatible_jobs_are_rejected_before_any_work(nl, ctx):
     (atom, atm), (atom2, atm2) = mixed_inputs()[:2]
     base = dict(method=nl.FAS, nlev=2, nu1=2, nu2=2, nu3=8)
-    for other in (dict(precision=nl.FP64), dict(nu3=4), dict(sc_interp=nl.SC_HERMITE), dict(nlev=1)):
+    for other in (dict(precision=nl.FP64), dict(nu3=4), dict(sc_interp=nl.SC_HERMITE), dict(nlev=1), dict(graph=1)):
         p2 = dict(base, precision=nl.MIXED)
         p2.update(other)
         a = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(precision=nl.MIXED, **base))
