@@ -1585,11 +1585,15 @@ struct Batch {
     // Runs `work` for the jobs in `set`: eagerly, or as a captured graph (see `graphs`).
     template <typename F>
     void run_step(const std::vector<int>& set, int kind, bool repeatable, F&& work) {
+        if (!graphs || !repeatable) {
+            work();
+            return;
+        }
         const auto key = std::make_pair(set, kind);
         Replay& r = replays[key];
-        if (!graphs || !repeatable || r.eager_only || eager_runs[key] < 1) {
+        if (r.eager_only || eager_runs[key] < 1) {
             work();
-            if (repeatable) ++eager_runs[key];
+            ++eager_runs[key];
             return;
         }
         if (!r.exec) {
@@ -1899,6 +1903,7 @@ struct Batch {
                     stale = stale || std::find(ended.begin(), ended.end(), j) != ended.end();
                 if (stale) {
                     drop(it->second);
+                    eager_runs.erase(it->first);
                     it = replays.erase(it);
                 } else {
                     ++it;
