@@ -238,3 +238,48 @@ def test_serving_batches_only_small_grids_of_similar_size(nl):
     for j in jobs:
         j.close()
     ctx.close()
+
+
+def test_served_graph_jobs_batch_and_equal_alone(nl):
+    """Served jobs that ask for graph replay share batches with each other (not with eager
+    jobs); each result equals the job alone."""
+    import torch
+    ctx = nl.Context(0, torch.cuda.current_stream().cuda_stream)
+
+    def req(n, nz, seed, graph):
+        atm = synth.atmos_stratified(nx=n, ny=n, nz=nz, dx=150 * synth.KM, seed=seed)
+        atm["ntot"] = atm["ntot"] * 0.1
+        return (synth.caii_like_atom(9), atm,
+                nl.SolveParams(method=nl.FAS, precision=nl.MIXED, nlev=2, nu1=2, nu2=2, nu3=8, E_target=1e-4,
+                               max_iter=20, graph=graph))
+
+    # the first request (Hermite, never batched) keeps the one worker busy while the
+    # others queue behind it
+    blocker = req(32, 33, 870, 0)
+    blocker = (blocker[0], blocker[1], nl.SolveParams(method=nl.FAS, precision=nl.MIXED, nlev=2, nu1=2, nu2=2,
+                                                      nu3=8, E_target=1e-4, max_iter=20, sc_interp=nl.SC_HERMITE))
+    reqs = [blocker, req(8, 9, 871, 1), req(8, 17, 872, 1), req(16, 9, 873, 0), req(8, 9, 874, 1)]
+    alone = []
+    for atom, atm, p in reqs:
+        job = ctx.job(ctx.atmos(atm), ctx.atom(atom), p)
+        job.run()
+        alone.append((job.history(), job.populations(1, (len(atom["levels"]), atm["nz"], atm["ny"], atm["nx"]))))
+        job.close()
+    ctx.serve_config(1)
+    ctx.serve_batching(8)
+    handles = [(ctx.atmos(atm), ctx.atom(atom)) for atom, atm, _ in reqs]
+    jobs = [ctx.submit(M, A, p) for (M, A), (_, _, p) in zip(handles, reqs)]
+    for j in jobs:
+        assert j.wait() >= 0
+    b = [j.info().batch for j in jobs]
+    print(f"batch ids {b}")
+    for i, (j, (atom, atm, _)) in enumerate(zip(jobs, reqs)):
+        assert np.array_equal(j.history(), alone[i][0]), f"request {i}: history differs"
+        got = j.populations(1, (len(atom["levels"]), atm["nz"], atm["ny"], atm["nx"]))
+        assert np.array_equal(got, alone[i][1]), f"request {i}: populations differ"
+    assert b[0] == 0
+    assert b[1] != 0 and b[2] == b[1] and b[4] == b[1]      # the graph jobs share one batch
+    assert b[3] not in (0, b[1])                             # the eager one runs in a batch of its own
+    for j in jobs:
+        j.close()
+    ctx.close()
