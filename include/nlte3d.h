@@ -16,7 +16,9 @@
  *  - The caller owns every buffer it passes.  *_create copies what it needs, so the
  *    caller may free descriptor memory when the call returns.  Output buffers are
  *    caller-allocated; a flag says whether a pointer is host or device memory.
- *  - All device work is enqueued on the context's HIP stream.  Calls that return host
+ *  - Device work is enqueued on the context's HIP stream, except where an entry point
+ *    says otherwise (graph replay and graph batches run on private streams ordered after
+ *    the context's; served jobs run on streams of their own).  Calls that return host
  *    data synchronise that stream.  Calls on one context are serialised by a mutex.
  *  - Return value: 0 = success; negative = failure with nothing partially returned
  *    (nlte_last_error gives the message); positive = warning with the result valid.
