@@ -214,42 +214,46 @@ def continuum_formal_solution(lev, n, want_j=False):
 
     At a continuum frequency nu every continuum t open there (nu >= its edge) adds
     opacity chi_t = alpha_t (n_l - n_c g_t)^+ and emissivity eta_t = n_c g_t alpha_t 2 h nu^3/c^2
-    (g_t = (n_l*/n_c*) exp(-h nu/kT)); there is no background; S = sum eta / sum chi.
-    Boundaries as for the lines: I = B_nu(T) below, I = 0 above.  The net radiative rate
-    of continuum t, 4 pi int dnu/(h nu) (chi_t J - eta_t), with J = Jeff + L* S at the
-    point, is made linear in the new populations the way Rybicki & Hummer (1991, 1992)
-    precondition overlapping transitions: the local part L* S uses the new emissivity,
-    n_c E with E = sum_s g_s alpha_s 2 h nu^3/c^2 over the continua open at nu, and the
-    opacity ratio chi_t / chi of the current populations.  Per voxel and continuum this
-    gives three sums over directions and frequencies,
+    (g_t = (n_l*/n_c*) exp(-h nu/kT), n_l and n_c the populations of t's lower and upper
+    level); there is no background; S = sum eta / sum chi.  Boundaries as for the lines:
+    I = B_nu(T) below, I = 0 above.  The net radiative rate of continuum t,
+    4 pi int dnu/(h nu) (chi_t J - eta_t), with J = Jeff + L* S at the point, is made linear
+    in the new populations the way Rybicki & Hummer (1991, 1992) precondition overlapping
+    transitions: the local part L* S uses the new emissivity, sum_u n_u E_u with
+    E_u = sum_s g_s alpha_s 2 h nu^3/c^2 over the continua s open at nu whose upper level
+    is u, and the opacity ratio chi_t / chi of the current populations.  Per voxel and
+    continuum this gives the sums over directions and frequencies
 
-        U_t = 4 pi sum w_d w_tk alpha_t Jeff_d / (h nu)              (times n_l: upward)
-        G_t = 4 pi sum w_d w_tk alpha_t g_t Jeff_d / (h nu)          (times n_c: downward)
-        L_t = 4 pi sum w_d w_tk (chi_t / chi) Psi_o E / (h nu)       (times n_c: removed)
+        U_t   = 4 pi sum w_d w_tk alpha_t Jeff_d / (h nu)            (times n_l: upward)
+        G_t   = 4 pi sum w_d w_tk alpha_t g_t Jeff_d / (h nu)        (times n_c: downward)
+        L_t,u = 4 pi sum w_d w_tk (chi_t / chi) Psi_o E_u / (h nu)   (times n_u: upward)
 
-    with Jeff_d = I_u e + Psi_u S_u on a segment and the fixed I at a boundary, so that
-    the downward rate coefficient is G_t + F_t - L_t (F_t, the spontaneous part, is the
-    level's cont_F).  Returns an array (3, ncont, nz, ny, nx) of (U, G, L), and the mean
-    intensity J (nfc, nz, ny, nx) too if want_j.
+    with Jeff_d = I_u e + Psi_u S_u on a segment and the fixed I at a boundary.  The net
+    upward rate of continuum t is n_l U_t - n_c (G_t + F_t) + sum_u n_u L_t,u (F_t, the
+    spontaneous part, is the level's cont_F); the term of t's own upper level joins the
+    downward rate coefficient, G_t + F_t - L_t,c.  The upper levels u are lev.cont_uppers.
+    Returns an array (2 + nup, ncont, nz, ny, nx) of (U, G, L_.,0, ..., L_.,nup-1), and the
+    mean intensity J (nfc, nz, ny, nx) too if want_j.
     """
     nfc = lev.cont_nu.size
     shape = (lev.nz, lev.ny, lev.nx)
-    acc = np.zeros((3, lev.ncont) + shape)
+    nup = len(lev.cont_uppers)
+    acc = np.zeros((2 + nup, lev.ncont) + shape)
     Jm = np.zeros((nfc,) + shape) if want_j else None
     f = 4.0 * np.pi / (ph.H * lev.cont_nu)                         # (nfc,)
     wa = lev.cont_w * lev.cont_alpha * f[None, :]                   # (ncont, nfc)
     nl = [n[l] for l in lev.cont_lower]
     nc = [n[c] for c in lev.cont_upper]
-    if len(set(lev.cont_upper)) != 1:
-        raise ValueError("active continua must share one upper level")
+    nu_up = [n[u] for u in lev.cont_uppers]
     e2 = lev.cont_e[:, :, :, 0]                                     # (nfc, 1, 1)
 
     def plane(k):
         chis = [lev.cont_alpha[t][:, None, None] * np.maximum(nl[t][k] - nc[t][k] * lev.cont_g[t][:, k], 0.0)
                 for t in range(lev.ncont)]
-        E = sum(lev.cont_alpha[t][:, None, None] * lev.cont_g[t][:, k] for t in range(lev.ncont)) * e2
+        E = [sum(lev.cont_alpha[t][:, None, None] * lev.cont_g[t][:, k]
+                 for t in range(lev.ncont) if lev.cont_uidx[t] == u) * e2 for u in range(nup)]
         chi = sum(chis)
-        eta = nc[0][k] * E
+        eta = sum(nu_up[u][k] * E[u] for u in range(nup))
         S = safe_div(eta, chi)
         return chis, chi, E, S
 
@@ -281,8 +285,9 @@ def continuum_formal_solution(lev, n, want_j=False):
                 acc[1, t, k] += wd * np.tensordot(wa[t], lev.cont_g[t][:, k] * Jd, axes=(0, 0))
                 if lam is not None:
                     chis, chi, psi_o, E = lam
-                    acc[2, t, k] += wd * np.tensordot(f * lev.cont_w[t], safe_div(chis[t], chi) * psi_o * E,
-                                                      axes=(0, 0))
+                    for u in range(nup):
+                        acc[2 + u, t, k] += wd * np.tensordot(f * lev.cont_w[t], safe_div(chis[t], chi) * psi_o * E[u],
+                                                              axes=(0, 0))
             if want_j:
                 Jm[:, k] += wd * Io
 

@@ -13,6 +13,8 @@ Readings:
 * Normalisation: phi~ = phi / sum_d sum_m w_d w_m phi per (voxel, line), so that an
   isotropic I = B gives Jbar = B exactly.  Used only inside the Jbar and Lambda*
   quadratures.
+* Active continua: every line frequency must lie below every continuum edge (the line
+  sweeps carry no bound-free opacity); an atom whose lines reach an edge is refused.
 * Grid hierarchy (Sect. 4.1, 4.2, 4.7): the coarse level keeps every second point;
   its atmosphere is the restriction of the finer one (full weighting unless another
   operator is asked for).  Level index
@@ -86,6 +88,18 @@ class Level:
         self.cont_lower = [ct["lower"] for ct in atom["continua"]]
         self.cont_upper = [ct["upper"] for ct in atom["continua"]]
         self.ncont = len(self.cont_lower)
+        # the distinct upper levels, in order of first appearance, and each continuum's
+        # index among them
+        self.cont_uppers = list(dict.fromkeys(self.cont_upper))
+        self.cont_uidx = [self.cont_uppers.index(c) for c in self.cont_upper]
+        # the line sweeps carry no bound-free opacity, so every line must lie below every
+        # edge, where the continua's cross-sections vanish
+        edge = min(ph.C * (atom["levels"][c]["E"] - atom["levels"][l]["E"])
+                   for l, c in zip(self.cont_lower, self.cont_upper))
+        for l in range(self.nline):
+            top = self.nu0[l] * (1.0 + np.max(atom["lines"][l]["q"]) / ph.C)
+            if top >= edge:
+                raise ValueError("line %d reaches %.6e Hz, at or above the continuum edge %.6e Hz" % (l, top, edge))
         nu = self.cont_nu[:, None, None, None]
         x = np.exp(-ph.H * nu / (ph.KB * T[None]))                  # (nfc, nz, ny, nx)
         self.cont_g = np.stack([(self.nstar[l] / self.nstar[c])[None] * x

@@ -25,8 +25,9 @@ import numpy as np
 def rate_matrix(lev, Jeff, omL, cont=None):
     """P[i, j] (rate coefficient i -> j) per voxel, shape (N, N, nz, ny, nx).
 
-    Active continua (cont = (U, G, L) from formal.continuum_formal_solution, or None for
-    no radiation) add upward U_t and downward G_t + F_t - L_t."""
+    Active continua (cont = (U, G, L_.,0, ...) from formal.continuum_formal_solution, or
+    None for no radiation) add upward U_t and downward G_t + F_t - L_t,c, c the continuum's
+    own upper level; the terms in the populations of other upper levels are cross_terms()."""
     P = lev.fixed.copy()
     for l in range(lev.nline):
         Aji, Bij, Bji = lev.einstein[l]
@@ -39,12 +40,30 @@ def rate_matrix(lev, Jeff, omL, cont=None):
             P[c, i] += lev.cont_F[t]
             if cont is not None:
                 P[i, c] += cont[0, t]
-                P[c, i] += cont[1, t] - cont[2, t]
+                P[c, i] += cont[1, t] - cont[2 + lev.cont_uidx[t], t]
     return P
 
 
-def system_matrix(P):
-    """A with A[i,i] = sum_{j!=i} P_ij, A[i,j] = -P_ji, and row 0 replaced by ones.
+def cross_terms(lev, cont):
+    """X[i, j] per voxel, shape (N, N, nz, ny, nx), added to the system matrix: the net
+    upward rate of continuum t (lower l, upper c) holds n_u L_t,u for every upper level u
+    of the continua; for u != c that is a flux l -> c proportional to n_u, which leaves l
+    (X[l, u] += L_t,u) and enters c (X[c, u] -= L_t,u).  None when there is nothing to add."""
+    if cont is None or not getattr(lev, "active_continua", False) or len(lev.cont_uppers) == 1:
+        return None
+    X = np.zeros((lev.N, lev.N) + cont.shape[2:])
+    for t in range(lev.ncont):
+        l, c = lev.cont_lower[t], lev.cont_upper[t]
+        for u, lu in enumerate(lev.cont_uppers):
+            if lu != c:
+                X[l, lu] += cont[2 + u, t]
+                X[c, lu] -= cont[2 + u, t]
+    return X
+
+
+def system_matrix(P, X=None):
+    """A with A[i,i] = sum_{j!=i} P_ij, A[i,j] = -P_ji, plus X[i, j] if given, and row 0
+    replaced by ones.
 
     Returned with the voxel axis first: shape (nvox, N, N)."""
     N = P.shape[0]
@@ -53,13 +72,15 @@ def system_matrix(P):
     out = Pv.sum(axis=1) - np.einsum("iiv->iv", Pv)  # sum_{j != i} P_ij
     idx = np.arange(N)
     A[:, idx, idx] = out.T
+    if X is not None:
+        A += np.transpose(X.reshape(N, N, -1), (2, 0, 1))
     A[:, 0, :] = 1.0
     return A
 
 
 def apply_W(lev, n, Jeff, omL, cont=None):
     """W(n) per level and voxel, shape (N, nz, ny, nx): row 0 = sum n, others stat. eq."""
-    A = system_matrix(rate_matrix(lev, Jeff, omL, cont))
+    A = system_matrix(rate_matrix(lev, Jeff, omL, cont), cross_terms(lev, cont))
     N = n.shape[0]
     nv = n.reshape(N, -1).T
     return np.einsum("vij,vj->vi", A, nv).T.reshape(n.shape)
@@ -68,7 +89,7 @@ def apply_W(lev, n, Jeff, omL, cont=None):
 def solve(lev, Jeff, omL, f, cont=None):
     """Solve A n = f per voxel (LAPACK gesv, partial pivoting) and rescale so that
     sum_i n_i = f_0 exactly."""
-    A = system_matrix(rate_matrix(lev, Jeff, omL, cont))
+    A = system_matrix(rate_matrix(lev, Jeff, omL, cont), cross_terms(lev, cont))
     N = f.shape[0]
     rhs = f.reshape(N, -1).T
     n = np.linalg.solve(A, rhs[..., None])[..., 0]

@@ -132,6 +132,21 @@ def caii_like_atom(nfreq=101):
     }
 
 
+def two_ion_level_atom(nfreq=101):
+    """caii_like_atom() plus the next ion's first excited level (level 6), reached by two
+    more bound-free transitions, from levels 3 and 4, and by collisions, so that the
+    continua end on two upper levels.  Round synthetic values."""
+    atom = caii_like_atom(nfreq)
+    atom = dict(atom, name="caii-like-7",
+                levels=atom["levels"] + [{"E": 96000.0 + 13650.0, "g": 4.0, "stage": 2}],
+                continua=atom["continua"] + [{"lower": 3, "upper": 6, "alpha0": 1.5e-18},
+                                             {"lower": 4, "upper": 6, "alpha0": 1.5e-18}])
+    atom["collisions"] = [dict(c) for c in atom["collisions"]] + [
+        {"lower": l, "upper": 6, "c_ul": 3.0e-7 if l == 5 else 2.0e-9, "T_ref": 5000.0, "beta": -0.5}
+        for l in range(6)]
+    return atom
+
+
 def continuum_grid(atom, n_seg=6, n_top=16, top=1.6):
     """Frequencies (Hz) for treating the atom's continua as active transitions: every
     edge, n_seg geometric steps between consecutive edges and n_top from the highest edge

@@ -1,19 +1,24 @@
 """Pins of the oracle's active continua (no GPU): the frequency quadrature against the
 analytic photo-ionisation rate, detailed balance in a Planck field, the fixed point of
-the preconditioned rates, and convergence of MALI and FAS with active continua."""
+the preconditioned rates (continua ending on one upper level and on two, where the
+cross terms must be there), convergence of MALI and FAS with active continua, and the
+refusal of lines that reach a continuum edge."""
 import numpy as np
 import pytest
 
 from oracle import physics as ph
 from oracle.formal import continuum_formal_solution, formal_solution
 from oracle.levels import Level
-from oracle.rates import apply_W, fine_rhs, zero_radiation
+from oracle.rates import apply_W, fine_rhs, rate_matrix, system_matrix, zero_radiation
 from oracle.solver import Params, mali, solve_fas, solve_mali
 from paper_1701_01607_amd import synth
 
 
-def small_case(nx=4, ny=4, nz=9, seed=7, **grid):
-    atom = synth.with_active_continua(synth.caii_like_atom(9), **grid)
+ATOMS = {"one_upper": synth.caii_like_atom, "two_upper": synth.two_ion_level_atom}
+
+
+def small_case(nx=4, ny=4, nz=9, seed=7, kind="one_upper", **grid):
+    atom = synth.with_active_continua(ATOMS[kind](9), **grid)
     atm = synth.atmos_stratified(nx=nx, ny=ny, nz=nz, dx=150 * synth.KM, seed=seed)
     atm["ntot"] = atm["ntot"] * 0.1
     return atom, atm
@@ -42,9 +47,10 @@ def test_planck_photo_rates_converge_to_the_analytic_integral(T):
     assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
 
 
-def test_detailed_balance_in_a_planck_field():
+@pytest.mark.parametrize("kind", list(ATOMS))
+def test_detailed_balance_in_a_planck_field(kind):
     # J = B at every frequency: n_l* U_t = n_c* (G_t + F_t) for every continuum, any grid
-    atom, atm = small_case()
+    atom, atm = small_case(kind=kind)
     lev = Level(atom, atm)
     f = 4.0 * np.pi / (ph.H * lev.cont_nu)
     for t in range(lev.ncont):
@@ -55,10 +61,13 @@ def test_detailed_balance_in_a_planck_field():
         assert np.allclose(lev.nstar[l] * U, lev.nstar[c] * (G + lev.cont_F[t]), rtol=1e-12)
 
 
-def test_preconditioned_rates_equal_the_plain_rates_at_the_populations_they_came_from():
+@pytest.mark.parametrize("kind", list(ATOMS))
+def test_preconditioned_rates_equal_the_plain_rates_at_the_populations_they_came_from(kind):
     # Built from a formal solution at n, the preconditioned matrix applied to n gives the
-    # statistical equilibrium with the actual mean intensities, lines and continua
-    atom, atm = small_case()
+    # statistical equilibrium with the actual mean intensities, lines and continua.  With
+    # two upper levels the local part of J holds both levels' emissivities, so the identity
+    # needs the cross terms in the other upper level's population as well.
+    atom, atm = small_case(kind=kind)
     lev = Level(atom, atm)
     n = zero_radiation(lev)
     n, _ = mali(lev, 1, n, fine_rhs(lev), 2)
@@ -83,6 +92,21 @@ def test_preconditioned_rates_equal_the_plain_rates_at_the_populations_they_came
     assert np.max(np.abs(W[1:] - out[1:]) / scale) < 1e-9
     # the continua carry real radiative rates here (not a vacuous check)
     assert np.max(np.abs(cont[2])) > 0 and np.max(cont[0]) > 0
+    assert cont.shape[0] == 2 + len(lev.cont_uppers)
+    if kind == "two_upper":
+        assert lev.cont_uppers == [5, 6]
+        # every continuum has a non-zero sum for the other upper level, and leaving the
+        # cross terms out breaks the identity
+        for t in range(lev.ncont):
+            assert np.max(np.abs(cont[2 + (1 - lev.cont_uidx[t]), t])) > 0
+        # per level, against the level's own outflow: the identity holds to rounding
+        # (measured 6e-14), and without the cross terms it fails by 3e-8
+        own = np.einsum("i...,ij...->i...", n, P)
+        A0 = system_matrix(rate_matrix(lev, Jeff, omL, cont))
+        N = lev.N
+        W0 = np.einsum("vij,vj->vi", A0, n.reshape(N, -1).T).T.reshape(n.shape)
+        assert np.max(np.abs(W[1:] - out[1:]) / own[1:]) < 1e-12
+        assert np.max(np.abs(W0[1:] - out[1:]) / own[1:]) > 1e-8
 
 
 def test_mali_and_fas_converge_to_the_same_solution_with_active_continua():
@@ -97,3 +121,25 @@ def test_mali_and_fas_converge_to_the_same_solution_with_active_continua():
     atom0 = synth.caii_like_atom(9)
     n0, _, _ = solve_mali(atom0, atm, p)
     assert np.max(np.abs(n0 / nm - 1)) > 1e-3
+
+
+def test_mali_and_fas_converge_to_the_same_solution_with_two_upper_levels():
+    atom, atm = small_case(nz=9, kind="two_upper")
+    p = Params(nlev=2, nu1=2, nu2=2, nu3=12, E_target=1e-8, max_iter=400)
+    nm, stm, lev = solve_mali(atom, atm, p)
+    nf, stf, _ = solve_fas(atom, atm, p)
+    tol = 4 * (stm.E_est[-1] + stf.E_est[-1]) + 1e-12
+    assert np.max(np.abs(nf / nm - 1)) < max(tol, 1e-8)
+    assert np.all(nm > 0) and np.allclose(nm.sum(axis=0), lev.ntot, rtol=1e-13)
+
+
+def test_lines_reaching_a_continuum_edge_are_refused():
+    # the line sweeps carry no bound-free opacity: a continuum whose edge lies below a
+    # line's frequencies is refused when continua are active, accepted as fixed rates
+    atom, atm = small_case()
+    low = synth.caii_like_atom(9)
+    low["levels"] = [dict(lv) for lv in low["levels"]]
+    low["levels"][5]["E"] = 40000.0          # edge from level 4 at 14600 cm^-1, below the lines
+    Level(low, atm)
+    with pytest.raises(ValueError, match="continuum edge"):
+        Level(synth.with_active_continua(low), atm)
