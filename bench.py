@@ -419,6 +419,10 @@ def main():
     ap.add_argument("--active-continua", action="store_true",
                     help="sweep the atom's continua as active transitions (41 continuum frequencies); the "
                          "line-sweep roofline is then not reported")
+    ap.add_argument("--seven-level", action="store_true",
+                    help="the workload's atmosphere with the seven-level atom, whose continua end on two upper "
+                         "levels (with --active-continua: continuum sweeps with two upper levels); no "
+                         "roofline or CPU baseline")
     ap.add_argument("--batch", type=int, default=0,
                     help="N > 0: time N small solves (two_level_16x16x32 with that workload, else six-level "
                          "16x16x33) one after another and as one batch; prints its own JSON line")
@@ -444,10 +448,12 @@ def main():
     t_gen = time.perf_counter()
     atom, atm = synth.workload(args.workload)
     log(f"generated in {time.perf_counter() - t_gen:.1f} s")
+    if args.seven_level:
+        atom = synth.two_ion_level_atom(len(atom["lines"][0]["q"]))
     if args.active_continua:
         atom = synth.with_active_continua(atom)
     sample = None
-    if not args.no_cpu_baseline and not args.kernel_probe:
+    if not args.no_cpu_baseline and not args.kernel_probe and not args.seven_level:
         log("cpu baseline (oracle sample, before the GPU is initialised) ...")
         sample = cpu_baseline_sample()
         log(f"oracle: {sample['updates'] / (sample['t_fs'] + sample['t_rates']):.3e} updates/s on "
@@ -588,9 +594,9 @@ def main():
                    "lines": len(atom["lines"]), "frequencies": nf, "directions": 24, "method": wl["method"],
                    "levels": wl["nlev"], "nu": [wl["nu_fmg"], wl["nu0"], wl["nu1"], wl["nu2"], wl["nu3"]],
                    "E_target": wl["E_target"] or None, "tol_C": wl["tol_C"] or None,
-                   "continua": "active" if args.active_continua else "fixed"},
+                   "continua": "active" if args.active_continua else "fixed", "atom": atom["name"]},
         "updates_per_s_sweep": updates_per_s_sweep,
-        "roofline": None if args.active_continua or args.graph else
+        "roofline": None if args.active_continua or args.graph or args.seven_level else
         roofline(atom, atm, wl["fp64"], upd, sweep_ms, launches, dpb, args.workload),
     }
     out.update(extra)

@@ -116,8 +116,12 @@ typedef struct {
     const nlte_coll_desc* collisions;
     int ncont_nu;              /* > 0: the continua are active transitions of the formal
                                   solution, swept at these frequencies (RH92 preconditioning
-                                  of the overlapping continua, which must share one upper
-                                  level); 0: fixed continua with photo-rates at J = B(T) */
+                                  of the overlapping continua, with the terms in every upper
+                                  level's population: at most 4 distinct upper levels); every
+                                  line frequency must then lie below every continuum edge,
+                                  since the line sweeps carry no bound-free opacity
+                                  (NLTE_E_INVALID otherwise); 0: fixed continua with
+                                  photo-rates at J = B(T) */
     const double* cont_nu;     /* ncont_nu frequencies (Hz), increasing, containing every
                                   continuum edge; host memory, copied */
 } nlte_atom_desc;

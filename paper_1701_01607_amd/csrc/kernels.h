@@ -30,6 +30,9 @@ struct AtomInfo {
     LineInfo line[kMaxLines];
     int cont_lower[kMaxLevels], cont_upper[kMaxLevels];
     double cont_alpha0[kMaxLevels];
+    int cont_nup;                   // active continua: distinct upper levels,
+    int cont_ulev[kMaxLevels];      // in order of first appearance,
+    int cont_uidx[kMaxLevels];      // and each continuum's index among them
     int coll_lower[kMaxLevels * kMaxLevels], coll_upper[kMaxLevels * kMaxLevels];
     double coll_cul[kMaxLevels * kMaxLevels], coll_Tref[kMaxLevels * kMaxLevels],
         coll_beta[kMaxLevels * kMaxLevels];
@@ -799,6 +802,7 @@ __global__ void emergent_step_kernel(EmergentArgs<R> a, int k) {
 // n_l*/n_c* of every continuum, h/kT, and the spontaneous part of the downward rate,
 // F_t = sum_k (4 pi w_tk / h nu_k) alpha_tk g_tk 2 h nu_k^3/c^2 with g = (n_l*/n_c*) e^{-h nu/kT}.
 constexpr int kMaxCont = 8;
+constexpr int kMaxContUp = 4;   // distinct upper levels of the active continua
 
 template <typename R>
 __global__ void cont_setup_kernel(const AtomInfo* atom, const double* prim, const double* nstar, const double* cnu,
@@ -858,21 +862,26 @@ struct ContArgs {
     const R* hkT;         // [nvox] h/kT
     const R* ctab;        // [nfc][kContRow]: nu, 2 h nu^3/c^2, alpha_t (8), 4 pi w_t/(h nu) (8), pad
     CCell<R>* state;      // [2][24][nfc][nxy]
-    R* acc;               // [3 ncont][8 slots][nvox]: U, G, L per continuum
+    R* acc;               // [(2 + nup) ncont][8 slots][nvox]: U_t, G_t, then L_t,u (t major)
 };
 
 // One plane step of the formal solution at the continuum frequencies, for three
 // directions per block over 64 plane points, the frequencies split into FC contiguous
 // chunks (block = 3 x FC waves, FC = blockDim / 192).  Opacity and emissivity at a point
-// sum over the continua open at the frequency; the three sums per continuum (U: alpha
-// Jeff, G: alpha g Jeff, L: the preconditioned local part (chi_t/chi) Psi_o E, each times
-// 4 pi w / h nu and the direction weight 1/24) are added over the chunks in order, then
-// over the block's three directions as (d0 + d1) + d2, and stored per direction group;
-// the rate kernel finishes the fixed tree.
+// sum over the continua open at the frequency, the emissivity as sum_u n_u E_u over the
+// NUP distinct upper levels (E_u: alpha g 2 h nu^3/c^2 summed over the continua ending on
+// u).  The sums per continuum t (U: alpha Jeff, G: alpha g Jeff, and per upper level u
+// the preconditioned local part L_t,u: (chi_t/chi) Psi_o E_u, each times 4 pi w / h nu and
+// the direction weight 1/24) are added over the chunks in order, then over the block's
+// three directions as (d0 + d1) + d2, and stored per direction group; the rate kernel
+// finishes the fixed tree.
+// FP64 keeps to two chunks (six waves per block), which leaves it 256 registers per lane.
 constexpr int kContMaxChunks = 4;
-
 template <typename R>
-__global__ __launch_bounds__(3 * kContMaxChunks * 64) void sweep_cont_kernel(ContArgs<R> a, int s) {
+constexpr int cont_max_chunks() { return sizeof(R) == 8 ? 2 : kContMaxChunks; }
+
+template <typename R, int NUP>
+__global__ __launch_bounds__(3 * cont_max_chunks<R>() * 64) void sweep_cont_kernel(ContArgs<R> a, int s) {
     constexpr int kW = 64;
     const int lane = int(threadIdx.x) & (kW - 1);
     const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kW);
@@ -904,18 +913,28 @@ __global__ __launch_bounds__(3 * kContMaxChunks * 64) void sweep_cont_kernel(Con
     constexpr unsigned csz = sizeof(CCell<R>);
     const unsigned rowb = nxy * csz;                  // bytes per frequency row
     const auto rcur = cell_rsrc(a.state + size_t(s & 1) * slot_stride + size_t(d) * dstride, unsigned(nfc) * rowb);
-    const R nc = R(fmax(a.n[size_t(at.cont_upper[0]) * nv + v], 0.0));
-    R nl[kMaxCont], ratio[kMaxCont];
+    R ncu[NUP];
+#pragma unroll
+    for (int u = 0; u < NUP; ++u) ncu[u] = R(fmax(a.n[size_t(at.cont_ulev[u]) * nv + v], 0.0));
+    R nl[kMaxCont], ratio[kMaxCont], nc[kMaxCont];
 #pragma unroll
     for (int t = 0; t < kMaxCont; ++t) {
         nl[t] = t < nct ? R(fmax(a.n[size_t(at.cont_lower[t]) * nv + v], 0.0)) : R(0);
         ratio[t] = t < nct ? a.cr[size_t(t) * nv + v] : R(0);
+        nc[t] = ncu[0];   // the population of t's upper level
+#pragma unroll
+        for (int u = 1; u < NUP; ++u)
+            if (at.cont_uidx[t] == u) nc[t] = ncu[u];
     }
     const R hk = a.hkT[v];
     const R wd = R(1.0 / kNDir);
-    R aU[kMaxCont], aG[kMaxCont], aL[kMaxCont];
+    R aU[kMaxCont], aG[kMaxCont], aL[kMaxCont][NUP];
 #pragma unroll
-    for (int t = 0; t < kMaxCont; ++t) aU[t] = aG[t] = aL[t] = R(0);
+    for (int t = 0; t < kMaxCont; ++t) {
+        aU[t] = aG[t] = R(0);
+#pragma unroll
+        for (int u = 0; u < NUP; ++u) aL[t][u] = R(0);
+    }
     // upwind geometry (planes after the boundary)
     unsigned o00 = 0, o01 = 0, o10 = 0, o11 = 0;
     R w00 = R(0), w01 = R(0), w10 = R(0), w11 = R(0), rds = R(0);
@@ -947,18 +966,27 @@ __global__ __launch_bounds__(3 * kContMaxChunks * 64) void sweep_cont_kernel(Con
         const R x = dev_exp_neg(hk * row[0]);
         const R e = row[1];
         R chis[kMaxCont], gg[kMaxCont];
-        R chi = R(0), E = R(0);
+        R chi = R(0), E[NUP];
+#pragma unroll
+        for (int u = 0; u < NUP; ++u) E[u] = R(0);
 #pragma unroll
         for (int t = 0; t < kMaxCont; ++t) {
             const R al = row[2 + t];   // 0 for absent continua and below the edge
             gg[t] = ratio[t] * x;
-            chis[t] = al * fmax(nl[t] - nc * gg[t], R(0));
+            chis[t] = al * fmax(nl[t] - nc[t] * gg[t], R(0));
             chi += chis[t];
-            E = fma(al, gg[t], E);
+#pragma unroll
+            for (int u = 0; u < NUP; ++u)
+                if (NUP == 1 || at.cont_uidx[t] == u) E[u] = fma(al, gg[t], E[u]);
         }
-        E *= e;
+        R eta = R(0);
+#pragma unroll
+        for (int u = 0; u < NUP; ++u) {
+            E[u] *= e;
+            eta = u == 0 ? ncu[0] * E[0] : fma(ncu[u], E[u], eta);
+        }
         const R rchi = chi > R(0) ? dev_rcp(chi) : R(0);
-        const R S = nc * E * rchi;
+        const R S = eta * rchi;
         R Jd, Io, po = R(0);
         if (s == 0) {
             Io = (h == 0) ? e * x / (R(1) - x) : R(0);
@@ -984,29 +1012,38 @@ __global__ __launch_bounds__(3 * kContMaxChunks * 64) void sweep_cont_kernel(Con
                 const R wa = wd * fw * row[2 + t];
                 aU[t] = fma(wa, Jd, aU[t]);
                 aG[t] = fma(wa * gg[t], Jd, aG[t]);
-                aL[t] = fma(wd * fw, chis[t] * rchi * po * E, aL[t]);
+#pragma unroll
+                for (int u = 0; u < NUP; ++u) aL[t][u] = fma(wd * fw, chis[t] * rchi * po * E[u], aL[t][u]);
             }
         }
     }
     // per quantity and continuum: chunks in order, then (d0 + d1) + d2
     __shared__ R red[3 * kContMaxChunks * kW];
-#pragma unroll
-    for (int q = 0; q < 3; ++q)
-#pragma unroll
-        for (int t = 0; t < kMaxCont; ++t) {
-            if (t >= nct) continue;
-            red[threadIdx.x] = q == 0 ? aU[t] : (q == 1 ? aG[t] : aL[t]);
-            __syncthreads();
-            if (wv == 0 && valid) {
-                R dsum[3];
-                for (int dd = 0; dd < 3; ++dd) {
-                    R c = red[dd * kW + lane];
-                    for (int ch = 1; ch < FC; ++ch) c += red[(ch * 3 + dd) * kW + lane];
-                    dsum[dd] = c;
-                }
-                a.acc[(size_t(q * nct + t) * kMaxSlots + grp) * nv + v] = (dsum[0] + dsum[1]) + dsum[2];
+    auto store = [&](R val, int q) {
+        red[threadIdx.x] = val;
+        __syncthreads();
+        if (wv == 0 && valid) {
+            R dsum[3];
+            for (int dd = 0; dd < 3; ++dd) {
+                R c = red[dd * kW + lane];
+                for (int ch = 1; ch < FC; ++ch) c += red[(ch * 3 + dd) * kW + lane];
+                dsum[dd] = c;
             }
-            __syncthreads();
+            a.acc[(size_t(q) * kMaxSlots + grp) * nv + v] = (dsum[0] + dsum[1]) + dsum[2];
+        }
+        __syncthreads();
+    };
+#pragma unroll
+    for (int t = 0; t < kMaxCont; ++t)
+        if (t < nct) store(aU[t], t);
+#pragma unroll
+    for (int t = 0; t < kMaxCont; ++t)
+        if (t < nct) store(aG[t], nct + t);
+#pragma unroll
+    for (int t = 0; t < kMaxCont; ++t)
+        if (t < nct) {
+#pragma unroll
+            for (int u = 0; u < NUP; ++u) store(aL[t][u], 2 * nct + t * NUP + u);
         }
 }
 
@@ -1031,7 +1068,7 @@ struct RateArgs {
     double sign;
     int mode;
     double* partial;      // [gridDim.x] max relative change (modes 0/1)
-    const R* cacc;        // active continua: [3 ncont][8 slots][nvox] (U, G, L), else null
+    const R* cacc;        // active continua: [(2 + nup) ncont][8 slots][nvox] (U, G, L), else null
     const double* cF;     // active continua: [ncont][nvox] spontaneous recombination
 };
 
@@ -1118,6 +1155,12 @@ __device__ inline void lu_solve(double (&A)[N][N], double (&b)[N]) {
     }
 }
 
+// One continuum sum (index q of the [(2 + nup) ncont] quantities) over its 8 slots.
+template <typename R>
+__device__ inline double cont_sum(const R* cacc, int q, size_t nv, size_t v) {
+    return double(tree_slots(cacc + (size_t(q) * kMaxSlots) * nv + v, nv, kMaxSlots));
+}
+
 template <typename R, int N>
 __global__ __launch_bounds__(256) void rate_kernel(RateArgs<R> a) {
     const size_t v = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1145,15 +1188,33 @@ __global__ __launch_bounds__(256) void rate_kernel(RateArgs<R> a) {
                 cdn[t] = F;
             } else {
                 const int nc3 = at.ncont;
-                auto sum = [&](int q) {
-                    return double(tree_slots(a.cacc + (size_t(q * nc3 + t) * kMaxSlots) * nv + v, nv, kMaxSlots));
-                };
-                cup[t] = sum(0);
-                cdn[t] = sum(1) + F - sum(2);
+                cup[t] = cont_sum(a.cacc, t, nv, v);
+                cdn[t] = cont_sum(a.cacc, nc3 + t, nv, v) + F -
+                         cont_sum(a.cacc, 2 * nc3 + t * at.cont_nup + at.cont_uidx[t], nv, v);
             }
         }
         double A[N][N];
         build_matrix<N>(at, a.pfix, nv, v, Jeff, omL, cup, cdn, A);
+        // active continua ending on several upper levels: the net upward rate of continuum
+        // t (l -> c) also holds n_u L_t,u for the other upper levels u, a flux out of l
+        // (A[l][u] += L) into c (A[c][u] -= L); row 0 stays the conservation row
+        if (a.mode != 1 && at.cont_active && at.cont_nup > 1) {
+            const int nc3 = at.ncont, nup = at.cont_nup;
+            for (int t = 0; t < nc3; ++t)
+                for (int u = 0; u < nup; ++u) {
+                    if (u == at.cont_uidx[t]) continue;
+                    const double x = cont_sum(a.cacc, 2 * nc3 + t * nup + u, nv, v);
+                    const int lo = at.cont_lower[t], up = at.cont_upper[t], ul = at.cont_ulev[u];
+#pragma unroll
+                    for (int i = 1; i < N; ++i)
+#pragma unroll
+                        for (int j = 0; j < N; ++j)
+                            if (j == ul) {
+                                if (i == lo) A[i][j] += x;
+                                if (i == up) A[i][j] -= x;
+                            }
+                }
+        }
         double nold[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) nold[i] = a.n[size_t(i) * nv + v];

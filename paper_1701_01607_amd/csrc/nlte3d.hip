@@ -599,7 +599,7 @@ struct Job : JobBase {
                 dalloc(L.cr, sizeof(R) * nct * L.nvox);
                 dalloc(L.chkT, sizeof(R) * L.nvox);
                 dalloc(L.cF, sizeof(double) * nct * L.nvox);
-                dalloc(L.cacc, sizeof(R) * 3 * nct * kMaxSlots * L.nvox);
+                dalloc(L.cacc, sizeof(R) * (2 + info.cont_nup) * nct * kMaxSlots * L.nvox);
                 cont_setup_kernel<R><<<blocks_for(L.nvox, 128), 128, 0, st()>>>(
                     atom_d.as<AtomInfo>(), L.prim.as<double>(), L.nstar.as<double>(), cnu_d.as<double>(),
                     ce_d.as<double>(), cfw_d.as<double>(), calpha_d.as<double>(), nfc, L.cr.as<R>(), L.chkT.as<R>(),
@@ -921,10 +921,19 @@ struct Job : JobBase {
         const dim3 grid(blocks_for(L.nxy, 64), 1, kNDir / 3);
         // frequency chunks: as for the line sweep, until a launch holds two rounds of waves
         int fc = 1;
-        while (fc < kContMaxChunks && sweep_waves(L.nxy, 1) * fc < kSweepWaveTarget) fc *= 2;
+        while (fc < cont_max_chunks<R>() && sweep_waves(L.nxy, 1) * fc < kSweepWaveTarget) fc *= 2;
         const bool own = stream == st();
         if (own) ev_begin(EV_SWEEP);
-        for (int s = 0; s < L.nz; ++s) sweep_cont_kernel<R><<<grid, unsigned(3 * fc * 64), 0, stream>>>(c, s);
+        const dim3 block(unsigned(3 * fc * 64));
+        for (int s = 0; s < L.nz; ++s) {
+            switch (info.cont_nup) {
+                case 1: sweep_cont_kernel<R, 1><<<grid, block, 0, stream>>>(c, s); break;
+                case 2: sweep_cont_kernel<R, 2><<<grid, block, 0, stream>>>(c, s); break;
+                case 3: sweep_cont_kernel<R, 3><<<grid, block, 0, stream>>>(c, s); break;
+                case 4: sweep_cont_kernel<R, 4><<<grid, block, 0, stream>>>(c, s); break;
+                default: throw Error(NLTE_E_INVALID, "continuum upper-level count out of range");
+            }
+        }
         HIPCHK(hipGetLastError());
         if (own) ev_end();
     }
@@ -2035,7 +2044,8 @@ size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom
         bytes += 8 * (size_t(N) * 6 + size_t(N) * N + 1) * nvox + R * (2 * slots + 2) * nline * nvox;
         bytes += 8 * std::max<size_t>((nvox + 255) / 256, 1024);
         if (atom->info.cont_active)   // LTE ratios, h/kT, spontaneous rates, U/G/L sums
-            bytes += (R * (atom->info.ncont + 1) + 8 * atom->info.ncont + R * 3 * atom->info.ncont * kMaxSlots) * nvox;
+            bytes += (R * (atom->info.ncont + 1) + 8 * atom->info.ncont +
+                      R * (2 + atom->info.cont_nup) * atom->info.ncont * kMaxSlots) * nvox;
         nx /= 2; ny /= 2; nz = (nz - 1) / 2 + 1;
     }
     const char* envb = std::getenv("NLTE3D_SWEEP_STATE_MB");
@@ -2475,8 +2485,26 @@ nlte_status nlte_atom_create(nlte_ctx* ctx, const nlte_atom_desc* d, nlte_atom**
             for (int k = 0; k < nfc; ++k) a->ce[k] = 2.0 * kH * a->cnu[k] * a->cnu[k] * a->cnu[k] / (kC * kC);
             a->calpha.assign(size_t(I.ncont) * nfc, 0.0);
             a->cfw.assign(size_t(I.ncont) * nfc, 0.0);
+            // the distinct upper levels, in order of first appearance
+            I.cont_nup = 0;
             for (int c = 0; c < I.ncont; ++c) {
-                REQUIRE(I.cont_upper[c] == I.cont_upper[0], "active continua must share one upper level");
+                int u = 0;
+                while (u < I.cont_nup && I.cont_ulev[u] != I.cont_upper[c]) ++u;
+                if (u == I.cont_nup) {
+                    REQUIRE(I.cont_nup < kMaxContUp, "active continua may end on at most 4 upper levels");
+                    I.cont_ulev[I.cont_nup++] = I.cont_upper[c];
+                }
+                I.cont_uidx[c] = u;
+            }
+            // the line sweeps carry no bound-free opacity: every line must lie below every edge
+            double edge = HUGE_VAL;
+            for (int c = 0; c < I.ncont; ++c) edge = std::min(edge, kC * (I.E[I.cont_upper[c]] - I.E[I.cont_lower[c]]));
+            for (int l = 0; l < I.nline; ++l) {
+                const nlte_line_desc& s = d->lines[l];
+                REQUIRE(I.line[l].nu0 * (1.0 + s.q[s.nfreq - 1] / kC) < edge,
+                        "with active continua every line frequency must lie below every continuum edge");
+            }
+            for (int c = 0; c < I.ncont; ++c) {
                 const double nue = kC * (I.E[I.cont_upper[c]] - I.E[I.cont_lower[c]]);
                 int k0 = 0;
                 while (k0 < nfc && a->cnu[k0] < nue * (1.0 - 1e-12)) ++k0;

@@ -1,13 +1,18 @@
 """Active overlapping continua on the GPU against the oracle (FP64 and mixed precision):
-zero-radiation start, MALI iterations and FAS cycles."""
+zero-radiation start, MALI iterations and FAS cycles, for continua ending on one upper
+level and on two (the seven-level atom), the residual with the cross terms of two upper
+levels, and the atoms the library refuses."""
 import numpy as np
 import pytest
 
+from oracle.formal import continuum_formal_solution, formal_solution
 from oracle.levels import Level
-from oracle.rates import fine_rhs, zero_radiation
+from oracle.rates import apply_W, cross_terms, fine_rhs, rate_matrix, system_matrix, zero_radiation
 from oracle.solver import Params as OParams
 from oracle.solver import mali, solve_fas
 from paper_1701_01607_amd import synth
+
+ATOMS = {"one_upper": synth.caii_like_atom, "two_upper": synth.two_ion_level_atom}
 
 pytestmark = pytest.mark.gpu
 
@@ -32,15 +37,15 @@ def ctx(nl):
     c.close()
 
 
-def case(nx=12, ny=10, nz=9, seed=21):
-    atom = synth.with_active_continua(synth.caii_like_atom(9))
+def case(nx=12, ny=10, nz=9, seed=21, kind="one_upper"):
+    atom = synth.with_active_continua(ATOMS[kind](9))
     atm = synth.atmos_stratified(nx=nx, ny=ny, nz=nz, dx=120 * synth.KM, seed=seed)
     return atom, atm
 
 
-@pytest.fixture(scope="module")
-def ragged():
-    atom, atm = case()
+@pytest.fixture(scope="module", params=list(ATOMS))
+def ragged(request):
+    atom, atm = case(kind=request.param)
     lev = Level(atom, atm)
     n0 = zero_radiation(lev)
     return atom, atm, lev, n0
@@ -57,7 +62,7 @@ def test_active_continua_mali_parity(nl, ctx, ragged, prec, tol):
     n3, _ = mali(lev, 1, n0, fine_rhs(lev), 3)
     e3 = relerr(job.populations(0, shape), n3)
     # the fixed-continuum solution differs by far more than the tolerance
-    lev_fixed = Level(synth.caii_like_atom(9), atm)
+    lev_fixed = Level({k: v for k, v in atom.items() if k != "continuum_nu"}, atm)
     d = relerr(zero_radiation(lev_fixed), n0)
     print(f"prec={prec} active continua: zero-radiation err {e0:.2e}, MALI x3 err {e3:.2e}; "
           f"fixed continua differ by {d:.2e}")
@@ -69,9 +74,9 @@ def test_active_continua_mali_parity(nl, ctx, ragged, prec, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [(0, 1e-7), (1, 1e-5)])
-@pytest.mark.parametrize("fmg", [False, True])
-def test_active_continua_fas_parity(nl, ctx, prec, tol, fmg):
-    atom, atm = case(nx=8, ny=8, nz=17, seed=31)
+@pytest.mark.parametrize("fmg,kind", [(False, "one_upper"), (True, "one_upper"), (False, "two_upper")])
+def test_active_continua_fas_parity(nl, ctx, prec, tol, fmg, kind):
+    atom, atm = case(nx=8, ny=8, nz=17, seed=31, kind=kind)
     atm["ntot"] = atm["ntot"] * 0.1
     n_or, st, _ = solve_fas(atom, atm, OParams(nlev=3, nu1=2, nu2=2, nu3=6, nu_fmg=4), fmg=fmg, cycles=2)
     job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
@@ -83,3 +88,54 @@ def test_active_continua_fas_parity(nl, ctx, prec, tol, fmg):
     print(f"prec={prec} fmg={fmg} active continua FAS 2 cycles err {e:.2e}")
     assert r.cycles == 2 and e < tol
     assert abs(r.C / st.C[-1] - 1) < 0.05
+
+
+def test_two_upper_level_residual_parity_with_cross_terms(nl, ctx):
+    # W(n) after an extra formal solution, element by element against the oracle's, with
+    # the error measured against the terms each entry sums; leaving out the terms in the
+    # other upper level's population moves the oracle's W by far more than the tolerance
+    atom, atm = case(kind="two_upper")
+    lev = Level(atom, atm)
+    n0 = zero_radiation(lev)
+    N = len(atom["levels"])
+    npop = (N, atm["nz"], atm["ny"], atm["nx"])
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=0, nlev=1))
+    job.mali(0, 2)
+    n2, _ = mali(lev, 1, n0, fine_rhs(lev), 2)
+    rg = job.residual(0, npop)
+    Jeff, omL = formal_solution(lev, n2)
+    cont = continuum_formal_solution(lev, n2)
+    ro = fine_rhs(lev) - apply_W(lev, n2, Jeff, omL, cont)
+    A = system_matrix(rate_matrix(lev, Jeff, omL, cont), cross_terms(lev, cont))
+    nv = n2.reshape(N, -1).T
+    scale = np.einsum("vij,vj->vi", np.abs(A), np.abs(nv)).T.reshape(n2.shape)
+    err = float(np.max(np.abs(rg - ro) / scale))
+    A0 = system_matrix(rate_matrix(lev, Jeff, omL, cont))
+    r0 = fine_rhs(lev) - np.einsum("vij,vj->vi", A0, nv).T.reshape(n2.shape)
+    d = float(np.max(np.abs(r0 - ro) / scale))
+    print(f"two upper levels: residual err relative to its terms {err:.2e}; without cross terms {d:.2e}")
+    assert err < 1e-10
+    assert d > 100 * 1e-10
+
+
+def test_atoms_the_active_continua_cannot_represent_are_refused(nl, ctx):
+    # a line reaching above a continuum edge (no bound-free opacity in the line sweeps)
+    low = synth.caii_like_atom(9)
+    low["levels"] = [dict(lv) for lv in low["levels"]]
+    low["levels"][5]["E"] = 40000.0
+    ctx.atom(low)                               # fine as fixed continua
+    with pytest.raises(nl.NlteError) as ei:
+        ctx.atom(synth.with_active_continua(low))
+    assert ei.value.code == nl.E_INVALID
+    # continua ending on five upper levels
+    q = synth.caii_like_atom(9)["lines"][0]["q"]
+    wide = {"name": "five-uppers", "mass_amu": 40.0, "xi": 2.0 * synth.KM, "epsilon": None,
+            "levels": [{"E": 0.0, "g": 2.0, "stage": 1}, {"E": 13700.0, "g": 4.0, "stage": 1}]
+            + [{"E": 90000.0 + 1000.0 * i, "g": 1.0, "stage": 2} for i in range(5)],
+            "lines": [{"lower": 0, "upper": 1, "A": 1.0e7, "gamma_rad": 1.5e8, "gamma_vdw": 2.0e-8, "q": q}],
+            "continua": [{"lower": 0, "upper": 2 + i, "alpha0": 1.0e-18} for i in range(5)],
+            "collisions": [{"lower": 0, "upper": 1, "c_ul": 1.0e-7, "T_ref": 5000.0, "beta": -0.5}]}
+    ctx.atom(wide)
+    with pytest.raises(nl.NlteError) as ei:
+        ctx.atom(synth.with_active_continua(wide))
+    assert ei.value.code == nl.E_INVALID
