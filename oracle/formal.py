@@ -208,6 +208,27 @@ def formal_solution(lev, n, want_jbar=False, dirs=None):
     return Jeff, omL
 
 
+def _continuum_bilinear_only(lev):
+    if getattr(lev, "sc_interp", "bilinear") != "bilinear":
+        raise ValueError("the continuum frequencies are swept with bilinear upwind interpolation only")
+
+
+def continuum_opacity_source(lev, n, k):
+    """At plane k and every continuum frequency, from populations n: the opacities chi_t of
+    the continua, chi = sum_t chi_t, E_u per upper level u (both in the continuum_formal_
+    solution notation) and S = sum_u n_u E_u / chi (0 where chi = 0).  Arrays (nfc, ny, nx)."""
+    nup = len(lev.cont_uppers)
+    e2 = lev.cont_e[:, :, :, 0]                                     # (nfc, 1, 1)
+    chis = [lev.cont_alpha[t][:, None, None]
+            * np.maximum(n[lev.cont_lower[t]][k] - n[lev.cont_upper[t]][k] * lev.cont_g[t][:, k], 0.0)
+            for t in range(lev.ncont)]
+    E = [sum(lev.cont_alpha[t][:, None, None] * lev.cont_g[t][:, k]
+             for t in range(lev.ncont) if lev.cont_uidx[t] == u) * e2 for u in range(nup)]
+    chi = sum(chis)
+    eta = sum(n[lev.cont_uppers[u]][k] * E[u] for u in range(nup))
+    return chis, chi, E, safe_div(eta, chi)
+
+
 def continuum_formal_solution(lev, n, want_j=False):
     """Formal solution at the frequencies of the active continua, with the accumulations
     of the preconditioned continuum rates.
@@ -235,6 +256,7 @@ def continuum_formal_solution(lev, n, want_j=False):
     Returns an array (2 + nup, ncont, nz, ny, nx) of (U, G, L_.,0, ..., L_.,nup-1), and the
     mean intensity J (nfc, nz, ny, nx) too if want_j.
     """
+    _continuum_bilinear_only(lev)
     nfc = lev.cont_nu.size
     shape = (lev.nz, lev.ny, lev.nx)
     nup = len(lev.cont_uppers)
@@ -242,20 +264,9 @@ def continuum_formal_solution(lev, n, want_j=False):
     Jm = np.zeros((nfc,) + shape) if want_j else None
     f = 4.0 * np.pi / (ph.H * lev.cont_nu)                         # (nfc,)
     wa = lev.cont_w * lev.cont_alpha * f[None, :]                   # (ncont, nfc)
-    nl = [n[l] for l in lev.cont_lower]
-    nc = [n[c] for c in lev.cont_upper]
-    nu_up = [n[u] for u in lev.cont_uppers]
-    e2 = lev.cont_e[:, :, :, 0]                                     # (nfc, 1, 1)
 
     def plane(k):
-        chis = [lev.cont_alpha[t][:, None, None] * np.maximum(nl[t][k] - nc[t][k] * lev.cont_g[t][:, k], 0.0)
-                for t in range(lev.ncont)]
-        E = [sum(lev.cont_alpha[t][:, None, None] * lev.cont_g[t][:, k]
-                 for t in range(lev.ncont) if lev.cont_uidx[t] == u) * e2 for u in range(nup)]
-        chi = sum(chis)
-        eta = sum(nu_up[u][k] * E[u] for u in range(nup))
-        S = safe_div(eta, chi)
-        return chis, chi, E, S
+        return continuum_opacity_source(lev, n, k)
 
     for d in range(len(lev.wmu)):
         mu = lev.mu[d]
@@ -315,6 +326,28 @@ def emergent_intensity(lev, n, mus):
 
         def boundary(k):
             return np.broadcast_to(lev.B[lo, k], (lev.nf, lev.ny, lev.nx)).copy()
+
+        out.append(sweep(lev, mu, local, boundary, None, keep_top=True))
+    return np.stack(out)
+
+
+def continuum_emergent_intensity(lev, n, mus):
+    """I at the top plane at every continuum frequency for each upward direction in mus:
+    shape (ndir, nfc, ny, nx).  Opacity and source function as in continuum_formal_solution,
+    I = B_nu(T) at the lower boundary, bilinear upwind interpolation."""
+    _continuum_bilinear_only(lev)
+    out = []
+    for mu in np.atleast_2d(np.asarray(mus, dtype=np.float64)):
+        mu = mu / np.linalg.norm(mu)
+        if not mu[2] > 0:
+            raise ValueError("emergent directions must point upward")
+
+        def local(k):
+            _, chi, _, S = continuum_opacity_source(lev, n, k)
+            return chi, S, None
+
+        def boundary(k):
+            return lev.cont_B[:, k].copy()
 
         out.append(sweep(lev, mu, local, boundary, None, keep_top=True))
     return np.stack(out)

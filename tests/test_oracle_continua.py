@@ -1,13 +1,14 @@
 """Pins of the oracle's active continua (no GPU): the frequency quadrature against the
 analytic photo-ionisation rate, detailed balance in a Planck field, the fixed point of
 the preconditioned rates (continua ending on one upper level and on two, where the
-cross terms must be there), convergence of MALI and FAS with active continua, and the
-refusal of lines that reach a continuum edge."""
+cross terms must be there), convergence of MALI and FAS with active continua, the
+refusal of lines that reach a continuum edge, and the emergent intensity at the
+continuum frequencies (isothermal LTE gives B, empty upper levels give Beer's law)."""
 import numpy as np
 import pytest
 
 from oracle import physics as ph
-from oracle.formal import continuum_formal_solution, formal_solution
+from oracle.formal import continuum_emergent_intensity, continuum_formal_solution, formal_solution
 from oracle.levels import Level
 from oracle.rates import apply_W, fine_rhs, rate_matrix, system_matrix, zero_radiation
 from oracle.solver import Params, mali, solve_fas, solve_mali
@@ -143,3 +144,64 @@ def test_lines_reaching_a_continuum_edge_are_refused():
     Level(low, atm)
     with pytest.raises(ValueError, match="continuum edge"):
         Level(synth.with_active_continua(low), atm)
+
+
+# ---------------------------------------------------------------- emergent intensity
+
+def _planck(nu, T):
+    # B_nu(T) from its definition, not the oracle's
+    return 2.0 * ph.H * nu ** 3 / ph.C ** 2 / np.expm1(ph.H * nu / (ph.KB * T))
+
+
+@pytest.mark.parametrize("kind", list(ATOMS))
+def test_continuum_emergent_intensity_of_an_isothermal_lte_atmosphere_is_planck(kind):
+    # LTE populations: chi_t = alpha n_l* (1 - e^{-h nu/kT}) and eta = e^{-h nu/kT} 2 h nu^3/c^2
+    # sum alpha n_l*, so S = B at every continuum frequency, and I = B along every ray
+    atom, atm = small_case(kind=kind, nx=6, ny=5)
+    T = 6400.0
+    atm["T"] = np.full_like(atm["T"], T)
+    lev = Level(atom, atm)
+    mus = np.array([[0.0, 0.0, 1.0], [0.3, -0.2, 0.93], [1.0, 2.0, 3.0], [-0.7, 0.1, 0.2]])
+    I = continuum_emergent_intensity(lev, lev.nstar, mus)
+    assert I.shape == (4, lev.cont_nu.size, 5, 6)
+    assert np.allclose(I, _planck(lev.cont_nu, T)[None, :, None, None], rtol=1e-11, atol=0)
+
+
+def test_continuum_emergent_intensity_with_empty_upper_levels_follows_beers_law():
+    # n_c = 0: no emission, so B(T) from below is attenuated by exp(-chi L / mu_z) with
+    # chi = sum_t alpha0_t (nu_edge/nu)^3 n_l over the continua open at nu (hydrogenic)
+    atom = synth.with_active_continua(synth.two_ion_level_atom(9))
+    z = np.array([0.0, 1.0, 3.0, 4.0, 7.0, 11.0]) * synth.KM
+    shape = (z.size, 2, 3)
+    T = 5500.0
+    atm = {"nx": 3, "ny": 2, "nz": z.size, "dx": 50 * synth.KM, "dy": 70 * synth.KM, "z": z,
+           "T": np.full(shape, T), "ne": np.full(shape, 1e12), "nH": np.full(shape, 1e16),
+           "ntot": np.full(shape, 1e8), "vx": np.zeros(shape), "vy": np.zeros(shape), "vz": np.zeros(shape),
+           "chi_c": None}
+    lev = Level(atom, atm)
+    n = np.zeros((7,) + shape)
+    for i, v in enumerate((9.0e11, 6.0e11, 4.5e11, 1.2e12, 7.5e11)):
+        n[i] = v
+    mus = np.array([[0.6, -0.3, 1.5], [0.0, 0.0, 2.0], [-1.0, 1.0, 1.0]])
+    I = continuum_emergent_intensity(lev, n, mus)
+    nu = lev.cont_nu
+    lv = atom["levels"]
+    chi = np.zeros_like(nu)
+    for ct in atom["continua"]:
+        nue = ph.C * (lv[ct["upper"]]["E"] - lv[ct["lower"]]["E"])
+        on = nu >= nue * (1 - 1e-12)
+        chi[on] += ct["alpha0"] * (nue / nu[on]) ** 3 * n[ct["lower"], 0, 0, 0]
+    assert chi.min() * (z[-1] - z[0]) > 1.0   # optically thick at every continuum frequency
+    for d, mu in enumerate(mus):
+        muz = mu[2] / np.linalg.norm(mu)
+        expect = _planck(nu, T) * np.exp(-chi * (z[-1] - z[0]) / muz)
+        assert np.allclose(I[d], expect[:, None, None], rtol=1e-10, atol=0)
+
+
+def test_continuum_sweeps_refuse_bicubic_upwind_interpolation():
+    atom, atm = small_case()
+    lev = Level(atom, atm, sc_interp="hermite")
+    with pytest.raises(ValueError, match="bilinear"):
+        continuum_emergent_intensity(lev, lev.nstar, [[0.0, 0.0, 1.0]])
+    with pytest.raises(ValueError, match="bilinear"):
+        continuum_formal_solution(lev, lev.nstar)
