@@ -120,7 +120,8 @@ typedef struct {
                                   level's population: at most 4 distinct upper levels); every
                                   line frequency must then lie below every continuum edge,
                                   since the line sweeps carry no bound-free opacity
-                                  (NLTE_E_INVALID otherwise); 0: fixed continua with
+                                  (NLTE_E_INVALID otherwise), and jobs take the bilinear
+                                  upwind interpolation (sc_interp); 0: fixed continua with
                                   photo-rates at J = B(T) */
     const double* cont_nu;     /* ncont_nu frequencies (Hz), increasing, containing every
                                   continuum edge; host memory, copied */
@@ -288,6 +289,15 @@ nlte_status nlte_get_source_function(nlte_ctx* ctx, nlte_job job, double* dst, i
  * frequencies of all lines in atom order. */
 nlte_status nlte_emergent_intensity(nlte_ctx* ctx, nlte_job job, int ndir, const double* mu,
                                     float* dst, int dst_mem);
+/* Emergent intensity at the continuum frequencies of an atom with active continua
+ * (nlte_atom_desc.ncont_nu > 0; NLTE_E_INVALID otherwise), for `ndir` upward directions
+ * mu[ndir][3] (normalised internally): an upward formal solution in FP64 from the finest
+ * populations with the continua's opacity and source function, B_nu(T) at the lower
+ * boundary and bilinear upwind interpolation (the emergent spectrum of Sect. 5, Fig. 10,
+ * at the continuum frequencies).  dst: [ndir][ncont_nu][ny][nx] FP32, frequencies in the
+ * order of cont_nu; dst_mem says whether dst is host or device memory. */
+nlte_status nlte_emergent_continuum_intensity(nlte_ctx* ctx, nlte_job job, int ndir, const double* mu,
+                                              float* dst, int dst_mem);
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): nlte_emergent_intensity with the
  * output in device memory (dst: [ndir][nf][ny][nx] FP32, host memory is rejected with

@@ -1047,6 +1047,82 @@ __global__ __launch_bounds__(3 * cont_max_chunks<R>() * 64) void sweep_cont_kern
         }
 }
 
+// Emergent intensity at the continuum frequencies: one upward plane step for every
+// (continuum frequency, plane point) of one direction, FP64 throughout from the
+// populations, the LTE populations and T (opacity sum_t alpha_t (n_l - n_c g_t)^+,
+// emissivity sum_t n_c alpha_t g_t 2 h nu^3/c^2, g_t = (n_l*/n_c*) e^{-h nu/kT}), B_nu(T)
+// at the lower boundary, bilinear upwind interpolation.
+struct EmergentContArgs {
+    const AtomInfo* atom;
+    int nx, ny, nz, nfc;
+    size_t nxy, nvox;
+    double dx, dy, mux, muy, muz;
+    const double* z;
+    const double* prim;      // FP64 primitive fields (T)
+    const double* nstar;     // [N][nvox]
+    const double* n;         // [N][nvox]
+    const double* cnu;       // [nfc]
+    const double* ce;        // [nfc] 2 h nu^3 / c^2
+    const double* calpha;    // [ncont][nfc], 0 below the edge
+    double* state;           // [2][3][nfc][nxy]
+    float* out;              // [nfc][nxy]
+};
+
+__global__ void emergent_cont_step_kernel(EmergentContArgs a, int k) {
+    const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= size_t(a.nfc) * a.nxy) return;
+    const int f = int(idx / a.nxy);
+    const size_t g = idx % a.nxy;
+    const AtomInfo& at = *a.atom;
+    const size_t nv = a.nvox, v = size_t(k) * a.nxy + g;
+    const double x = exp(-kH / (kKB * a.prim[P_T * nv + v]) * a.cnu[f]);
+    const double e = a.ce[f];
+    double chi = 0.0, eta = 0.0;
+    for (int t = 0; t < at.ncont; ++t) {
+        const double al = a.calpha[size_t(t) * a.nfc + f];
+        const int lo = at.cont_lower[t], up = at.cont_upper[t];
+        const double gg = a.nstar[size_t(lo) * nv + v] / a.nstar[size_t(up) * nv + v] * x;
+        const double nl = fmax(a.n[size_t(lo) * nv + v], 0.0), nc = fmax(a.n[size_t(up) * nv + v], 0.0);
+        chi += al * fmax(nl - nc * gg, 0.0);
+        eta += nc * al * gg * e;
+    }
+    const double S = chi > 0.0 ? eta / chi : 0.0;
+    const size_t ps = size_t(a.nfc) * a.nxy;
+    double* cur = a.state + size_t(k & 1) * 3 * ps;
+    double I;
+    if (k == 0) {
+        I = e * x / (1.0 - x);
+    } else {
+        const double* prv = a.state + size_t((k - 1) & 1) * 3 * ps;
+        const double ds = (a.z[k] - a.z[k - 1]) / a.muz;
+        const double sx = -ds * a.mux / a.dx, sy = -ds * a.muy / a.dy;
+        const double fsx = floor(sx), fsy = floor(sy);
+        const double fx = sx - fsx, fy = sy - fsy;
+        const int xx = int(g % a.nx), yy = int(g / a.nx);
+        int x0 = int((long long)(xx + (long long)fsx) % a.nx); if (x0 < 0) x0 += a.nx;
+        int y0 = int((long long)(yy + (long long)fsy) % a.ny); if (y0 < 0) y0 += a.ny;
+        const int x1 = (x0 + 1 == a.nx) ? 0 : x0 + 1;
+        const int y1 = (y0 + 1 == a.ny) ? 0 : y0 + 1;
+        const size_t fo = size_t(f) * a.nxy;
+        const size_t g00 = fo + size_t(y0) * a.nx + x0, g01 = fo + size_t(y0) * a.nx + x1;
+        const size_t g10 = fo + size_t(y1) * a.nx + x0, g11 = fo + size_t(y1) * a.nx + x1;
+        const double w00 = (1.0 - fx) * (1.0 - fy), w01 = fx * (1.0 - fy);
+        const double w10 = (1.0 - fx) * fy, w11 = fx * fy;
+        const double Iu = w00 * prv[g00] + w01 * prv[g01] + w10 * prv[g10] + w11 * prv[g11];
+        const double Su = w00 * prv[ps + g00] + w01 * prv[ps + g01] + w10 * prv[ps + g10] + w11 * prv[ps + g11];
+        const double Cu = w00 * prv[2 * ps + g00] + w01 * prv[2 * ps + g01] + w10 * prv[2 * ps + g10] +
+                          w11 * prv[2 * ps + g11];
+        const double dtau = 0.5 * (Cu + chi) * ds;
+        double ex, pu, po, omp;
+        sc_coeffs(dtau, ex, pu, po, omp);
+        I = Iu * ex + pu * Su + po * S;
+    }
+    cur[size_t(f) * a.nxy + g] = I;
+    cur[ps + size_t(f) * a.nxy + g] = S;
+    cur[2 * ps + size_t(f) * a.nxy + g] = chi;
+    if (k == a.nz - 1) a.out[size_t(f) * a.nxy + g] = float(I);
+}
+
 // ------------------------------------------------------------------ rate equations
 // Rate matrix from the fixed rates and the preconditioned radiative rates of
 // Rybicki & Hummer (1991): upward B_ij Jeff, downward A_ji (1 - L*) + B_ji Jeff.

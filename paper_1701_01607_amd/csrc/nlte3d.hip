@@ -332,6 +332,7 @@ struct JobBase {
     virtual void source_function(double* dst, int mem) = 0;
     virtual void emergent(int ndir, const double* mu, float* dst, int mem) = 0;
     virtual void emergent_into(int ndir, const double* mu, float* dst, double* state, size_t state_bytes) = 0;
+    virtual void emergent_continuum(int ndir, const double* mu, float* dst, int mem) = 0;
     virtual void restrict_hook(int level, int nq, const double* src, double* dst) = 0;
     virtual void prolong_hook(int level, int nq, const double* src, double* dst) = 0;
 };
@@ -387,7 +388,7 @@ struct Job : JobBase {
     std::vector<std::unique_ptr<Level>> lev;
     DevBuf atom_d, qf, wf, line_of_d, state, topI, scalar, repairs, estate, eout, flag, nprev;
     // active continua: frequency tables (R for the sweep, FP64 for the setup) and plane state
-    DevBuf ctab_r, cnu_d, ce_d, cfw_d, calpha_d, cstate;
+    DevBuf ctab_r, cnu_d, ce_d, cfw_d, calpha_d, cstate, cestate;
     int nfc = 0;
     AtomInfo info{};
     int DB = 0;   // directions per sweep block (0: autotuned per level)
@@ -1493,6 +1494,45 @@ struct Job : JobBase {
         }
     }
 
+    // Emergent intensity at the continuum frequencies (active continua): an upward formal
+    // solution per direction in FP64 from the finest populations, I of the top plane to
+    // dst[d][nfc][nxy].
+    void emergent_continuum(int ndir, const double* mu, float* dst, int mem) override {
+        REQUIRE(info.cont_active, "the atom has no active continua");
+        Level& F = *lev[nlev - 1];
+        check_mu(ndir, mu);
+        if (!cestate.p) dalloc(cestate, sizeof(double) * 2 * 3 * size_t(nfc) * F.nxy);
+        DevBuf o;
+        float* target = dst;
+        if (mem != NLTE_MEM_DEVICE) {
+            dalloc(o, sizeof(float) * size_t(ndir) * nfc * F.nxy);
+            target = o.as<float>();
+        }
+        for (int d = 0; d < ndir; ++d) {
+            const double m[3] = {mu[3 * d], mu[3 * d + 1], mu[3 * d + 2]};
+            const double nrm = std::sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+            EmergentContArgs a;
+            a.atom = atom_d.as<AtomInfo>();
+            a.nx = F.nx; a.ny = F.ny; a.nz = F.nz; a.nfc = nfc;
+            a.nxy = F.nxy; a.nvox = F.nvox;
+            a.dx = F.dx; a.dy = F.dy;
+            a.mux = m[0] / nrm; a.muy = m[1] / nrm; a.muz = m[2] / nrm;
+            a.z = F.dz.as<double>();
+            a.prim = F.prim.as<double>();
+            a.nstar = F.nstar.as<double>();
+            a.n = F.n.as<double>();
+            a.cnu = cnu_d.as<double>(); a.ce = ce_d.as<double>(); a.calpha = calpha_d.as<double>();
+            a.state = cestate.as<double>();
+            a.out = target + size_t(d) * nfc * F.nxy;
+            for (int k = 0; k < F.nz; ++k)
+                emergent_cont_step_kernel<<<blocks_for(size_t(nfc) * F.nxy, 256), 256, 0, st()>>>(a, k);
+            HIPCHK(hipGetLastError());
+        }
+        if (mem != NLTE_MEM_DEVICE)
+            HIPCHK(hipMemcpyAsync(dst, target, sizeof(float) * size_t(ndir) * nfc * F.nxy, hipMemcpyDeviceToHost, st()));
+        HIPCHK(hipStreamSynchronize(st()));
+    }
+
     void restrict_hook(int level, int nq, const double* src, double* dst) override {
         REQUIRE(level >= 1 && level < nlev, "restriction needs 1 <= level < nlev");
         restrict_fields(level, nq, src, dst);
@@ -2594,7 +2634,9 @@ static bool transfer_ops_ok(const nlte_params* p) {
 }
 
 // Checks of the solve parameters shared by nlte_job_create and nlte_submit.
-static void check_params(const nlte_params* p) {
+static void check_params(const nlte_params* p, const nlte_atom* atom) {
+    REQUIRE(!(atom->info.cont_active && p->sc_interp == NLTE_SC_HERMITE),
+            "active continua are swept with bilinear upwind interpolation only");
     REQUIRE(p->method >= NLTE_MALI && p->method <= NLTE_FMG, "unknown method");
     REQUIRE(p->precision == NLTE_FP64 || p->precision == NLTE_MIXED, "unknown precision");
     REQUIRE(transfer_ops_ok(p), "unknown restriction or interpolation scheme");
@@ -2615,7 +2657,7 @@ nlte_status nlte_job_create(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_a
                             const nlte_params* params, nlte_job* job) {
     return guarded(ctx, [&]() -> nlte_status {
         REQUIRE(atmos && atom && params && job, "null argument");
-        check_params(params);
+        check_params(params, atom);
         std::unique_ptr<JobBase> j;
         if (params->precision == NLTE_FP64) {
             auto* p = new Job<double>(ctx);
@@ -2710,6 +2752,15 @@ nlte_status nlte_emergent_intensity(nlte_ctx* ctx, nlte_job job, int ndir, const
     return guarded(ctx, [&]() -> nlte_status {
         REQUIRE(ndir >= 1 && mu && dst, "bad emergent-intensity arguments");
         find_job(ctx, job)->emergent(ndir, mu, dst, dst_mem);
+        return NLTE_OK;
+    });
+}
+
+nlte_status nlte_emergent_continuum_intensity(nlte_ctx* ctx, nlte_job job, int ndir, const double* mu, float* dst,
+                                              int dst_mem) {
+    return guarded(ctx, [&]() -> nlte_status {
+        REQUIRE(ndir >= 1 && mu && dst, "bad emergent-intensity arguments");
+        find_job(ctx, job)->emergent_continuum(ndir, mu, dst, dst_mem);
         return NLTE_OK;
     });
 }
@@ -2878,7 +2929,7 @@ nlte_status nlte_submit(nlte_ctx* ctx, const nlte_atmos* atmos, const nlte_atom*
                         nlte_job* job) {
     return guarded(ctx, [&]() -> nlte_status {
         REQUIRE(atmos && atom && params && job, "null argument");
-        check_params(params);
+        check_params(params, atom);
         REQUIRE(params->init != NLTE_INIT_USER && params->top_I == nullptr,
                 "served jobs take no host arrays in params");
         const int nlev = std::max(1, params->method == NLTE_MALI ? 1 : params->nlev);

@@ -32,7 +32,8 @@ SYMBOLS = (
     "nlte_atom_create", "nlte_atom_destroy", "nlte_atmos_create", "nlte_atmos_destroy",
     "nlte_job_create", "nlte_job_run", "nlte_solve", "nlte_release", "nlte_batch_run",
     "nlte_get_populations", "nlte_set_populations", "nlte_get_source_function", "nlte_job_stats",
-    "nlte_emergent_intensity", "nlte_emergent_intensity_noalloc", "nlte_history",
+    "nlte_emergent_intensity", "nlte_emergent_intensity_noalloc", "nlte_emergent_continuum_intensity",
+    "nlte_history",
     "nlte_formal_solution", "nlte_mali", "nlte_rate_solve", "nlte_residual", "nlte_vcycle",
     "nlte_restrict", "nlte_prolong", "nlte_voigt",
     "nlte_serve_config", "nlte_serve_batching", "nlte_estimate_footprint", "nlte_submit", "nlte_poll", "nlte_wait",
@@ -152,6 +153,7 @@ def load(path=None):
     lib.nlte_get_source_function.argtypes = [P, I64, P, ct.c_int]
     lib.nlte_emergent_intensity.argtypes = [P, I64, ct.c_int, P, P, ct.c_int]
     lib.nlte_emergent_intensity_noalloc.argtypes = [P, I64, ct.c_int, P, P]
+    lib.nlte_emergent_continuum_intensity.argtypes = [P, I64, ct.c_int, P, P, ct.c_int]
     lib.nlte_history.argtypes = [P, I64, P, ct.c_int]
     lib.nlte_job_stats.argtypes = [P, I64, ct.POINTER(Result)]
     lib.nlte_formal_solution.argtypes = [P, I64, ct.c_int, P, P, ct.c_int]
@@ -413,6 +415,13 @@ class Job:
         out = np.empty((mus.shape[0], nf, ny, nx), dtype=np.float32)
         self.ctx.check(self.lib.nlte_emergent_intensity(self.ctx.h, self.id, mus.shape[0], _ptr(mus), _ptr(out),
                                                         MEM_HOST))
+        return out
+
+    def emergent_continuum(self, mus, nfc, ny, nx):
+        mus = _f64(np.atleast_2d(mus))
+        out = np.empty((mus.shape[0], nfc, ny, nx), dtype=np.float32)
+        self.ctx.check(self.lib.nlte_emergent_continuum_intensity(self.ctx.h, self.id, mus.shape[0], _ptr(mus),
+                                                                  _ptr(out), MEM_HOST))
         return out
 
     def history(self):

@@ -1,11 +1,12 @@
 """Active overlapping continua on the GPU against the oracle (FP64 and mixed precision):
 zero-radiation start, MALI iterations and FAS cycles, for continua ending on one upper
 level and on two (the seven-level atom), the residual with the cross terms of two upper
-levels, and the atoms the library refuses."""
+levels, the emergent intensity at the continuum frequencies, and the atoms and settings
+the library refuses."""
 import numpy as np
 import pytest
 
-from oracle.formal import continuum_formal_solution, formal_solution
+from oracle.formal import continuum_emergent_intensity, continuum_formal_solution, formal_solution
 from oracle.levels import Level
 from oracle.rates import apply_W, cross_terms, fine_rhs, rate_matrix, system_matrix, zero_radiation
 from oracle.solver import Params as OParams
@@ -138,4 +139,37 @@ def test_atoms_the_active_continua_cannot_represent_are_refused(nl, ctx):
     ctx.atom(wide)
     with pytest.raises(nl.NlteError) as ei:
         ctx.atom(synth.with_active_continua(wide))
+    assert ei.value.code == nl.E_INVALID
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_continuum_emergent_intensity_parity(nl, ctx, ragged, prec):
+    # the kernel works in FP64 from the job's populations in both precisions: against the
+    # oracle at the same populations only the FP32 output rounding is left
+    atom, atm, lev, n0 = ragged
+    N = len(atom["levels"])
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=prec, nlev=1))
+    job.mali(0, 2)
+    n = job.populations(0, (N, atm["nz"], atm["ny"], atm["nx"]))
+    mus = np.array([[0.0, 0.0, 1.0], [0.3, -0.2, 0.93], [-1.0, 2.0, 3.0]])
+    nfc = len(atom["continuum_nu"])
+    Ig = job.emergent_continuum(mus, nfc, atm["ny"], atm["nx"])
+    Io = continuum_emergent_intensity(lev, n, mus)
+    e = relerr(Ig, Io)
+    print(f"prec={prec} {len(lev.cont_uppers)} upper level(s): continuum emergent intensity err {e:.2e}")
+    assert Ig.shape == Io.shape and np.all(Io > 0)
+    assert e < 2e-7
+
+
+def test_continuum_emergent_intensity_is_refused_where_it_does_not_apply(nl, ctx):
+    atom, atm = case()
+    # no active continua
+    plain = {k: v for k, v in atom.items() if k != "continuum_nu"}
+    job = ctx.job(ctx.atmos(atm), ctx.atom(plain), nl.SolveParams(method=nl.MALI, precision=0, nlev=1))
+    with pytest.raises(nl.NlteError) as ei:
+        job.emergent_continuum([[0.0, 0.0, 1.0]], 41, atm["ny"], atm["nx"])
+    assert ei.value.code == nl.E_INVALID
+    # the continuum sweeps have no bicubic upwind interpolation
+    with pytest.raises(nl.NlteError) as ei:
+        ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=0, nlev=1, sc_interp=1))
     assert ei.value.code == nl.E_INVALID
