@@ -2096,9 +2096,12 @@ size_t job_footprint(const nlte_ctx* ctx, const nlte_atmos* atm, const nlte_atom
     Q = std::max(1, std::min(Q, int(4294967295.0 / (double(cell) * double(fine_nxy)))));
     bytes += cell * nstate * kNDir * size_t(nline) * Q * fine_nxy;
     bytes += 8 * size_t(N) * fine_nvox;
-    if (atom->info.cont_active)       // continuum plane state and frequency tables
+    // active continua: plane state, frequency tables, and the continuum emergent intensity's
+    // state with one direction of its output
+    if (atom->info.cont_active)
         bytes += 3 * R * 2 * kNDir * atom->cnu.size() * fine_nxy +
-                 8 * (2 + 2 * size_t(atom->info.ncont)) * atom->cnu.size() + R * kContRow * atom->cnu.size();
+                 8 * (2 + 2 * size_t(atom->info.ncont)) * atom->cnu.size() + R * kContRow * atom->cnu.size() +
+                 (8 * 6 + 4) * atom->cnu.size() * fine_nxy;
     if (p->top_I) bytes += R * size_t(nf) * fine_nxy;
     bytes += 8 * 6 * size_t(nf) * fine_nxy;             // emergent-intensity state
     bytes += 4 * size_t(nf) * fine_nxy;                  // one direction of host-bound output

@@ -161,6 +161,22 @@ def test_continuum_emergent_intensity_parity(nl, ctx, ragged, prec):
     assert e < 2e-7
 
 
+def test_continuum_emergent_intensity_into_device_memory_equals_the_host_copy(nl, ctx):
+    import ctypes as ct
+    import torch
+    atom, atm = case(kind="two_upper")
+    job = ctx.job(ctx.atmos(atm), ctx.atom(atom), nl.SolveParams(method=nl.MALI, precision=1, nlev=1))
+    job.mali(0, 1)
+    mus = np.ascontiguousarray([[0.0, 0.0, 1.0], [0.5, 0.1, 0.8]], dtype=np.float64)
+    nfc = len(atom["continuum_nu"])
+    host = job.emergent_continuum(mus, nfc, atm["ny"], atm["nx"])
+    dev = torch.full((2, nfc, atm["ny"], atm["nx"]), float("nan"), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    ctx.check(ctx.lib.nlte_emergent_continuum_intensity(ctx.h, job.id, 2, mus.ctypes.data_as(ct.c_void_p),
+                                                        ct.c_void_p(dev.data_ptr()), nl.MEM_DEVICE))
+    assert np.array_equal(dev.cpu().numpy(), host)
+
+
 def test_continuum_emergent_intensity_is_refused_where_it_does_not_apply(nl, ctx):
     atom, atm = case()
     # no active continua
