@@ -161,6 +161,29 @@ def test_continuum_emergent_intensity_parity(nl, ctx, ragged, prec):
     assert e < 2e-7
 
 
+@pytest.mark.parametrize("method", ["FAS", "MALI"])
+def test_graph_replay_with_active_continua_equals_eager(nl, ctx, method):
+    # under capture the continuum sweep follows the line sweep on the job's stream instead
+    # of running beside it: histories and populations must stay bitwise the same
+    atom, atm = case(nx=8, ny=8, nz=17, seed=31, kind="two_upper")
+    atm["ntot"] = atm["ntot"] * 0.1
+    m = nl.FAS if method == "FAS" else nl.MALI
+    nlev = 3 if m == nl.FAS else 1
+    N = len(atom["levels"])
+    outs = []
+    for graph in (0, 1):
+        job = ctx.job(ctx.atmos(atm), ctx.atom(atom),
+                      nl.SolveParams(method=m, precision=nl.MIXED, nlev=nlev, nu0=3, nu1=2, nu2=2, nu3=6,
+                                     E_target=0.0, max_iter=4, graph=graph))
+        rc, r = job.run()
+        assert rc >= 0
+        outs.append((job.history(), job.populations(nlev - 1, (N, atm["nz"], atm["ny"], atm["nx"]))))
+        job.close()
+    assert len(outs[0][0]) > 0
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_continuum_emergent_intensity_into_device_memory_equals_the_host_copy(nl, ctx):
     import ctypes as ct
     import torch
