@@ -47,10 +47,10 @@ STATE_BYTES_PER_UPDATE = {False: 16.0, True: 48.0}   # keyed by "FP64 sweep"
 # HBM bytes per update of the finest-grid sweep launches from FETCH_SIZE + WRITE_SIZE
 # counter runs of `bench.py --kernel-probe` (each scaled by the counter's reading for a
 # plain device copy of known size), keyed by (workload, directions per block).  Only for
-# the kernel as it was when the counters were taken: FETCH 11.24 B + WRITE 8.03 B on the
-# 504x504x497 grid with three-direction blocks (each upwind cell reaches HBM about 1.4
-# times for its four readers).
-MEASURED_BYTES_PER_UPDATE = {("caii6_504x504x497", 3): 19.27}
+# the kernel as it was when the counters were taken: FETCH 9.35 B + WRITE 8.03 B on the
+# 504x504x497 grid with three-direction blocks and non-temporal cell stores (each upwind
+# cell reaches HBM about 1.17 times for its four readers).
+MEASURED_BYTES_PER_UPDATE = {("caii6_504x504x497", 3): 17.38}
 VOXEL_BYTES_PER_GROUP = (11 + 2) * 4.0   # FP32; twice that in FP64
 
 # Algorithmic flops per update (FMA = 2; a reciprocal, exponential or cosine = 1) of the
