@@ -205,3 +205,28 @@ def test_continuum_sweeps_refuse_bicubic_upwind_interpolation():
         continuum_emergent_intensity(lev, lev.nstar, [[0.0, 0.0, 1.0]])
     with pytest.raises(ValueError, match="bilinear"):
         continuum_formal_solution(lev, lev.nstar)
+
+
+def test_cross_terms_by_hand():
+    # Two continua, 0 -> 2 and 1 -> 3, so two upper levels.  The net upward rate of
+    # continuum 0 holds n_3 L_0,3: a flux out of level 0 (X[0, 3] = +L) into level 2
+    # (X[2, 3] = -L); likewise continuum 1 with n_2 L_1,2 (X[1, 2] = +L, X[3, 2] = -L).  The
+    # terms in each continuum's own upper level stay out of X (they are in P).
+    from types import SimpleNamespace
+    from oracle.rates import cross_terms
+    lev = SimpleNamespace(active_continua=True, N=4, ncont=2, cont_lower=[0, 1], cont_upper=[2, 3],
+                          cont_uppers=[2, 3])
+    cont = np.zeros((4, 2, 1, 1, 1))
+    cont[2, 0] = 5.0      # L_0,2 (own)
+    cont[3, 0] = 3.0      # L_0,3
+    cont[2, 1] = 7.0      # L_1,2
+    cont[3, 1] = 11.0     # L_1,3 (own)
+    X = cross_terms(lev, cont)[..., 0, 0, 0]
+    expect = np.zeros((4, 4))
+    expect[0, 3], expect[2, 3] = 3.0, -3.0
+    expect[1, 2], expect[3, 2] = 7.0, -7.0
+    assert np.array_equal(X, expect)
+    # one upper level: nothing to add
+    lev1 = SimpleNamespace(active_continua=True, N=4, ncont=2, cont_lower=[0, 1], cont_upper=[2, 2],
+                           cont_uppers=[2])
+    assert cross_terms(lev1, np.zeros((3, 2, 1, 1, 1))) is None
